@@ -1,0 +1,162 @@
+/*
+ * bwrank: rank of large sparse integer matrices modulo a prime by the block
+ * Wiedemann method, on AMD MI355X (gfx950).
+ *
+ * Method (Dumas, Elbaz-Vincent, Giorgi, Urbanska, "Parallel computation of the
+ * rank of large sparse matrices from algebraic K-theory"):
+ *   Section 2.2  the block Wiedemann sequence X A^i Y of s x s matrices;
+ *   Section 2.3  preconditioners of the form A^T A and projections by blocks;
+ *   Section 2.4  the minimal matrix generator through a sigma-basis (PM-Basis),
+ *                polynomial matrix products with FFT primes and the CRT;
+ *   Section 2.5  the "Block Wiedemann Rank Algorithm": precondition, compute
+ *                S_i = Y^T A~^i Y for i = 0 .. 2n/s + O(1), take the minimal
+ *                generator F, return deg det F - codeg det F.
+ *
+ * Conventions for every entry point:
+ *   - Return value 0 (BWR_OK) or a negative error code below; on error nothing
+ *     is written to host outputs and bwr_last_error() describes the failure
+ *     (thread-local, valid until the next call on the same thread).
+ *   - Matrices are CSR with int64 row pointers (m + 1 entries, row_ptr[0] = 0,
+ *     non-decreasing, row_ptr[m] = nnz), int32 column indices in [0, n) and
+ *     int32 values (any sign; duplicates are summed).  They are read only and
+ *     never retained after a call returns.
+ *   - Residues are uint32.  Inputs may be any uint32 (they are reduced mod p);
+ *     outputs are canonical in [0, p).
+ *   - Blocks are row-major: an n x s block X has X[r * s + c].
+ *   - "_dev" entry points take device pointers (memory of the current HIP
+ *     device) and a hipStream_t passed as void* (NULL = the null stream); they
+ *     return after the work on that stream has completed.  Every other entry
+ *     point takes host pointers.
+ *   - p must be a prime with 3 <= p < 2^31 (BWR_EPRIME otherwise).
+ *   - Block sizes s are 1 .. 64.
+ */
+#ifndef BWRANK_H
+#define BWRANK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BWR_OK 0
+#define BWR_EINVAL (-1)  /* NULL pointer, bad size, malformed CSR, zero diagonal entry */
+#define BWR_EPRIME (-2)  /* p is not a prime in [3, 2^31) */
+#define BWR_ENOMEM (-3)  /* device or host allocation failed */
+#define BWR_EDEVICE (-4) /* HIP runtime error */
+#define BWR_EBUSY (-5)   /* server queue full */
+#define BWR_ESHORT (-6)  /* the generator failed on the check terms (sequence too short) */
+
+typedef struct {
+    int64_t m, n;            /* rows, columns */
+    int64_t nnz;             /* number of stored entries = row_ptr[m] */
+    const int64_t* row_ptr;  /* m + 1 */
+    const int32_t* col_idx;  /* nnz, 0 <= col < n */
+    const int32_t* val;      /* nnz */
+} bwr_csr;
+
+/* Timings and sizes of one rank computation (all optional to read). */
+typedef struct {
+    int64_t rank;         /* the result */
+    int64_t nb;           /* dimension B acts on: min(m, n) */
+    int32_t s;            /* block size used: min(block, nb) */
+    int32_t transposed;   /* 1 when B = D_c A D_r A^T D_c (m < n) */
+    int64_t len;          /* sequence terms used for the generator: 2 + ceil(2 nb / s) */
+    int64_t check_terms;  /* extra terms the generator was verified on */
+    int64_t sum_delta;    /* sum of the generator's row degrees */
+    double t_encode;      /* seconds: validation and device encoding of A */
+    double t_sequence;    /* seconds: the L + check terms on the device */
+    double t_sigma;       /* seconds: sigma-basis on the host */
+    double t_readout;     /* seconds: check and read-out */
+    int32_t sigma_threads;
+    int32_t pad;
+} bwr_rank_info;
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int bwr_version(void);
+
+/* Message for the last non-zero return on this thread ("" if none). */
+const char* bwr_last_error(void);
+
+/* 1 if p is a prime in [3, 2^31), else 0 (deterministic Miller-Rabin, bases 2, 7, 61). */
+int bwr_is_prime(uint32_t p);
+
+/* Sequence length the rank uses for an nb-dimensional B and block size s:
+ * 2 + ceil(2 nb / s) (Section 2.5, step 2: 2n/s + O(1) terms).  -1 if s < 1 or nb < 0. */
+int64_t bwr_sequence_length(int64_t nb, int32_t s);
+
+/* Host threads used by the sigma-basis (default: min(hardware threads, 16)). */
+int bwr_set_threads(int32_t n);
+
+/* The random residues the rank draws, from a counter-based SplitMix64
+ * (Steele, Lea, Flood 2014): with mix() the SplitMix64 finaliser and
+ * gamma = 0x9E3779B97F4A7C15, output(state, i) = mix(state + (i + 1) gamma),
+ * key = output(seed, stream) and element i = output(key, i).
+ * out[r * s + c] = element(r * s + c) for r < rows, c < s, from stream
+ * `stream` (0 = V, 1 = U, 2 = row diagonal, 3 = column diagonal); block
+ * entries are h mod p, diagonal entries (diag != 0) 1 + h mod (p - 1).
+ * Host computation (the device draws the same values). */
+int bwr_random_block(uint64_t seed, int32_t stream, int64_t rows, int32_t s, uint32_t p, int32_t diag,
+                     uint32_t* out);
+
+/* The projected sequence (Sections 2.2-2.3): S_k = U^T B^k V mod p for
+ * k < len, with B = D_c A^T D_r A D_c (n x n).  d_row (m) and d_col (n) are the
+ * diagonals (NULL = identity; d_col entries must be non-zero mod p).  U, V are
+ * n x s.  S_out has len * s * s entries: S_out[(k * s + i) * s + j] = S_k[i][j].
+ * No transposition: B always acts on GF(p)^n. */
+int bwr_sequence(const bwr_csr* A, const uint32_t* d_row, const uint32_t* d_col, const uint32_t* U,
+                 const uint32_t* V, uint32_t p, int32_t s, int64_t len, uint32_t* S_out);
+
+/* Same with every pointer (the CSR arrays included) in device memory. */
+int bwr_sequence_dev(const bwr_csr* A_dev, const uint32_t* d_row, const uint32_t* d_col, const uint32_t* U,
+                     const uint32_t* V, uint32_t p, int32_t s, int64_t len, uint32_t* S_out, void* stream);
+
+/* One application of B (the two sparse products and both diagonal scales of
+ * a step): Z = D_c A^T D_r A D_c X mod p, X and Z n x s, device memory. */
+int bwr_apply_dev(const bwr_csr* A_dev, const uint32_t* d_row, const uint32_t* d_col, const uint32_t* X,
+                  uint32_t p, int32_t s, uint32_t* Z, void* stream);
+
+/* Rank of A over GF(p) by the block Wiedemann rank algorithm (Section 2.5):
+ * B = D_c A^T D_r A D_c on the smaller side (A and A^T swap when m < n),
+ * D_r, D_c, U, V drawn from `seed`, 2 + ceil(2 nb / s) terms plus 4 check
+ * terms, sigma-basis generator, rank = deg det F - codeg det F.  Monte Carlo:
+ * the result never exceeds the true rank and equals it with high
+ * probability.  An all-zero or empty matrix returns 0 without a launch.
+ * info may be NULL. */
+int bwr_rank_modp(const bwr_csr* A, uint32_t p, int32_t block, uint64_t seed, int64_t* rank_out,
+                  bwr_rank_info* info);
+
+/* Same with the CSR arrays in device memory. */
+int bwr_rank_modp_dev(const bwr_csr* A_dev, uint32_t p, int32_t block, uint64_t seed, void* stream,
+                      int64_t* rank_out, bwr_rank_info* info);
+
+/* Average device time in microseconds (HIP events on `stream`) of the three
+ * kernels of one step of the sequence, each launched `iters` times back to
+ * back on A (device CSR) with random blocks of width s: us_out[0] = the first
+ * sparse product with the row scale (A X, or A^T X when transpose != 0),
+ * us_out[1] = the second sparse product with the column scale, us_out[2] =
+ * the U^T projection.  For measurement; computes nothing the caller keeps. */
+int bwr_time_step_kernels_dev(const bwr_csr* A_dev, uint32_t p, int32_t s, int32_t transpose, int32_t iters,
+                              void* stream, double* us_out);
+
+/* Minimal generator of a host sequence S (len x s x s, residues mod p) via
+ * the sigma-basis of [S(x); -I] of order len (Section 2.4).  delta_out (s):
+ * shifted row degrees; P_out ((max_deg + 1) x s x s, capacity given by
+ * P_cap_terms >= len + 1): P_out[(k * s + i) * s + j] = coefficient of x^k in
+ * the p-part of generator row i, so that F_i(x) = x^delta_i P_i(1/x)
+ * satisfies sum_j F_{i,j} S_{l+j} = 0.  *max_deg_out = max delta. */
+int bwr_min_generator(const uint32_t* S, int64_t len, int32_t s, uint32_t p, int64_t* delta_out,
+                      uint32_t* P_out, int64_t P_cap_terms, int64_t* max_deg_out);
+
+/* Rank read-out from a host sequence: generator from the first `len` terms,
+ * verified on `check` further terms (S holds len + check terms), then
+ * deg det F - codeg det F (Section 2.5, steps 3-4). */
+int bwr_rank_from_sequence(const uint32_t* S, int64_t len, int64_t check, int32_t s, uint32_t p,
+                           int64_t* rank_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BWRANK_H */

@@ -1,0 +1,8 @@
+"""MI355X-native block Wiedemann rank of sparse integer matrices modulo p.
+
+The computation runs in libbwrank.so (HIP kernels for gfx950 plus host C++);
+this package is its ctypes binding.  See include/bwrank.h for the C-ABI.
+"""
+from .binding import (BwrError, LIB_PATH, EXPORTED, lib, version, is_prime, sequence_length, set_threads,
+                      random_block, sequence, rank_modp, min_generator, rank_from_sequence, csr_to_device,
+                      sequence_dev, apply_dev, rank_modp_dev, time_step_kernels_dev)

@@ -1,0 +1,254 @@
+"""ctypes binding of libbwrank.so: argument marshalling only.
+
+Every function forwards to the C-ABI of the same name (include/bwrank.h).
+Host variants take numpy arrays; ``*_dev`` variants take torch tensors that
+live on a HIP device and use torch's current stream.  There is no Python or
+CPU fallback: if the library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbwrank.so")
+
+BWR_OK, BWR_EINVAL, BWR_EPRIME, BWR_ENOMEM, BWR_EDEVICE, BWR_EBUSY, BWR_ESHORT = 0, -1, -2, -3, -4, -5, -6
+EXPORTED = ("bwr_version", "bwr_last_error", "bwr_is_prime", "bwr_sequence_length", "bwr_set_threads",
+            "bwr_random_block", "bwr_sequence", "bwr_sequence_dev", "bwr_apply_dev", "bwr_rank_modp",
+            "bwr_rank_modp_dev", "bwr_min_generator", "bwr_rank_from_sequence", "bwr_time_step_kernels_dev")
+
+
+class BwrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"bwrank error {code}: {msg}")
+        self.code = code
+
+
+class CSRStruct(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class RankInfo(ctypes.Structure):
+    _fields_ = [("rank", ctypes.c_int64), ("nb", ctypes.c_int64), ("s", ctypes.c_int32),
+                ("transposed", ctypes.c_int32), ("len", ctypes.c_int64), ("check_terms", ctypes.c_int64),
+                ("sum_delta", ctypes.c_int64), ("t_encode", ctypes.c_double), ("t_sequence", ctypes.c_double),
+                ("t_sigma", ctypes.c_double), ("t_readout", ctypes.c_double), ("sigma_threads", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+_lib = None
+
+
+def lib():
+    """Load libbwrank.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_0704_2351_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, u32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
+        sig = {
+            "bwr_version": (ctypes.c_int, []),
+            "bwr_last_error": (ctypes.c_char_p, []),
+            "bwr_is_prime": (ctypes.c_int, [u32]),
+            "bwr_sequence_length": (i64, [i64, i32]),
+            "bwr_set_threads": (ctypes.c_int, [i32]),
+            "bwr_random_block": (ctypes.c_int, [u64, i32, i64, i32, u32, i32, vp]),
+            "bwr_sequence": (ctypes.c_int, [vp, vp, vp, vp, vp, u32, i32, i64, vp]),
+            "bwr_sequence_dev": (ctypes.c_int, [vp, vp, vp, vp, vp, u32, i32, i64, vp, vp]),
+            "bwr_apply_dev": (ctypes.c_int, [vp, vp, vp, vp, u32, i32, vp, vp]),
+            "bwr_rank_modp": (ctypes.c_int, [vp, u32, i32, u64, vp, vp]),
+            "bwr_rank_modp_dev": (ctypes.c_int, [vp, u32, i32, u64, vp, vp, vp]),
+            "bwr_min_generator": (ctypes.c_int, [vp, i64, i32, u32, vp, vp, i64, vp]),
+            "bwr_rank_from_sequence": (ctypes.c_int, [vp, i64, i64, i32, u32, vp]),
+            "bwr_time_step_kernels_dev": (ctypes.c_int, [vp, u32, i32, i32, i32, vp, vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != BWR_OK:
+        raise BwrError(code, lib().bwr_last_error().decode())
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _u32(a, shape=None):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.uint32)
+    if shape is not None and a.size != int(np.prod(shape)):
+        raise ValueError(f"expected {shape} entries, got {a.shape}")
+    return a
+
+
+def _host_csr(A):
+    rp = np.ascontiguousarray(A.row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(A.col_idx, dtype=np.int32)
+    vv = np.ascontiguousarray(A.val, dtype=np.int32)
+    st = CSRStruct(int(A.m), int(A.n), int(rp[-1]) if rp.size else 0, rp.ctypes.data, ci.ctypes.data,
+                   vv.ctypes.data)
+    return st, (rp, ci, vv)
+
+
+# ------------------------------------------------------------------ host-side helpers
+def version() -> int:
+    return lib().bwr_version()
+
+
+def is_prime(p: int) -> bool:
+    return bool(lib().bwr_is_prime(int(p)))
+
+
+def sequence_length(nb: int, s: int) -> int:
+    return int(lib().bwr_sequence_length(int(nb), int(s)))
+
+
+def set_threads(n: int) -> None:
+    _check(lib().bwr_set_threads(int(n)))
+
+
+def random_block(seed: int, stream: int, rows: int, s: int, p: int, diag: bool = False) -> np.ndarray:
+    out = np.zeros(max(rows * s, 1), dtype=np.uint32)
+    _check(lib().bwr_random_block(int(seed), int(stream), int(rows), int(s), int(p), int(diag), out.ctypes.data))
+    return out[: rows * s].reshape(rows, s)
+
+
+# ------------------------------------------------------------------ host-pointer entry points
+def sequence(A, U, V, p: int, length: int, d_row=None, d_col=None) -> np.ndarray:
+    """S_k = U^T (D_c A^T D_r A D_c)^k V mod p, k < length; returns (length, s, s) uint32."""
+    st, keep = _host_csr(A)
+    U = _u32(U)
+    s = U.shape[1]
+    V = _u32(V, (A.n, s))
+    U = _u32(U, (A.n, s))
+    dr = _u32(d_row, (A.m,))
+    dc = _u32(d_col, (A.n,))
+    out = np.zeros(max(length * s * s, 1), dtype=np.uint32)
+    _check(lib().bwr_sequence(ctypes.byref(st), _ptr(dr), _ptr(dc), _ptr(U), _ptr(V), int(p), int(s),
+                              int(length), out.ctypes.data))
+    return out[: length * s * s].reshape(length, s, s)
+
+
+def rank_modp(A, p: int, block: int, seed: int):
+    """(rank, info dict) of A over GF(p) by block Wiedemann (host CSR input)."""
+    st, keep = _host_csr(A)
+    r = ctypes.c_int64(0)
+    info = RankInfo()
+    _check(lib().bwr_rank_modp(ctypes.byref(st), int(p), int(block), int(seed), ctypes.byref(r), ctypes.byref(info)))
+    return int(r.value), info.as_dict()
+
+
+def min_generator(S, p: int):
+    """(delta, P) of the minimal generator of S (len, s, s); P has shape (max_deg + 1, s, s)."""
+    S = _u32(S)
+    L, s, _ = S.shape
+    delta = np.zeros(s, dtype=np.int64)
+    P = np.zeros((L + 2) * s * s, dtype=np.uint32)
+    md = ctypes.c_int64(0)
+    _check(lib().bwr_min_generator(S.ctypes.data, int(L), int(s), int(p), delta.ctypes.data, P.ctypes.data,
+                                   int(L + 2), ctypes.byref(md)))
+    return delta, P[: (md.value + 1) * s * s].reshape(md.value + 1, s, s)
+
+
+def rank_from_sequence(S, length: int, check: int, p: int) -> int:
+    S = _u32(S)
+    s = S.shape[1]
+    if S.shape[0] < length + check:
+        raise ValueError("S holds fewer than length + check terms")
+    r = ctypes.c_int64(0)
+    _check(lib().bwr_rank_from_sequence(S.ctypes.data, int(length), int(check), int(s), int(p), ctypes.byref(r)))
+    return int(r.value)
+
+
+# ------------------------------------------------------------------ device entry points (torch tensors)
+def _torch():
+    import torch
+    return torch
+
+
+def csr_to_device(A, device="cuda"):
+    """Copy a host CSR to device tensors: dict(m, n, nnz, row_ptr, col_idx, val)."""
+    torch = _torch()
+    return {
+        "m": int(A.m), "n": int(A.n), "nnz": int(A.row_ptr[-1]) if len(A.row_ptr) else 0,
+        "row_ptr": torch.from_numpy(np.ascontiguousarray(A.row_ptr, dtype=np.int64)).to(device),
+        "col_idx": torch.from_numpy(np.ascontiguousarray(A.col_idx, dtype=np.int32)).to(device),
+        "val": torch.from_numpy(np.ascontiguousarray(A.val, dtype=np.int32)).to(device),
+    }
+
+
+def _dev_csr(Ad):
+    for k in ("row_ptr", "col_idx", "val"):
+        t = Ad[k]
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{k} must be a contiguous device tensor")
+    return CSRStruct(Ad["m"], Ad["n"], Ad["nnz"], Ad["row_ptr"].data_ptr(), Ad["col_idx"].data_ptr(),
+                     Ad["val"].data_ptr())
+
+
+def _dptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return t.data_ptr()
+
+
+def _stream():
+    return _torch().cuda.current_stream().cuda_stream
+
+
+def sequence_dev(Ad, U, V, p: int, length: int, d_row=None, d_col=None, out=None):
+    """Device sequence: U, V (n, s) uint32/int32 device tensors; returns (length, s, s) device tensor."""
+    torch = _torch()
+    st = _dev_csr(Ad)
+    s = U.shape[1]
+    if out is None:
+        out = torch.empty((max(length, 1), s, s), dtype=torch.int32, device=U.device)
+    _check(lib().bwr_sequence_dev(ctypes.byref(st), _dptr(d_row), _dptr(d_col), _dptr(U), _dptr(V), int(p), int(s),
+                                  int(length), _dptr(out), _stream()))
+    return out[:length]
+
+
+def apply_dev(Ad, X, p: int, d_row=None, d_col=None, out=None):
+    torch = _torch()
+    st = _dev_csr(Ad)
+    s = X.shape[1]
+    if out is None:
+        out = torch.empty_like(X)
+    _check(lib().bwr_apply_dev(ctypes.byref(st), _dptr(d_row), _dptr(d_col), _dptr(X), int(p), int(s), _dptr(out),
+                               _stream()))
+    return out
+
+
+def rank_modp_dev(Ad, p: int, block: int, seed: int):
+    st = _dev_csr(Ad)
+    r = ctypes.c_int64(0)
+    info = RankInfo()
+    _check(lib().bwr_rank_modp_dev(ctypes.byref(st), int(p), int(block), int(seed), _stream(), ctypes.byref(r),
+                                   ctypes.byref(info)))
+    return int(r.value), info.as_dict()
+
+
+def time_step_kernels_dev(Ad, p: int, s: int, transpose: bool = False, iters: int = 20):
+    """Average microseconds of [first product, second product, projection] (HIP events on torch's stream)."""
+    st = _dev_csr(Ad)
+    us = np.zeros(3, dtype=np.float64)
+    _check(lib().bwr_time_step_kernels_dev(ctypes.byref(st), int(p), int(s), int(transpose), int(iters), _stream(),
+                                           us.ctypes.data))
+    return us

@@ -1,0 +1,423 @@
+// C-ABI of libbwrank (declared and documented in include/bwrank.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/bwrank.h"
+#include "engine.h"
+#include "kernels.h"
+#include "sigma.h"
+#include "splitmix.h"
+
+using namespace bwr;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(const Error& e) {
+    g_err = e.msg;
+    return e.code;
+}
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+bool is_prime_u32(uint32_t p) {
+    if (p < 2) return false;
+    for (uint32_t d : {2u, 3u, 5u, 7u, 11u, 13u, 17u, 19u, 23u, 29u, 31u, 37u})
+        if (p % d == 0) return p == d;
+    uint32_t dd = p - 1;
+    int r = 0;
+    while (!(dd & 1)) {
+        dd >>= 1;
+        ++r;
+    }
+    ModP mp = ModP::make(p);
+    for (uint32_t a : {2u, 7u, 61u}) {
+        if (a % p == 0) continue;
+        uint32_t x = powmod(mp, a % p, dd);
+        if (x == 1 || x == p - 1) continue;
+        bool comp = true;
+        for (int i = 1; i < r; ++i) {
+            x = mulmod(mp, x, x);
+            if (x == p - 1) {
+                comp = false;
+                break;
+            }
+        }
+        if (comp) return false;
+    }
+    return true;
+}
+
+Error check_prime(uint32_t p) {
+    if (p < 3 || p >= (1u << 31) || !is_prime_u32(p)) return {EPRIME_, "p must be a prime in [3, 2^31)"};
+    return {};
+}
+
+// One library stream per device for the host-pointer entry points.
+hipStream_t lib_stream(Error* err) {
+    static std::mutex mu;
+    static std::vector<hipStream_t> streams;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        *err = Error::device(e, "hipGetDevice");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
+    if (!streams[dev]) {
+        e = hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            *err = Error::device(e, "hipStreamCreate");
+            return nullptr;
+        }
+        // keep freed device memory cached by the pool between calls
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+            uint64_t thr = UINT64_MAX;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+        }
+    }
+    return streams[dev];
+}
+
+CsrView view(const bwr_csr* A) { return CsrView{A->m, A->n, A->nnz, A->row_ptr, A->col_idx, A->val}; }
+
+// Host CSR -> device copies (owned by the returned buffers).
+struct HostUpload {
+    DevBuf rp, col, val;
+    CsrView dev{};
+};
+
+Error upload(const bwr_csr* A, hipStream_t st, HostUpload* u) {
+    Error e = check_host_csr(view(A));
+    if (!e.ok()) return e;
+    const size_t nnz = (size_t)A->nnz;
+    if (!(e = u->rp.alloc(sizeof(int64_t) * (size_t)(A->m + 1), st)).ok()) return e;
+    if (!(e = u->col.alloc(sizeof(int32_t) * std::max<size_t>(nnz, 1), st)).ok()) return e;
+    if (!(e = u->val.alloc(sizeof(int32_t) * std::max<size_t>(nnz, 1), st)).ok()) return e;
+    hipError_t he = hipMemcpyAsync(u->rp.as<void>(), A->row_ptr, sizeof(int64_t) * (size_t)(A->m + 1),
+                                   hipMemcpyHostToDevice, st);
+    if (he == hipSuccess && nnz)
+        he = hipMemcpyAsync(u->col.as<void>(), A->col_idx, sizeof(int32_t) * nnz, hipMemcpyHostToDevice, st);
+    if (he == hipSuccess && nnz)
+        he = hipMemcpyAsync(u->val.as<void>(), A->val, sizeof(int32_t) * nnz, hipMemcpyHostToDevice, st);
+    if (he != hipSuccess) return Error::device(he, "upload");
+    u->dev = CsrView{A->m, A->n, A->nnz, u->rp.as<int64_t>(), u->col.as<int32_t>(), u->val.as<int32_t>()};
+    return {};
+}
+
+Error copy_to_dev(const uint32_t* h, size_t count, hipStream_t st, DevBuf* d) {
+    Error e = d->alloc(sizeof(uint32_t) * std::max<size_t>(count, 1), st);
+    if (!e.ok()) return e;
+    if (count) {
+        hipError_t he = hipMemcpyAsync(d->as<void>(), h, sizeof(uint32_t) * count, hipMemcpyHostToDevice, st);
+        if (he != hipSuccess) return Error::device(he, "hipMemcpyAsync");
+    }
+    return {};
+}
+
+Error sequence_dev_impl(const CsrView& A, const uint32_t* d_row, const uint32_t* d_col, const uint32_t* U,
+                        const uint32_t* V, uint32_t p, int32_t s, int64_t len, uint32_t* S_out, hipStream_t st) {
+    Error e = check_prime(p);
+    if (!e.ok()) return e;
+    if (s < 1 || s > 64) return Error::inval("block size must be in 1..64");
+    if (len < 0) return Error::inval("len must be >= 0");
+    if (len > 0 && (!S_out || (A.n > 0 && (!U || !V)))) return Error::inval("NULL output or block");
+    if (len == 0) return {};
+    DeviceMatrix M;
+    if (!(e = encode_matrix(A, p, st, &M)).ok()) return e;
+    SequenceArgs a;
+    a.M = &M;
+    a.transpose = false;
+    a.mp = ModP::make(p);
+    a.s = s;
+    a.d_row = d_row;
+    a.d_col = d_col;
+    a.U = U;
+    a.V = V;
+    a.len = len;
+    a.S_out = S_out;
+    return run_sequence(a, st);
+}
+
+struct RankOut {
+    int64_t rank = 0;
+    bwr_rank_info info{};
+};
+
+constexpr int64_t CHECK_TERMS = 4;
+
+Error rank_dev_impl(const CsrView& A, uint32_t p, int32_t block, uint64_t seed, hipStream_t st, RankOut* out) {
+    Error e = check_prime(p);
+    if (!e.ok()) return e;
+    if (block < 1 || block > 64) return Error::inval("block size must be in 1..64");
+    bwr_rank_info& info = out->info;
+    std::memset(&info, 0, sizeof(info));
+    const double t0 = now_s();
+    const bool transpose = A.m < A.n;
+    const int64_t nb = std::min(A.m, A.n);
+    const int64_t outer = std::max(A.m, A.n);
+    info.nb = nb;
+    info.transposed = transpose ? 1 : 0;
+    DeviceMatrix M;
+    if (!(e = encode_matrix(A, p, st, &M)).ok()) return e;
+    info.t_encode = now_s() - t0;
+    if (nb == 0 || A.nnz == 0) {
+        out->rank = 0;
+        info.rank = 0;
+        return {};
+    }
+    const int32_t s = (int32_t)std::min<int64_t>(block, nb);
+    const int64_t L = 2 + (2 * nb + s - 1) / s;
+    const int64_t total = L + CHECK_TERMS;
+    info.s = s;
+    info.len = L;
+    info.check_terms = CHECK_TERMS;
+    const ModP mp = ModP::make(p);
+    DevBuf U, V, dr, dc, S;
+    if (!(e = U.alloc(sizeof(uint32_t) * (size_t)(nb * s), st)).ok()) return e;
+    if (!(e = V.alloc(sizeof(uint32_t) * (size_t)(nb * s), st)).ok()) return e;
+    if (!(e = dr.alloc(sizeof(uint32_t) * (size_t)outer, st)).ok()) return e;
+    if (!(e = dc.alloc(sizeof(uint32_t) * (size_t)nb, st)).ok()) return e;
+    if (!(e = S.alloc(sizeof(uint32_t) * (size_t)(total * s * s), st)).ok()) return e;
+    hipError_t he = launch_rng_block(seed, STREAM_V, nb, s, s, mp, 0, V.as<uint32_t>(), st);
+    if (he == hipSuccess) he = launch_rng_block(seed, STREAM_U, nb, s, s, mp, 0, U.as<uint32_t>(), st);
+    if (he == hipSuccess) he = launch_rng_block(seed, STREAM_DROW, outer, 1, 1, mp, 1, dr.as<uint32_t>(), st);
+    if (he == hipSuccess) he = launch_rng_block(seed, STREAM_DCOL, nb, 1, 1, mp, 1, dc.as<uint32_t>(), st);
+    if (he != hipSuccess) return Error::device(he, "rng launch");
+    SequenceArgs a;
+    a.M = &M;
+    a.transpose = transpose;
+    a.mp = mp;
+    a.s = s;
+    a.d_row = dr.as<uint32_t>();
+    a.d_col = dc.as<uint32_t>();
+    a.U = U.as<uint32_t>();
+    a.V = V.as<uint32_t>();
+    a.len = total;
+    a.S_out = S.as<uint32_t>();
+    const double t1 = now_s();
+    if (!(e = run_sequence(a, st)).ok()) return e;
+    std::vector<uint32_t> Sh((size_t)(total * s * s));
+    he = hipMemcpyAsync(Sh.data(), S.as<void>(), sizeof(uint32_t) * Sh.size(), hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    if (he != hipSuccess) return Error::device(he, "sequence download");
+    const double t2 = now_s();
+    info.t_sequence = t2 - t1;
+    Generator g;
+    SigmaStats ss;
+    if (!(e = min_generator(Sh.data(), L, s, p, &g, &ss)).ok()) return e;
+    const double t3 = now_s();
+    info.t_sigma = t3 - t2;
+    info.sigma_threads = ss.threads;
+    if (!(e = check_generator(g, Sh.data(), L, total, p)).ok()) return e;
+    int64_t r = 0;
+    if (!(e = rank_from_generator(g, p, &r)).ok()) return e;
+    info.t_readout = now_s() - t3;
+    for (int64_t x : g.delta) info.sum_delta += x;
+    info.rank = r;
+    out->rank = r;
+    return {};
+}
+
+}  // namespace
+
+extern "C" {
+
+int bwr_version(void) { return 100; }
+
+const char* bwr_last_error(void) { return g_err.c_str(); }
+
+int bwr_is_prime(uint32_t p) { return (p >= 3 && p < (1u << 31) && is_prime_u32(p)) ? 1 : 0; }
+
+int64_t bwr_sequence_length(int64_t nb, int32_t s) {
+    if (s < 1 || nb < 0) return -1;
+    return 2 + (2 * nb + s - 1) / s;
+}
+
+int bwr_set_threads(int32_t n) {
+    if (n < 1) return fail(BWR_EINVAL, "thread count must be positive");
+    set_sigma_threads(n);
+    g_err.clear();
+    return BWR_OK;
+}
+
+int bwr_random_block(uint64_t seed, int32_t stream, int64_t rows, int32_t s, uint32_t p, int32_t diag,
+                     uint32_t* out) {
+    Error e = check_prime(p);
+    if (!e.ok()) return fail(e);
+    if (rows < 0 || s < 1 || stream < 0 || (rows > 0 && !out)) return fail(BWR_EINVAL, "bad arguments");
+    ModP mp = ModP::make(p);
+    uint64_t key = sm_key(seed, stream);
+    for (int64_t i = 0; i < rows * (int64_t)s; ++i) out[i] = sm_residue(mp, key, (uint64_t)i, diag ? 1 : 0);
+    g_err.clear();
+    return BWR_OK;
+}
+
+int bwr_sequence(const bwr_csr* A, const uint32_t* d_row, const uint32_t* d_col, const uint32_t* U,
+                 const uint32_t* V, uint32_t p, int32_t s, int64_t len, uint32_t* S_out) {
+    if (!A) return fail(BWR_EINVAL, "A is NULL");
+    Error e = check_prime(p);
+    if (!e.ok()) return fail(e);
+    if (s < 1 || s > 64 || len < 0) return fail(BWR_EINVAL, "block size must be in 1..64 and len >= 0");
+    if (len > 0 && (!S_out || (A->n > 0 && (!U || !V)))) return fail(BWR_EINVAL, "NULL output or block");
+    if (!(e = check_host_csr(view(A))).ok()) return fail(e);
+    if (len == 0) {
+        g_err.clear();
+        return BWR_OK;
+    }
+    hipStream_t st = lib_stream(&e);
+    if (!e.ok()) return fail(e);
+    HostUpload up;
+    DevBuf dU, dV, ddr, ddc, dS;
+    if (!(e = upload(A, st, &up)).ok()) return fail(e);
+    const size_t ns = (size_t)A->n * s;
+    if (!(e = copy_to_dev(U, ns, st, &dU)).ok()) return fail(e);
+    if (!(e = copy_to_dev(V, ns, st, &dV)).ok()) return fail(e);
+    if (d_row && !(e = copy_to_dev(d_row, (size_t)A->m, st, &ddr)).ok()) return fail(e);
+    if (d_col && !(e = copy_to_dev(d_col, (size_t)A->n, st, &ddc)).ok()) return fail(e);
+    const size_t nS = (size_t)len * s * s;
+    if (!(e = dS.alloc(sizeof(uint32_t) * nS, st)).ok()) return fail(e);
+    e = sequence_dev_impl(up.dev, d_row ? ddr.as<uint32_t>() : nullptr, d_col ? ddc.as<uint32_t>() : nullptr,
+                          dU.as<uint32_t>(), dV.as<uint32_t>(), p, s, len, dS.as<uint32_t>(), st);
+    if (!e.ok()) return fail(e);
+    std::vector<uint32_t> tmp(nS);
+    hipError_t he = hipMemcpyAsync(tmp.data(), dS.as<void>(), sizeof(uint32_t) * nS, hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    if (he != hipSuccess) return fail(Error::device(he, "download"));
+    std::memcpy(S_out, tmp.data(), sizeof(uint32_t) * nS);
+    g_err.clear();
+    return BWR_OK;
+}
+
+int bwr_sequence_dev(const bwr_csr* A_dev, const uint32_t* d_row, const uint32_t* d_col, const uint32_t* U,
+                     const uint32_t* V, uint32_t p, int32_t s, int64_t len, uint32_t* S_out, void* stream) {
+    if (!A_dev) return fail(BWR_EINVAL, "A is NULL");
+    Error e = sequence_dev_impl(view(A_dev), d_row, d_col, U, V, p, s, len, S_out, (hipStream_t)stream);
+    if (!e.ok()) return fail(e);
+    g_err.clear();
+    return BWR_OK;
+}
+
+int bwr_apply_dev(const bwr_csr* A_dev, const uint32_t* d_row, const uint32_t* d_col, const uint32_t* X,
+                  uint32_t p, int32_t s, uint32_t* Z, void* stream) {
+    if (!A_dev) return fail(BWR_EINVAL, "A is NULL");
+    Error e = check_prime(p);
+    if (!e.ok()) return fail(e);
+    if (s < 1 || s > 64) return fail(BWR_EINVAL, "block size must be in 1..64");
+    if (A_dev->n > 0 && (!X || !Z)) return fail(BWR_EINVAL, "NULL block");
+    hipStream_t st = (hipStream_t)stream;
+    DeviceMatrix M;
+    if (!(e = encode_matrix(view(A_dev), p, st, &M)).ok()) return fail(e);
+    if (!(e = apply_once(M, false, ModP::make(p), s, d_row, d_col, X, Z, st)).ok()) return fail(e);
+    g_err.clear();
+    return BWR_OK;
+}
+
+int bwr_rank_modp(const bwr_csr* A, uint32_t p, int32_t block, uint64_t seed, int64_t* rank_out,
+                  bwr_rank_info* info) {
+    if (!A || !rank_out) return fail(BWR_EINVAL, "NULL argument");
+    Error e = check_prime(p);
+    if (!e.ok()) return fail(e);
+    if (block < 1 || block > 64) return fail(BWR_EINVAL, "block size must be in 1..64");
+    if (!(e = check_host_csr(view(A))).ok()) return fail(e);
+    if (A->nnz == 0 || A->m == 0 || A->n == 0) {
+        *rank_out = 0;
+        if (info) {
+            std::memset(info, 0, sizeof(*info));
+            info->nb = std::min(A->m, A->n);
+        }
+        g_err.clear();
+        return BWR_OK;
+    }
+    hipStream_t st = lib_stream(&e);
+    if (!e.ok()) return fail(e);
+    HostUpload up;
+    if (!(e = upload(A, st, &up)).ok()) return fail(e);
+    RankOut ro;
+    if (!(e = rank_dev_impl(up.dev, p, block, seed, st, &ro)).ok()) return fail(e);
+    *rank_out = ro.rank;
+    if (info) *info = ro.info;
+    g_err.clear();
+    return BWR_OK;
+}
+
+int bwr_rank_modp_dev(const bwr_csr* A_dev, uint32_t p, int32_t block, uint64_t seed, void* stream,
+                      int64_t* rank_out, bwr_rank_info* info) {
+    if (!A_dev || !rank_out) return fail(BWR_EINVAL, "NULL argument");
+    RankOut ro;
+    Error e = rank_dev_impl(view(A_dev), p, block, seed, (hipStream_t)stream, &ro);
+    if (!e.ok()) return fail(e);
+    *rank_out = ro.rank;
+    if (info) *info = ro.info;
+    g_err.clear();
+    return BWR_OK;
+}
+
+int bwr_time_step_kernels_dev(const bwr_csr* A_dev, uint32_t p, int32_t s, int32_t transpose, int32_t iters,
+                              void* stream, double* us_out) {
+    if (!A_dev || !us_out) return fail(BWR_EINVAL, "NULL argument");
+    Error e = check_prime(p);
+    if (!e.ok()) return fail(e);
+    hipStream_t st = (hipStream_t)stream;
+    DeviceMatrix M;
+    if (!(e = encode_matrix(view(A_dev), p, st, &M)).ok()) return fail(e);
+    if (!(e = time_step_kernels(M, transpose != 0, ModP::make(p), s, iters, st, us_out)).ok()) return fail(e);
+    g_err.clear();
+    return BWR_OK;
+}
+
+int bwr_min_generator(const uint32_t* S, int64_t len, int32_t s, uint32_t p, int64_t* delta_out, uint32_t* P_out,
+                      int64_t P_cap_terms, int64_t* max_deg_out) {
+    Error e = check_prime(p);
+    if (!e.ok()) return fail(e);
+    if (s < 1 || s > 64 || len < 0 || (len > 0 && !S) || !delta_out || !P_out || !max_deg_out)
+        return fail(BWR_EINVAL, "bad arguments");
+    Generator g;
+    if (!(e = min_generator(S, len, s, p, &g)).ok()) return fail(e);
+    int64_t maxd = 0;
+    for (int64_t x : g.delta) maxd = std::max(maxd, x);
+    if (maxd + 1 > P_cap_terms) return fail(BWR_EINVAL, "P_out capacity too small");
+    std::memset(P_out, 0, sizeof(uint32_t) * (size_t)(maxd + 1) * s * s);
+    for (int i = 0; i < s; ++i) {
+        delta_out[i] = g.delta[i];
+        for (int j = 0; j < s; ++j) {
+            const uint32_t* src = g.P.at(i, j);
+            for (int64_t k = 0; k < g.P.len && k <= maxd; ++k) P_out[((size_t)k * s + i) * s + j] = src[k];
+        }
+    }
+    *max_deg_out = maxd;
+    g_err.clear();
+    return BWR_OK;
+}
+
+int bwr_rank_from_sequence(const uint32_t* S, int64_t len, int64_t check, int32_t s, uint32_t p, int64_t* rank_out) {
+    Error e = check_prime(p);
+    if (!e.ok()) return fail(e);
+    if (s < 1 || s > 64 || len < 0 || check < 0 || (len + check > 0 && !S) || !rank_out)
+        return fail(BWR_EINVAL, "bad arguments");
+    Generator g;
+    if (!(e = min_generator(S, len, s, p, &g)).ok()) return fail(e);
+    if (!(e = check_generator(g, S, len, len + check, p)).ok()) return fail(e);
+    int64_t r = 0;
+    if (!(e = rank_from_generator(g, p, &r)).ok()) return fail(e);
+    *rank_out = r;
+    g_err.clear();
+    return BWR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+// Device runtime of the block Wiedemann path: the encoded matrix store and the
+// sequence driver.  Internal C++; the public surface is the C-ABI in bwrank.h.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "modp.h"
+
+namespace bwr {
+
+// Error codes of the C-ABI (mirrored in bwrank.h).
+enum : int { OK = 0, EINVAL_ = -1, EPRIME_ = -2, ENOMEM_ = -3, EDEVICE_ = -4, EBUSY_ = -5, ESHORT_ = -6 };
+
+struct Error {
+    int code = OK;
+    std::string msg;
+    bool ok() const { return code == OK; }
+    static Error inval(const std::string& m) { return {EINVAL_, m}; }
+    static Error device(hipError_t e, const char* where);
+};
+
+// Device buffer owned by the library (freed on destruction, stream-ordered).
+class DevBuf {
+   public:
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    DevBuf(DevBuf&& o) noexcept { *this = std::move(o); }
+    DevBuf& operator=(DevBuf&& o) noexcept;
+    ~DevBuf() { release(); }
+    Error alloc(size_t bytes, hipStream_t st);
+    void release();
+    template <class T>
+    T* as() const { return reinterpret_cast<T*>(ptr_); }
+    size_t bytes() const { return bytes_; }
+
+   private:
+    void* ptr_ = nullptr;
+    size_t bytes_ = 0;
+    hipStream_t st_ = nullptr;
+};
+
+// A sparse integer matrix on the device, encoded for the two products of a
+// step: CSR of A and CSR of A^T.  Packed form (prime independent): column
+// index in the low 24 bits and the int8 value in the high 8 bits of one
+// uint32.  Wide form (one prime): int32 columns and uint32 residues.
+struct DeviceMatrix {
+    int64_t m = 0, n = 0, nnz = 0;
+    int32_t max_len_a = 0, max_len_t = 0, max_abs = 0;
+    bool packed = true;
+    uint32_t wide_p = 0;  // prime the wide values are reduced for
+    DevBuf rp_a, ent_a, rp_t, ent_t;     // packed (ent) or wide columns (ent as int32)
+    DevBuf val_a, val_t;                 // wide residues
+};
+
+struct CsrView {  // caller-owned CSR (host or device pointers)
+    int64_t m, n, nnz;
+    const int64_t* row_ptr;
+    const int32_t* col_idx;
+    const int32_t* val;
+};
+
+// Validate and encode a device-resident CSR.  p is used only by the wide form
+// (values beyond int8 or dimensions beyond 2^24).
+Error encode_matrix(const CsrView& A_dev, uint32_t p, hipStream_t st, DeviceMatrix* out);
+
+// Host CSR checks (row pointers, column range) before any upload.
+Error check_host_csr(const CsrView& A);
+
+struct Operand {  // one product of a step: out[r] = scale[r] * sum a_rt in[col_t]
+    int64_t rows;
+    int32_t max_len;
+    const int32_t* rp;
+    const uint32_t* ent;  // packed entries, or wide columns
+    const uint32_t* val;  // wide residues (null when packed)
+};
+
+// One sequence run: S_k = U^T B^k V for k < len, B = D_c A^T D_r A D_c, or with
+// the roles of A and A^T swapped (transpose = true: B acts on GF(p)^m).
+struct SequenceArgs {
+    const DeviceMatrix* M;
+    bool transpose = false;
+    ModP mp;
+    int32_t s;
+    const uint32_t* d_row = nullptr;  // device, rows of the first product, or null
+    const uint32_t* d_col = nullptr;  // device, length of the iterated dimension, or null
+    const uint32_t* U = nullptr;      // device, nb x s
+    const uint32_t* V = nullptr;      // device, nb x s
+    int64_t len = 0;
+    uint32_t* S_out = nullptr;  // device, len x s x s
+};
+
+Error run_sequence(const SequenceArgs& a, hipStream_t st);
+
+// Z = B X for one block (no projection): parity hook for a single step.
+Error apply_once(const DeviceMatrix& M, bool transpose, ModP mp, int32_t s, const uint32_t* d_row,
+                 const uint32_t* d_col, const uint32_t* X, uint32_t* Z, hipStream_t st);
+
+int padded_width(int32_t s);  // 0 if unsupported
+
+// Average device time (microseconds, HIP events on stream st) of each kernel
+// of one step, launched `iters` times back to back on the encoded matrix with
+// random blocks: [0] first sparse product + row scale, [1] second sparse
+// product + column scale, [2] projection.
+Error time_step_kernels(const DeviceMatrix& M, bool transpose, ModP mp, int32_t s, int iters, hipStream_t st,
+                        double us[3]);
+
+}  // namespace bwr

@@ -1,0 +1,85 @@
+// Launchers for the gfx950 kernels of the block Wiedemann sequence.
+//
+// Device layouts (all row-major, residues uint32 in [0, p)):
+//   packed CSR   rp[nrows + 1] (int32), ent[nnz] (uint32) with
+//                ent = column | (uint8)value << 24 (columns < 2^24, |value| <= 127)
+//   wide CSR     rp[nrows + 1] (int32), col[nnz] (int32), val[nnz] (uint32 residue)
+//   blocks       X[n][W], Y[m][W] with W the padded block width (1..64, power of two);
+//                padding columns are zero and stay zero
+//   S            S[k][s][s]
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "modp.h"
+
+namespace bwr {
+
+struct CsrStats {
+    int32_t bad;       // non-zero: malformed input (see flags below)
+    int32_t max_len;   // longest row
+    int32_t max_abs;   // largest |value| (saturated at 2^31 - 1)
+    int32_t pad;
+};
+enum : int32_t { BAD_ROWPTR = 1, BAD_COL = 2 };
+
+// Row-pointer check (reads only rp): bad_dev = BAD_ROWPTR unless 0 = rp[0] <= ... <= rp[m] = nnz.
+hipError_t launch_rowptr_check(int64_t m, int64_t nnz, const int64_t* rp, int32_t* bad_dev, hipStream_t st);
+// out_dev = max(0, max in[i])
+hipError_t launch_max_i32(int64_t count, const int32_t* in, int32_t* out_dev, hipStream_t st);
+// Input validation and statistics over a device CSR with int64 row pointers (call after the row-pointer check).
+hipError_t launch_csr_stats(int64_t m, int64_t n, const int64_t* rp, const int32_t* col,
+                            const int32_t* val, CsrStats* out_dev, hipStream_t st);
+
+// Packed encoding of A (rows kept in input order).
+hipError_t launch_pack_rows(int64_t m, const int64_t* rp64, const int32_t* col, const int32_t* val,
+                            int32_t* rp32, uint32_t* ent, hipStream_t st);
+// Wide encoding of A for one prime: columns copied, values reduced mod p.
+hipError_t launch_wide_rows(int64_t m, const int64_t* rp64, const int32_t* col, const int32_t* val,
+                            ModP mp, int32_t* rp32, int32_t* colw, uint32_t* valw, hipStream_t st);
+
+// Transpose support: column histogram, exclusive scan, scatter, per-row sort.
+hipError_t launch_col_count(int64_t m, const int64_t* rp64, const int32_t* col, int32_t* cnt, hipStream_t st);
+hipError_t launch_exclusive_scan(int64_t count, const int32_t* in, int32_t* out /* count + 1 */,
+                                 int32_t* tmp /* >= scan_tmp_words(count) */, hipStream_t st);
+int64_t scan_tmp_words(int64_t count);
+hipError_t launch_scatter_packed_t(int64_t m, const int64_t* rp64, const int32_t* col, const int32_t* val,
+                                   const int32_t* rpT, int32_t* cursor, uint32_t* entT, hipStream_t st);
+hipError_t launch_scatter_wide_t(int64_t m, const int64_t* rp64, const int32_t* col, const int32_t* val,
+                                 ModP mp, const int32_t* rpT, int32_t* cursor, int32_t* colT, uint32_t* valT,
+                                 hipStream_t st);
+hipError_t launch_sort_rows_packed(int64_t nrows, const int32_t* rp, uint32_t* ent, hipStream_t st);
+hipError_t launch_sort_rows_wide(int64_t nrows, const int32_t* rp, int32_t* col, uint32_t* val, hipStream_t st);
+
+// Random residues from the counter-based SplitMix64 stream (seed, stream):
+// out[r * ld + c] = element(r * s + c) for r < rows, c < s (and 0 for s <= c < ld).
+hipError_t launch_rng_block(uint64_t seed, int stream, int64_t rows, int32_t s, int32_t ld, ModP mp,
+                            int diag, uint32_t* out, hipStream_t st);
+
+// Copy an n x s block into an n x W padded block, optionally scaled row-wise
+// by d[r] (mode 1) or by d[r]^-1 (mode 2); mode 0 copies.  Entries are reduced mod p.
+hipError_t launch_pad_scale(int64_t n, int32_t s, int32_t W, const uint32_t* in, const uint32_t* d, int mode,
+                            ModP mp, uint32_t* out, hipStream_t st);
+// out[r * s + c] = in[r * W + c] for c < s
+hipError_t launch_unpad(int64_t n, int32_t s, int32_t W, const uint32_t* in, uint32_t* out, hipStream_t st);
+// d2[r] = d[r]^2 mod p; also checks d[r] mod p != 0 (bad != 0 otherwise).
+hipError_t launch_square_diag(int64_t n, const uint32_t* d, ModP mp, uint32_t* d2, int32_t* bad, hipStream_t st);
+// reduce an arbitrary uint32 diagonal into [0, p)
+hipError_t launch_reduce_vec(int64_t n, const uint32_t* in, ModP mp, uint32_t* out, hipStream_t st);
+
+// Y[r] = scale[r] * sum_t a_rt X[col_t]  (mod p), for r < nrows.  scale may be null (1).
+// acc32: the caller guarantees max_len * max|a| * (p - 1) < 2^31 and p <= 2^16.
+hipError_t launch_spmm_packed(int W, bool acc32, bool smallp, int64_t nrows, const int32_t* rp, const uint32_t* ent,
+                              const uint32_t* X, const uint32_t* scale, uint32_t* Y, ModP mp, hipStream_t st);
+hipError_t launch_spmm_wide(int W, int64_t nrows, const int32_t* rp, const int32_t* col, const uint32_t* val,
+                            const uint32_t* X, const uint32_t* scale, uint32_t* Y, ModP mp, hipStream_t st);
+
+// Projection partials: partial[b][i * W + c] = sum over the rows of block b of U[r][i] X[r][c] mod p.
+int proj_blocks(int64_t n, int W);
+hipError_t launch_project(int W, bool smallp, int64_t n, const uint32_t* U, const uint32_t* X, uint32_t* partial,
+                          int nblocks, ModP mp, hipStream_t st);
+// S[k][i][j] (i, j < s) = sum_b partial[k][b][i * W + j] mod p, for k < nsteps.
+hipError_t launch_reduce_partials(int W, int32_t s, int nblocks, int64_t nsteps, const uint32_t* partial, uint32_t* S,
+                                  ModP mp, hipStream_t st);
+
+}  // namespace bwr

@@ -1,0 +1,148 @@
+"""The C-ABI library loads and exports every declared symbol; its host-side
+logic (primality, sequence length, random streams, sigma-basis generator and
+rank read-out) agrees with the oracle.  No GPU needed."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_0704_2351_amd as bw
+from oracle import sequence as oseq
+from oracle import sigma, splitmix
+from workloads import planted
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    with open(os.path.join(ROOT, "include", "bwrank.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\s*(?:int|int64_t|const char\*)\s+(bwr_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = bw.lib()
+    names = declared_symbols()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(bw.EXPORTED)
+
+
+def test_primality():
+    def trial(p):
+        return p >= 2 and all(p % d for d in range(2, int(p**0.5) + 1))
+
+    for p in list(range(0, 400)) + [65519, 65521, 65535, 65537, 65539, 2**31 - 1, 2**31 - 3, 2147483629]:
+        assert bw.is_prime(p) == (trial(p) and p >= 3 and p < 2**31), p
+    # strong pseudoprimes to some bases
+    for c in (2047, 3215031751, 25326001 % (2**31), 4759123141 % (2**31)):
+        if c < 2**31:
+            assert bw.is_prime(c) == trial(c)
+
+
+def test_sequence_length_matches_oracle_and_table():
+    for nb in (0, 1, 7, 1500, 150000, 1000000):
+        for s in (1, 3, 4, 8, 16, 50):
+            assert bw.sequence_length(nb, s) == sigma.sequence_length(nb, s)
+    assert bw.sequence_length(1033568, 50) == 41345  # GL7d19 row of Table "tab:r-time"
+    assert bw.sequence_length(10, 0) == -1
+
+
+@pytest.mark.parametrize("stream", [0, 1, 2, 3])
+@pytest.mark.parametrize("p", [65521, 2**31 - 1, 3])
+def test_random_block_matches_splitmix_oracle(stream, p):
+    diag = stream >= 2
+    got = bw.random_block(20240601, stream, 5, 3, p, diag)
+    want = splitmix.block(20240601, stream, 15, p, diag)
+    assert got.reshape(-1).tolist() == want
+
+
+def _case(seed, m, n, r, k, s, p):
+    rng = np.random.default_rng(seed)
+    A = planted(m, n, r, k, 500 + seed)
+    U = rng.integers(0, p, size=(n, s))
+    V = rng.integers(0, p, size=(n, s))
+    dr = rng.integers(1, p, size=m)
+    dc = rng.integers(1, p, size=n)
+    L = sigma.sequence_length(n, s)
+    return A, oseq.sequence(A, U, V, p, L + 4, dr, dc), L
+
+
+def reversed_generator(delta, P, s):
+    D = max(delta)
+    F = np.zeros((D + 1, s, s), dtype=np.int64)
+    for i in range(s):
+        for j in range(min(P.shape[0], delta[i] + 1)):
+            F[delta[i] - j, i, :] = P[j, i, :]
+    return F
+
+
+@pytest.mark.parametrize("p", [65521, 2**31 - 1])
+@pytest.mark.parametrize("s", [1, 2, 3, 4])
+def test_generator_popov_matches_oracle(p, s):
+    A, S, L = _case(s, 40, 28, 19, 3, s, p)
+    delta, P = bw.min_generator(S[:L], p)
+    F = reversed_generator(delta.tolist(), P.astype(np.int64), s)
+    Fo, delta_o, _ = sigma.min_generator(S[:L], p)
+    assert sorted(delta.tolist()) == sorted(delta_o)
+    assert sigma.annihilates(F, S, p)
+    assert np.array_equal(sigma.popov_form(F, p), sigma.popov_form(Fo, p))
+
+
+@pytest.mark.parametrize("p", [65521, 2**31 - 1, 65537])
+@pytest.mark.parametrize("shape", [(120, 90, 70, 5, 4), (300, 260, 200, 7, 8), (500, 400, 380, 9, 16),
+                                   (90, 70, 60, 4, 5)])
+def test_rank_readout_matches_oracle(p, shape):
+    m, n, r, k, s = shape
+    A, S, L = _case(7, m, n, r, k, s, p)
+    got = bw.rank_from_sequence(S, L, 4, p)
+    assert got == r
+    if L <= 200:
+        assert got == sigma.rank_from_sequence(S[:L], p)
+
+
+def test_long_sequence_pmbasis_against_mbasis_oracle():
+    # long enough for several levels of divide and conquer and NTT products
+    p = 65521
+    A, S, L = _case(3, 1300, 1000, 900, 8, 4, p)
+    delta, P = bw.min_generator(S[:L], p)
+    Fo, delta_o, _ = sigma.min_generator(S[:L], p)
+    assert sorted(delta.tolist()) == sorted(delta_o)
+    F = reversed_generator(delta.tolist(), P.astype(np.int64), 4)
+    assert sigma.annihilates(F, S, p)
+    assert bw.rank_from_sequence(S, L, 4, p) == 900
+
+
+def test_short_sequence_is_reported():
+    p = 65521
+    A, S, L = _case(5, 200, 150, 140, 6, 4, p)
+    # half the terms: the generator cannot be right on the check terms
+    with pytest.raises(bw.BwrError) as ei:
+        bw.rank_from_sequence(S, L // 2, 4, p)
+    assert ei.value.code == -6
+
+
+def test_error_codes():
+    S = np.zeros((4, 2, 2), dtype=np.uint32)
+    for p in (0, 2, 4, 65535, 2**31 + 11):
+        with pytest.raises(bw.BwrError) as ei:
+            bw.rank_from_sequence(S, 2, 2, p)
+        assert ei.value.code == -2
+    with pytest.raises(bw.BwrError) as ei:
+        bw.lib()  # noqa
+        bw.random_block(1, 0, 2, 0, 65521)
+    assert ei.value.code == -1
+    with pytest.raises(bw.BwrError) as ei:
+        bw.rank_from_sequence(np.full((4, 2, 2), 65521, dtype=np.uint32), 2, 2, 65521)
+    assert ei.value.code == -1  # entries not reduced
+
+
+def test_zero_sequence_generator():
+    # V = 0 gives S = 0: the generator is the identity (degree 0), rank 0
+    p = 65521
+    S = np.zeros((10, 3, 3), dtype=np.uint32)
+    delta, P = bw.min_generator(S, p)
+    assert delta.tolist() == [0, 0, 0]
+    assert bw.rank_from_sequence(S, 6, 4, p) == 0
