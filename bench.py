@@ -67,6 +67,96 @@ def cpu_baseline(A, p, s, target_s=15.0):
                       f"block, then U^T W mod {p}) on the same matrix, {el:.1f} s single-threaded"}
 
 
+def batch_mode(args):
+    """Batched ranks against one-at-a-time ranks on the same matrices and primes."""
+    import paper_0704_2351_amd as bw
+    from workloads import CONFIG4_PRIMES, config4_matrix, config4_shapes
+
+    shapes = config4_shapes()
+    order = sorted(range(len(shapes)), key=lambda j: shapes[j][1])
+    step = max(1, len(order) // max(1, args.batch_count))
+    pick = order[::step][: args.batch_count]
+    log(f"generating {len(pick)} planted matrices (n from {shapes[pick[0]][1]} to {shapes[pick[-1]][1]})")
+    mats = [config4_matrix(j, shapes) for j in pick]
+    primes = CONFIG4_PRIMES
+    nsolves = len(mats) * len(primes)
+    work = sum(2.0 * A.nnz * 8 * (bw.sequence_length(min(A.m, A.n), 8) + 3) for A in mats) * len(primes)
+    log("batched: warmup on the smallest matrix")
+    bw.rank_modp_batch(mats[:1], primes, 8, 1)
+    t0 = time.perf_counter()
+    ranks, info = bw.rank_modp_batch(mats, primes, 8, 1)
+    tb = time.perf_counter() - t0
+    ok_b = all(ranks[j, t] == A.planted_rank for j, A in enumerate(mats) for t in range(len(primes)))
+    log(f"batched {tb:.2f} s, ranks ok: {ok_b}")
+    t0 = time.perf_counter()
+    plain_ok = True
+    for j, A in enumerate(mats):
+        for t, p in enumerate(primes):
+            r, _ = bw.rank_modp(A, p, 8, 1)
+            plain_ok &= (r == ranks[j, t])
+    tp = time.perf_counter() - t0
+    log(f"plain {tp:.2f} s, identical ranks: {plain_ok}")
+    print(json.dumps({
+        "metric": METRIC, "mode": "batched", "value": round(nsolves / tb, 4), "unit": "solves/s",
+        "plain_solves_per_s": round(nsolves / tp, 4), "speedup_vs_plain": round(tp / tb, 3),
+        "batched_gnnzvec_per_s": round(work / tb / 1e9, 3), "plain_gnnzvec_per_s": round(work / tp / 1e9, 3),
+        "ranks_equal_planted": bool(ok_b), "ranks_equal_plain": bool(plain_ok), "solves": nsolves,
+        "batch_info": info, "higher_is_better": True, "n_gpus": 1, "dtype": "u32",
+        "data": "synthetic planted-rank matrices (seeded)",
+        "config": {"workload": f"{len(mats)} of the 64 batched-configuration matrices (n log-uniform 5e3..2e5, "
+                               f"m = 1.2-2.0 n, rank 70-95 % of n) x primes {list(primes)}, block 8",
+                   "matrices": [[A.m, A.n, A.nnz] for A in mats]}}), flush=True)
+
+
+def serve_mode(args):
+    """Seeded Poisson trace of rank requests through the continuous-batching server."""
+    import math
+
+    import numpy as np
+
+    import paper_0704_2351_amd as bw
+    from workloads import CONFIG4_PRIMES, config_seed, planted
+
+    rng = np.random.default_rng(config_seed(5, 999_999))
+    trace = []
+    t = 0.0
+    for j in range(args.serve_count):
+        t += rng.exponential(1.0 / args.serve_rate)
+        n = int(round(math.exp(rng.uniform(math.log(1e3), math.log(args.serve_nmax)))))
+        m = int(round(1.5 * n))
+        r = int(round(n * rng.uniform(0.70, 0.95)))
+        p = int(CONFIG4_PRIMES[rng.integers(0, 4)])
+        trace.append((t, m, n, r, p, config_seed(5, j)))
+    log(f"generating {len(trace)} request matrices (n up to {max(x[2] for x in trace)})")
+    mats = [planted(m, n, r, 9, sd) for (_, m, n, r, _, sd) in trace]
+    srv = bw.Server(64 << 30, 128, 8)
+    warm = srv.submit(mats[0], trace[0][4], 1)
+    srv.wait(warm)
+    srv.close()
+    srv = bw.Server(64 << 30, 128, 8)
+    tickets = []
+    t0 = time.perf_counter()
+    for (at, m, n, r, p, sd), A in zip(trace, mats):
+        delay = at - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(srv.submit(A, p, 1))
+    ranks = [srv.wait(tk) for tk in tickets]
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    ok = all(rk == A.planted_rank for rk, A in zip(ranks, mats))
+    print(json.dumps({
+        "metric": METRIC, "mode": "serving", "value": round(st["solves_per_s"], 4), "unit": "solves/s",
+        "p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2), "wall_s": round(wall, 2),
+        "completed": st["completed"], "max_queue": st["max_queue"], "max_active": st["max_active"],
+        "ranks_equal_planted": bool(ok), "higher_is_better": True, "n_gpus": 1, "dtype": "u32",
+        "data": "synthetic planted-rank matrices (seeded), seeded Poisson arrivals",
+        "config": {"workload": f"{args.serve_count} requests, Poisson {args.serve_rate}/s, n log-uniform "
+                               f"1e3..{args.serve_nmax:g}, m = 1.5 n, rank 70-95 % of n, prime from {list(CONFIG4_PRIMES)}, "
+                               f"block 8"}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +164,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-iters", type=int, default=50)
+    ap.add_argument("--batch", action="store_true",
+                    help="batched workload: planted matrices of the batched configuration, 4 primes, block 8; "
+                         "solves/s of one batched call against the same ranks one call at a time")
+    ap.add_argument("--batch-count", type=int, default=16, help="matrices of the batched configuration to use")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving workload: a seeded Poisson trace of rank requests through the server")
+    ap.add_argument("--serve-count", type=int, default=40)
+    ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--serve-nmax", type=float, default=2e4)
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only the per-kernel timing loop at p = 65521 plus a 256 MiB device copy "
+                         "(a plain copy kernel of known size, for calibrating memory counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described, "
@@ -87,6 +189,10 @@ def main():
     from workloads import config2
 
     torch.cuda.set_device(0)
+    if args.batch:
+        return batch_mode(args)
+    if args.serve:
+        return serve_mode(args)
     s = 8
     primes = (65521, 2**31 - 1)
     log("generating the planted 200000 x 150000 matrix")
@@ -95,6 +201,15 @@ def main():
     Ad = bw.csr_to_device(A, "cuda:0")
     torch.cuda.synchronize()
     planted = A.planted_rank
+
+    if args.kernels_only:
+        us = bw.time_step_kernels_dev(Ad, primes[0], s, False, args.kernel_iters)
+        src = torch.empty(64 << 20, dtype=torch.int32, device="cuda:0").fill_(1)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"kernels_us": [round(x, 3) for x in us], "copy_bytes": 256 << 20}), flush=True)
+        return
 
     def one_step():
         infos = []

@@ -73,6 +73,18 @@ typedef struct {
     int32_t pad;
 } bwr_rank_info;
 
+/* Timings of one batched rank computation. */
+typedef struct {
+    double t_encode;    /* seconds: upload, validation and encoding of every matrix */
+    double t_sequence;  /* seconds: batched sequence steps */
+    double t_sigma;     /* seconds: sigma-bases (device) of the finished jobs */
+    double t_total;     /* seconds: the whole call */
+    int64_t steps;      /* batched steps (one launch per product each) */
+    int32_t jobs;       /* (matrix, group of primes) jobs */
+    int32_t width;      /* block width of the batch (primes per job x block size, padded) */
+    int32_t g1, g2;     /* lanes per row slice of the two products */
+} bwr_batch_info;
+
 /* Library version (major * 10000 + minor * 100 + patch). */
 int bwr_version(void);
 
@@ -140,6 +152,57 @@ int bwr_rank_modp_dev(const bwr_csr* A_dev, uint32_t p, int32_t block, uint64_t 
 int bwr_time_step_kernels_dev(const bwr_csr* A_dev, uint32_t p, int32_t s, int32_t transpose, int32_t iters,
                               void* stream, double* us_out);
 
+/* Ranks of nmat matrices, each at nprimes primes, with their sequences
+ * advanced together: one launch per sparse product per step covers every
+ * (matrix, group of primes) job, and the primes of a job share one pass over
+ * the matrix (their blocks sit side by side in one block of width
+ * primes x block).  Each rank equals bwr_rank_modp(A[j], primes[t], block,
+ * seed) exactly: same draws, same sequence, same read-out.
+ * ranks_out[j * nprimes + t].  Matrices with entries outside [-127, 127] or
+ * a dimension above 2^24 take the single-matrix path.  info may be NULL. */
+int bwr_rank_modp_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* primes, int32_t nprimes,
+                        int32_t block, uint64_t seed, int64_t* ranks_out, bwr_batch_info* info);
+
+/* The sequences bwr_rank_modp_batch computes, returned instead of ranked:
+ * for matrix j (B on its smaller side, as in bwr_rank_modp) and prime t,
+ * S_out[j][(t * len[j] + k) * s * s + i * s + c] = S_k[i][c] for k < len[j],
+ * with U, V, D_r, D_c drawn from `seed` as bwr_rank_modp draws them. */
+int bwr_sequence_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* primes, int32_t nprimes, int32_t s,
+                       uint64_t seed, const int64_t* len, uint32_t* const* S_out);
+
+/* ---- serving: a continuous-batching rank server ---------------------------
+ * A worker thread keeps one batch of sequences running on the current device.
+ * Submitted requests queue up and join the running batch at the next step
+ * boundary while the HBM budget (estimated footprint of encoded matrix,
+ * blocks and sequence) and the slot count allow.  A finished sequence gets
+ * its sigma-basis and read-out and the request is answered; results are
+ * identical to bwr_rank_modp(A, p, block, seed).  Calls on one server are
+ * thread-safe. */
+typedef struct bwr_server bwr_server;
+
+typedef struct {
+    double p50_ms, p99_ms;  /* latency quantiles: answer time - submit time */
+    double solves_per_s;    /* answered requests / (last answer - first submit) */
+    double busy_s;          /* worker time spent advancing the batch and answering */
+    int64_t completed;      /* answered requests */
+    int64_t max_queue;      /* largest queue length seen */
+    int64_t max_active;     /* largest number of requests in the batch at once */
+    int64_t steps;          /* batched steps run */
+} bwr_server_stats;
+
+/* Creates a server on the current device (block size 1..32). */
+int bwr_server_create(uint64_t hbm_budget_bytes, int32_t max_slots, int32_t block, bwr_server** out);
+/* Copies A (host CSR) to the device and queues the request; BWR_ENOMEM if it
+ * alone exceeds the budget.  *ticket identifies the request. */
+int bwr_server_submit(bwr_server* srv, const bwr_csr* A, uint32_t p, uint64_t seed, uint64_t* ticket);
+/* *done = 1 and *rank set once answered (the request's error code otherwise). */
+int bwr_server_poll(bwr_server* srv, uint64_t ticket, int32_t* done, int64_t* rank);
+/* Blocks until the request is answered. */
+int bwr_server_wait(bwr_server* srv, uint64_t ticket, int64_t* rank);
+int bwr_server_get_stats(bwr_server* srv, bwr_server_stats* out);
+/* Stops the worker (requests still running are abandoned) and frees everything. */
+void bwr_server_destroy(bwr_server* srv);
+
 /* Minimal generator of a host sequence S (len x s x s, residues mod p) via
  * the sigma-basis of [S(x); -I] of order len (Section 2.4).  delta_out (s):
  * shifted row degrees; P_out ((max_deg + 1) x s x s, capacity given by
@@ -148,6 +211,12 @@ int bwr_time_step_kernels_dev(const bwr_csr* A_dev, uint32_t p, int32_t s, int32
  * satisfies sum_j F_{i,j} S_{l+j} = 0.  *max_deg_out = max delta. */
 int bwr_min_generator(const uint32_t* S, int64_t len, int32_t s, uint32_t p, int64_t* delta_out,
                       uint32_t* P_out, int64_t P_cap_terms, int64_t* max_deg_out);
+
+/* bwr_min_generator on a device sequence S_dev (len x s x s, device memory),
+ * with the sigma-basis computed on the device (PM-Basis over NTT/CRT products
+ * and M-Basis leaves, s <= 32); delta_out and P_out are host memory. */
+int bwr_min_generator_dev(const uint32_t* S_dev, int64_t len, int32_t s, uint32_t p, void* stream,
+                          int64_t* delta_out, uint32_t* P_out, int64_t P_cap_terms, int64_t* max_deg_out);
 
 /* Rank read-out from a host sequence: generator from the first `len` terms,
  * verified on `check` further terms (S holds len + check terms), then

@@ -18,7 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libbwrank.so")
 BWR_OK, BWR_EINVAL, BWR_EPRIME, BWR_ENOMEM, BWR_EDEVICE, BWR_EBUSY, BWR_ESHORT = 0, -1, -2, -3, -4, -5, -6
 EXPORTED = ("bwr_version", "bwr_last_error", "bwr_is_prime", "bwr_sequence_length", "bwr_set_threads",
             "bwr_random_block", "bwr_sequence", "bwr_sequence_dev", "bwr_apply_dev", "bwr_rank_modp",
-            "bwr_rank_modp_dev", "bwr_min_generator", "bwr_rank_from_sequence", "bwr_time_step_kernels_dev")
+            "bwr_rank_modp_dev", "bwr_min_generator", "bwr_rank_from_sequence", "bwr_time_step_kernels_dev",
+            "bwr_min_generator_dev", "bwr_rank_modp_batch", "bwr_sequence_batch", "bwr_server_create",
+            "bwr_server_submit", "bwr_server_poll", "bwr_server_wait", "bwr_server_get_stats", "bwr_server_destroy")
 
 
 class BwrError(RuntimeError):
@@ -30,6 +32,15 @@ class BwrError(RuntimeError):
 class CSRStruct(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
                 ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("t_encode", ctypes.c_double), ("t_sequence", ctypes.c_double), ("t_sigma", ctypes.c_double),
+                ("t_total", ctypes.c_double), ("steps", ctypes.c_int64), ("jobs", ctypes.c_int32),
+                ("width", ctypes.c_int32), ("g1", ctypes.c_int32), ("g2", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class RankInfo(ctypes.Structure):
@@ -69,6 +80,15 @@ def lib():
             "bwr_min_generator": (ctypes.c_int, [vp, i64, i32, u32, vp, vp, i64, vp]),
             "bwr_rank_from_sequence": (ctypes.c_int, [vp, i64, i64, i32, u32, vp]),
             "bwr_time_step_kernels_dev": (ctypes.c_int, [vp, u32, i32, i32, i32, vp, vp]),
+            "bwr_min_generator_dev": (ctypes.c_int, [vp, i64, i32, u32, vp, vp, vp, i64, vp]),
+            "bwr_rank_modp_batch": (ctypes.c_int, [vp, i32, vp, i32, i32, u64, vp, vp]),
+            "bwr_sequence_batch": (ctypes.c_int, [vp, i32, vp, i32, i32, u64, vp, vp]),
+            "bwr_server_create": (ctypes.c_int, [u64, i32, i32, vp]),
+            "bwr_server_submit": (ctypes.c_int, [vp, vp, u32, u64, vp]),
+            "bwr_server_poll": (ctypes.c_int, [vp, u64, vp, vp]),
+            "bwr_server_wait": (ctypes.c_int, [vp, u64, vp]),
+            "bwr_server_get_stats": (ctypes.c_int, [vp, vp]),
+            "bwr_server_destroy": (None, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -252,3 +272,99 @@ def time_step_kernels_dev(Ad, p: int, s: int, transpose: bool = False, iters: in
     _check(lib().bwr_time_step_kernels_dev(ctypes.byref(st), int(p), int(s), int(transpose), int(iters), _stream(),
                                            us.ctypes.data))
     return us
+
+
+def min_generator_dev(S_dev, p: int):
+    """Device sigma-basis of a device sequence tensor (len, s, s): (delta, P) on the host."""
+    L, s, _ = S_dev.shape
+    delta = np.zeros(s, dtype=np.int64)
+    P = np.zeros((L + 2) * s * s, dtype=np.uint32)
+    md = ctypes.c_int64(0)
+    _check(lib().bwr_min_generator_dev(_dptr(S_dev), int(L), int(s), int(p), _stream(), delta.ctypes.data,
+                                       P.ctypes.data, int(L + 2), ctypes.byref(md)))
+    return delta, P[: (md.value + 1) * s * s].reshape(md.value + 1, s, s)
+
+
+def _csr_array(mats):
+    structs, keep = [], []
+    for A in mats:
+        st, k = _host_csr(A)
+        structs.append(st)
+        keep.append(k)
+    arr = (CSRStruct * max(len(structs), 1))(*structs)
+    ptrs = (ctypes.c_void_p * max(len(structs), 1))(*[ctypes.addressof(arr[i]) for i in range(len(structs))])
+    return ptrs, (arr, keep)
+
+
+def rank_modp_batch(mats, primes, block: int, seed: int):
+    """(ranks (len(mats), len(primes)), info dict): all sequences advanced together."""
+    ptrs, keep = _csr_array(mats)
+    pr = np.ascontiguousarray(primes, dtype=np.uint32)
+    out = np.zeros(max(len(mats) * len(pr), 1), dtype=np.int64)
+    info = BatchInfo()
+    _check(lib().bwr_rank_modp_batch(ptrs, len(mats), pr.ctypes.data, len(pr), int(block), int(seed),
+                                     out.ctypes.data, ctypes.byref(info)))
+    return out[: len(mats) * len(pr)].reshape(len(mats), len(pr)), info.as_dict()
+
+
+def sequence_batch(mats, primes, s: int, seed: int, lengths):
+    """Batched sequences: list over matrices of arrays (len(primes), length, s, s)."""
+    ptrs, keep = _csr_array(mats)
+    pr = np.ascontiguousarray(primes, dtype=np.uint32)
+    ln = np.ascontiguousarray(lengths, dtype=np.int64)
+    outs = [np.zeros(len(pr) * int(l) * s * s, dtype=np.uint32) for l in ln]
+    optrs = (ctypes.c_void_p * max(len(outs), 1))(*[o.ctypes.data for o in outs])
+    _check(lib().bwr_sequence_batch(ptrs, len(mats), pr.ctypes.data, len(pr), int(s), int(seed), ln.ctypes.data,
+                                    optrs))
+    return [o.reshape(len(pr), int(l), s, s) for o, l in zip(outs, ln)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("solves_per_s", ctypes.c_double),
+                ("busy_s", ctypes.c_double), ("completed", ctypes.c_int64), ("max_queue", ctypes.c_int64),
+                ("max_active", ctypes.c_int64), ("steps", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Server:
+    """Continuous-batching rank server (bwr_server_*): submit host CSR requests, wait for ranks."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 64, block: int = 8):
+        h = ctypes.c_void_p()
+        _check(lib().bwr_server_create(int(hbm_budget_bytes), int(max_slots), int(block), ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, A, p: int, seed: int) -> int:
+        st, keep = _host_csr(A)
+        t = ctypes.c_uint64(0)
+        _check(lib().bwr_server_submit(self._h, ctypes.byref(st), int(p), int(seed), ctypes.byref(t)))
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        d = ctypes.c_int32(0)
+        r = ctypes.c_int64(0)
+        _check(lib().bwr_server_poll(self._h, int(ticket), ctypes.byref(d), ctypes.byref(r)))
+        return (True, int(r.value)) if d.value else (False, None)
+
+    def wait(self, ticket: int) -> int:
+        r = ctypes.c_int64(0)
+        _check(lib().bwr_server_wait(self._h, int(ticket), ctypes.byref(r)))
+        return int(r.value)
+
+    def stats(self):
+        st = ServerStats()
+        _check(lib().bwr_server_get_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if self._h:
+            lib().bwr_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -12,6 +12,9 @@
 #include "engine.h"
 #include "kernels.h"
 #include "sigma.h"
+#include "sigma_gpu.h"
+#include "batch_runner.h"
+#include "server.h"
 #include "splitmix.h"
 
 using namespace bwr;
@@ -92,6 +95,18 @@ hipStream_t lib_stream(Error* err) {
         }
     }
     return streams[dev];
+}
+
+// Device entry points run on the library stream (which sequence capture needs:
+// the legacy null stream cannot be captured), after the caller's stream has
+// drained; they return once their own work has completed.
+hipStream_t work_stream(void* user, Error* err) {
+    hipError_t e = hipStreamSynchronize((hipStream_t)user);
+    if (e != hipSuccess) {
+        *err = Error::device(e, "hipStreamSynchronize (caller stream)");
+        return nullptr;
+    }
+    return lib_stream(err);
 }
 
 CsrView view(const bwr_csr* A) { return CsrView{A->m, A->n, A->nnz, A->row_ptr, A->col_idx, A->val}; }
@@ -212,18 +227,28 @@ Error rank_dev_impl(const CsrView& A, uint32_t p, int32_t block, uint64_t seed, 
     a.S_out = S.as<uint32_t>();
     const double t1 = now_s();
     if (!(e = run_sequence(a, st)).ok()) return e;
-    std::vector<uint32_t> Sh((size_t)(total * s * s));
-    he = hipMemcpyAsync(Sh.data(), S.as<void>(), sizeof(uint32_t) * Sh.size(), hipMemcpyDeviceToHost, st);
-    if (he == hipSuccess) he = hipStreamSynchronize(st);
-    if (he != hipSuccess) return Error::device(he, "sequence download");
+    he = hipStreamSynchronize(st);
+    if (he != hipSuccess) return Error::device(he, "sequence");
     const double t2 = now_s();
     info.t_sequence = t2 - t1;
     Generator g;
     SigmaStats ss;
-    if (!(e = min_generator(Sh.data(), L, s, p, &g, &ss)).ok()) return e;
+    const bool on_device = gpu_leaf_order(s) > 0 && !getenv("BWR_HOST_SIGMA");
+    std::vector<uint32_t> Sh((size_t)(total * s * s));
+    if (on_device) {
+        if (!(e = gpu_min_generator(S.as<uint32_t>(), L, s, p, st, &g, &ss)).ok()) return e;
+        he = hipMemcpyAsync(Sh.data(), S.as<void>(), sizeof(uint32_t) * Sh.size(), hipMemcpyDeviceToHost, st);
+        if (he == hipSuccess) he = hipStreamSynchronize(st);
+        if (he != hipSuccess) return Error::device(he, "sequence download");
+    } else {
+        he = hipMemcpyAsync(Sh.data(), S.as<void>(), sizeof(uint32_t) * Sh.size(), hipMemcpyDeviceToHost, st);
+        if (he == hipSuccess) he = hipStreamSynchronize(st);
+        if (he != hipSuccess) return Error::device(he, "sequence download");
+        if (!(e = min_generator(Sh.data(), L, s, p, &g, &ss)).ok()) return e;
+    }
     const double t3 = now_s();
     info.t_sigma = t3 - t2;
-    info.sigma_threads = ss.threads;
+    info.sigma_threads = on_device ? 0 : ss.threads;
     if (!(e = check_generator(g, Sh.data(), L, total, p)).ok()) return e;
     int64_t r = 0;
     if (!(e = rank_from_generator(g, p, &r)).ok()) return e;
@@ -234,7 +259,71 @@ Error rank_dev_impl(const CsrView& A, uint32_t p, int32_t block, uint64_t seed, 
     return {};
 }
 
+
+int pow2_at_most(double x, int lo, int hi) {
+    int g = lo;
+    while (g * 2 <= hi && g * 2 <= x) g *= 2;
+    return g;
+}
+
+// Read-out of one finished (job, prime): device sigma-basis, check terms, rank.
+Error rank_of_sequence_dev(const uint32_t* S_dev, int64_t L, int64_t total, int32_t s, uint32_t p, hipStream_t st,
+                           int64_t* rank, double* t_sigma) {
+    const double t0 = now_s();
+    Generator g;
+    Error e;
+    std::vector<uint32_t> Sh((size_t)(total * s * s));
+    if (gpu_leaf_order(s) > 0 && !getenv("BWR_HOST_SIGMA")) {
+        if (!(e = gpu_min_generator(S_dev, L, s, p, st, &g)).ok()) return e;
+        hipError_t he = hipMemcpyAsync(Sh.data(), S_dev, 4 * Sh.size(), hipMemcpyDeviceToHost, st);
+        if (he == hipSuccess) he = hipStreamSynchronize(st);
+        if (he != hipSuccess) return Error::device(he, "sequence download");
+    } else {
+        hipError_t he = hipMemcpyAsync(Sh.data(), S_dev, 4 * Sh.size(), hipMemcpyDeviceToHost, st);
+        if (he == hipSuccess) he = hipStreamSynchronize(st);
+        if (he != hipSuccess) return Error::device(he, "sequence download");
+        if (!(e = min_generator(Sh.data(), L, s, p, &g)).ok()) return e;
+    }
+    *t_sigma += now_s() - t0;
+    if (!(e = check_generator(g, Sh.data(), L, total, p)).ok()) return e;
+    return rank_from_generator(g, p, rank);
+}
+
+struct BatchPlan {
+    int W = 0, G1 = 0, G2 = 0, per_job = 0;
+};
+
+struct Shape {
+    int64_t rows1, rows2, nnz;
+};
+
+BatchPlan plan_batch(const std::vector<Shape>& shapes, int nprimes, int s) {
+    BatchPlan bp;
+    const int spad = (s + 3) & ~3;
+    if (spad > 32) return bp;
+    bp.per_job = std::max(1, std::min(nprimes, 32 / spad));
+    bp.W = BatchRunner::width_for(bp.per_job, s);
+    double r1 = 0, r2 = 0, nz = 0;
+    for (const Shape& sh : shapes) {
+        r1 += (double)sh.rows1;
+        r2 += (double)sh.rows2;
+        nz += (double)sh.nnz;
+    }
+    const double a1 = r1 > 0 ? nz / r1 : 1, a2 = r2 > 0 ? nz / r2 : 1;
+    const int cg = bp.W / 4;
+    bp.G1 = pow2_at_most(a1 / 4.0 + 1.0, 1, std::max(1, 64 / cg));
+    bp.G2 = pow2_at_most(a2 / 4.0 + 1.0, std::max(1, bp.W / 4), std::max(1, 64 / cg));
+    if (const char* e = getenv("BWR_BATCH_G1")) bp.G1 = atoi(e);
+    if (const char* e = getenv("BWR_BATCH_G2")) bp.G2 = atoi(e);
+    if (!batch_supported(bp.W, bp.G1, false) || !batch_supported(bp.W, bp.G2, true)) bp.W = 0;
+    return bp;
+}
+
 }  // namespace
+
+struct bwr_server {
+    std::unique_ptr<bwr::Server> impl;
+};
 
 extern "C" {
 
@@ -307,7 +396,10 @@ int bwr_sequence(const bwr_csr* A, const uint32_t* d_row, const uint32_t* d_col,
 int bwr_sequence_dev(const bwr_csr* A_dev, const uint32_t* d_row, const uint32_t* d_col, const uint32_t* U,
                      const uint32_t* V, uint32_t p, int32_t s, int64_t len, uint32_t* S_out, void* stream) {
     if (!A_dev) return fail(BWR_EINVAL, "A is NULL");
-    Error e = sequence_dev_impl(view(A_dev), d_row, d_col, U, V, p, s, len, S_out, (hipStream_t)stream);
+    Error e;
+    hipStream_t st = work_stream(stream, &e);
+    if (!e.ok()) return fail(e);
+    e = sequence_dev_impl(view(A_dev), d_row, d_col, U, V, p, s, len, S_out, st);
     if (!e.ok()) return fail(e);
     g_err.clear();
     return BWR_OK;
@@ -320,7 +412,8 @@ int bwr_apply_dev(const bwr_csr* A_dev, const uint32_t* d_row, const uint32_t* d
     if (!e.ok()) return fail(e);
     if (s < 1 || s > 64) return fail(BWR_EINVAL, "block size must be in 1..64");
     if (A_dev->n > 0 && (!X || !Z)) return fail(BWR_EINVAL, "NULL block");
-    hipStream_t st = (hipStream_t)stream;
+    hipStream_t st = work_stream(stream, &e);
+    if (!e.ok()) return fail(e);
     DeviceMatrix M;
     if (!(e = encode_matrix(view(A_dev), p, st, &M)).ok()) return fail(e);
     if (!(e = apply_once(M, false, ModP::make(p), s, d_row, d_col, X, Z, st)).ok()) return fail(e);
@@ -360,7 +453,10 @@ int bwr_rank_modp_dev(const bwr_csr* A_dev, uint32_t p, int32_t block, uint64_t 
                       int64_t* rank_out, bwr_rank_info* info) {
     if (!A_dev || !rank_out) return fail(BWR_EINVAL, "NULL argument");
     RankOut ro;
-    Error e = rank_dev_impl(view(A_dev), p, block, seed, (hipStream_t)stream, &ro);
+    Error e;
+    hipStream_t st = work_stream(stream, &e);
+    if (!e.ok()) return fail(e);
+    e = rank_dev_impl(view(A_dev), p, block, seed, st, &ro);
     if (!e.ok()) return fail(e);
     *rank_out = ro.rank;
     if (info) *info = ro.info;
@@ -373,7 +469,8 @@ int bwr_time_step_kernels_dev(const bwr_csr* A_dev, uint32_t p, int32_t s, int32
     if (!A_dev || !us_out) return fail(BWR_EINVAL, "NULL argument");
     Error e = check_prime(p);
     if (!e.ok()) return fail(e);
-    hipStream_t st = (hipStream_t)stream;
+    hipStream_t st = work_stream(stream, &e);
+    if (!e.ok()) return fail(e);
     DeviceMatrix M;
     if (!(e = encode_matrix(view(A_dev), p, st, &M)).ok()) return fail(e);
     if (!(e = time_step_kernels(M, transpose != 0, ModP::make(p), s, iters, st, us_out)).ok()) return fail(e);
@@ -405,6 +502,212 @@ int bwr_min_generator(const uint32_t* S, int64_t len, int32_t s, uint32_t p, int
     return BWR_OK;
 }
 
+int bwr_sequence_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* primes, int32_t nprimes, int32_t s,
+                       uint64_t seed, const int64_t* len, uint32_t* const* S_out) {
+    if (nmat < 0 || nprimes < 1 || (nmat > 0 && (!A || !primes || !len || !S_out)))
+        return fail(BWR_EINVAL, "bad arguments");
+    Error e;
+    for (int t = 0; t < nprimes; ++t)
+        if (!(e = check_prime(primes[t])).ok()) return fail(e);
+    for (int j = 0; j < nmat; ++j) {
+        if (!A[j] || !S_out[j] || len[j] < 1) return fail(BWR_EINVAL, "bad matrix, output or length");
+        if (!(e = check_host_csr(view(A[j]))).ok()) return fail(e);
+    }
+    hipStream_t st = lib_stream(&e);
+    if (!e.ok()) return fail(e);
+    std::vector<HostUpload> ups(nmat);
+    std::vector<DeviceMatrix> Ms(nmat);
+    std::vector<bool> tr(nmat);
+    for (int j = 0; j < nmat; ++j) {
+        if (!(e = upload(A[j], st, &ups[j])).ok()) return fail(e);
+        if (!(e = encode_matrix(ups[j].dev, primes[0], st, &Ms[j])).ok()) return fail(e);
+        if (!Ms[j].packed) return fail(BWR_EINVAL, "batched sequences need entries in [-127, 127] and sizes <= 2^24");
+        tr[j] = A[j]->m < A[j]->n;
+    }
+    std::vector<Shape> shapes;
+    for (int j = 0; j < nmat; ++j)
+        shapes.push_back({tr[j] ? Ms[j].n : Ms[j].m, tr[j] ? Ms[j].m : Ms[j].n, Ms[j].nnz});
+    BatchPlan bp = plan_batch(shapes, nprimes, s);
+    if (!bp.W) return fail(BWR_EINVAL, "block size too large for batched sequences");
+    BatchRunner R(bp.W, bp.G1, bp.G2, st);
+    std::vector<std::pair<int, int>> owner;  // job -> (matrix, first prime index)
+    for (int j = 0; j < nmat; ++j)
+        for (int t0 = 0; t0 < nprimes; t0 += bp.per_job) {
+            BatchSpec sp;
+            sp.M = &Ms[j];
+            sp.transpose = tr[j];
+            sp.primes.assign(primes + t0, primes + std::min(nprimes, t0 + bp.per_job));
+            sp.s = s;
+            sp.seed = seed;
+            sp.len = len[j];
+            int id = 0;
+            if (!(e = R.add(sp, &id)).ok()) return fail(e);
+            owner.emplace_back(j, t0);
+        }
+    std::vector<int> done;
+    while (true) {
+        size_t before = done.size();
+        if (!(e = R.advance(INT64_MAX, &done)).ok()) return fail(e);
+        if (R.active() == 0 && done.size() == before) break;
+        if (R.active() == 0 && done.size() == owner.size()) break;
+    }
+    for (size_t id = 0; id < owner.size(); ++id) {
+        const int j = owner[id].first, t0 = owner[id].second;
+        const int np = (int)R.spec((int)id).primes.size();
+        for (int t = 0; t < np; ++t) {
+            const size_t n = (size_t)len[j] * s * s;
+            hipError_t he = hipMemcpyAsync(S_out[j] + (size_t)(t0 + t) * n, R.sequence((int)id, t), 4 * n,
+                                           hipMemcpyDeviceToHost, st);
+            if (he != hipSuccess) return fail(Error::device(he, "download"));
+        }
+    }
+    hipError_t he = hipStreamSynchronize(st);
+    if (he != hipSuccess) return fail(Error::device(he, "batch"));
+    g_err.clear();
+    return BWR_OK;
+}
+
+int bwr_rank_modp_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* primes, int32_t nprimes,
+                        int32_t block, uint64_t seed, int64_t* ranks_out, bwr_batch_info* info) {
+    if (nmat < 0 || nprimes < 1 || (nmat > 0 && (!A || !primes || !ranks_out)))
+        return fail(BWR_EINVAL, "bad arguments");
+    if (block < 1 || block > 64) return fail(BWR_EINVAL, "block size must be in 1..64");
+    Error e;
+    for (int t = 0; t < nprimes; ++t)
+        if (!(e = check_prime(primes[t])).ok()) return fail(e);
+    for (int j = 0; j < nmat; ++j) {
+        if (!A[j]) return fail(BWR_EINVAL, "NULL matrix");
+        if (!(e = check_host_csr(view(A[j]))).ok()) return fail(e);
+    }
+    const double t0 = now_s();
+    bwr_batch_info bi;
+    std::memset(&bi, 0, sizeof(bi));
+    hipStream_t st = lib_stream(&e);
+    if (!e.ok()) return fail(e);
+    std::vector<HostUpload> ups(nmat);
+    std::vector<DeviceMatrix> Ms(nmat);
+    std::vector<bool> tr(nmat), batched(nmat, false);
+    std::vector<int64_t> ranks((size_t)nmat * nprimes, 0);
+    for (int j = 0; j < nmat; ++j) {
+        tr[j] = A[j]->m < A[j]->n;
+        if (A[j]->nnz == 0 || A[j]->m == 0 || A[j]->n == 0) continue;
+        if (!(e = upload(A[j], st, &ups[j])).ok()) return fail(e);
+        if (!(e = encode_matrix(ups[j].dev, primes[0], st, &Ms[j])).ok()) return fail(e);
+        batched[j] = Ms[j].packed;
+    }
+    bi.t_encode = now_s() - t0;
+    // matrices the batch kernels cannot take (wide entries) go through the single-matrix path
+    for (int j = 0; j < nmat; ++j) {
+        if (batched[j] || A[j]->nnz == 0 || A[j]->m == 0 || A[j]->n == 0) continue;
+        for (int t = 0; t < nprimes; ++t) {
+            RankOut ro;
+            if (!(e = rank_dev_impl(ups[j].dev, primes[t], block, seed, st, &ro)).ok()) return fail(e);
+            ranks[(size_t)j * nprimes + t] = ro.rank;
+            bi.t_sequence += ro.info.t_sequence;
+            bi.t_sigma += ro.info.t_sigma;
+        }
+    }
+    std::vector<int> live_of;
+    for (int j = 0; j < nmat; ++j)
+        if (batched[j]) live_of.push_back(j);
+    if (!live_of.empty()) {
+        // plan with the largest block any batched matrix uses
+        int smax = 1;
+        std::vector<Shape> shapes;
+        for (int j : live_of) {
+            smax = std::max<int>(smax, (int)std::min<int64_t>(block, std::min(A[j]->m, A[j]->n)));
+            shapes.push_back({tr[j] ? Ms[j].n : Ms[j].m, tr[j] ? Ms[j].m : Ms[j].n, Ms[j].nnz});
+        }
+        const BatchPlan bp = plan_batch(shapes, nprimes, smax);
+        if (!bp.W) return fail(BWR_EINVAL, "block size too large for batched ranks");
+        bi.width = bp.W;
+        bi.g1 = bp.G1;
+        bi.g2 = bp.G2;
+        BatchRunner R(bp.W, bp.G1, bp.G2, st);
+        struct Own {
+            int j, t0;
+            int64_t L;
+            int32_t s;
+        };
+        std::vector<Own> owner;
+        for (int j : live_of) {
+            const int64_t nb = std::min(A[j]->m, A[j]->n);
+            const int32_t s = (int32_t)std::min<int64_t>(block, nb);
+            const int64_t L = 2 + (2 * nb + s - 1) / s;
+            for (int t0 = 0; t0 < nprimes; t0 += bp.per_job) {
+                BatchSpec sp;
+                sp.M = &Ms[j];
+                sp.transpose = tr[j];
+                sp.primes.assign(primes + t0, primes + std::min(nprimes, t0 + bp.per_job));
+                sp.s = s;
+                sp.seed = seed;
+                sp.len = L + CHECK_TERMS;
+                int id = 0;
+                if (!(e = R.add(sp, &id)).ok()) return fail(e);
+                owner.push_back({j, t0, L, s});
+                ++bi.jobs;
+            }
+        }
+        const double t1 = now_s();
+        double t_sig = 0;
+        size_t finished = 0;
+        while (finished < owner.size()) {
+            std::vector<int> done;
+            if (!(e = R.advance(INT64_MAX, &done)).ok()) return fail(e);
+            if (done.empty() && R.active() == 0) break;
+            for (int id : done) {
+                const Own& o = owner[id];
+                const BatchSpec& sp = R.spec(id);
+                for (size_t t = 0; t < sp.primes.size(); ++t) {
+                    int64_t r = 0;
+                    if (!(e = rank_of_sequence_dev(R.sequence(id, (int)t), o.L, R.length(id), o.s, sp.primes[t], st, &r,
+                                                   &t_sig))
+                             .ok())
+                        return fail(e);
+                    ranks[(size_t)o.j * nprimes + o.t0 + t] = r;
+                }
+                R.release(id);
+                ++finished;
+            }
+        }
+        bi.steps = R.global_step();
+        bi.t_sigma += t_sig;
+        bi.t_sequence += now_s() - t1 - t_sig;
+    }
+    std::memcpy(ranks_out, ranks.data(), sizeof(int64_t) * ranks.size());
+    bi.t_total = now_s() - t0;
+    if (info) *info = bi;
+    g_err.clear();
+    return BWR_OK;
+}
+
+int bwr_min_generator_dev(const uint32_t* S_dev, int64_t len, int32_t s, uint32_t p, void* stream,
+                          int64_t* delta_out, uint32_t* P_out, int64_t P_cap_terms, int64_t* max_deg_out) {
+    Error e = check_prime(p);
+    if (!e.ok()) return fail(e);
+    if (s < 1 || s > 64 || len < 0 || (len > 0 && !S_dev) || !delta_out || !P_out || !max_deg_out)
+        return fail(BWR_EINVAL, "bad arguments");
+    if (gpu_leaf_order(s) == 0) return fail(BWR_EINVAL, "block size too large for the device sigma-basis");
+    hipStream_t st = work_stream(stream, &e);
+    if (!e.ok()) return fail(e);
+    Generator g;
+    if (!(e = gpu_min_generator(S_dev, len, s, p, st, &g)).ok()) return fail(e);
+    int64_t maxd = 0;
+    for (int64_t x : g.delta) maxd = std::max(maxd, x);
+    if (maxd + 1 > P_cap_terms) return fail(BWR_EINVAL, "P_out capacity too small");
+    std::memset(P_out, 0, sizeof(uint32_t) * (size_t)(maxd + 1) * s * s);
+    for (int i = 0; i < s; ++i) {
+        delta_out[i] = g.delta[i];
+        for (int j = 0; j < s; ++j) {
+            const uint32_t* src = g.P.at(i, j);
+            for (int64_t k = 0; k < g.P.len && k <= maxd; ++k) P_out[((size_t)k * s + i) * s + j] = src[k];
+        }
+    }
+    *max_deg_out = maxd;
+    g_err.clear();
+    return BWR_OK;
+}
+
 int bwr_rank_from_sequence(const uint32_t* S, int64_t len, int64_t check, int32_t s, uint32_t p, int64_t* rank_out) {
     Error e = check_prime(p);
     if (!e.ok()) return fail(e);
@@ -419,5 +722,63 @@ int bwr_rank_from_sequence(const uint32_t* S, int64_t len, int64_t check, int32_
     g_err.clear();
     return BWR_OK;
 }
+
+int bwr_server_create(uint64_t hbm_budget_bytes, int32_t max_slots, int32_t block, bwr_server** out) {
+    if (!out || max_slots < 1 || block < 1 || block > 32 || hbm_budget_bytes == 0)
+        return fail(BWR_EINVAL, "bad arguments");
+    auto srv = std::make_unique<bwr_server>();
+    srv->impl = std::make_unique<Server>((int64_t)std::min<uint64_t>(hbm_budget_bytes, (uint64_t)INT64_MAX), max_slots,
+                                         block);
+    Error e = srv->impl->start();
+    if (!e.ok()) return fail(e);
+    *out = srv.release();
+    g_err.clear();
+    return BWR_OK;
+}
+
+int bwr_server_submit(bwr_server* srv, const bwr_csr* A, uint32_t p, uint64_t seed, uint64_t* ticket) {
+    if (!srv || !A || !ticket) return fail(BWR_EINVAL, "NULL argument");
+    Error e = check_prime(p);
+    if (!e.ok()) return fail(e);
+    if (!(e = check_host_csr(view(A))).ok()) return fail(e);
+    if (!(e = srv->impl->submit(view(A), p, seed, ticket)).ok()) return fail(e);
+    g_err.clear();
+    return BWR_OK;
+}
+
+int bwr_server_poll(bwr_server* srv, uint64_t ticket, int32_t* done, int64_t* rank) {
+    if (!srv || !done || !rank) return fail(BWR_EINVAL, "NULL argument");
+    bool d = false;
+    Error e = srv->impl->poll(ticket, &d, rank);
+    *done = d ? 1 : 0;
+    if (!e.ok()) return fail(e);
+    g_err.clear();
+    return BWR_OK;
+}
+
+int bwr_server_wait(bwr_server* srv, uint64_t ticket, int64_t* rank) {
+    if (!srv || !rank) return fail(BWR_EINVAL, "NULL argument");
+    Error e = srv->impl->wait(ticket, rank);
+    if (!e.ok()) return fail(e);
+    g_err.clear();
+    return BWR_OK;
+}
+
+int bwr_server_get_stats(bwr_server* srv, bwr_server_stats* out) {
+    if (!srv || !out) return fail(BWR_EINVAL, "NULL argument");
+    ServerStats st = srv->impl->stats();
+    out->p50_ms = st.p50_ms;
+    out->p99_ms = st.p99_ms;
+    out->solves_per_s = st.solves_per_s;
+    out->busy_s = st.busy_s;
+    out->completed = st.completed;
+    out->max_queue = st.max_queue;
+    out->max_active = st.max_active;
+    out->steps = st.steps;
+    g_err.clear();
+    return BWR_OK;
+}
+
+void bwr_server_destroy(bwr_server* srv) { delete srv; }
 
 }  // extern "C"

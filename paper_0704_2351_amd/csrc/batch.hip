@@ -1,0 +1,343 @@
+// Batched sequence kernels: one launch advances one product of a step for
+// every active job (matrix x set of primes).  The row mapping is that of the
+// row-split kernel (W/4 column groups x G non-zero slices per row); each
+// column group belongs to one prime of the job, so a single pass over a
+// matrix serves all its primes and a gathered row of the block is W * 4 bytes
+// (128 bytes for 4 primes x 8 columns: one cache line per non-zero).
+// Accumulators are 64-bit (primes of any size mix in one launch).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "batch.h"
+#include "kernels.h"
+
+namespace bwr {
+
+namespace {
+
+constexpr int TPB = 256;
+
+inline unsigned grid_for(int64_t work, int per_block) {
+    int64_t g = (work + per_block - 1) / per_block;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    lo = __shfl_xor(lo, mask, 64);
+    hi = __shfl_xor(hi, mask, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ int find_job(const int32_t* __restrict__ start, int njobs, int b) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int W, int G, bool SECOND>
+__global__ __launch_bounds__(TPB) void k_batch(const BatchJob* __restrict__ jobs, const int32_t* __restrict__ start,
+                                               int njobs, int parity, uint32_t* __restrict__ partial,
+                                               int64_t slot_off) {
+    constexpr int CG = W / 4;
+    constexpr int LPR = CG * G;
+    static_assert(LPR <= 64 && 64 % LPR == 0, "row group must divide a wave");
+    constexpr int RPW = 64 / LPR;
+    constexpr int RPB = (TPB / 64) * RPW;
+    constexpr int IPL = SECOND ? W / G : 1;
+    static_assert(!SECOND || (W % G == 0 && IPL <= 4), "projection needs W / G <= 4");
+
+    const int jb = find_job(start, njobs, (int)blockIdx.x);
+    const BatchJob& J = jobs[jb];
+    const int lb = (int)blockIdx.x - start[jb];
+    const int nblk = start[jb + 1] - start[jb];
+    const int64_t rows = SECOND ? J.rows2 : J.rows1;
+    const int32_t* __restrict__ rp = SECOND ? J.rp2 : J.rp1;
+    const uint32_t* __restrict__ ent = SECOND ? J.ent2 : J.ent1;
+    const int cur = (parity + J.par) & 1;
+    const uint32_t* __restrict__ X = SECOND ? J.Y : J.X[cur];
+    uint32_t* __restrict__ Y = SECOND ? J.X[cur ^ 1] : J.Y;
+    const uint32_t* __restrict__ scale = SECOND ? J.dc2 : J.dr;
+    const int spad = J.spad, np = J.nprimes;
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int sub = lane % LPR;
+    const int cg = sub % CG;
+    const int j = sub / CG;
+    const int slot = lane / LPR;
+    const int tp = (cg * 4) / spad;  // prime of this lane's columns
+    const bool live = tp < np;
+    const ModP mp = J.mp[live ? tp : 0];
+
+    uint64_t pacc[IPL][4];
+#pragma unroll
+    for (int u = 0; u < IPL; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) pacc[u][v] = 0;
+
+    for (int64_t tile = lb; tile * RPB < rows; tile += nblk) {
+        const int64_t row = tile * RPB + wave * RPW + slot;
+        const bool active = row < rows;
+        int64_t acc[4] = {0, 0, 0, 0};
+        if (active && live) {
+            const int32_t b = rp[row], e = rp[row + 1];
+            const uint32_t* Xs = X + cg * 4;
+            int32_t t = b + j;
+            for (; t + 3 * G < e; t += 4 * G) {
+                uint32_t en[4];
+                uint4 x[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) en[u] = ent[t + u * G];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) x[u] = *reinterpret_cast<const uint4*>(Xs + (size_t)(en[u] & 0xFFFFFFu) * W);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t a = (int32_t)en[u] >> 24;
+                    acc[0] += a * (int64_t)x[u].x;
+                    acc[1] += a * (int64_t)x[u].y;
+                    acc[2] += a * (int64_t)x[u].z;
+                    acc[3] += a * (int64_t)x[u].w;
+                }
+            }
+            for (; t < e; t += G) {
+                const uint32_t en0 = ent[t];
+                const uint4 x = *reinterpret_cast<const uint4*>(Xs + (size_t)(en0 & 0xFFFFFFu) * W);
+                const int64_t a = (int32_t)en0 >> 24;
+                acc[0] += a * (int64_t)x.x;
+                acc[1] += a * (int64_t)x.y;
+                acc[2] += a * (int64_t)x.z;
+                acc[3] += a * (int64_t)x.w;
+            }
+        }
+#pragma unroll
+        for (int off = CG; off < LPR; off <<= 1)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c] += (int64_t)shfl_xor_u64((uint64_t)acc[c], off);
+        if (active) {
+            uint32_t y[4] = {0, 0, 0, 0};
+            if (live) {
+                const uint32_t sc = scale[(size_t)tp * rows + row];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) y[c] = mulmod(mp, reds64(mp, acc[c]), sc);
+            }
+            if (j == 0)
+                *reinterpret_cast<uint4*>(Y + (size_t)row * W + cg * 4) = make_uint4(y[0], y[1], y[2], y[3]);
+            if constexpr (SECOND) {
+                if (live) {
+#pragma unroll
+                    for (int q = 0; q < IPL; ++q) {
+                        const int i = j * IPL + q;
+                        if (i / spad != tp) continue;  // only the diagonal blocks of one prime
+                        const uint32_t u = J.Ut[(size_t)row * W + i];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) pacc[q][c] += mulmod(mp, u, y[c]);
+                    }
+                }
+            }
+        }
+    }
+    if constexpr (SECOND) {
+#pragma unroll
+        for (int off = LPR; off < 64; off <<= 1)
+#pragma unroll
+            for (int q = 0; q < IPL; ++q)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) pacc[q][c] += shfl_xor_u64(pacc[q][c], off);
+        __shared__ uint64_t sh[TPB / 64][W * W];
+        if (lane < LPR) {
+#pragma unroll
+            for (int q = 0; q < IPL; ++q)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) sh[wave][(j * IPL + q) * W + cg * 4 + c] = pacc[q][c];
+        }
+        __syncthreads();
+        const int per = spad * spad;
+        uint32_t* out = partial + slot_off + J.part_off + (int64_t)lb * np * per;
+        for (int e = threadIdx.x; e < np * per; e += TPB) {
+            const int t = e / per, ii = (e % per) / spad, cc = e % spad;
+            const int wi = (t * spad + ii) * W + t * spad + cc;
+            uint64_t s = 0;
+#pragma unroll
+            for (int w = 0; w < TPB / 64; ++w) s += sh[w][wi];
+            out[e] = red64(J.mp[t], s);
+        }
+    }
+}
+
+// grid: x over (prime, i, j, step) of the chunk, y over jobs
+__global__ __launch_bounds__(TPB) void k_batch_reduce(const BatchJob* __restrict__ jobs, int64_t g_first, int nsteps,
+                                                      const uint32_t* __restrict__ partial, int64_t slot_words) {
+    const BatchJob& J = jobs[blockIdx.y];
+    const int s = J.s, spad = J.spad, np = J.nprimes;
+    const int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    const int64_t per_step = (int64_t)np * s * s;
+    if (idx >= per_step * nsteps) return;
+    const int k = (int)(idx / per_step);
+    const int e = (int)(idx % per_step);
+    const int t = e / (s * s), i = (e % (s * s)) / s, c = e % s;
+    const int64_t kl = g_first + k - J.g0 + 1;  // the job's sequence index
+    if (kl < 1 || kl >= J.len) return;
+    const int per = spad * spad;
+    const uint32_t* src = partial + (int64_t)k * slot_words + J.part_off + (int64_t)t * per + i * spad + c;
+    uint64_t acc = 0;
+    for (int b = 0; b < J.nblk2; ++b) acc += src[(int64_t)b * np * per];
+    J.S[((int64_t)t * J.len + kl) * s * s + i * s + c] = red64(J.mp[t], acc);
+}
+
+// S_0: thread t owns diagonal entries e = t, t + TPB, ... of the job; blocks split the rows
+template <int W>
+__global__ __launch_bounds__(TPB) void k_batch_s0(BatchJob J, uint32_t* __restrict__ partial) {
+    const int spad = J.spad, np = J.nprimes, per = spad * spad;
+    const int64_t nb = J.rows2;
+    const int64_t rpb = (nb + gridDim.x - 1) / gridDim.x;
+    const int64_t r0 = (int64_t)blockIdx.x * rpb;
+    const int64_t r1 = r0 + rpb < nb ? r0 + rpb : nb;
+    const uint32_t* X0 = J.X[0];  // the initial block (the first step reads X[0])
+    for (int e = threadIdx.x; e < np * per; e += TPB) {
+        const int t = e / per, ii = (e % per) / spad, cc = e % spad;
+        const ModP mp = J.mp[t];
+        uint64_t acc = 0;
+        for (int64_t r = r0; r < r1; ++r) acc += mulmod(mp, J.Ut[r * W + t * spad + ii], X0[r * W + t * spad + cc]);
+        partial[(int64_t)blockIdx.x * np * per + e] = red64(mp, acc);
+    }
+}
+
+__global__ __launch_bounds__(TPB) void k_batch_s0_reduce(BatchJob J, const uint32_t* __restrict__ partial, int nblk) {
+    const int s = J.s, spad = J.spad, np = J.nprimes, per = spad * spad;
+    const int idx = blockIdx.x * TPB + threadIdx.x;
+    if (idx >= np * s * s) return;
+    const int t = idx / (s * s), i = (idx % (s * s)) / s, c = idx % s;
+    uint64_t acc = 0;
+    for (int b = 0; b < nblk; ++b) acc += partial[(int64_t)b * np * per + t * per + i * spad + c];
+    J.S[((int64_t)t * J.len) * s * s + i * s + c] = red64(J.mp[t], acc);
+}
+
+__global__ __launch_bounds__(TPB) void k_place_block(int64_t n, int32_t s, int W, int off, const uint32_t* __restrict__ in,
+                                                     const uint32_t* __restrict__ d, int mode, ModP mp,
+                                                     uint32_t* __restrict__ out) {
+    int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (idx >= n * (int64_t)s) return;
+    int64_t r = idx / s;
+    int c = (int)(idx - r * s);
+    uint32_t x = red32(mp, in[idx]);
+    if (mode == 1) x = mulmod(mp, x, red32(mp, d[r]));
+    else if (mode == 2) x = mulmod(mp, x, invmod(mp, red32(mp, d[r])));
+    out[r * W + off + c] = x;
+}
+
+template <int W, int G>
+hipError_t first_wg(const BatchJob* jobs, const int32_t* start, int njobs, int nblocks, int parity, hipStream_t st) {
+    if constexpr ((W / 4) * G <= 64) {
+        k_batch<W, G, false><<<nblocks, TPB, 0, st>>>(jobs, start, njobs, parity, nullptr, 0);
+        return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int W, int G>
+hipError_t second_wg(const BatchJob* jobs, const int32_t* start, int njobs, int nblocks, int parity, uint32_t* partial,
+                     int64_t slot_off, hipStream_t st) {
+    if constexpr ((W / 4) * G <= 64 && W % G == 0 && W / G <= 4) {
+        k_batch<W, G, true><<<nblocks, TPB, 0, st>>>(jobs, start, njobs, parity, partial, slot_off);
+        return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int W>
+hipError_t first_w(int G, const BatchJob* jobs, const int32_t* start, int njobs, int nblocks, int parity,
+                   hipStream_t st) {
+    switch (G) {
+        case 1: return first_wg<W, 1>(jobs, start, njobs, nblocks, parity, st);
+        case 2: return first_wg<W, 2>(jobs, start, njobs, nblocks, parity, st);
+        case 4: return first_wg<W, 4>(jobs, start, njobs, nblocks, parity, st);
+        case 8: return first_wg<W, 8>(jobs, start, njobs, nblocks, parity, st);
+        case 16: return first_wg<W, 16>(jobs, start, njobs, nblocks, parity, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int W>
+hipError_t second_w(int G, const BatchJob* jobs, const int32_t* start, int njobs, int nblocks, int parity,
+                    uint32_t* partial, int64_t slot_off, hipStream_t st) {
+    switch (G) {
+        case 1: return second_wg<W, 1>(jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        case 2: return second_wg<W, 2>(jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        case 4: return second_wg<W, 4>(jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        case 8: return second_wg<W, 8>(jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        case 16: return second_wg<W, 16>(jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+int batch_rows_per_block(int W, int G) { return (TPB / 64) * (64 / ((W / 4) * G)); }
+
+bool batch_supported(int W, int G, bool second) {
+    if (W != 4 && W != 8 && W != 16 && W != 32) return false;
+    if (G < 1 || G > 16 || (G & (G - 1))) return false;
+    if ((W / 4) * G > 64) return false;
+    return !second || (W % G == 0 && W / G <= 4);
+}
+
+hipError_t launch_batch_first(int W, int G, const BatchJob* jobs, const int32_t* start, int njobs, int nblocks,
+                              int parity, hipStream_t st) {
+    if (nblocks <= 0 || njobs <= 0) return hipSuccess;
+    switch (W) {
+        case 4: return first_w<4>(G, jobs, start, njobs, nblocks, parity, st);
+        case 8: return first_w<8>(G, jobs, start, njobs, nblocks, parity, st);
+        case 16: return first_w<16>(G, jobs, start, njobs, nblocks, parity, st);
+        case 32: return first_w<32>(G, jobs, start, njobs, nblocks, parity, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batch_second(int W, int G, const BatchJob* jobs, const int32_t* start, int njobs, int nblocks,
+                               int parity, uint32_t* partial, int64_t slot_off, hipStream_t st) {
+    if (nblocks <= 0 || njobs <= 0) return hipSuccess;
+    switch (W) {
+        case 4: return second_w<4>(G, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        case 8: return second_w<8>(G, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        case 16: return second_w<16>(G, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        case 32: return second_w<32>(G, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batch_reduce(const BatchJob* jobs, int njobs, int64_t g_first, int nsteps, const uint32_t* partial,
+                               int64_t slot_words, int max_entries, hipStream_t st) {
+    if (njobs <= 0 || nsteps <= 0) return hipSuccess;
+    dim3 grid(grid_for((int64_t)max_entries * nsteps, TPB), (unsigned)njobs);
+    k_batch_reduce<<<grid, TPB, 0, st>>>(jobs, g_first, nsteps, partial, slot_words);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_s0(int W, const BatchJob& job, uint32_t* partial, int nblk, hipStream_t st) {
+    switch (W) {
+        case 4: k_batch_s0<4><<<nblk, TPB, 0, st>>>(job, partial); break;
+        case 8: k_batch_s0<8><<<nblk, TPB, 0, st>>>(job, partial); break;
+        case 16: k_batch_s0<16><<<nblk, TPB, 0, st>>>(job, partial); break;
+        case 32: k_batch_s0<32><<<nblk, TPB, 0, st>>>(job, partial); break;
+        default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_batch_s0_reduce<<<grid_for((int64_t)job.nprimes * job.s * job.s, TPB), TPB, 0, st>>>(job, partial, nblk);
+    return hipGetLastError();
+}
+
+hipError_t launch_place_block(int64_t n, int32_t s, int W, int off, const uint32_t* in, const uint32_t* d, int mode,
+                              ModP mp, uint32_t* out, hipStream_t st) {
+    int64_t total = n * (int64_t)s;
+    if (total == 0) return hipSuccess;
+    k_place_block<<<grid_for(total, TPB), TPB, 0, st>>>(n, s, W, off, in, d, mode, mp, out);
+    return hipGetLastError();
+}
+
+}  // namespace bwr

@@ -5,6 +5,7 @@
 #include "engine.h"
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 
 #include "kernels.h"
@@ -133,7 +134,8 @@ Error encode_matrix(const CsrView& A, uint32_t p, hipStream_t st, DeviceMatrix* 
         BWR_HIP(launch_wide_rows(A.m, A.row_ptr, A.col_idx, A.val, mp, M->rp_a.as<int32_t>(), M->ent_a.as<int32_t>(),
                                  M->val_a.as<uint32_t>(), st));
     }
-    // CSR of A^T: column histogram, exclusive scan, scatter, per-row sort
+    // CSR of A^T: column histogram, exclusive scan, scatter (the order inside a
+    // row of A^T is that of the atomics; sums do not depend on it)
     DevBuf cnt, cursor, tmp, mx;
     BWR_TRY(cnt.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(A.n, 1), st));
     BWR_TRY(cursor.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(A.n, 1), st));
@@ -146,12 +148,9 @@ Error encode_matrix(const CsrView& A, uint32_t p, hipStream_t st, DeviceMatrix* 
     if (M->packed) {
         BWR_HIP(launch_scatter_packed_t(A.m, A.row_ptr, A.col_idx, A.val, M->rp_t.as<int32_t>(), cursor.as<int32_t>(),
                                         M->ent_t.as<uint32_t>(), st));
-        BWR_HIP(launch_sort_rows_packed(A.n, M->rp_t.as<int32_t>(), M->ent_t.as<uint32_t>(), st));
     } else {
         BWR_HIP(launch_scatter_wide_t(A.m, A.row_ptr, A.col_idx, A.val, mp, M->rp_t.as<int32_t>(),
                                       cursor.as<int32_t>(), M->ent_t.as<int32_t>(), M->val_t.as<uint32_t>(), st));
-        BWR_HIP(launch_sort_rows_wide(A.n, M->rp_t.as<int32_t>(), M->ent_t.as<int32_t>(), M->val_t.as<uint32_t>(),
-                                      st));
     }
     BWR_HIP(launch_max_i32(A.n, cnt.as<int32_t>(), mx.as<int32_t>(), st));
     int32_t mlt = 0;
@@ -189,9 +188,194 @@ void operands(const DeviceMatrix& M, bool transpose, Operand* first, Operand* se
 
 }  // namespace
 
+namespace {
+
+int env_int(const char* name, int dflt) {
+    const char* v = getenv(name);
+    return (v && *v) ? atoi(v) : dflt;
+}
+
+int pow2_ceil(double x) {
+    int g = 1;
+    while (g < x && g < 16) g <<= 1;
+    return g;
+}
+
+// Lanes per row slice: about a quarter of the average row length, so that one
+// unrolled pass (4 non-zeros per lane) covers a typical row.
+int heuristic_g(const Operand& op, int64_t nnz, int W, bool proj) {
+    double avg = op.rows > 0 ? (double)nnz / (double)op.rows : 1.0;
+    int g = pow2_ceil(avg / 4.0);
+    if (proj && g < W / 4) g = W / 4;
+    while (g > 1 && !split_supported(W, g, proj)) g >>= 1;
+    if (!split_supported(W, g, proj)) {
+        for (g = 1; g <= 16 && !split_supported(W, g, proj); g <<= 1) {
+        }
+    }
+    return split_supported(W, g, proj) ? g : 0;
+}
+
+struct Bufs {
+    const uint32_t* dr;
+    const uint32_t* dc2;
+    const void* Ut;  // pl.esize-byte residues
+    void* Y;
+};
+
+Error launch_step(const DeviceMatrix& M, const Operand& op1, const Operand& op2, const StepPlan& pl, ModP mp,
+                  const Bufs& b, const void* cur, void* nxt, uint32_t* slot, hipStream_t st) {
+    const bool smallp = mp.p <= 65536u;
+    const int64_t nb = op2.rows;
+    hipError_t e;
+    if (pl.G1 > 0) {
+        e = launch_spmm_split(pl.W, pl.G1, false, use_acc32(M, op1.max_len, mp.p), smallp, pl.esize, op1.rows, op1.rp,
+                              op1.ent, cur, b.dr, b.Y, nullptr, nullptr, 0, mp, st);
+        if (e != hipSuccess) return Error::device(e, "spmm_split (first product)");
+    } else {
+        BWR_TRY(spmm(M, op1, pl.W, mp, (const uint32_t*)cur, b.dr, (uint32_t*)b.Y, st));
+    }
+    if (pl.fused) {
+        e = launch_spmm_split(pl.W, pl.G2, true, use_acc32(M, op2.max_len, mp.p), smallp, pl.esize, op2.rows, op2.rp,
+                              op2.ent, b.Y, b.dc2, nxt, b.Ut, slot, pl.NB, mp, st);
+        if (e != hipSuccess) return Error::device(e, "spmm_split (second product + projection)");
+        return {};
+    }
+    if (pl.G2 > 0) {
+        e = launch_spmm_split(pl.W, pl.G2, false, use_acc32(M, op2.max_len, mp.p), smallp, pl.esize, op2.rows, op2.rp,
+                              op2.ent, b.Y, b.dc2, nxt, nullptr, nullptr, 0, mp, st);
+        if (e != hipSuccess) return Error::device(e, "spmm_split (second product)");
+    } else {
+        BWR_TRY(spmm(M, op2, pl.W, mp, (const uint32_t*)b.Y, b.dc2, (uint32_t*)nxt, st));
+    }
+    if (nb > 0) {
+        e = launch_project(pl.W, smallp, nb, b.Ut, nxt, pl.esize, slot, pl.NB, mp, st);
+        if (e != hipSuccess) return Error::device(e, "project launch");
+    }
+    return {};
+}
+
+// Times `iters` launches of fn with HIP events (after one untimed launch).
+template <class Fn>
+Error time_launches(int iters, hipStream_t st, Fn fn, double* us) {
+    hipEvent_t ev[2];
+    BWR_HIP(hipEventCreate(&ev[0]));
+    BWR_HIP(hipEventCreate(&ev[1]));
+    Error err = fn();
+    if (err.ok()) (void)hipEventRecord(ev[0], st);
+    for (int it = 0; it < iters && err.ok(); ++it) err = fn();
+    if (err.ok()) {
+        (void)hipEventRecord(ev[1], st);
+        hipError_t e = hipEventSynchronize(ev[1]);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+        if (e != hipSuccess) err = Error::device(e, "event timing");
+        *us = 1000.0 * ms / iters;
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    return err;
+}
+
+}  // namespace
+
+StepPlan plan_step(const DeviceMatrix& M, bool transpose, int32_t s, uint32_t p) {
+    StepPlan pl;
+    pl.W = padded_width(s);
+    Operand op1, op2;
+    operands(M, transpose, &op1, &op2);
+    const int64_t nb = op2.rows;
+    if (M.packed && pl.W >= 4) {
+        pl.G1 = env_int("BWR_G1", heuristic_g(op1, M.nnz, pl.W, false));
+        int g2 = env_int("BWR_G2", heuristic_g(op2, M.nnz, pl.W, true));
+        if (!split_supported(pl.W, pl.G1, false)) pl.G1 = heuristic_g(op1, M.nnz, pl.W, false);
+        pl.fused = split_supported(pl.W, g2, true);
+        pl.G2 = pl.fused ? g2 : (split_supported(pl.W, g2, false) ? g2 : heuristic_g(op2, M.nnz, pl.W, false));
+    }
+    // 16-bit storage of the iterated blocks when every kernel of the step can read it
+    pl.esize = (p <= 65536u && pl.G1 > 0 && pl.G2 > 0 && env_int("BWR_E32", 0) == 0) ? 2 : 4;
+    if (pl.fused) {
+        const int rpb = split_rows_per_block(pl.W, pl.G2);
+        int64_t tiles = (nb + rpb - 1) / rpb;
+        int64_t cap = std::max<int64_t>(1, std::min<int64_t>(1024, 262144 / ((int64_t)pl.W * pl.W)));
+        pl.NB = (int)std::max<int64_t>(1, std::min(tiles, cap));
+    } else {
+        pl.NB = proj_blocks(nb, pl.W);
+    }
+    (void)p;
+    return pl;
+}
+
+Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl, hipStream_t st) {
+    if (pl->G1 <= 0 && pl->G2 <= 0) return {};
+    Operand op1, op2;
+    operands(M, transpose, &op1, &op2);
+    const int W = pl->W;
+    const int64_t nb = op2.rows, outer = op1.rows;
+    const bool smallp = mp.p <= 65536u;
+    const size_t es = (size_t)pl->esize;
+    DevBuf X, Y, Z, U, part;
+    BWR_TRY(X.alloc(es * (size_t)std::max<int64_t>(nb * W, 1), st));
+    BWR_TRY(Z.alloc(es * (size_t)std::max<int64_t>(nb * W, 1), st));
+    BWR_TRY(U.alloc(es * (size_t)std::max<int64_t>(nb * W, 1), st));
+    BWR_TRY(Y.alloc(es * (size_t)std::max<int64_t>(outer * W, 1), st));
+    BWR_TRY(part.alloc(sizeof(uint32_t) * (size_t)1024 * W * W, st));
+    // timing inputs: contents do not change the memory traffic
+    BWR_HIP(hipMemsetAsync(X.as<void>(), 0, X.bytes(), st));
+    BWR_HIP(hipMemsetAsync(U.as<void>(), 0, U.bytes(), st));
+    BWR_HIP(hipMemsetAsync(Y.as<void>(), 0, Y.bytes(), st));
+    if (pl->G1 > 0) {
+        double best = 1e30;
+        int bestg = pl->G1;
+        for (int g = 1; g <= 16; g <<= 1) {
+            if (!split_supported(W, g, false)) continue;
+            double us = 0;
+            BWR_TRY(time_launches(3, st, [&]() -> Error {
+                hipError_t e = launch_spmm_split(W, g, false, use_acc32(M, op1.max_len, mp.p), smallp, pl->esize,
+                                                 op1.rows, op1.rp, op1.ent, X.as<void>(), nullptr, Y.as<void>(),
+                                                 nullptr, nullptr, 0, mp, st);
+                return e == hipSuccess ? Error{} : Error::device(e, "autotune");
+            }, &us));
+            if (us < best) {
+                best = us;
+                bestg = g;
+            }
+        }
+        pl->G1 = bestg;
+    }
+    if (pl->G2 > 0) {
+        double best = 1e30;
+        int bestg = pl->G2;
+        const bool proj = pl->fused;
+        for (int g = 1; g <= 16; g <<= 1) {
+            if (!split_supported(W, g, proj)) continue;
+            const int rpb = split_rows_per_block(W, g);
+            int64_t tiles = (nb + rpb - 1) / rpb;
+            int nbk = proj ? (int)std::max<int64_t>(1, std::min<int64_t>(tiles, pl->NB)) : 0;
+            double us = 0;
+            BWR_TRY(time_launches(3, st, [&]() -> Error {
+                hipError_t e = launch_spmm_split(W, g, proj, use_acc32(M, op2.max_len, mp.p), smallp, pl->esize,
+                                                 op2.rows, op2.rp, op2.ent, Y.as<void>(), nullptr, Z.as<void>(),
+                                                 U.as<void>(), part.as<uint32_t>(), nbk, mp, st);
+                return e == hipSuccess ? Error{} : Error::device(e, "autotune");
+            }, &us));
+            if (us < best) {
+                best = us;
+                bestg = g;
+            }
+        }
+        pl->G2 = bestg;
+        if (pl->fused) {
+            const int rpb = split_rows_per_block(W, pl->G2);
+            int64_t tiles = (nb + rpb - 1) / rpb;
+            pl->NB = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, pl->NB));
+        }
+    }
+    return {};
+}
+
 Error run_sequence(const SequenceArgs& a, hipStream_t st) {
     const DeviceMatrix& M = *a.M;
-    if (a.M->packed == false && a.M->wide_p != a.mp.p) return Error::inval("matrix was encoded for another prime");
+    if (!M.packed && M.wide_p != a.mp.p) return Error::inval("matrix was encoded for another prime");
     const int W = padded_width(a.s);
     if (!W) return Error::inval("block size must be in 1..64");
     if (a.len <= 0) return {};
@@ -202,11 +386,18 @@ Error run_sequence(const SequenceArgs& a, hipStream_t st) {
     const ModP mp = a.mp;
     const bool smallp = mp.p <= 65536u;
 
+    StepPlan pl = plan_step(M, a.transpose, a.s, mp.p);
+    if (a.len >= 64 && M.nnz >= 100000 && env_int("BWR_NO_TUNE", 0) == 0 && getenv("BWR_G1") == nullptr &&
+        getenv("BWR_G2") == nullptr)
+        BWR_TRY(autotune_step(M, a.transpose, mp, &pl, st));
+    if (a.plan_out) *a.plan_out = pl;
+
+    const size_t es = (size_t)pl.esize;
     DevBuf Ut, X0, X1, Y, dr, dc2, part, flag;
-    BWR_TRY(Ut.alloc(sizeof(uint32_t) * (size_t)(nb * W), st));
-    BWR_TRY(X0.alloc(sizeof(uint32_t) * (size_t)(nb * W), st));
-    BWR_TRY(X1.alloc(sizeof(uint32_t) * (size_t)(nb * W), st));
-    BWR_TRY(Y.alloc(sizeof(uint32_t) * (size_t)std::max<int64_t>(outer * W, 1), st));
+    BWR_TRY(Ut.alloc(es * (size_t)(nb * W), st));
+    BWR_TRY(X0.alloc(es * (size_t)(nb * W), st));
+    BWR_TRY(X1.alloc(es * (size_t)(nb * W), st));
+    BWR_TRY(Y.alloc(es * (size_t)std::max<int64_t>(outer * W, 1), st));
     BWR_TRY(flag.alloc(sizeof(int32_t), st));
     BWR_HIP(hipMemsetAsync(flag.as<int32_t>(), 0, sizeof(int32_t), st));
     const uint32_t* drp = nullptr;
@@ -222,37 +413,71 @@ Error run_sequence(const SequenceArgs& a, hipStream_t st) {
         dc2p = dc2.as<uint32_t>();
     }
     // X_0 = D_c V and U~ = D_c^{-1} U, so that S_k = U~^T X_k with X_{k+1} = D_c^2 A^T D_r A X_k
-    BWR_HIP(launch_pad_scale(nb, a.s, W, a.U, a.d_col, a.d_col ? 2 : 0, mp, Ut.as<uint32_t>(), st));
-    BWR_HIP(launch_pad_scale(nb, a.s, W, a.V, a.d_col, a.d_col ? 1 : 0, mp, X0.as<uint32_t>(), st));
+    BWR_HIP(launch_pad_scale(nb, a.s, W, a.U, a.d_col, a.d_col ? 2 : 0, mp, Ut.as<void>(), pl.esize, st));
+    BWR_HIP(launch_pad_scale(nb, a.s, W, a.V, a.d_col, a.d_col ? 1 : 0, mp, X0.as<void>(), pl.esize, st));
 
-    const int NB = proj_blocks(nb, W);
-    const size_t per_step = (size_t)NB * W * W;
-    int64_t CH = std::min<int64_t>(a.len, 1024);
-    CH = std::max<int64_t>(1, std::min<int64_t>(CH, (int64_t)((256u << 20) / (per_step * 4))));
+    const size_t per_step = (size_t)pl.NB * W * W;
+    int64_t CH = 256;
+    CH = std::max<int64_t>(2, std::min<int64_t>(CH, (int64_t)((256u << 20) / (per_step * 4))) & ~(int64_t)1);
     BWR_TRY(part.alloc(sizeof(uint32_t) * per_step * (size_t)CH, st));
+    uint32_t* slots = part.as<uint32_t>();
+    Bufs bufs{drp, dc2p, Ut.as<void>(), Y.as<void>()};
 
-    uint32_t* cur = X0.as<uint32_t>();
-    uint32_t* nxt = X1.as<uint32_t>();
-    int64_t k0 = 0;
-    for (int64_t k = 0; k < a.len; ++k) {
-        if (k > 0) {
-            BWR_TRY(spmm(M, op1, W, mp, cur, drp, Y.as<uint32_t>(), st));
-            BWR_TRY(spmm(M, op2, W, mp, Y.as<uint32_t>(), dc2p, nxt, st));
-            std::swap(cur, nxt);
-        }
-        uint32_t* slot = part.as<uint32_t>() + per_step * (size_t)(k - k0);
-        if (nb > 0) {
-            hipError_t e = launch_project(W, smallp, nb, Ut.as<uint32_t>(), cur, slot, NB, mp, st);
-            if (e != hipSuccess) return Error::device(e, "project launch");
-        } else {
-            BWR_HIP(hipMemsetAsync(slot, 0, sizeof(uint32_t) * per_step, st));
-        }
-        if (k - k0 + 1 == CH || k == a.len - 1) {
-            BWR_HIP(launch_reduce_partials(W, a.s, NB, k - k0 + 1, part.as<uint32_t>(),
-                                           a.S_out + (size_t)k0 * a.s * a.s, mp, st));
-            k0 = k + 1;
-        }
+    // S_0
+    if (nb > 0) {
+        hipError_t e = launch_project(W, smallp, nb, Ut.as<void>(), X0.as<void>(), pl.esize, slots, pl.NB, mp, st);
+        if (e != hipSuccess) return Error::device(e, "project launch");
+    } else {
+        BWR_HIP(hipMemsetAsync(slots, 0, sizeof(uint32_t) * per_step, st));
     }
+    BWR_HIP(launch_reduce_partials(W, a.s, pl.NB, 1, slots, a.S_out, mp, st));
+
+    void* cur = X0.as<void>();
+    void* nxt = X1.as<void>();
+    const bool use_graph = env_int("BWR_NO_GRAPH", 0) == 0 && a.len - 1 >= 2 * CH && nb > 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    Error err;
+    for (int64_t k = 1; k < a.len && err.ok();) {
+        const int64_t cnt = std::min<int64_t>(CH, a.len - k);
+        if (use_graph && cnt == CH) {
+            if (!exec) {
+                hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+                if (e != hipSuccess) {
+                    err = Error::device(e, "hipStreamBeginCapture");
+                    break;
+                }
+                for (int64_t i = 0; i < CH && err.ok(); ++i) {
+                    err = launch_step(M, op1, op2, pl, mp, bufs, cur, nxt, slots + per_step * (size_t)i, st);
+                    std::swap(cur, nxt);
+                }
+                e = hipStreamEndCapture(st, &graph);
+                if (err.ok() && e != hipSuccess) err = Error::device(e, "hipStreamEndCapture");
+                if (err.ok()) {
+                    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                    if (e != hipSuccess) err = Error::device(e, "hipGraphInstantiate");
+                }
+                if (!err.ok()) break;
+            }
+            hipError_t e = hipGraphLaunch(exec, st);
+            if (e != hipSuccess) {
+                err = Error::device(e, "hipGraphLaunch");
+                break;
+            }
+        } else {
+            for (int64_t i = 0; i < cnt && err.ok(); ++i) {
+                err = launch_step(M, op1, op2, pl, mp, bufs, cur, nxt, slots + per_step * (size_t)i, st);
+                std::swap(cur, nxt);
+            }
+            if (!err.ok()) break;
+        }
+        hipError_t e = launch_reduce_partials(W, a.s, pl.NB, cnt, slots, a.S_out + (size_t)k * a.s * a.s, mp, st);
+        if (e != hipSuccess) err = Error::device(e, "reduce launch");
+        k += cnt;
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (!err.ok()) return err;
     int32_t bad = 0;
     BWR_HIP(hipMemcpyAsync(&bad, flag.as<int32_t>(), sizeof(bad), hipMemcpyDeviceToHost, st));
     BWR_HIP(hipStreamSynchronize(st));
@@ -285,60 +510,71 @@ Error apply_once(const DeviceMatrix& M, bool transpose, ModP mp, int32_t s, cons
         dcp = dc.as<uint32_t>();
     }
     // Z = D_c A^T D_r A D_c X
-    BWR_HIP(launch_pad_scale(nb, s, W, X, dcp, dcp ? 1 : 0, mp, Xp.as<uint32_t>(), st));
+    BWR_HIP(launch_pad_scale(nb, s, W, X, dcp, dcp ? 1 : 0, mp, Xp.as<void>(), 4, st));
     BWR_TRY(spmm(M, op1, W, mp, Xp.as<uint32_t>(), drp, Y.as<uint32_t>(), st));
     BWR_TRY(spmm(M, op2, W, mp, Y.as<uint32_t>(), dcp, Zp.as<uint32_t>(), st));
-    BWR_HIP(launch_unpad(nb, s, W, Zp.as<uint32_t>(), Z, st));
+    BWR_HIP(launch_unpad(nb, s, W, Zp.as<void>(), 4, Z, st));
     BWR_HIP(hipStreamSynchronize(st));
     return {};
 }
 
 Error time_step_kernels(const DeviceMatrix& M, bool transpose, ModP mp, int32_t s, int iters, hipStream_t st,
-                        double us[3]) {
+                        double us[3], StepPlan* plan_out) {
     const int W = padded_width(s);
     if (!W || iters < 1) return Error::inval("bad block size or iteration count");
     Operand op1, op2;
     operands(M, transpose, &op1, &op2);
     const int64_t nb = op2.rows, outer = op1.rows;
+    StepPlan pl = plan_step(M, transpose, s, mp.p);
+    if (M.nnz >= 100000 && env_int("BWR_NO_TUNE", 0) == 0 && getenv("BWR_G1") == nullptr && getenv("BWR_G2") == nullptr)
+        BWR_TRY(autotune_step(M, transpose, mp, &pl, st));
+    if (plan_out) *plan_out = pl;
+    const size_t es = (size_t)pl.esize;
     DevBuf X, Y, Z, U, d1, d2, part;
-    BWR_TRY(X.alloc(sizeof(uint32_t) * (size_t)std::max<int64_t>(nb * W, 1), st));
-    BWR_TRY(Z.alloc(sizeof(uint32_t) * (size_t)std::max<int64_t>(nb * W, 1), st));
-    BWR_TRY(U.alloc(sizeof(uint32_t) * (size_t)std::max<int64_t>(nb * W, 1), st));
-    BWR_TRY(Y.alloc(sizeof(uint32_t) * (size_t)std::max<int64_t>(outer * W, 1), st));
+    BWR_TRY(X.alloc(es * (size_t)std::max<int64_t>(nb * W, 1), st));
+    BWR_TRY(Z.alloc(es * (size_t)std::max<int64_t>(nb * W, 1), st));
+    BWR_TRY(U.alloc(es * (size_t)std::max<int64_t>(nb * W, 1), st));
+    BWR_TRY(Y.alloc(es * (size_t)std::max<int64_t>(outer * W, 1), st));
     BWR_TRY(d1.alloc(sizeof(uint32_t) * (size_t)std::max<int64_t>(outer, 1), st));
     BWR_TRY(d2.alloc(sizeof(uint32_t) * (size_t)std::max<int64_t>(nb, 1), st));
-    const int NB = proj_blocks(nb, W);
-    BWR_TRY(part.alloc(sizeof(uint32_t) * (size_t)NB * W * W, st));
-    BWR_HIP(launch_rng_block(12345, 0, nb, W, W, mp, 0, X.as<uint32_t>(), st));
-    BWR_HIP(launch_rng_block(12345, 1, nb, W, W, mp, 0, U.as<uint32_t>(), st));
+    BWR_TRY(part.alloc(sizeof(uint32_t) * (size_t)std::max(pl.NB, 1) * W * W, st));
+    // random residues (in [0, p), so valid for either storage width)
+    DevBuf tmp;
+    BWR_TRY(tmp.alloc(sizeof(uint32_t) * (size_t)std::max<int64_t>(nb * W, 1), st));
+    BWR_HIP(launch_rng_block(12345, 0, nb, W, W, mp, 0, tmp.as<uint32_t>(), st));
+    BWR_HIP(launch_pad_scale(nb, W, W, tmp.as<uint32_t>(), nullptr, 0, mp, X.as<void>(), pl.esize, st));
+    BWR_HIP(launch_rng_block(12345, 1, nb, W, W, mp, 0, tmp.as<uint32_t>(), st));
+    BWR_HIP(launch_pad_scale(nb, W, W, tmp.as<uint32_t>(), nullptr, 0, mp, U.as<void>(), pl.esize, st));
     BWR_HIP(launch_rng_block(12345, 2, outer, 1, 1, mp, 1, d1.as<uint32_t>(), st));
     BWR_HIP(launch_rng_block(12345, 3, nb, 1, 1, mp, 1, d2.as<uint32_t>(), st));
-    hipEvent_t ev[2];
-    BWR_HIP(hipEventCreate(&ev[0]));
-    BWR_HIP(hipEventCreate(&ev[1]));
-    Error err;
-    for (int which = 0; which < 3 && err.ok(); ++which) {
-        // one untimed launch, then `iters` timed ones
-        for (int it = 0; it <= iters && err.ok(); ++it) {
-            if (it == 1) (void)hipEventRecord(ev[0], st);
-            if (which == 0) err = spmm(M, op1, W, mp, X.as<uint32_t>(), d1.as<uint32_t>(), Y.as<uint32_t>(), st);
-            else if (which == 1) err = spmm(M, op2, W, mp, Y.as<uint32_t>(), d2.as<uint32_t>(), Z.as<uint32_t>(), st);
-            else if (nb > 0) {
-                hipError_t e = launch_project(W, mp.p <= 65536u, nb, U.as<uint32_t>(), Z.as<uint32_t>(),
-                                              part.as<uint32_t>(), NB, mp, st);
-                if (e != hipSuccess) err = Error::device(e, "project");
-            }
+    const bool smallp = mp.p <= 65536u;
+    // [0] first product, [1] second product (+ projection when fused), [2] separate projection (0 when fused)
+    BWR_TRY(time_launches(iters, st, [&]() -> Error {
+        if (pl.G1 > 0) {
+            hipError_t e = launch_spmm_split(W, pl.G1, false, use_acc32(M, op1.max_len, mp.p), smallp, pl.esize,
+                                             op1.rows, op1.rp, op1.ent, X.as<void>(), d1.as<uint32_t>(), Y.as<void>(),
+                                             nullptr, nullptr, 0, mp, st);
+            return e == hipSuccess ? Error{} : Error::device(e, "spmm_split");
         }
-        (void)hipEventRecord(ev[1], st);
-        hipError_t e = hipEventSynchronize(ev[1]);
-        float ms = 0;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
-        if (e != hipSuccess && err.ok()) err = Error::device(e, "event timing");
-        us[which] = 1000.0 * ms / iters;
-    }
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
-    return err;
+        return spmm(M, op1, W, mp, X.as<uint32_t>(), d1.as<uint32_t>(), Y.as<uint32_t>(), st);
+    }, &us[0]));
+    BWR_TRY(time_launches(iters, st, [&]() -> Error {
+        if (pl.G2 > 0) {
+            hipError_t e = launch_spmm_split(W, pl.G2, pl.fused, use_acc32(M, op2.max_len, mp.p), smallp, pl.esize,
+                                             op2.rows, op2.rp, op2.ent, Y.as<void>(), d2.as<uint32_t>(), Z.as<void>(),
+                                             U.as<void>(), part.as<uint32_t>(), pl.NB, mp, st);
+            return e == hipSuccess ? Error{} : Error::device(e, "spmm_split");
+        }
+        return spmm(M, op2, W, mp, Y.as<uint32_t>(), d2.as<uint32_t>(), Z.as<uint32_t>(), st);
+    }, &us[1]));
+    us[2] = 0;
+    if (!pl.fused && nb > 0)
+        BWR_TRY(time_launches(iters, st, [&]() -> Error {
+            hipError_t e = launch_project(W, smallp, nb, U.as<void>(), Z.as<void>(), pl.esize, part.as<uint32_t>(),
+                                          pl.NB, mp, st);
+            return e == hipSuccess ? Error{} : Error::device(e, "project");
+        }, &us[2]));
+    return {};
 }
 
 }  // namespace bwr

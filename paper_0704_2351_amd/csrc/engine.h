@@ -80,6 +80,18 @@ struct Operand {  // one product of a step: out[r] = scale[r] * sum a_rt in[col_
 
 // One sequence run: S_k = U^T B^k V for k < len, B = D_c A^T D_r A D_c, or with
 // the roles of A and A^T swapped (transpose = true: B acts on GF(p)^m).
+// Kernel choice for one step: padded width W, lanes per row slice of each
+// product (0 = one lane group per row, the legacy kernels), whether the
+// projection is fused into the second product, and the number of projection
+// partials per step.
+struct StepPlan {
+    int W = 0;
+    int G1 = 0, G2 = 0;
+    bool fused = false;
+    int NB = 0;
+    int esize = 4;  // bytes per stored residue of the iterated blocks (2 when p <= 2^16)
+};
+
 struct SequenceArgs {
     const DeviceMatrix* M;
     bool transpose = false;
@@ -91,6 +103,7 @@ struct SequenceArgs {
     const uint32_t* V = nullptr;      // device, nb x s
     int64_t len = 0;
     uint32_t* S_out = nullptr;  // device, len x s x s
+    StepPlan* plan_out = nullptr;  // optional: the plan used
 };
 
 Error run_sequence(const SequenceArgs& a, hipStream_t st);
@@ -104,8 +117,13 @@ int padded_width(int32_t s);  // 0 if unsupported
 // Average device time (microseconds, HIP events on stream st) of each kernel
 // of one step, launched `iters` times back to back on the encoded matrix with
 // random blocks: [0] first sparse product + row scale, [1] second sparse
-// product + column scale, [2] projection.
+// product + column scale (+ the projection when fused), [2] the separate
+// projection (0 when fused).
 Error time_step_kernels(const DeviceMatrix& M, bool transpose, ModP mp, int32_t s, int iters, hipStream_t st,
-                        double us[3]);
+                        double us[3], StepPlan* plan_out = nullptr);
+
+// Heuristic plan, and its refinement by timing every valid split factor on M.
+StepPlan plan_step(const DeviceMatrix& M, bool transpose, int32_t s, uint32_t p);
+Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl, hipStream_t st);
 
 }  // namespace bwr

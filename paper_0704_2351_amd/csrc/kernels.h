@@ -38,7 +38,7 @@ hipError_t launch_pack_rows(int64_t m, const int64_t* rp64, const int32_t* col, 
 hipError_t launch_wide_rows(int64_t m, const int64_t* rp64, const int32_t* col, const int32_t* val,
                             ModP mp, int32_t* rp32, int32_t* colw, uint32_t* valw, hipStream_t st);
 
-// Transpose support: column histogram, exclusive scan, scatter, per-row sort.
+// Transpose support: column histogram, exclusive scan, scatter.
 hipError_t launch_col_count(int64_t m, const int64_t* rp64, const int32_t* col, int32_t* cnt, hipStream_t st);
 hipError_t launch_exclusive_scan(int64_t count, const int32_t* in, int32_t* out /* count + 1 */,
                                  int32_t* tmp /* >= scan_tmp_words(count) */, hipStream_t st);
@@ -48,20 +48,19 @@ hipError_t launch_scatter_packed_t(int64_t m, const int64_t* rp64, const int32_t
 hipError_t launch_scatter_wide_t(int64_t m, const int64_t* rp64, const int32_t* col, const int32_t* val,
                                  ModP mp, const int32_t* rpT, int32_t* cursor, int32_t* colT, uint32_t* valT,
                                  hipStream_t st);
-hipError_t launch_sort_rows_packed(int64_t nrows, const int32_t* rp, uint32_t* ent, hipStream_t st);
-hipError_t launch_sort_rows_wide(int64_t nrows, const int32_t* rp, int32_t* col, uint32_t* val, hipStream_t st);
 
 // Random residues from the counter-based SplitMix64 stream (seed, stream):
 // out[r * ld + c] = element(r * s + c) for r < rows, c < s (and 0 for s <= c < ld).
 hipError_t launch_rng_block(uint64_t seed, int stream, int64_t rows, int32_t s, int32_t ld, ModP mp,
                             int diag, uint32_t* out, hipStream_t st);
 
-// Copy an n x s block into an n x W padded block, optionally scaled row-wise
-// by d[r] (mode 1) or by d[r]^-1 (mode 2); mode 0 copies.  Entries are reduced mod p.
+// Copy an n x s block into an n x W padded block of esize-byte residues
+// (esize 2 needs p <= 2^16), optionally scaled row-wise by d[r] (mode 1) or by
+// d[r]^-1 (mode 2); mode 0 copies.  Entries are reduced mod p.
 hipError_t launch_pad_scale(int64_t n, int32_t s, int32_t W, const uint32_t* in, const uint32_t* d, int mode,
-                            ModP mp, uint32_t* out, hipStream_t st);
-// out[r * s + c] = in[r * W + c] for c < s
-hipError_t launch_unpad(int64_t n, int32_t s, int32_t W, const uint32_t* in, uint32_t* out, hipStream_t st);
+                            ModP mp, void* out, int esize, hipStream_t st);
+// out[r * s + c] = in[r * W + c] for c < s (in: esize-byte residues)
+hipError_t launch_unpad(int64_t n, int32_t s, int32_t W, const void* in, int esize, uint32_t* out, hipStream_t st);
 // d2[r] = d[r]^2 mod p; also checks d[r] mod p != 0 (bad != 0 otherwise).
 hipError_t launch_square_diag(int64_t n, const uint32_t* d, ModP mp, uint32_t* d2, int32_t* bad, hipStream_t st);
 // reduce an arbitrary uint32 diagonal into [0, p)
@@ -76,10 +75,22 @@ hipError_t launch_spmm_wide(int W, int64_t nrows, const int32_t* rp, const int32
 
 // Projection partials: partial[b][i * W + c] = sum over the rows of block b of U[r][i] X[r][c] mod p.
 int proj_blocks(int64_t n, int W);
-hipError_t launch_project(int W, bool smallp, int64_t n, const uint32_t* U, const uint32_t* X, uint32_t* partial,
+hipError_t launch_project(int W, bool smallp, int64_t n, const void* U, const void* X, int esize, uint32_t* partial,
                           int nblocks, ModP mp, hipStream_t st);
 // S[k][i][j] (i, j < s) = sum_b partial[k][b][i * W + j] mod p, for k < nsteps.
 hipError_t launch_reduce_partials(int W, int32_t s, int nblocks, int64_t nsteps, const uint32_t* partial, uint32_t* S,
                                   ModP mp, hipStream_t st);
 
+}  // namespace bwr
+
+namespace bwr {
+// Row-split sparse x block product (spmm.hip): W in {4..64}, G lanes per row
+// slice (1..16, power of two), optional fused projection into per-block W x W
+// partials (nblocks blocks in a grid-stride loop).
+bool split_supported(int W, int G, bool proj);
+int split_rows_per_block(int W, int G);
+// X, Y, U hold esize-byte residues (2: p <= 2^16, 4: any p).
+hipError_t launch_spmm_split(int W, int G, bool proj, bool acc32, bool smallp, int esize, int64_t nrows,
+                             const int32_t* rp, const uint32_t* ent, const void* X, const uint32_t* scale, void* Y,
+                             const void* U, uint32_t* partial, int nblocks, ModP mp, hipStream_t st);
 }  // namespace bwr

@@ -208,48 +208,6 @@ __global__ __launch_bounds__(TPB) void k_scatter_wide_t(int64_t m, const int64_t
     }
 }
 
-// insertion sort of each row segment by column (rows of up to 512 entries;
-// longer rows keep scatter order, which changes no result)
-constexpr int SORT_MAX = 512;
-
-__global__ __launch_bounds__(TPB) void k_sort_rows_packed(int64_t nrows, const int32_t* __restrict__ rp,
-                                                          uint32_t* __restrict__ ent) {
-    int64_t r = (int64_t)blockIdx.x * TPB + threadIdx.x;
-    if (r >= nrows) return;
-    int32_t b = rp[r], e = rp[r + 1];
-    if (e - b > SORT_MAX) return;
-    for (int32_t t = b + 1; t < e; ++t) {
-        uint32_t x = ent[t];
-        uint32_t key = x & 0xFFFFFFu;
-        int32_t u = t - 1;
-        while (u >= b && (ent[u] & 0xFFFFFFu) > key) {
-            ent[u + 1] = ent[u];
-            --u;
-        }
-        ent[u + 1] = x;
-    }
-}
-
-__global__ __launch_bounds__(TPB) void k_sort_rows_wide(int64_t nrows, const int32_t* __restrict__ rp,
-                                                        int32_t* __restrict__ col, uint32_t* __restrict__ val) {
-    int64_t r = (int64_t)blockIdx.x * TPB + threadIdx.x;
-    if (r >= nrows) return;
-    int32_t b = rp[r], e = rp[r + 1];
-    if (e - b > SORT_MAX) return;
-    for (int32_t t = b + 1; t < e; ++t) {
-        int32_t c = col[t];
-        uint32_t v = val[t];
-        int32_t u = t - 1;
-        while (u >= b && col[u] > c) {
-            col[u + 1] = col[u];
-            val[u + 1] = val[u];
-            --u;
-        }
-        col[u + 1] = c;
-        val[u + 1] = v;
-    }
-}
-
 // ---------------------------------------------------------------- random blocks and scaling
 __global__ __launch_bounds__(TPB) void k_rng_block(uint64_t key, int64_t rows, int32_t s, int32_t ld, ModP mp,
                                                    int diag, uint32_t* __restrict__ out) {
@@ -260,9 +218,10 @@ __global__ __launch_bounds__(TPB) void k_rng_block(uint64_t key, int64_t rows, i
     out[idx] = c < s ? sm_residue(mp, key, (uint64_t)(r * s + c), diag) : 0u;
 }
 
+template <typename E>
 __global__ __launch_bounds__(TPB) void k_pad_scale(int64_t n, int32_t s, int32_t W, const uint32_t* __restrict__ in,
                                                    const uint32_t* __restrict__ d, int mode, ModP mp,
-                                                   uint32_t* __restrict__ out) {
+                                                   E* __restrict__ out) {
     int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x;
     if (idx >= n * (int64_t)W) return;
     int64_t r = idx / W;
@@ -274,10 +233,11 @@ __global__ __launch_bounds__(TPB) void k_pad_scale(int64_t n, int32_t s, int32_t
         if (mode == 1) x = mulmod(mp, x, red32(mp, d[r]));
         else if (mode == 2) x = mulmod(mp, x, invmod(mp, red32(mp, d[r])));
     }
-    out[idx] = x;
+    out[idx] = (E)x;
 }
 
-__global__ __launch_bounds__(TPB) void k_unpad(int64_t n, int32_t s, int32_t W, const uint32_t* __restrict__ in,
+template <typename E>
+__global__ __launch_bounds__(TPB) void k_unpad(int64_t n, int32_t s, int32_t W, const E* __restrict__ in,
                                                uint32_t* __restrict__ out) {
     int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x;
     if (idx >= n * (int64_t)s) return;
@@ -434,10 +394,9 @@ __global__ __launch_bounds__(TPB) void k_spmm_wide(int64_t nrows, const int32_t*
 // Thread t of a block owns entries e = t + TPB q of the W x W result (E = W^2)
 // and, when E < TPB, the row phase t / E.  Partial sums are exact in 64 bits:
 // for p <= 2^16 products are < 2^32; otherwise each product is reduced first.
-template <int W, bool SMALLP>
-__global__ __launch_bounds__(TPB) void k_project(int64_t n, const uint32_t* __restrict__ U,
-                                                 const uint32_t* __restrict__ X, uint32_t* __restrict__ partial,
-                                                 int64_t rows_per_block, ModP mp) {
+template <int W, bool SMALLP, typename T>
+__global__ __launch_bounds__(TPB) void k_project(int64_t n, const T* __restrict__ U, const T* __restrict__ X,
+                                                 uint32_t* __restrict__ partial, int64_t rows_per_block, ModP mp) {
     constexpr int E = W * W;
     constexpr int EPT = E >= TPB ? E / TPB : 1;
     constexpr int R = E >= TPB ? 1 : TPB / E;
@@ -568,18 +527,6 @@ hipError_t launch_scatter_wide_t(int64_t m, const int64_t* rp64, const int32_t* 
     return hipGetLastError();
 }
 
-hipError_t launch_sort_rows_packed(int64_t nrows, const int32_t* rp, uint32_t* ent, hipStream_t st) {
-    if (nrows == 0) return hipSuccess;
-    k_sort_rows_packed<<<grid_for(nrows, TPB), TPB, 0, st>>>(nrows, rp, ent);
-    return hipGetLastError();
-}
-
-hipError_t launch_sort_rows_wide(int64_t nrows, const int32_t* rp, int32_t* col, uint32_t* val, hipStream_t st) {
-    if (nrows == 0) return hipSuccess;
-    k_sort_rows_wide<<<grid_for(nrows, TPB), TPB, 0, st>>>(nrows, rp, col, val);
-    return hipGetLastError();
-}
-
 hipError_t launch_rng_block(uint64_t seed, int stream, int64_t rows, int32_t s, int32_t ld, ModP mp, int diag,
                             uint32_t* out, hipStream_t st) {
     int64_t total = rows * (int64_t)ld;
@@ -589,17 +536,23 @@ hipError_t launch_rng_block(uint64_t seed, int stream, int64_t rows, int32_t s, 
 }
 
 hipError_t launch_pad_scale(int64_t n, int32_t s, int32_t W, const uint32_t* in, const uint32_t* d, int mode,
-                            ModP mp, uint32_t* out, hipStream_t st) {
+                            ModP mp, void* out, int esize, hipStream_t st) {
     int64_t total = n * (int64_t)W;
     if (total == 0) return hipSuccess;
-    k_pad_scale<<<grid_for(total, TPB), TPB, 0, st>>>(n, s, W, in, d, mode, mp, out);
+    if (esize == 2)
+        k_pad_scale<uint16_t><<<grid_for(total, TPB), TPB, 0, st>>>(n, s, W, in, d, mode, mp, (uint16_t*)out);
+    else
+        k_pad_scale<uint32_t><<<grid_for(total, TPB), TPB, 0, st>>>(n, s, W, in, d, mode, mp, (uint32_t*)out);
     return hipGetLastError();
 }
 
-hipError_t launch_unpad(int64_t n, int32_t s, int32_t W, const uint32_t* in, uint32_t* out, hipStream_t st) {
+hipError_t launch_unpad(int64_t n, int32_t s, int32_t W, const void* in, int esize, uint32_t* out, hipStream_t st) {
     int64_t total = n * (int64_t)s;
     if (total == 0) return hipSuccess;
-    k_unpad<<<grid_for(total, TPB), TPB, 0, st>>>(n, s, W, in, out);
+    if (esize == 2)
+        k_unpad<uint16_t><<<grid_for(total, TPB), TPB, 0, st>>>(n, s, W, (const uint16_t*)in, out);
+    else
+        k_unpad<uint32_t><<<grid_for(total, TPB), TPB, 0, st>>>(n, s, W, (const uint32_t*)in, out);
     return hipGetLastError();
 }
 
@@ -674,29 +627,37 @@ int proj_blocks(int64_t n, int W) {
     return (int)b;
 }
 
-template <int W>
-static hipError_t project_w(bool smallp, int64_t n, const uint32_t* U, const uint32_t* X, uint32_t* partial,
-                            int nblocks, ModP mp, hipStream_t st) {
+template <int W, typename T>
+static hipError_t project_w(bool smallp, int64_t n, const T* U, const T* X, uint32_t* partial, int nblocks, ModP mp,
+                            hipStream_t st) {
     int64_t rpb = (n + nblocks - 1) / nblocks;
     if (smallp)
-        k_project<W, true><<<nblocks, TPB, 0, st>>>(n, U, X, partial, rpb, mp);
+        k_project<W, true, T><<<nblocks, TPB, 0, st>>>(n, U, X, partial, rpb, mp);
     else
-        k_project<W, false><<<nblocks, TPB, 0, st>>>(n, U, X, partial, rpb, mp);
+        k_project<W, false, T><<<nblocks, TPB, 0, st>>>(n, U, X, partial, rpb, mp);
     return hipGetLastError();
 }
 
-hipError_t launch_project(int W, bool smallp, int64_t n, const uint32_t* U, const uint32_t* X, uint32_t* partial,
-                          int nblocks, ModP mp, hipStream_t st) {
+template <typename T>
+static hipError_t project_t(int W, bool smallp, int64_t n, const T* U, const T* X, uint32_t* partial, int nblocks,
+                            ModP mp, hipStream_t st) {
     switch (W) {
-        case 1: return project_w<1>(smallp, n, U, X, partial, nblocks, mp, st);
-        case 2: return project_w<2>(smallp, n, U, X, partial, nblocks, mp, st);
-        case 4: return project_w<4>(smallp, n, U, X, partial, nblocks, mp, st);
-        case 8: return project_w<8>(smallp, n, U, X, partial, nblocks, mp, st);
-        case 16: return project_w<16>(smallp, n, U, X, partial, nblocks, mp, st);
-        case 32: return project_w<32>(smallp, n, U, X, partial, nblocks, mp, st);
-        case 64: return project_w<64>(smallp, n, U, X, partial, nblocks, mp, st);
+        case 1: return project_w<1, T>(smallp, n, U, X, partial, nblocks, mp, st);
+        case 2: return project_w<2, T>(smallp, n, U, X, partial, nblocks, mp, st);
+        case 4: return project_w<4, T>(smallp, n, U, X, partial, nblocks, mp, st);
+        case 8: return project_w<8, T>(smallp, n, U, X, partial, nblocks, mp, st);
+        case 16: return project_w<16, T>(smallp, n, U, X, partial, nblocks, mp, st);
+        case 32: return project_w<32, T>(smallp, n, U, X, partial, nblocks, mp, st);
+        case 64: return project_w<64, T>(smallp, n, U, X, partial, nblocks, mp, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_project(int W, bool smallp, int64_t n, const void* U, const void* X, int esize, uint32_t* partial,
+                          int nblocks, ModP mp, hipStream_t st) {
+    if (esize == 2)
+        return project_t<uint16_t>(W, smallp, n, (const uint16_t*)U, (const uint16_t*)X, partial, nblocks, mp, st);
+    return project_t<uint32_t>(W, smallp, n, (const uint32_t*)U, (const uint32_t*)X, partial, nblocks, mp, st);
 }
 
 hipError_t launch_reduce_partials(int W, int32_t s, int nblocks, int64_t nsteps, const uint32_t* partial, uint32_t* S,

@@ -1,0 +1,284 @@
+// Rank server: requests (matrix, prime, seed) arrive at any time; a worker
+// thread keeps one batch of sequences running on the device and admits
+// queued requests at step boundaries whenever the HBM budget and the slot
+// count allow (continuous batching).  A request whose sequence is complete
+// gets its sigma-basis and read-out, frees its memory and is answered.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "../../include/bwrank.h"
+#include "batch_runner.h"
+#include "server.h"
+#include "sigma.h"
+#include "sigma_gpu.h"
+
+namespace bwr {
+
+namespace {
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+constexpr int64_t CHECK_TERMS = 4;
+
+}  // namespace
+
+struct Server::Req {
+    uint64_t ticket = 0;
+    DevBuf rp, col, val;  // device copy of the CSR
+    DeviceMatrix M;
+    bool transpose = false;
+    uint32_t p = 0;
+    uint64_t seed = 0;
+    int32_t s = 0;
+    int64_t L = 0;
+    int64_t footprint = 0;
+    double arrival = 0, admitted = 0, finished = 0;
+    int job = -1;
+    bool done = false;
+    int64_t rank = 0;
+    int code = 0;
+    std::string msg;
+};
+
+Server::Server(int64_t budget, int max_slots, int32_t block) : budget_(budget), max_slots_(max_slots), block_(block) {}
+
+Server::~Server() { stop(); }
+
+Error Server::start() {
+    hipError_t e = hipGetDevice(&device_);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&compute_, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&upload_, hipStreamNonBlocking);
+    if (e != hipSuccess) return Error::device(e, "server streams");
+    const int spad = (block_ + 3) & ~3;
+    W_ = BatchRunner::width_for(1, block_);
+    if (spad > 32 || !batch_supported(W_, std::max(1, W_ / 4), true)) return Error::inval("block size unsupported by the server");
+    // matrices of the paper's kind have ~10-20 entries per row
+    G1_ = std::max(1, std::min(4, 64 / (W_ / 4)));
+    G2_ = std::max(W_ / 4, std::min(4, 64 / (W_ / 4)));
+    if (!batch_supported(W_, G1_, false)) G1_ = 1;
+    if (!batch_supported(W_, G2_, true)) G2_ = W_ / 4;
+    runner_ = std::make_unique<BatchRunner>(W_, G1_, G2_, compute_);
+    worker_ = std::thread([this] { loop(); });
+    return {};
+}
+
+void Server::stop() {
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        quit_ = true;
+    }
+    cv_.notify_all();
+    if (worker_.joinable()) worker_.join();
+    runner_.reset();
+    reqs_.clear();
+    if (compute_) (void)hipStreamDestroy(compute_);
+    if (upload_) (void)hipStreamDestroy(upload_);
+    compute_ = upload_ = nullptr;
+}
+
+Error Server::submit(const CsrView& A, uint32_t p, uint64_t seed, uint64_t* ticket) {
+    auto R = std::make_shared<Req>();
+    R->arrival = now_s();
+    R->p = p;
+    R->seed = seed;
+    R->transpose = A.m < A.n;
+    (void)hipSetDevice(device_);
+    {
+        std::lock_guard<std::mutex> up(upload_mu_);
+        const size_t nnz = (size_t)A.nnz;
+        Error e;
+        if (!(e = R->rp.alloc(sizeof(int64_t) * (size_t)(A.m + 1), upload_)).ok()) return e;
+        if (!(e = R->col.alloc(4 * std::max<size_t>(nnz, 1), upload_)).ok()) return e;
+        if (!(e = R->val.alloc(4 * std::max<size_t>(nnz, 1), upload_)).ok()) return e;
+        hipError_t he = hipMemcpyAsync(R->rp.as<void>(), A.row_ptr, 8 * (size_t)(A.m + 1), hipMemcpyHostToDevice,
+                                       upload_);
+        if (he == hipSuccess && nnz)
+            he = hipMemcpyAsync(R->col.as<void>(), A.col_idx, 4 * nnz, hipMemcpyHostToDevice, upload_);
+        if (he == hipSuccess && nnz) he = hipMemcpyAsync(R->val.as<void>(), A.val, 4 * nnz, hipMemcpyHostToDevice, upload_);
+        if (he != hipSuccess) return Error::device(he, "server upload");
+        CsrView dv{A.m, A.n, A.nnz, R->rp.as<int64_t>(), R->col.as<int32_t>(), R->val.as<int32_t>()};
+        if (!(e = encode_matrix(dv, p, upload_, &R->M)).ok()) return e;
+        he = hipStreamSynchronize(upload_);
+        if (he != hipSuccess) return Error::device(he, "server upload");
+        // the encoded copy is all the request needs from here on
+        R->rp.release();
+        R->col.release();
+        R->val.release();
+    }
+    const int64_t nb = std::min(A.m, A.n);
+    if (nb == 0 || A.nnz == 0 || !R->M.packed) {
+        // nothing to iterate, or entries the batch kernels cannot take: answer at once
+        R->done = true;
+        R->finished = now_s();
+        if (nb > 0 && A.nnz > 0) {
+            R->code = BWR_EINVAL;
+            R->msg = "server requests need entries in [-127, 127] and sizes <= 2^24";
+        }
+    } else {
+        R->s = (int32_t)std::min<int64_t>(block_, nb);
+        R->L = 2 + (2 * nb + R->s - 1) / R->s;
+        R->footprint = BatchRunner::footprint(R->M, R->transpose, W_, 1, R->s, R->L + CHECK_TERMS) +
+                       8 * (R->M.m + R->M.n + 2) + 8 * R->M.nnz;
+        if (R->footprint > budget_) return Error{ENOMEM_, "request larger than the server's HBM budget"};
+    }
+    std::lock_guard<std::mutex> lk(mu_);
+    R->ticket = ++next_ticket_;
+    *ticket = R->ticket;
+    reqs_[R->ticket] = R;
+    if (R->done) {
+        latencies_.push_back(R->finished - R->arrival);
+        ++completed_;
+        done_cv_.notify_all();
+    } else {
+        queue_.push_back(R->ticket);
+        max_queue_ = std::max<int64_t>(max_queue_, (int64_t)queue_.size());
+    }
+    if (first_arrival_ == 0) first_arrival_ = R->arrival;
+    cv_.notify_all();
+    return {};
+}
+
+Error Server::poll(uint64_t ticket, bool* done, int64_t* rank) {
+    std::lock_guard<std::mutex> lk(mu_);
+    auto it = reqs_.find(ticket);
+    if (it == reqs_.end()) return Error::inval("unknown ticket");
+    *done = it->second->done;
+    if (*done) {
+        if (it->second->code) return Error{it->second->code, it->second->msg};
+        *rank = it->second->rank;
+    }
+    return {};
+}
+
+Error Server::wait(uint64_t ticket, int64_t* rank) {
+    std::unique_lock<std::mutex> lk(mu_);
+    auto it = reqs_.find(ticket);
+    if (it == reqs_.end()) return Error::inval("unknown ticket");
+    std::shared_ptr<Req> R = it->second;
+    done_cv_.wait(lk, [&] { return R->done || quit_; });
+    if (!R->done) return Error::inval("server stopped");
+    if (R->code) return Error{R->code, R->msg};
+    *rank = R->rank;
+    return {};
+}
+
+ServerStats Server::stats() {
+    std::lock_guard<std::mutex> lk(mu_);
+    ServerStats st{};
+    std::vector<double> l = latencies_;
+    std::sort(l.begin(), l.end());
+    auto q = [&](double f) { return l.empty() ? 0.0 : l[std::min(l.size() - 1, (size_t)(f * (double)l.size()))]; };
+    st.p50_ms = 1000.0 * q(0.50);
+    st.p99_ms = 1000.0 * q(0.99);
+    st.completed = completed_;
+    st.max_queue = max_queue_;
+    st.max_active = max_active_;
+    st.steps = steps_;
+    const double span = last_finish_ - first_arrival_;
+    st.solves_per_s = (span > 0 && completed_ > 0) ? (double)completed_ / span : 0.0;
+    st.busy_s = busy_s_;
+    return st;
+}
+
+void Server::loop() {
+    (void)hipSetDevice(device_);
+    std::vector<std::shared_ptr<Req>> active;
+    for (;;) {
+        // admission at a step boundary
+        {
+            std::unique_lock<std::mutex> lk(mu_);
+            if (active.empty())
+                cv_.wait(lk, [&] { return quit_ || !queue_.empty(); });
+            if (quit_) break;
+            while (!queue_.empty() && (int)active.size() < max_slots_) {
+                std::shared_ptr<Req> R = reqs_[queue_.front()];
+                if (runner_->bytes_in_use() + R->footprint > budget_ && !active.empty()) break;
+                queue_.pop_front();
+                lk.unlock();
+                BatchSpec sp;
+                sp.M = &R->M;
+                sp.transpose = R->transpose;
+                sp.primes = {R->p};
+                sp.s = R->s;
+                sp.seed = R->seed;
+                sp.len = R->L + CHECK_TERMS;
+                Error e = runner_->add(sp, &R->job);
+                lk.lock();
+                R->admitted = now_s();
+                if (!e.ok()) {
+                    R->done = true;
+                    R->code = e.code;
+                    R->msg = e.msg;
+                    R->finished = now_s();
+                    done_cv_.notify_all();
+                    continue;
+                }
+                active.push_back(R);
+            }
+            max_active_ = std::max<int64_t>(max_active_, (int64_t)active.size());
+        }
+        if (active.empty()) continue;
+        const double t0 = now_s();
+        std::vector<int> fin;
+        Error e = runner_->advance(64, &fin);
+        steps_ = runner_->global_step();
+        for (int id : fin) {
+            auto it = std::find_if(active.begin(), active.end(), [&](const std::shared_ptr<Req>& r) { return r->job == id; });
+            if (it == active.end()) continue;
+            std::shared_ptr<Req> R = *it;
+            active.erase(it);
+            int64_t rank = 0;
+            Error er = e;
+            if (er.ok()) {
+                Generator g;
+                const uint32_t* S = runner_->sequence(id, 0);
+                const int64_t total = runner_->length(id);
+                std::vector<uint32_t> Sh((size_t)total * R->s * R->s);
+                if (gpu_leaf_order(R->s) > 0) er = gpu_min_generator(S, R->L, R->s, R->p, compute_, &g);
+                hipError_t he = hipMemcpyAsync(Sh.data(), S, 4 * Sh.size(), hipMemcpyDeviceToHost, compute_);
+                if (he == hipSuccess) he = hipStreamSynchronize(compute_);
+                if (er.ok() && he != hipSuccess) er = Error::device(he, "server download");
+                if (er.ok() && gpu_leaf_order(R->s) == 0) er = min_generator(Sh.data(), R->L, R->s, R->p, &g);
+                if (er.ok()) er = check_generator(g, Sh.data(), R->L, total, R->p);
+                if (er.ok()) er = rank_from_generator(g, R->p, &rank);
+            }
+            runner_->release(id);
+            std::lock_guard<std::mutex> lk(mu_);
+            R->done = true;
+            R->rank = rank;
+            R->code = er.code;
+            R->msg = er.msg;
+            R->finished = now_s();
+            latencies_.push_back(R->finished - R->arrival);
+            ++completed_;
+            last_finish_ = R->finished;
+            R->M = DeviceMatrix();
+            done_cv_.notify_all();
+        }
+        if (!e.ok()) {
+            std::lock_guard<std::mutex> lk(mu_);
+            for (auto& R : active) {
+                R->done = true;
+                R->code = e.code;
+                R->msg = e.msg;
+            }
+            active.clear();
+            done_cv_.notify_all();
+        }
+        busy_s_ += now_s() - t0;
+    }
+}
+
+}  // namespace bwr

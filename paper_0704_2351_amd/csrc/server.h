@@ -1,0 +1,61 @@
+// Continuous-batching rank server (server.cpp).  Internal C++; the public
+// surface is bwr_server_* in bwrank.h.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "batch_runner.h"
+#include "engine.h"
+
+namespace bwr {
+
+struct ServerStats {
+    double p50_ms, p99_ms;  // latency = answer time - submit time
+    double solves_per_s;    // completed / (last answer - first submit)
+    double busy_s;          // worker time spent advancing and answering
+    int64_t completed, max_queue, max_active, steps;
+};
+
+class Server {
+   public:
+    Server(int64_t hbm_budget, int max_slots, int32_t block);
+    ~Server();
+    Error start();
+    void stop();
+    // Copies and encodes A on the device before returning, then queues it.
+    Error submit(const CsrView& A_host, uint32_t p, uint64_t seed, uint64_t* ticket);
+    Error poll(uint64_t ticket, bool* done, int64_t* rank);
+    Error wait(uint64_t ticket, int64_t* rank);
+    ServerStats stats();
+
+   private:
+    struct Req;
+    void loop();
+    int64_t budget_;
+    int max_slots_;
+    int32_t block_;
+    int device_ = 0;
+    int W_ = 0, G1_ = 0, G2_ = 0;
+    hipStream_t compute_ = nullptr, upload_ = nullptr;
+    std::unique_ptr<BatchRunner> runner_;
+    std::thread worker_;
+    std::mutex mu_, upload_mu_;
+    std::condition_variable cv_, done_cv_;
+    std::map<uint64_t, std::shared_ptr<Req>> reqs_;
+    std::deque<uint64_t> queue_;
+    uint64_t next_ticket_ = 0;
+    bool quit_ = false;
+    std::vector<double> latencies_;
+    int64_t completed_ = 0, max_queue_ = 0, max_active_ = 0, steps_ = 0;
+    double first_arrival_ = 0, last_finish_ = 0, busy_s_ = 0;
+};
+
+}  // namespace bwr

@@ -286,6 +286,18 @@ void mul_naive(const PolyMat& A, const PolyMat& B, int64_t lo, int64_t hi, const
 
 }  // namespace
 
+void ntt_tables(int t, int lg, uint32_t* q, const uint32_t** tw, const uint32_t** tws, const uint32_t** itw,
+                const uint32_t** itws) {
+    init_primes();
+    NttPrime& P = g_primes[t];
+    ensure_tables(P, lg);
+    *q = P.q;
+    *tw = P.tw.data();
+    *tws = P.tws.data();
+    *itw = P.itw.data();
+    *itws = P.itws.data();
+}
+
 void set_sigma_threads(int n) {
     std::lock_guard<std::mutex> lk(g_pool_mu);
     pool().resize(std::max(1, n));

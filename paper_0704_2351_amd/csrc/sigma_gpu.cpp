@@ -1,0 +1,265 @@
+// Driver of the device sigma-basis: the PM-Basis recursion (Section 2.4) over
+// device polynomial matrices.  Every size in the recursion is fixed by the
+// order alone (a basis of order sigma has degree <= sigma), so the whole
+// recursion is enqueued without waiting on the device; only the final
+// shifted degrees and the chosen generator rows come back to the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "sigma_gpu.h"
+
+namespace bwr {
+
+#define BWR_HIP(call)                                          \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
+        if (e_ != hipSuccess) return Error::device(e_, #call); \
+    } while (0)
+
+#define BWR_TRY(expr)              \
+    do {                           \
+        Error er_ = (expr);        \
+        if (!er_.ok()) return er_; \
+    } while (0)
+
+namespace {
+
+constexpr int MAX_LG = 20;
+
+// Twiddle tables on the device, per device: [prime][value | shoup][2^MAX_LG]
+struct DevTables {
+    uint32_t* tw = nullptr;
+    uint32_t* itw = nullptr;
+    uint32_t q[3] = {0, 0, 0};
+};
+
+std::mutex g_tab_mu;
+std::vector<DevTables> g_tabs;
+
+Error device_tables(DevTables* out) {
+    int dev = 0;
+    BWR_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_tab_mu);
+    if ((int)g_tabs.size() <= dev) g_tabs.resize(dev + 1);
+    DevTables& T = g_tabs[dev];
+    if (!T.tw) {
+        const size_t N = (size_t)1 << MAX_LG;
+        std::vector<uint32_t> h_tw(3 * 2 * N), h_itw(3 * 2 * N);
+        for (int t = 0; t < 3; ++t) {
+            const uint32_t *tw, *tws, *itw, *itws;
+            ntt_tables(t, MAX_LG, &T.q[t], &tw, &tws, &itw, &itws);
+            std::memcpy(&h_tw[(2 * t) * N], tw, N * 4);
+            std::memcpy(&h_tw[(2 * t + 1) * N], tws, N * 4);
+            std::memcpy(&h_itw[(2 * t) * N], itw, N * 4);
+            std::memcpy(&h_itw[(2 * t + 1) * N], itws, N * 4);
+        }
+        uint32_t *a = nullptr, *b = nullptr;
+        BWR_HIP(hipMalloc(&a, h_tw.size() * 4));
+        BWR_HIP(hipMalloc(&b, h_itw.size() * 4));
+        BWR_HIP(hipMemcpy(a, h_tw.data(), h_tw.size() * 4, hipMemcpyHostToDevice));
+        BWR_HIP(hipMemcpy(b, h_itw.data(), h_itw.size() * 4, hipMemcpyHostToDevice));
+        T.tw = a;
+        T.itw = b;
+    }
+    *out = T;
+    return {};
+}
+
+uint32_t shoup(uint32_t w, uint32_t q) { return (uint32_t)(((uint64_t)w << 32) / q); }
+
+NttConsts make_consts(const DevTables& T, int lg, uint32_t p) {
+    NttConsts c{};
+    const ModP mp = ModP::make(p);
+    for (int t = 0; t < 3; ++t) {
+        c.q[t] = T.q[t];
+        c.mq[t] = ModP::make(T.q[t]);
+        c.r32[t] = red64(c.mq[t], (uint64_t)1 << 32);
+        c.ninv[t] = invmod(c.mq[t], (uint32_t)(((uint64_t)1 << lg) % T.q[t]));
+        c.ninvp[t] = shoup(c.ninv[t], T.q[t]);
+    }
+    c.inv01 = invmod(c.mq[1], T.q[0] % T.q[1]);
+    c.inv012 = invmod(c.mq[2], mulmod(c.mq[2], T.q[0] % T.q[2], T.q[1] % T.q[2]));
+    c.q0p = red64(mp, T.q[0]);
+    c.q01p = mulmod(mp, red64(mp, T.q[0]), red64(mp, T.q[1]));
+    c.tw_stride = (int64_t)1 << MAX_LG;
+    return c;
+}
+
+int ceil_log2(int64_t x) {
+    int l = 0;
+    while (((int64_t)1 << l) < x) ++l;
+    return l;
+}
+
+Error alloc_poly(int rows, int cols, int64_t len, hipStream_t st, DevBuf* buf, DPoly* P) {
+    BWR_TRY(buf->alloc(sizeof(uint32_t) * (size_t)rows * cols * (size_t)std::max<int64_t>(len, 1), st));
+    P->rows = rows;
+    P->cols = cols;
+    P->len = len;
+    P->ld = len;
+    P->ptr = buf->as<uint32_t>();
+    return {};
+}
+
+}  // namespace
+
+int gpu_leaf_order(int s) {
+    const int m = 2 * s, n = s;
+    for (int sg = 32; sg >= 1; sg >>= 1)
+        if (mbasis_leaf_lds(m, n, sg) <= 60 * 1024 && m <= 128) return sg;
+    return 0;
+}
+
+Error gpu_polymat_mul(const DPoly& A, const DPoly& B, int64_t lo, int64_t hi, uint32_t p, DPoly* C, DevBuf* Cbuf,
+                      hipStream_t st) {
+    const int r = A.rows, k = A.cols, c = B.cols;
+    const int64_t W = hi - lo;
+    BWR_TRY(alloc_poly(r, c, W, st, Cbuf, C));
+    const ModP mp = ModP::make(p);
+    const int64_t minlen = std::min(A.len, B.len);
+    if (minlen <= 32) {
+        if (A.ld != A.len || B.ld != B.len) {
+            // compact copies so the schoolbook kernel can assume dense rows
+            DevBuf ab, bb;
+            DPoly Ac, Bc;
+            BWR_TRY(alloc_poly(A.rows, A.cols, A.len, st, &ab, &Ac));
+            BWR_TRY(alloc_poly(B.rows, B.cols, B.len, st, &bb, &Bc));
+            BWR_HIP(hipMemcpy2DAsync(Ac.ptr, A.len * 4, A.ptr, A.ld * 4, A.len * 4, (size_t)A.rows * A.cols,
+                                     hipMemcpyDeviceToDevice, st));
+            BWR_HIP(hipMemcpy2DAsync(Bc.ptr, B.len * 4, B.ptr, B.ld * 4, B.len * 4, (size_t)B.rows * B.cols,
+                                     hipMemcpyDeviceToDevice, st));
+            BWR_HIP(gpu_schoolbook(Ac.ptr, A.len, Bc.ptr, B.len, r, k, c, lo, W, mp, C->ptr, st));
+            return {};
+        }
+        BWR_HIP(gpu_schoolbook(A.ptr, A.len, B.ptr, B.len, r, k, c, lo, W, mp, C->ptr, st));
+        return {};
+    }
+    DevTables T;
+    BWR_TRY(device_tables(&T));
+    const double bound = (double)k * (double)minlen * (double)(p - 1) * (double)(p - 1);
+    int np = 1;
+    double prod = (double)T.q[0];
+    while (prod <= bound * 1.0001 && np < 3) prod *= (double)T.q[np++];
+    if (prod <= bound) return Error::inval("polynomial product exceeds the CRT range");
+    const int lg = ceil_log2(std::max<int64_t>(hi, A.len + B.len - 1 - lo));
+    if (lg > MAX_LG) return Error::inval("polynomial product too long for the transform tables");
+    const int64_t N = (int64_t)1 << lg;
+    const NttConsts cs = make_consts(T, lg, p);
+    DevBuf fa, fb, fc;
+    BWR_TRY(fa.alloc(sizeof(uint32_t) * (size_t)np * r * k * N, st));
+    BWR_TRY(fb.alloc(sizeof(uint32_t) * (size_t)np * k * c * N, st));
+    BWR_TRY(fc.alloc(sizeof(uint32_t) * (size_t)np * r * c * N, st));
+    BWR_HIP(gpu_load_polys(A.ptr, A.ld, A.len, 0, r * k, N, np, cs, fa.as<uint32_t>(), st));
+    BWR_HIP(gpu_load_polys(B.ptr, B.ld, B.len, 0, k * c, N, np, cs, fb.as<uint32_t>(), st));
+    BWR_HIP(gpu_ntt(fa.as<uint32_t>(), lg, r * k, np, cs, T.tw, T.itw, true, st));
+    BWR_HIP(gpu_ntt(fb.as<uint32_t>(), lg, k * c, np, cs, T.tw, T.itw, true, st));
+    BWR_HIP(gpu_pointwise(fa.as<uint32_t>(), fb.as<uint32_t>(), fc.as<uint32_t>(), r, k, c, N, np, cs, st));
+    BWR_HIP(gpu_ntt(fc.as<uint32_t>(), lg, r * c, np, cs, T.tw, T.itw, false, st));
+    BWR_HIP(gpu_crt(fc.as<uint32_t>(), r * c, N, lo, W, np, cs, mp, C->ptr, st));
+    return {};
+}
+
+namespace {
+
+struct Recur {
+    uint32_t p;
+    ModP mp;
+    int m, n, leaf;
+    int64_t* d;  // device shifted degrees
+    hipStream_t st;
+};
+
+// P (m x m, len sigma + 1) = order-sigma basis of G (m x n, coefficients 0 .. sigma - 1, stride G.ld)
+Error pm(const Recur& R, const DPoly& G, int64_t sigma, DPoly* P, DevBuf* Pbuf) {
+    if (sigma <= R.leaf) {
+        BWR_TRY(alloc_poly(R.m, R.m, sigma + 1, R.st, Pbuf, P));
+        BWR_HIP(gpu_mbasis_leaf(G.ptr, G.ld, R.m, R.n, (int)sigma, R.d, P->ptr, P->ld, R.mp, R.st));
+        return {};
+    }
+    const int64_t s1 = sigma / 2, s2 = sigma - s1;
+    DevBuf b1, bg2, b2;
+    DPoly P1, G2, P2;
+    BWR_TRY(pm(R, G, s1, &P1, &b1));
+    DPoly Gs = G;
+    Gs.len = sigma;
+    BWR_TRY(gpu_polymat_mul(P1, Gs, s1, sigma, R.p, &G2, &bg2, R.st));
+    BWR_TRY(pm(R, G2, s2, &P2, &b2));
+    BWR_TRY(gpu_polymat_mul(P2, P1, 0, sigma + 1, R.p, P, Pbuf, R.st));
+    return {};
+}
+
+}  // namespace
+
+Error gpu_min_generator(const uint32_t* S_dev, int64_t L, int32_t s, uint32_t p, hipStream_t st, Generator* out,
+                        SigmaStats* stats) {
+    auto t0 = std::chrono::steady_clock::now();
+    const int leaf = gpu_leaf_order(s);
+    if (!leaf) return Error::inval("block size too large for the device sigma-basis");
+    const int m = 2 * s, n = s;
+    const int64_t len = std::max<int64_t>(L, 1);
+    // G = [S; -I] as an m x n device polynomial matrix
+    DevBuf gb, db;
+    DPoly G;
+    BWR_TRY(alloc_poly(m, n, len, st, &gb, &G));
+    BWR_HIP(gpu_build_G(S_dev, L, s, p, G.ptr, len, st));
+    std::vector<int64_t> d0(m, 0);
+    for (int i = s; i < m; ++i) d0[i] = 1;
+    BWR_TRY(db.alloc(sizeof(int64_t) * m, st));
+    BWR_HIP(hipMemcpyAsync(db.as<void>(), d0.data(), sizeof(int64_t) * m, hipMemcpyHostToDevice, st));
+    BWR_HIP(hipStreamSynchronize(st));  // the host buffers above must outlive their copies
+    Recur R{p, ModP::make(p), m, n, leaf, db.as<int64_t>(), st};
+    DevBuf pb;
+    DPoly P;
+    BWR_TRY(pm(R, G, L, &P, &pb));
+    std::vector<int64_t> d(m);
+    BWR_HIP(hipMemcpyAsync(d.data(), db.as<void>(), sizeof(int64_t) * m, hipMemcpyDeviceToHost, st));
+    BWR_HIP(hipStreamSynchronize(st));
+    std::vector<int> rows(m);
+    for (int r = 0; r < m; ++r) rows[r] = r;
+    std::stable_sort(rows.begin(), rows.end(), [&](int a, int b) { return d[a] < d[b]; });
+    out->s = s;
+    out->delta.assign(s, 0);
+    int64_t maxd = 0;
+    for (int i = 0; i < s; ++i) {
+        out->delta[i] = d[rows[i]];
+        maxd = std::max(maxd, out->delta[i]);
+    }
+    const int64_t keep = std::min<int64_t>(maxd + 1, P.len);
+    out->P.resize(s, s, maxd + 1);
+    for (int i = 0; i < s; ++i)
+        BWR_HIP(hipMemcpy2DAsync(out->P.at(i, 0), (size_t)(maxd + 1) * 4, P.ptr + (size_t)rows[i] * m * P.ld,
+                                 (size_t)P.ld * 4, (size_t)keep * 4, (size_t)s, hipMemcpyDeviceToHost, st));
+    // coefficients above delta must vanish
+    std::vector<uint32_t> tail;
+    for (int i = 0; i < s; ++i) {
+        const int64_t di = out->delta[i];
+        if (P.len > di + 1) {
+            tail.assign((size_t)s * (P.len - di - 1), 0);
+            BWR_HIP(hipMemcpy2DAsync(tail.data(), (size_t)(P.len - di - 1) * 4, P.ptr + (size_t)rows[i] * m * P.ld + di + 1,
+                                     (size_t)P.ld * 4, (size_t)(P.len - di - 1) * 4, (size_t)s, hipMemcpyDeviceToHost,
+                                     st));
+            BWR_HIP(hipStreamSynchronize(st));
+            for (uint32_t v : tail)
+                if (v) return {ESHORT_, "generator row degree exceeds its shifted degree"};
+        }
+    }
+    BWR_HIP(hipStreamSynchronize(st));
+    // zero the coefficients of P^(i) above delta_i that the copy brought in from keep
+    for (int i = 0; i < s; ++i)
+        for (int c = 0; c < s; ++c) {
+            uint32_t* row = out->P.at(i, c);
+            for (int64_t k = out->delta[i] + 1; k <= maxd; ++k) row[k] = 0;
+        }
+    if (stats) {
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        stats->threads = 0;
+    }
+    return {};
+}
+
+}  // namespace bwr

@@ -1,0 +1,56 @@
+// Device sigma-basis: launchers (sigma_gpu.hip) and the PM-Basis driver (sigma_gpu.cpp).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "modp.h"
+#include "sigma.h"
+
+namespace bwr {
+
+// Constants of one transform size N and one target prime p over T <= 3 FFT primes.
+struct NttConsts {
+    uint32_t q[3];
+    ModP mq[3];
+    uint32_t r32[3];              // 2^32 mod q_t
+    uint32_t ninv[3], ninvp[3];   // N^-1 mod q_t and its Shoup constant
+    uint32_t inv01, inv012;       // q0^-1 mod q1, (q0 q1)^-1 mod q2
+    uint32_t q0p, q01p;           // q0 mod p, q0 q1 mod p
+    int64_t tw_stride;            // twiddle table length per prime
+};
+
+hipError_t gpu_load_polys(const uint32_t* src, int64_t ld, int64_t len, int64_t off, int nb, int64_t N, int T,
+                          const NttConsts& c, uint32_t* dst, hipStream_t st);
+hipError_t gpu_ntt(uint32_t* a, int lg, int nb, int T, const NttConsts& c, const uint32_t* tw, const uint32_t* itw,
+                   bool forward, hipStream_t st);
+hipError_t gpu_pointwise(const uint32_t* A, const uint32_t* B, uint32_t* C, int r, int k, int c, int64_t N, int T,
+                         const NttConsts& cs, hipStream_t st);
+hipError_t gpu_crt(const uint32_t* C, int npoly, int64_t N, int64_t lo, int64_t W, int T, const NttConsts& cs,
+                   ModP mp, uint32_t* out, hipStream_t st);
+hipError_t gpu_schoolbook(const uint32_t* A, int64_t lenA, const uint32_t* B, int64_t lenB, int r, int k, int c,
+                          int64_t lo, int64_t W, ModP mp, uint32_t* out, hipStream_t st);
+hipError_t gpu_mbasis_leaf(const uint32_t* G, int64_t ldG, int m, int n, int sigma, int64_t* d, uint32_t* P,
+                           int64_t ldP, ModP mp, hipStream_t st);
+size_t mbasis_leaf_lds(int m, int n, int sigma);
+// G = [S(x); -I_s] as a 2s x s polynomial matrix with entries of length len >= L.
+hipError_t gpu_build_G(const uint32_t* S, int64_t L, int s, uint32_t p, uint32_t* G, int64_t len, hipStream_t st);
+
+// Largest leaf order (power of two <= 32) whose M-Basis fits the LDS budget; 0 if none.
+int gpu_leaf_order(int s);
+
+// Minimal generator of the device sequence S (L x s x s) on the device; the
+// chosen rows come back to the host in `out`.
+Error gpu_min_generator(const uint32_t* S_dev, int64_t L, int32_t s, uint32_t p, hipStream_t st, Generator* out,
+                        SigmaStats* stats = nullptr);
+
+// Window [lo, hi) of the product of two device polynomial matrices (exposed for tests).
+struct DPoly {
+    int rows = 0, cols = 0;
+    int64_t len = 0;  // coefficients in use
+    int64_t ld = 0;   // stride between entries (>= len)
+    uint32_t* ptr = nullptr;
+};
+Error gpu_polymat_mul(const DPoly& A, const DPoly& B, int64_t lo, int64_t hi, uint32_t p, DPoly* C, DevBuf* Cbuf,
+                      hipStream_t st);
+
+}  // namespace bwr

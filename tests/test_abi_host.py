@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_symbols():
     with open(os.path.join(ROOT, "include", "bwrank.h")) as f:
         text = f.read()
-    return sorted(set(re.findall(r"^\s*(?:int|int64_t|const char\*)\s+(bwr_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|int64_t|void|const char\*)\s+(bwr_\w+)\s*\(", text, re.M)))
 
 
 def test_library_exports_every_declared_symbol():

@@ -1,0 +1,94 @@
+"""GPU tests of the continuous-batching server: ranks equal the planted ranks
+and the single-matrix path, a request's result is the same alone and in the
+mix, requests that arrive while others run join the running batch, and
+admission respects the HBM budget."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import paper_0704_2351_amd as bw
+from tests.gpu_util import announce, need_gpu
+from workloads import CONFIG4_PRIMES, planted
+
+pytestmark = pytest.mark.gpu
+
+
+def requests(count, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for j in range(count):
+        n = int(np.exp(rng.uniform(np.log(150), np.log(2500))))
+        m = int(1.5 * n)
+        r = int(n * rng.uniform(0.7, 0.95))
+        p = int(CONFIG4_PRIMES[rng.integers(0, 4)])
+        out.append((planted(m, n, r, 9, 7000 + seed * 100 + j), p, 11 + j))
+    return out
+
+
+def test_server_ranks_and_alone_vs_mix():
+    need_gpu()
+    announce("server mix")
+    reqs = requests(10, 1)
+    srv = bw.Server(4 << 30, 16, 8)
+    tickets = [srv.submit(A, p, sd) for A, p, sd in reqs]
+    ranks = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    announce(f"  stats {st}")
+    srv.close()
+    for (A, p, sd), r in zip(reqs, ranks):
+        assert r == A.planted_rank
+    assert st["completed"] == 10 and st["max_active"] > 1
+    # alone: a fresh server with one request
+    srv = bw.Server(4 << 30, 16, 8)
+    A, p, sd = reqs[3]
+    assert srv.wait(srv.submit(A, p, sd)) == ranks[3]
+    srv.close()
+    assert bw.rank_modp(A, p, 8, sd)[0] == ranks[3]
+
+
+def test_server_continuous_arrivals():
+    """Requests arrive while earlier ones are on the device; they join at step boundaries."""
+    need_gpu()
+    announce("server staggered arrivals")
+    reqs = requests(12, 2)
+    srv = bw.Server(4 << 30, 32, 8)
+    tickets = [None] * len(reqs)
+
+    def feeder():
+        for i, (A, p, sd) in enumerate(reqs):
+            tickets[i] = srv.submit(A, p, sd)
+            time.sleep(0.02)
+
+    th = threading.Thread(target=feeder)
+    th.start()
+    th.join()
+    ranks = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    announce(f"  stats {st}")
+    srv.close()
+    assert ranks == [A.planted_rank for A, _, _ in reqs]
+    assert st["p99_ms"] >= st["p50_ms"] > 0
+    assert st["solves_per_s"] > 0
+
+
+def test_server_admission_by_budget():
+    need_gpu()
+    announce("server budget")
+    reqs = requests(8, 3)
+    # a budget that holds only a couple of these requests at once
+    srv = bw.Server(40 << 20, 64, 8)
+    tickets = [srv.submit(A, p, sd) for A, p, sd in reqs]
+    ranks = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    announce(f"  stats {st}")
+    srv.close()
+    assert ranks == [A.planted_rank for A, _, _ in reqs]
+    assert st["max_active"] < len(reqs)
+    # a request larger than the whole budget is refused
+    srv = bw.Server(1 << 20, 4, 8)
+    with pytest.raises(bw.BwrError) as ei:
+        srv.submit(planted(30000, 20000, 15000, 9, 5), 65521, 1)
+    assert ei.value.code == -3
+    srv.close()
