@@ -11,11 +11,15 @@ value = whole-job throughput in Gnnz.vec/s: the sparse multiply-adds of the
 two products of every sequence step (2 nnz s per step), summed over the step's
 solves, divided by the step's wall time.
 
-roofline: the dominant kernel is the sparse x block product; its average
-device time comes from HIP events around back-to-back launches on the library
-stream (bwr_time_step_kernels_dev), its algorithmic bytes per launch from the
-plain encoding (4 B index + 1 B value per non-zero, 4 B row pointers, 4 B
-residues): B_launch = [4(rows+1) + 5 nnz] + 4 s (n + m).
+roofline: the dominant kernel is the second sparse product of a step (A^T
+times the block, column scale and the fused U^T projection); its average
+device time comes from HIP events around back-to-back launches on the stream
+the kernel runs on (bwr_time_step_kernels_dev), its algorithmic bytes per
+launch from the plain encoding (4 B index + 1 B value per non-zero, 4 B row
+pointers, 4 B residues): B_launch = 4(n+1) + 5 nnz + 4 s (n + m).  traffic is
+the measured memory traffic per launch from the committed counter summary
+(profiles/traffic.json), null when that summary belongs to another revision
+of the kernel source.
 
 cpu_baseline: the oracle's plain sequence (scipy CSR products and numpy
 reductions mod p) for a bounded number of steps of the same workload.
@@ -65,6 +69,82 @@ def cpu_baseline(A, p, s, target_s=15.0):
     return {"value": rate, "unit": "Gnnz·vec/s", "cores": 1, "kind": "oracle",
             "sample": f"{steps} steps of the oracle's plain sequence (B = D_c A^T D_r A D_c applied to an n x {s} "
                       f"block, then U^T W mod {p}) on the same matrix, {el:.1f} s single-threaded"}
+
+
+def kernel_traffic(kernel_name):
+    """HBM bytes per launch of `kernel_name` from the committed counter summary, or None when the
+    summary is missing or was taken on another revision of the kernel source."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src = os.path.join(ROOT, "paper_0704_2351_amd", "csrc", "spmm.hip")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    ent = rec.get("kernels", {}).get(kernel_name)
+    if not ent or ent.get("source_sha256") != digest:
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def roofline_entry(A, s, p, us, plan):
+    """Roofline of the dominant kernel of a step: the second sparse product (A^T times the
+    n_outer x s block, column scale, fused U^T projection).  Algorithmic bytes per launch with the
+    plain encoding: 4 B row pointers, 4 B index + 1 B value per non-zero, 4 B per residue read and
+    written (U and the diagonals are regenerable and not counted)."""
+    m, n, nnz = A.m, A.n, A.nnz
+    bytes_second = 4 * (n + 1) + 5 * nnz + 4 * s * (m + n)
+    bytes_first = 4 * (m + 1) + 5 * nnz + 4 * s * (n + m)
+    name = "spmm_second_fused" if plan["fused"] else "spmm_second"
+    ach = bytes_second / (us[1] * 1e-6) / 1e9
+    ach1 = bytes_first / (us[0] * 1e-6) / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": kernel_traffic(name),
+            "kernel": f"k_spmm_split (second product: A^T Y, column scale, projection fused={bool(plan['fused'])}, "
+                      f"W={plan['W']}, G={plan['G2']}, {plan['esize']}-byte residues), p = {p}",
+            "avg_launch_us": round(us[1], 3), "bytes_per_launch": int(bytes_second),
+            "first_product": {"achieved": round(ach1, 1), "frac": round(ach1 / PEAK_HBM_GBS, 4),
+                              "avg_launch_us": round(us[0], 3), "bytes_per_launch": int(bytes_first),
+                              "G": plan["G1"]}}
+
+
+def result_line(A, s, primes, steps, warmup, elapsed, infos, us, plans):
+    """The JSON record of a timed run: `infos` are the rank_modp infos of the timed solves, `us` and
+    `plans` the per-prime kernel timings and launch plans."""
+    nnz = A.nnz
+    work = sum(2.0 * nnz * i["s"] * (i["len"] + i["check_terms"] - 1) for i in infos)
+    seq_time = sum(i["t_sequence"] for i in infos)
+    sigma_time = sum(i["t_sigma"] for i in infos)
+    return {
+        "metric": METRIC,
+        "value": round(work / elapsed / 1e9, 3),
+        "unit": "Gnnz·vec/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": round(1000.0 * elapsed / steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic planted-rank matrix (seeded); no dataset",
+        "config": {"workload": f"rank mod p of a planted {A.m} x {A.n} sparse integer matrix "
+                               f"(rank {A.planted_rank}, {nnz / 1e6:.1f} M non-zeros), block {s}, "
+                               f"p = {' and '.join(str(p) for p in primes)}",
+                   "m": A.m, "n": A.n, "nnz": nnz, "block": s, "primes": list(primes), "parallelism": "single GPU"},
+        "solves_per_s": round(len(infos) / elapsed, 4),
+        "sequence_gnnzvec_per_s": round(work / seq_time / 1e9, 3),
+        "sequence_s_per_solve": round(seq_time / len(infos), 4),
+        "sigma_basis_s_per_solve": round(sigma_time / len(infos), 4),
+        "sigma_threads": infos[0]["sigma_threads"],
+        "step_kernel_us": {str(p): [round(float(x), 3) for x in us[p]] for p in primes},
+        "step_plan": {str(p): plans[p] for p in primes},
+        "roofline": roofline_entry(A, s, primes[0], us[primes[0]], plans[primes[0]]),
+    }
 
 
 def batch_mode(args):
@@ -203,12 +283,16 @@ def main():
     planted = A.planted_rank
 
     if args.kernels_only:
-        us = bw.time_step_kernels_dev(Ad, primes[0], s, False, args.kernel_iters)
+        out = {}
+        for p in primes:
+            us, plan = bw.time_step_kernels_dev(Ad, p, s, False, args.kernel_iters, with_plan=True)
+            out[str(p)] = {"kernels_us": [round(x, 3) for x in us], "plan": plan}
         src = torch.empty(64 << 20, dtype=torch.int32, device="cuda:0").fill_(1)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"kernels_us": [round(x, 3) for x in us], "copy_bytes": 256 << 20}), flush=True)
+        out["copy_bytes"] = 256 << 20
+        print(json.dumps(out), flush=True)
         return
 
     def one_step():
@@ -232,52 +316,12 @@ def main():
         log(f"step {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    work = sum(2.0 * nnz * i["s"] * (i["len"] + i["check_terms"] - 1) for i in all_infos)
-    value = work / elapsed / 1e9
-    seq_time = sum(i["t_sequence"] for i in all_infos)
-    sigma_time = sum(i["t_sigma"] for i in all_infos)
-
-    # live kernel timing for the roofline (HIP events on the library stream)
-    us = {}
+    # live kernel timing for the roofline (HIP events on the stream the kernels run on)
+    us, plans = {}, {}
     for p in primes:
-        us[p] = bw.time_step_kernels_dev(Ad, p, s, False, args.kernel_iters)
+        us[p], plans[p] = bw.time_step_kernels_dev(Ad, p, s, False, args.kernel_iters, with_plan=True)
     torch.cuda.synchronize()
-    m, n = A.m, A.n
-    bytes_first = 4 * (m + 1) + 5 * nnz + 4 * s * (n + m)
-    bytes_second = 4 * (n + 1) + 5 * nnz + 4 * s * (m + n)
-    p0 = primes[0]
-    avg_us = 0.5 * (us[p0][0] + us[p0][1])
-    avg_bytes = 0.5 * (bytes_first + bytes_second)
-    achieved = avg_bytes / (avg_us * 1e-6) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
-                "kernel": "k_spmm_packed (both products of a step, p = 65521)",
-                "avg_launch_us": round(avg_us, 3), "bytes_per_launch": int(avg_bytes)}
-
-    out = {
-        "metric": METRIC,
-        "value": round(value, 3),
-        "unit": "Gnnz·vec/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(1000.0 * elapsed / args.steps, 2),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic planted-rank matrix (seeded); no dataset",
-        "config": {"workload": "rank mod p of a planted 200000 x 150000 sparse integer matrix "
-                               "(rank 140000, 2.6 M non-zeros), block 8, p = 65521 and 2^31 - 1",
-                   "m": m, "n": n, "nnz": nnz, "block": s, "primes": list(primes), "parallelism": "single GPU"},
-        "solves_per_s": round(len(all_infos) / elapsed, 4),
-        "sequence_gnnzvec_per_s": round(work / seq_time / 1e9, 3),
-        "sequence_s_per_solve": round(seq_time / len(all_infos), 4),
-        "sigma_basis_s_per_solve": round(sigma_time / len(all_infos), 4),
-        "sigma_threads": all_infos[0]["sigma_threads"],
-        "step_kernel_us": {str(p): [round(x, 3) for x in us[p]] for p in primes},
-        "roofline": roofline,
-    }
+    out = result_line(A, s, primes, args.steps, args.warmup, elapsed, all_infos, us, plans)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sequence)")
         out["cpu_baseline"] = cpu_baseline(A, primes[0], s)

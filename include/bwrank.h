@@ -148,9 +148,14 @@ int bwr_rank_modp_dev(const bwr_csr* A_dev, uint32_t p, int32_t block, uint64_t 
  * back on A (device CSR) with random blocks of width s: us_out[0] = the first
  * sparse product with the row scale (A X, or A^T X when transpose != 0),
  * us_out[1] = the second sparse product with the column scale, us_out[2] =
- * the U^T projection.  For measurement; computes nothing the caller keeps. */
+ * the U^T projection (0 when it is fused into the second product).  If
+ * plan_out is not NULL it receives the launch plan the sequence would use:
+ * {block width W, row split of the first product, row split of the second,
+ * projection fused (0/1), projection blocks, bytes per stored residue}
+ * (row split 0 = the one-row-per-lane kernel).  For measurement; computes
+ * nothing the caller keeps. */
 int bwr_time_step_kernels_dev(const bwr_csr* A_dev, uint32_t p, int32_t s, int32_t transpose, int32_t iters,
-                              void* stream, double* us_out);
+                              void* stream, double* us_out, int32_t* plan_out);
 
 /* Ranks of nmat matrices, each at nprimes primes, with their sequences
  * advanced together: one launch per sparse product per step covers every

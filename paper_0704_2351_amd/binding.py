@@ -79,7 +79,7 @@ def lib():
             "bwr_rank_modp_dev": (ctypes.c_int, [vp, u32, i32, u64, vp, vp, vp]),
             "bwr_min_generator": (ctypes.c_int, [vp, i64, i32, u32, vp, vp, i64, vp]),
             "bwr_rank_from_sequence": (ctypes.c_int, [vp, i64, i64, i32, u32, vp]),
-            "bwr_time_step_kernels_dev": (ctypes.c_int, [vp, u32, i32, i32, i32, vp, vp]),
+            "bwr_time_step_kernels_dev": (ctypes.c_int, [vp, u32, i32, i32, i32, vp, vp, vp]),
             "bwr_min_generator_dev": (ctypes.c_int, [vp, i64, i32, u32, vp, vp, vp, i64, vp]),
             "bwr_rank_modp_batch": (ctypes.c_int, [vp, i32, vp, i32, i32, u64, vp, vp]),
             "bwr_sequence_batch": (ctypes.c_int, [vp, i32, vp, i32, i32, u64, vp, vp]),
@@ -265,12 +265,17 @@ def rank_modp_dev(Ad, p: int, block: int, seed: int):
     return int(r.value), info.as_dict()
 
 
-def time_step_kernels_dev(Ad, p: int, s: int, transpose: bool = False, iters: int = 20):
-    """Average microseconds of [first product, second product, projection] (HIP events on torch's stream)."""
+def time_step_kernels_dev(Ad, p: int, s: int, transpose: bool = False, iters: int = 20, with_plan: bool = False):
+    """Average microseconds of [first product, second product, projection] (HIP events on torch's stream);
+    with_plan=True also returns the launch plan {W, G1, G2, fused, NB, esize}."""
     st = _dev_csr(Ad)
     us = np.zeros(3, dtype=np.float64)
+    plan = np.zeros(6, dtype=np.int32)
     _check(lib().bwr_time_step_kernels_dev(ctypes.byref(st), int(p), int(s), int(transpose), int(iters), _stream(),
-                                           us.ctypes.data))
+                                           us.ctypes.data, plan.ctypes.data))
+    if with_plan:
+        keys = ("W", "G1", "G2", "fused", "NB", "esize")
+        return us, {k: int(v) for k, v in zip(keys, plan)}
     return us
 
 

@@ -465,7 +465,7 @@ int bwr_rank_modp_dev(const bwr_csr* A_dev, uint32_t p, int32_t block, uint64_t 
 }
 
 int bwr_time_step_kernels_dev(const bwr_csr* A_dev, uint32_t p, int32_t s, int32_t transpose, int32_t iters,
-                              void* stream, double* us_out) {
+                              void* stream, double* us_out, int32_t* plan_out) {
     if (!A_dev || !us_out) return fail(BWR_EINVAL, "NULL argument");
     Error e = check_prime(p);
     if (!e.ok()) return fail(e);
@@ -473,7 +473,12 @@ int bwr_time_step_kernels_dev(const bwr_csr* A_dev, uint32_t p, int32_t s, int32
     if (!e.ok()) return fail(e);
     DeviceMatrix M;
     if (!(e = encode_matrix(view(A_dev), p, st, &M)).ok()) return fail(e);
-    if (!(e = time_step_kernels(M, transpose != 0, ModP::make(p), s, iters, st, us_out)).ok()) return fail(e);
+    StepPlan pl;
+    if (!(e = time_step_kernels(M, transpose != 0, ModP::make(p), s, iters, st, us_out, &pl)).ok()) return fail(e);
+    if (plan_out) {
+        const int32_t v[6] = {pl.W, pl.G1, pl.G2, pl.fused ? 1 : 0, pl.NB, pl.esize};
+        std::memcpy(plan_out, v, sizeof(v));
+    }
     g_err.clear();
     return BWR_OK;
 }

@@ -116,13 +116,14 @@ def _distinct_earlier_columns(rng: np.random.Generator, r: int, k: int):
     big = np.arange(k + 1, r, dtype=np.int64)
     if big.size and k > 0:
         draw = np.floor(rng.random((big.size, k)) * big[:, None]).astype(np.int64)
-        while True:
-            srt = np.sort(draw, axis=1)
-            dup = np.any(srt[:, 1:] == srt[:, :-1], axis=1)
-            if not dup.any():
-                break
-            idx = np.flatnonzero(dup)
-            draw[idx] = np.floor(rng.random((idx.size, k)) * big[idx, None]).astype(np.int64)
+        # redraw rows with a repeated column until none is left; only redrawn rows can change,
+        # so each round re-checks just those
+        idx = np.arange(big.size)
+        while idx.size:
+            srt = np.sort(draw[idx], axis=1)
+            idx = idx[np.any(srt[:, 1:] == srt[:, :-1], axis=1)]
+            if idx.size:
+                draw[idx] = np.floor(rng.random((idx.size, k)) * big[idx, None]).astype(np.int64)
         rows_out.append(np.repeat(big, k))
         cols_out.append(draw.reshape(-1))
     if rows_out:
