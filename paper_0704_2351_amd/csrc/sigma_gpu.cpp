@@ -110,6 +110,19 @@ Error alloc_poly(int rows, int cols, int64_t len, hipStream_t st, DevBuf* buf, D
 
 int gpu_leaf_order(int s) {
     const int m = 2 * s, n = s;
+    if (s >= 1 && s <= LEAF2_MAX_S) {
+        // LDS per workgroup of this device, less what the kernel declares statically
+        int dev = 0, lds = 64 * 1024;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            int v = 0;
+            if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+                lds = std::min(v, 160 * 1024);
+        }
+        const size_t budget = (size_t)lds - 8 * 1024;
+        for (int sg = 32; sg >= 1; sg >>= 1)
+            if (mbasis_leaf2_lds(m, n, sg) <= budget) return sg;
+        return 0;
+    }
     for (int sg = 32; sg >= 1; sg >>= 1)
         if (mbasis_leaf_lds(m, n, sg) <= 60 * 1024 && m <= 128) return sg;
     return 0;

@@ -32,6 +32,9 @@ hipError_t gpu_schoolbook(const uint32_t* A, int64_t lenA, const uint32_t* B, in
 hipError_t gpu_mbasis_leaf(const uint32_t* G, int64_t ldG, int m, int n, int sigma, int64_t* d, uint32_t* P,
                            int64_t ldP, ModP mp, hipStream_t st);
 size_t mbasis_leaf_lds(int m, int n, int sigma);
+// LDS of the one-transform-per-order leaf (used for m = 2n, n <= LEAF2_MAX_S).
+constexpr int LEAF2_MAX_S = 16;
+size_t mbasis_leaf2_lds(int m, int n, int sigma);
 // G = [S(x); -I_s] as a 2s x s polynomial matrix with entries of length len >= L.
 hipError_t gpu_build_G(const uint32_t* S, int64_t L, int s, uint32_t p, uint32_t* G, int64_t len, hipStream_t st);
 

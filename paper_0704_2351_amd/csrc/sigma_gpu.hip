@@ -409,6 +409,288 @@ __global__ __launch_bounds__(LEAF_TPB) void k_mbasis_leaf(const uint32_t* __rest
     for (int i = tid; i < m; i += LEAF_TPB) d[i] = dl[i];
 }
 
+// ------------------------------------------------------------------ M-Basis leaf, one transform per order
+// The same basis as k_mbasis_leaf, organised for fewer passes over LDS.  At
+// order k only the residual coefficient E = R[., ., k] (m x n) decides the
+// pivots, so the eliminations run on E alone while their row operations are
+// collected in an m x m matrix T; one parallel pass then applies T (and the
+// multiplication of the pivot rows by x) to the rest of the residual window
+// and to P.  The eliminations are fraction-free: a row eliminated by pivot
+// value v is multiplied by v instead of dividing the pivot row by v, so no
+// inverse is needed inside the loop.  Every row of the result is then its
+// exact counterpart times the product lambda of the pivot values that
+// touched it (the zero pattern, hence every pivot choice and degree, is the
+// same); lambda is tracked per row and divided out once when the leaf ends,
+// so the output equals the eager per-pivot elimination entry for entry.
+//
+// Phase A (the waves holding T columns; each repeats the E elimination): lane
+// (row r = lane / LPRW, part = lane % LPRW) keeps columns part + LPRW i of its
+// row of E and T in registers.  Values of the pivot row come through
+// v_readlane (its lanes are known to the whole wave); the pivot-column value
+// of the lane's own row comes from a DPP broadcast inside its lane group.
+// Phase B (all threads): one thread per output column (c, kk) of the residual
+// window (orders k+1 .. sigma-1) or of P (degrees 0 .. k+1) loads the m
+// entries of that column and of the column before it once, then forms every
+// row r of T times the (shifted, for pivot rows) column with double-precision
+// FMAs; all products and sums stay below 2^53, so they are exact (residues of
+// large primes are split into 16-bit halves first).
+constexpr int LEAF2_TPB = 512;
+
+template <int M>
+struct LeafLanes {
+    static constexpr int q = 64 / M;
+    static constexpr int LPRW = q >= 32 ? 32 : q >= 16 ? 16 : q >= 8 ? 8 : q >= 4 ? 4 : q >= 2 ? 2 : 1;
+};
+
+// x mod p for 0 <= x < 2^53 held exactly in a double
+__device__ __forceinline__ uint32_t dmod(double x, double pd, double pinv) {
+    double q = floor(x * pinv);
+    double r = fma(-q, pd, x);
+    if (r < 0) r += pd;
+    if (r >= pd) r -= pd;
+    return (uint32_t)r;
+}
+
+// (u * a + v * b) mod p for residues, in exact double arithmetic: products of
+// residues below 2^16 fit directly; larger residues a, b are split into 16-bit
+// halves so that every partial sum stays below 2^53.
+template <bool SMALLP>
+__device__ __forceinline__ uint32_t comb2(uint32_t u, uint32_t a, uint32_t v, uint32_t b, double pd, double pinv) {
+    if (SMALLP) return dmod(fma((double)u, (double)a, (double)v * (double)b), pd, pinv);
+    const double du = (double)u, dv = (double)v;
+    const double hi = fma(du, (double)(a >> 16), dv * (double)(b >> 16));        // < 2^48
+    const double lo = fma(du, (double)(a & 0xffffu), dv * (double)(b & 0xffffu));  // < 2^48
+    return dmod(fma((double)dmod(hi, pd, pinv), 65536.0, (double)dmod(lo, pd, pinv)), pd, pinv);
+}
+
+__device__ __forceinline__ uint32_t readlane_u32(uint32_t v, int lane) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
+}
+
+// value of lane (lane / LPRW) * LPRW + sp (the same group of LPRW lanes)
+template <int LPRW>
+__device__ __forceinline__ uint32_t group_bcast(uint32_t v, int sp) {
+    if constexpr (LPRW == 1) {
+        return v;
+    } else if constexpr (LPRW == 2) {
+        return sp == 0 ? (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xA0, 0xF, 0xF, false)
+                       : (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xF5, 0xF, 0xF, false);
+    } else if constexpr (LPRW == 4) {
+        switch (sp) {
+            case 0: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x00, 0xF, 0xF, false);
+            case 1: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x55, 0xF, 0xF, false);
+            case 2: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xAA, 0xF, 0xF, false);
+            default: return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xFF, 0xF, 0xF, false);
+        }
+    } else {
+        const int lane = (int)(threadIdx.x & 63);
+        return (uint32_t)__shfl((int)v, (lane / LPRW) * LPRW + sp, 64);
+    }
+}
+
+template <int S, bool SMALLP>
+__global__ __launch_bounds__(LEAF2_TPB) void k_mbasis_leaf2(const uint32_t* __restrict__ G, int64_t ldG, int sigma,
+                                                           int64_t* __restrict__ d, uint32_t* __restrict__ P,
+                                                           int64_t ldP, ModP mp) {
+    constexpr int M = 2 * S, N = S;
+    constexpr int LPRW = LeafLanes<M>::LPRW;
+    constexpr int EC = (N + LPRW - 1) / LPRW;       // E columns per lane
+    constexpr int TS = (M + LPRW - 1) / LPRW;       // T column slots per row
+    constexpr int NWA = TS < LEAF2_TPB / 64 ? TS : LEAF2_TPB / 64;  // waves of phase A
+    constexpr int TSW = (TS + NWA - 1) / NWA;       // T slots per lane of a phase-A wave
+    extern __shared__ uint32_t smem[];
+    const int sp = sigma + 1;
+    // ping-pong buffers by offset from the LDS base (an array of pointers would lose the LDS address space)
+    const int RS = M * N * sigma, PS = M * M * sp;
+    __shared__ double Td[M * M];
+    __shared__ uint32_t lamS[M], linv[M];
+    __shared__ int pv[M];
+    __shared__ int64_t dl[M];
+    const int tid = threadIdx.x;
+    const double pd = (double)mp.p, pinv = 1.0 / (double)mp.p;
+    for (int i = tid; i < M; i += LEAF2_TPB) {
+        dl[i] = d[i];
+        lamS[i] = 1u;
+    }
+    for (int e = tid; e < M * N * sigma; e += LEAF2_TPB) {
+        const int k = e % sigma, rc = e / sigma;
+        smem[e] = G[(size_t)rc * ldG + k];
+    }
+    for (int e = tid; e < 2 * M * M * sp; e += LEAF2_TPB) {
+        const int k = e % sp, rc = (e / sp) % (M * M);
+        smem[2 * RS + e] = (e < PS && k == 0 && rc / M == rc % M) ? 1u : 0u;  // P0 = I, P1 = 0
+    }
+    __syncthreads();
+    const int wave = tid >> 6, lane = tid & 63;
+    for (int k = 0; k < sigma; ++k) {
+        const uint32_t* Rc = smem + (k & 1) * RS;
+        uint32_t* Rn = smem + ((k + 1) & 1) * RS;
+        const uint32_t* Pc = smem + 2 * RS + (k & 1) * PS;
+        uint32_t* Pn = smem + 2 * RS + ((k + 1) & 1) * PS;
+        if (wave < NWA) {
+            const int r = lane / LPRW, part = lane % LPRW;
+            const bool valid = r < M;
+            const int rr = valid ? r : 0;
+            uint32_t e[EC], t[TSW];
+#pragma unroll
+            for (int i = 0; i < EC; ++i) {
+                const int col = part + LPRW * i;
+                e[i] = (valid && col < N) ? Rc[(rr * N + col) * sigma + k] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < TSW; ++u) {
+                const int j = part + LPRW * (wave + NWA * u);
+                t[u] = (valid && j == r) ? 1u : 0u;
+            }
+            int rk = 0;
+            const int64_t dr = dl[rr];
+            for (int j = 0; j < M; ++j) rk += (dl[j] < dr || (dl[j] == dr && j < rr)) ? 1 : 0;
+            uint32_t lam = 1u;
+            int isp = 0;
+            for (int pos = 0; pos < M; ++pos) {
+                const uint64_t bal = __ballot(valid && part == 0 && rk == pos);
+                if (bal == 0) continue;  // every rank is taken by exactly one row
+                const int ql = (int)__ffsll((unsigned long long)bal) - 1;  // first lane of the row at pos
+                uint32_t mk = 0;
+#pragma unroll
+                for (int i = 0; i < EC; ++i) {
+                    const int col = part + LPRW * i;
+                    if (col < N && e[i]) mk |= 1u << col;
+                }
+                uint32_t mq = 0;
+#pragma unroll
+                for (int x = 0; x < LPRW; ++x) mq |= readlane_u32(mk, ql + x);
+                if (mq == 0) continue;
+                const int c = __ffs(mq) - 1;
+                const int slot = c / LPRW, spart = c % LPRW;
+                uint32_t sel = 0;
+#pragma unroll
+                for (int i = 0; i < EC; ++i)
+                    if (i == slot) sel = e[i];
+                const uint32_t piv = readlane_u32(sel, ql + spart);
+                const uint32_t fr = group_bcast<LPRW>(sel, spart);
+                const bool elim = valid && rk > pos && fr != 0u;
+                const uint32_t fneg = fr ? mp.p - fr : 0u;  // eliminated row: piv * row - fr * pivot row
+                // pivot-row values at this lane's columns, then every update at once (no branches,
+                // so the independent chains interleave)
+                uint32_t qe[EC], qt[TSW];
+#pragma unroll
+                for (int i = 0; i < EC; ++i) {
+                    qe[i] = 0;
+#pragma unroll
+                    for (int x = 0; x < LPRW; ++x) {
+                        const uint32_t v = readlane_u32(e[i], ql + x);
+                        qe[i] = part == x ? v : qe[i];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < TSW; ++u) {
+                    qt[u] = 0;
+#pragma unroll
+                    for (int x = 0; x < LPRW; ++x) {
+                        const uint32_t v = readlane_u32(t[u], ql + x);
+                        qt[u] = part == x ? v : qt[u];
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < EC; ++i) {
+                    const uint32_t nv = comb2<SMALLP>(piv, e[i], fneg, qe[i], pd, pinv);
+                    e[i] = elim ? nv : e[i];
+                }
+#pragma unroll
+                for (int u = 0; u < TSW; ++u) {
+                    const uint32_t nv = comb2<SMALLP>(piv, t[u], fneg, qt[u], pd, pinv);
+                    t[u] = elim ? nv : t[u];
+                }
+                {
+                    const uint32_t nv = comb2<SMALLP>(piv, lam, 0u, 0u, pd, pinv);
+                    lam = elim ? nv : lam;
+                }
+                if (lane == ql) isp = 1;
+            }
+            if (valid) {
+#pragma unroll
+                for (int u = 0; u < TSW; ++u) {
+                    const int j = part + LPRW * (wave + NWA * u);
+                    if (j < M && wave + NWA * u < TS) Td[r * M + j] = (double)t[u];
+                }
+                if (wave == 0 && part == 0) {
+                    pv[r] = isp;
+                    lamS[r] = mulmod(mp, lamS[r], lam);
+                }
+            }
+        }
+        __syncthreads();
+        // phase B: one thread per input column kk' of the residual window
+        // (orders k .. sigma-1) or of P (degrees 0 .. k): Y[r] = sum_j T[r][j] X[j][kk'],
+        // stored at order kk' + 1 for pivot rows (multiplied by x), kk' otherwise.
+        const int nkR = sigma - k;   // residual inputs k .. sigma-1
+        const int nkP = k + 1;       // P inputs 0 .. k (degree <= k after k orders)
+        const int nR = N * nkR, nP = M * nkP;
+        // rows of a column split over two threads when that fills the block better
+        const int rsplit = (nR + nP) * 2 <= LEAF2_TPB + LEAF2_TPB / 2 ? 2 : 1;
+        const int rows_per = M / rsplit;
+        for (int w = tid; w < (nR + nP) * rsplit; w += LEAF2_TPB) {
+            const int idx = w / rsplit, r0 = (w % rsplit) * rows_per;
+            const bool isR = idx < nR;
+            int c, kq;
+            if (isR) {
+                c = idx / nkR;
+                kq = k + idx % nkR;
+            } else {
+                c = (idx - nR) / nkP;
+                kq = (idx - nR) % nkP;
+            }
+            const uint32_t* src = isR ? Rc + c * sigma + kq : Pc + c * sp + kq;
+            uint32_t* dst = isR ? Rn + c * sigma + kq : Pn + c * sp + kq;
+            const int ld = isR ? N * sigma : M * sp;  // stride between rows
+            const int lim = isR ? sigma : sp;         // first order past the buffer
+            double xh[M], xl[SMALLP ? 1 : M];
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                const uint32_t a = src[j * ld];
+                if (SMALLP) {
+                    xh[j] = (double)a;
+                } else {
+                    xh[j] = (double)(a >> 16);
+                    xl[j] = (double)(a & 0xffffu);
+                }
+            }
+#pragma unroll 4
+            for (int r = r0; r < r0 + rows_per; ++r) {
+                const double* tr = Td + r * M;
+                double ah = 0.0, al = 0.0;
+#pragma unroll
+                for (int j = 0; j < M; ++j) {
+                    ah = fma(tr[j], xh[j], ah);
+                    if (!SMALLP) al = fma(tr[j], xl[j], al);
+                }
+                uint32_t v;
+                if (SMALLP) {
+                    v = dmod(ah, pd, pinv);
+                } else {
+                    v = dmod(fma((double)dmod(ah, pd, pinv), 65536.0, (double)dmod(al, pd, pinv)), pd, pinv);
+                }
+                const int sh = pv[r];
+                if (kq + sh < lim && (isR ? kq + sh > k : true)) dst[r * ld + sh] = v;
+                if (!isR && sh && kq == 0) dst[r * ld] = 0u;  // a pivot row has no constant term
+            }
+        }
+        for (int i = tid; i < M; i += LEAF2_TPB) dl[i] += pv[i];
+        __syncthreads();
+    }
+    for (int i = tid; i < M; i += LEAF2_TPB) {
+        linv[i] = invmod(mp, lamS[i]);
+        d[i] = dl[i];
+    }
+    __syncthreads();
+    const uint32_t* Pf = smem + 2 * RS + (sigma & 1) * PS;
+    for (int e = tid; e < M * M * sp; e += LEAF2_TPB) {
+        const int k = e % sp, rc = e / sp;
+        P[(size_t)rc * ldP + k] = mulmod(mp, Pf[e], linv[rc / M]);
+    }
+}
+
 // G[r][c][k] = S[k][r][c] for r < s, k < L; -1 (mod p) at r = s + c, k = 0; 0 elsewhere.
 __global__ __launch_bounds__(TPB) void k_build_G(const uint32_t* __restrict__ S, int64_t L, int s, uint32_t p,
                                                  uint32_t* __restrict__ G, int64_t len) {
@@ -483,8 +765,57 @@ hipError_t gpu_schoolbook(const uint32_t* A, int64_t lenA, const uint32_t* B, in
     return hipGetLastError();
 }
 
+size_t mbasis_leaf2_lds(int m, int n, int sigma) {
+    return sizeof(uint32_t) * (2 * (size_t)m * n * sigma + 2 * (size_t)m * m * (sigma + 1));
+}
+
+namespace {
+
+template <int S, bool SMALLP>
+hipError_t leaf2_launch(const uint32_t* G, int64_t ldG, int sigma, int64_t* d, uint32_t* P, int64_t ldP, ModP mp,
+                        hipStream_t st) {
+    const size_t lds = mbasis_leaf2_lds(2 * S, S, sigma);
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mbasis_leaf2<S, SMALLP>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    k_mbasis_leaf2<S, SMALLP><<<1, LEAF2_TPB, lds, st>>>(G, ldG, sigma, d, P, ldP, mp);
+    return hipGetLastError();
+}
+
+template <int S>
+hipError_t leaf2_s(const uint32_t* G, int64_t ldG, int sigma, int64_t* d, uint32_t* P, int64_t ldP, ModP mp,
+                   hipStream_t st) {
+    if (mp.p <= 65536u) return leaf2_launch<S, true>(G, ldG, sigma, d, P, ldP, mp, st);
+    return leaf2_launch<S, false>(G, ldG, sigma, d, P, ldP, mp, st);
+}
+
+}  // namespace
+
 hipError_t gpu_mbasis_leaf(const uint32_t* G, int64_t ldG, int m, int n, int sigma, int64_t* d, uint32_t* P,
                            int64_t ldP, ModP mp, hipStream_t st) {
+    if (m == 2 * n && n >= 1 && n <= LEAF2_MAX_S) {
+        switch (n) {
+            case 1: return leaf2_s<1>(G, ldG, sigma, d, P, ldP, mp, st);
+            case 2: return leaf2_s<2>(G, ldG, sigma, d, P, ldP, mp, st);
+            case 3: return leaf2_s<3>(G, ldG, sigma, d, P, ldP, mp, st);
+            case 4: return leaf2_s<4>(G, ldG, sigma, d, P, ldP, mp, st);
+            case 5: return leaf2_s<5>(G, ldG, sigma, d, P, ldP, mp, st);
+            case 6: return leaf2_s<6>(G, ldG, sigma, d, P, ldP, mp, st);
+            case 7: return leaf2_s<7>(G, ldG, sigma, d, P, ldP, mp, st);
+            case 8: return leaf2_s<8>(G, ldG, sigma, d, P, ldP, mp, st);
+            case 9: return leaf2_s<9>(G, ldG, sigma, d, P, ldP, mp, st);
+            case 10: return leaf2_s<10>(G, ldG, sigma, d, P, ldP, mp, st);
+            case 11: return leaf2_s<11>(G, ldG, sigma, d, P, ldP, mp, st);
+            case 12: return leaf2_s<12>(G, ldG, sigma, d, P, ldP, mp, st);
+            case 13: return leaf2_s<13>(G, ldG, sigma, d, P, ldP, mp, st);
+            case 14: return leaf2_s<14>(G, ldG, sigma, d, P, ldP, mp, st);
+            case 15: return leaf2_s<15>(G, ldG, sigma, d, P, ldP, mp, st);
+            case 16: return leaf2_s<16>(G, ldG, sigma, d, P, ldP, mp, st);
+            default: break;
+        }
+    }
     size_t lds = mbasis_leaf_lds(m, n, sigma);
     Mont mt;
     mt.p = mp.p;
