@@ -142,10 +142,8 @@ Error gpu_polymat_mul(const DPoly& A, const DPoly& B, int64_t lo, int64_t hi, ui
             DPoly Ac, Bc;
             BWR_TRY(alloc_poly(A.rows, A.cols, A.len, st, &ab, &Ac));
             BWR_TRY(alloc_poly(B.rows, B.cols, B.len, st, &bb, &Bc));
-            BWR_HIP(hipMemcpy2DAsync(Ac.ptr, A.len * 4, A.ptr, A.ld * 4, A.len * 4, (size_t)A.rows * A.cols,
-                                     hipMemcpyDeviceToDevice, st));
-            BWR_HIP(hipMemcpy2DAsync(Bc.ptr, B.len * 4, B.ptr, B.ld * 4, B.len * 4, (size_t)B.rows * B.cols,
-                                     hipMemcpyDeviceToDevice, st));
+            BWR_HIP(gpu_copy_rows(Ac.ptr, A.len, A.ptr, A.ld, A.len, (int64_t)A.rows * A.cols, st));
+            BWR_HIP(gpu_copy_rows(Bc.ptr, B.len, B.ptr, B.ld, B.len, (int64_t)B.rows * B.cols, st));
             BWR_HIP(gpu_schoolbook(Ac.ptr, A.len, Bc.ptr, B.len, r, k, c, lo, W, mp, C->ptr, st));
             return {};
         }
@@ -242,32 +240,25 @@ Error gpu_min_generator(const uint32_t* S_dev, int64_t L, int32_t s, uint32_t p,
         out->delta[i] = d[rows[i]];
         maxd = std::max(maxd, out->delta[i]);
     }
-    const int64_t keep = std::min<int64_t>(maxd + 1, P.len);
     out->P.resize(s, s, maxd + 1);
-    for (int i = 0; i < s; ++i)
-        BWR_HIP(hipMemcpy2DAsync(out->P.at(i, 0), (size_t)(maxd + 1) * 4, P.ptr + (size_t)rows[i] * m * P.ld,
-                                 (size_t)P.ld * 4, (size_t)keep * 4, (size_t)s, hipMemcpyDeviceToHost, st));
-    // coefficients above delta must vanish
-    std::vector<uint32_t> tail;
+    // gather the chosen rows on the device (coefficients above each delta zeroed and checked), then one copy
+    if (s > 64) return Error::inval("block size too large for the device sigma-basis");
+    GenRows gr{};
     for (int i = 0; i < s; ++i) {
-        const int64_t di = out->delta[i];
-        if (P.len > di + 1) {
-            tail.assign((size_t)s * (P.len - di - 1), 0);
-            BWR_HIP(hipMemcpy2DAsync(tail.data(), (size_t)(P.len - di - 1) * 4, P.ptr + (size_t)rows[i] * m * P.ld + di + 1,
-                                     (size_t)P.ld * 4, (size_t)(P.len - di - 1) * 4, (size_t)s, hipMemcpyDeviceToHost,
-                                     st));
-            BWR_HIP(hipStreamSynchronize(st));
-            for (uint32_t v : tail)
-                if (v) return {ESHORT_, "generator row degree exceeds its shifted degree"};
-        }
+        gr.row[i] = rows[i];
+        gr.delta[i] = out->delta[i];
     }
+    DevBuf ob, fb;
+    BWR_TRY(ob.alloc(sizeof(uint32_t) * out->P.a.size(), st));
+    BWR_TRY(fb.alloc(sizeof(int32_t), st));
+    BWR_HIP(hipMemsetAsync(fb.as<void>(), 0, sizeof(int32_t), st));
+    BWR_HIP(gpu_extract_rows(P.ptr, P.ld, P.len, m, s, gr, maxd + 1, ob.as<uint32_t>(), fb.as<int32_t>(), st));
+    int32_t bad = 0;
+    BWR_HIP(hipMemcpyAsync(out->P.a.data(), ob.as<void>(), sizeof(uint32_t) * out->P.a.size(), hipMemcpyDeviceToHost,
+                           st));
+    BWR_HIP(hipMemcpyAsync(&bad, fb.as<void>(), sizeof(int32_t), hipMemcpyDeviceToHost, st));
     BWR_HIP(hipStreamSynchronize(st));
-    // zero the coefficients of P^(i) above delta_i that the copy brought in from keep
-    for (int i = 0; i < s; ++i)
-        for (int c = 0; c < s; ++c) {
-            uint32_t* row = out->P.at(i, c);
-            for (int64_t k = out->delta[i] + 1; k <= maxd; ++k) row[k] = 0;
-        }
+    if (bad) return {ESHORT_, "generator row degree exceeds its shifted degree"};
     if (stats) {
         stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         stats->threads = 0;

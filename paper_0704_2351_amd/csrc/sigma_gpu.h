@@ -38,6 +38,19 @@ size_t mbasis_leaf2_lds(int m, int n, int sigma);
 // G = [S(x); -I_s] as a 2s x s polynomial matrix with entries of length len >= L.
 hipError_t gpu_build_G(const uint32_t* S, int64_t L, int s, uint32_t p, uint32_t* G, int64_t len, hipStream_t st);
 
+// Rows chosen for the generator (at most 64): basis row indices and their shifted degrees.
+struct GenRows {
+    int32_t row[64];
+    int64_t delta[64];
+};
+// dst[r * dld + x] = src[r * sld + x] for x < width, r < nrows (device memory)
+hipError_t gpu_copy_rows(uint32_t* dst, int64_t dld, const uint32_t* src, int64_t sld, int64_t width, int64_t nrows,
+                         hipStream_t st);
+// out (s x s x olen) = the first s columns of the chosen rows of P (m x m, stride ld, len coefficients),
+// coefficients above each row's shifted degree zeroed; *bad |= 1 if such a coefficient is non-zero.
+hipError_t gpu_extract_rows(const uint32_t* P, int64_t ld, int64_t len, int m, int s, const GenRows& gr, int64_t olen,
+                            uint32_t* out, int32_t* bad, hipStream_t st);
+
 // Largest leaf order (power of two <= 32) whose M-Basis fits the LDS budget; 0 if none.
 int gpu_leaf_order(int s);
 

@@ -708,6 +708,49 @@ __global__ __launch_bounds__(TPB) void k_build_G(const uint32_t* __restrict__ S,
     G[idx] = v;
 }
 
+// dst[r * dld + x] = src[r * sld + x] for x < width, r < nrows (strided copies as plain loads and stores)
+__global__ __launch_bounds__(TPB) void k_copy_rows(uint32_t* __restrict__ dst, int64_t dld, const uint32_t* __restrict__ src,
+                                                   int64_t sld, int64_t width, int64_t nrows) {
+    const int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (idx >= width * nrows) return;
+    const int64_t r = idx / width, x = idx % width;
+    dst[r * dld + x] = src[r * sld + x];
+}
+
+// Generator rows: out[(i * s + c) * olen + k] = P[(rows[i] * m + c) * ld + k] for k <= delta_i (zero above),
+// and bad = 1 if any coefficient of those entries above delta_i (up to len) is non-zero.
+__global__ __launch_bounds__(TPB) void k_extract_rows(const uint32_t* __restrict__ P, int64_t ld, int64_t len, int m,
+                                                      int s, GenRows gr, int64_t olen, uint32_t* __restrict__ out,
+                                                      int32_t* __restrict__ bad) {
+    const int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    const int64_t span = len > olen ? len : olen;
+    if (idx >= (int64_t)s * s * span) return;
+    const int64_t k = idx % span;
+    const int e = (int)(idx / span), i = e / s, c = e % s;
+    const uint32_t v = k < len ? P[((int64_t)gr.row[i] * m + c) * ld + k] : 0u;
+    if (k < olen) out[(int64_t)e * olen + k] = k <= gr.delta[i] ? v : 0u;
+    if (k > gr.delta[i] && v) atomicOr(bad, 1);
+}
+
+}  // namespace
+
+hipError_t gpu_copy_rows(uint32_t* dst, int64_t dld, const uint32_t* src, int64_t sld, int64_t width, int64_t nrows,
+                         hipStream_t st) {
+    if (width <= 0 || nrows <= 0) return hipSuccess;
+    k_copy_rows<<<grid_for(width * nrows, TPB), TPB, 0, st>>>(dst, dld, src, sld, width, nrows);
+    return hipGetLastError();
+}
+
+hipError_t gpu_extract_rows(const uint32_t* P, int64_t ld, int64_t len, int m, int s, const GenRows& gr, int64_t olen,
+                            uint32_t* out, int32_t* bad, hipStream_t st) {
+    const int64_t span = len > olen ? len : olen;
+    if (s <= 0 || span <= 0) return hipSuccess;
+    k_extract_rows<<<grid_for((int64_t)s * s * span, TPB), TPB, 0, st>>>(P, ld, len, m, s, gr, olen, out, bad);
+    return hipGetLastError();
+}
+
+namespace {
+
 }  // namespace
 
 hipError_t gpu_build_G(const uint32_t* S, int64_t L, int s, uint32_t p, uint32_t* G, int64_t len, hipStream_t st) {
