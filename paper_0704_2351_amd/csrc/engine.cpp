@@ -278,6 +278,12 @@ Error time_launches(int iters, hipStream_t st, Fn fn, double* us) {
 
 }  // namespace
 
+// Persistent blocks of the fused second product: at most `want`, and at most 2^18 partial words per step.
+constexpr int FUSED_NB_MAX = 2048;
+int64_t fused_nb_cap(int W, int want) {
+    return std::max<int64_t>(1, std::min<int64_t>(want, 262144 / ((int64_t)W * W)));
+}
+
 StepPlan plan_step(const DeviceMatrix& M, bool transpose, int32_t s, uint32_t p) {
     StepPlan pl;
     pl.W = padded_width(s);
@@ -296,8 +302,7 @@ StepPlan plan_step(const DeviceMatrix& M, bool transpose, int32_t s, uint32_t p)
     if (pl.fused) {
         const int rpb = split_rows_per_block(pl.W, pl.G2);
         int64_t tiles = (nb + rpb - 1) / rpb;
-        int64_t cap = std::max<int64_t>(1, std::min<int64_t>(1024, 262144 / ((int64_t)pl.W * pl.W)));
-        pl.NB = (int)std::max<int64_t>(1, std::min(tiles, cap));
+        pl.NB = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, fused_nb_cap(pl.W, 1024)));
     } else {
         pl.NB = proj_blocks(nb, pl.W);
     }
@@ -318,7 +323,8 @@ Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl
     BWR_TRY(Z.alloc(es * (size_t)std::max<int64_t>(nb * W, 1), st));
     BWR_TRY(U.alloc(es * (size_t)std::max<int64_t>(nb * W, 1), st));
     BWR_TRY(Y.alloc(es * (size_t)std::max<int64_t>(outer * W, 1), st));
-    BWR_TRY(part.alloc(sizeof(uint32_t) * (size_t)1024 * W * W, st));
+    const int64_t part_words = std::max<int64_t>((int64_t)FUSED_NB_MAX * W * W, (int64_t)proj_blocks(nb, W) * W * W);
+    BWR_TRY(part.alloc(sizeof(uint32_t) * (size_t)part_words, st));
     // timing inputs: contents do not change the memory traffic
     BWR_HIP(hipMemsetAsync(X.as<void>(), 0, X.bytes(), st));
     BWR_HIP(hipMemsetAsync(U.as<void>(), 0, U.bytes(), st));
@@ -343,32 +349,42 @@ Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl
         pl->G1 = bestg;
     }
     if (pl->G2 > 0) {
+        // second product and projection: fused with 1024 or FUSED_NB_MAX persistent blocks, or the
+        // plain product followed by the projection kernel; the fastest pair wins
         double best = 1e30;
-        int bestg = pl->G2;
-        const bool proj = pl->fused;
+        int bestg = pl->G2, bestnb = pl->NB;
+        bool bestf = pl->fused;
+        const int pnb = proj_blocks(nb, W);
         for (int g = 1; g <= 16; g <<= 1) {
-            if (!split_supported(W, g, proj)) continue;
             const int rpb = split_rows_per_block(W, g);
-            int64_t tiles = (nb + rpb - 1) / rpb;
-            int nbk = proj ? (int)std::max<int64_t>(1, std::min<int64_t>(tiles, pl->NB)) : 0;
-            double us = 0;
-            BWR_TRY(time_launches(3, st, [&]() -> Error {
-                hipError_t e = launch_spmm_split(W, g, proj, use_acc32(M, op2.max_len, mp.p), smallp, pl->esize,
-                                                 op2.rows, op2.rp, op2.ent, Y.as<void>(), nullptr, Z.as<void>(),
-                                                 U.as<void>(), part.as<uint32_t>(), nbk, mp, st);
-                return e == hipSuccess ? Error{} : Error::device(e, "autotune");
-            }, &us));
-            if (us < best) {
-                best = us;
-                bestg = g;
+            const int64_t tiles = (nb + rpb - 1) / rpb;
+            for (int variant = 0; variant < 3; ++variant) {
+                const bool fused = variant < 2;
+                if (!split_supported(W, g, fused)) continue;
+                const int64_t cap = fused ? fused_nb_cap(W, variant == 0 ? 1024 : FUSED_NB_MAX) : 0;
+                if (fused && variant == 1 && cap <= 1024) continue;
+                const int nbk = fused ? (int)std::max<int64_t>(1, std::min<int64_t>(tiles, cap)) : pnb;
+                double us = 0;
+                BWR_TRY(time_launches(3, st, [&]() -> Error {
+                    hipError_t e = launch_spmm_split(W, g, fused, use_acc32(M, op2.max_len, mp.p), smallp, pl->esize,
+                                                     op2.rows, op2.rp, op2.ent, Y.as<void>(), nullptr, Z.as<void>(),
+                                                     U.as<void>(), part.as<uint32_t>(), fused ? nbk : 0, mp, st);
+                    if (e == hipSuccess && !fused && nb > 0)
+                        e = launch_project(W, smallp, nb, U.as<void>(), Z.as<void>(), pl->esize, part.as<uint32_t>(),
+                                           nbk, mp, st);
+                    return e == hipSuccess ? Error{} : Error::device(e, "autotune");
+                }, &us));
+                if (us < best) {
+                    best = us;
+                    bestg = g;
+                    bestnb = nbk;
+                    bestf = fused;
+                }
             }
         }
         pl->G2 = bestg;
-        if (pl->fused) {
-            const int rpb = split_rows_per_block(W, pl->G2);
-            int64_t tiles = (nb + rpb - 1) / rpb;
-            pl->NB = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, pl->NB));
-        }
+        pl->NB = bestnb;
+        pl->fused = bestf;
     }
     return {};
 }

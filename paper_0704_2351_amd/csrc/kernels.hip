@@ -438,20 +438,35 @@ __global__ __launch_bounds__(TPB) void k_project(int64_t n, const T* __restrict_
     }
 }
 
-__global__ __launch_bounds__(TPB) void k_reduce_partials(int W, int32_t s, int nblocks, int64_t nsteps,
-                                                         const uint32_t* __restrict__ partial, uint32_t* __restrict__ S,
-                                                         ModP mp) {
-    int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x;
-    int64_t per = (int64_t)s * s;
-    if (idx >= nsteps * per) return;
-    int64_t k = idx / per;
-    int32_t e = (int32_t)(idx - k * per);
-    int32_t i = e / s, j = e % s;
+// S_k = sum over the nblocks partials of step k: one block per step; 16 groups of 64
+// lanes split the partials (each wave reads 64 consecutive words), then LDS adds the groups.
+constexpr int RED_TPB = 1024;
+__global__ __launch_bounds__(RED_TPB) void k_reduce_partials(int W, int32_t s, int nblocks,
+                                                             const uint32_t* __restrict__ partial,
+                                                             uint32_t* __restrict__ S, ModP mp) {
+    __shared__ uint64_t sh[RED_TPB / 64][64];
+    const int64_t k = blockIdx.x;
+    const int per = s * s;
     const int64_t E = (int64_t)W * W;
-    const uint32_t* src = partial + k * nblocks * E + (int64_t)i * W + j;
-    uint64_t acc = 0;
-    for (int b = 0; b < nblocks; ++b) acc += src[(int64_t)b * E];
-    S[idx] = red64(mp, acc);
+    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const uint32_t* base = partial + k * nblocks * E;
+    for (int e0 = 0; e0 < per; e0 += 64) {
+        const int e = e0 + lane;
+        uint64_t acc = 0;
+        if (e < per) {
+            const uint32_t* src = base + (int64_t)(e / s) * W + (e % s);
+            for (int b = g; b < nblocks; b += RED_TPB / 64) acc += src[(int64_t)b * E];
+        }
+        sh[g][lane] = acc;
+        __syncthreads();
+        if (g == 0 && e < per) {
+            uint64_t t = 0;
+#pragma unroll
+            for (int q = 0; q < RED_TPB / 64; ++q) t += sh[q][lane];
+            S[k * per + e] = red64(mp, t);
+        }
+        __syncthreads();
+    }
 }
 
 }  // namespace
@@ -662,9 +677,8 @@ hipError_t launch_project(int W, bool smallp, int64_t n, const void* U, const vo
 
 hipError_t launch_reduce_partials(int W, int32_t s, int nblocks, int64_t nsteps, const uint32_t* partial, uint32_t* S,
                                   ModP mp, hipStream_t st) {
-    int64_t total = nsteps * (int64_t)s * s;
-    if (total == 0) return hipSuccess;
-    k_reduce_partials<<<grid_for(total, TPB), TPB, 0, st>>>(W, s, nblocks, nsteps, partial, S, mp);
+    if (nsteps <= 0 || s <= 0) return hipSuccess;
+    k_reduce_partials<<<(unsigned)nsteps, RED_TPB, 0, st>>>(W, s, nblocks, partial, S, mp);
     return hipGetLastError();
 }
 
