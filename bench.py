@@ -9,7 +9,9 @@ against the planted rank.
 
 value = whole-job throughput in Gnnz.vec/s: the sparse multiply-adds of the
 two products of every sequence step (2 nnz s per step), summed over the step's
-solves, divided by the step's wall time.
+solves, divided by the step's wall time.  The two primes are solved from two
+host threads (one library stream each), so one prime's sigma-basis overlaps
+the other prime's sequence on the device.
 
 roofline: the dominant kernel is the second sparse product of a step (A^T
 times the block, column scale and the fused U^T projection); its average
@@ -295,14 +297,20 @@ def main():
         print(json.dumps(out), flush=True)
         return
 
+    from concurrent.futures import ThreadPoolExecutor
+
+    pool = ThreadPoolExecutor(max_workers=len(primes))
+
+    def solve(p):
+        r, info = bw.rank_modp_dev(Ad, p, s, 1)
+        if r != planted:
+            raise RuntimeError(f"rank {r} != planted {planted} at p = {p}")
+        return info
+
     def one_step():
-        infos = []
-        for p in primes:
-            r, info = bw.rank_modp_dev(Ad, p, s, 1)
-            if r != planted:
-                raise RuntimeError(f"rank {r} != planted {planted} at p = {p}")
-            infos.append(info)
-        return infos
+        # one host thread per prime: each runs on its own library stream, so one prime's
+        # sigma-basis overlaps the other prime's sequence on the device
+        return list(pool.map(solve, primes))
 
     for w in range(args.warmup):
         log(f"warmup {w + 1}/{args.warmup}")

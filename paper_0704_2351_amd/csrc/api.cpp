@@ -70,16 +70,16 @@ Error check_prime(uint32_t p) {
 }
 
 // One library stream per device for the host-pointer entry points.
+// One non-blocking library stream per (host thread, device): calls made from different host threads run
+// concurrently on the device (e.g. one prime's sigma-basis beside another prime's sequence).
 hipStream_t lib_stream(Error* err) {
-    static std::mutex mu;
-    static std::vector<hipStream_t> streams;
+    thread_local std::vector<hipStream_t> streams;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) {
         *err = Error::device(e, "hipGetDevice");
         return nullptr;
     }
-    std::lock_guard<std::mutex> lk(mu);
     if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
     if (!streams[dev]) {
         e = hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking);
@@ -88,6 +88,8 @@ hipStream_t lib_stream(Error* err) {
             return nullptr;
         }
         // keep freed device memory cached by the pool between calls
+        static std::mutex mu;
+        std::lock_guard<std::mutex> lk(mu);
         hipMemPool_t pool;
         if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
             uint64_t thr = UINT64_MAX;

@@ -169,24 +169,42 @@ __global__ __launch_bounds__(TPB) void k_batch(const BatchJob* __restrict__ jobs
     }
 }
 
-// grid: x over (prime, i, j, step) of the chunk, y over jobs
-__global__ __launch_bounds__(TPB) void k_batch_reduce(const BatchJob* __restrict__ jobs, int64_t g_first, int nsteps,
-                                                      const uint32_t* __restrict__ partial, int64_t slot_words) {
+// grid: x over the steps of the chunk, y over jobs; 16 groups of 64 lanes split the job's partial
+// blocks (each wave reads consecutive words), LDS adds the groups
+constexpr int BRED_TPB = 1024;
+__global__ __launch_bounds__(BRED_TPB) void k_batch_reduce(const BatchJob* __restrict__ jobs, int64_t g_first,
+                                                           const uint32_t* __restrict__ partial, int64_t slot_words) {
+    __shared__ uint64_t sh[BRED_TPB / 64][64];
     const BatchJob& J = jobs[blockIdx.y];
     const int s = J.s, spad = J.spad, np = J.nprimes;
-    const int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x;
-    const int64_t per_step = (int64_t)np * s * s;
-    if (idx >= per_step * nsteps) return;
-    const int k = (int)(idx / per_step);
-    const int e = (int)(idx % per_step);
-    const int t = e / (s * s), i = (e % (s * s)) / s, c = e % s;
+    const int k = blockIdx.x;
     const int64_t kl = g_first + k - J.g0 + 1;  // the job's sequence index
-    if (kl < 1 || kl >= J.len) return;
+    if (kl < 1 || kl >= J.len) return;          // uniform over the block
     const int per = spad * spad;
-    const uint32_t* src = partial + (int64_t)k * slot_words + J.part_off + (int64_t)t * per + i * spad + c;
-    uint64_t acc = 0;
-    for (int b = 0; b < J.nblk2; ++b) acc += src[(int64_t)b * np * per];
-    J.S[((int64_t)t * J.len + kl) * s * s + i * s + c] = red64(J.mp[t], acc);
+    const int per_step = np * s * s;
+    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const uint32_t* base = partial + (int64_t)k * slot_words + J.part_off;
+    for (int e0 = 0; e0 < per_step; e0 += 64) {
+        const int e = e0 + lane;
+        int t = 0, i = 0, c = 0;
+        uint64_t acc = 0;
+        if (e < per_step) {
+            t = e / (s * s);
+            i = (e % (s * s)) / s;
+            c = e % s;
+            const uint32_t* src = base + (int64_t)t * per + i * spad + c;
+            for (int b = g; b < J.nblk2; b += BRED_TPB / 64) acc += src[(int64_t)b * np * per];
+        }
+        sh[g][lane] = acc;
+        __syncthreads();
+        if (g == 0 && e < per_step) {
+            uint64_t tot = 0;
+#pragma unroll
+            for (int q = 0; q < BRED_TPB / 64; ++q) tot += sh[q][lane];
+            J.S[((int64_t)t * J.len + kl) * s * s + i * s + c] = red64(J.mp[t], tot);
+        }
+        __syncthreads();
+    }
 }
 
 // S_0: thread t owns diagonal entries e = t, t + TPB, ... of the job; blocks split the rows
@@ -312,9 +330,10 @@ hipError_t launch_batch_second(int W, int G, const BatchJob* jobs, const int32_t
 
 hipError_t launch_batch_reduce(const BatchJob* jobs, int njobs, int64_t g_first, int nsteps, const uint32_t* partial,
                                int64_t slot_words, int max_entries, hipStream_t st) {
+    (void)max_entries;
     if (njobs <= 0 || nsteps <= 0) return hipSuccess;
-    dim3 grid(grid_for((int64_t)max_entries * nsteps, TPB), (unsigned)njobs);
-    k_batch_reduce<<<grid, TPB, 0, st>>>(jobs, g_first, nsteps, partial, slot_words);
+    dim3 grid((unsigned)nsteps, (unsigned)njobs);
+    k_batch_reduce<<<grid, BRED_TPB, 0, st>>>(jobs, g_first, partial, slot_words);
     return hipGetLastError();
 }
 

@@ -38,6 +38,8 @@ namespace {
 
 int round4(int s) { return (s + 3) & ~3; }
 
+constexpr double SECOND_BLOCKS = 2048;
+
 }  // namespace
 
 int BatchRunner::width_for(int nprimes, int s) {
@@ -167,9 +169,7 @@ Error BatchRunner::add(const BatchSpec& sp, int* id) {
     d.len = sp.len;
     d.g0 = g_;
     d.par = (int32_t)(g_ & 1);
-    const int rpb2 = batch_rows_per_block(W_, G2_);
-    const int64_t tiles2 = std::max<int64_t>(1, (nb + rpb2 - 1) / rpb2);
-    d.nblk2 = (int32_t)std::min<int64_t>(tiles2, 64);
+    d.nblk2 = 1;  // persistent blocks of the second product: set for the active set in rebuild()
     // S_0
     const int nblk0 = (int)std::max<int64_t>(1, std::min<int64_t>(64, (nb + 255) / 256));
     DevBuf p0;
@@ -192,6 +192,17 @@ Error BatchRunner::rebuild() {
     int64_t off = 0;
     max_entries_ = 0;
     const int rpb1 = batch_rows_per_block(W_, G1_);
+    const int rpb2 = batch_rows_per_block(W_, G2_);
+    // the second product's persistent blocks (each writes one partial per prime and step) are shared out in
+    // proportion to the jobs' rows, about SECOND_BLOCKS in all: enough waves to fill the device
+    double rows_all = 0;
+    for (int id : active_) rows_all += (double)jobs_[id]->d.rows2;
+    for (int id : active_) {
+        BatchJob& dj = jobs_[id]->d;
+        const int64_t tiles2 = std::max<int64_t>(1, (dj.rows2 + rpb2 - 1) / rpb2);
+        const int64_t want = (int64_t)(SECOND_BLOCKS * (double)dj.rows2 / std::max(rows_all, 1.0) + 0.5);
+        dj.nblk2 = (int32_t)std::max<int64_t>(1, std::min<int64_t>(tiles2, want));
+    }
     for (int id : active_) {
         BatchJob d = jobs_[id]->d;
         d.part_off = off;

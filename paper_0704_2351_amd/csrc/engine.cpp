@@ -167,6 +167,16 @@ bool use_acc32(const DeviceMatrix& M, int32_t max_len, uint32_t p) {
     return (int64_t)max_len * (int64_t)M.max_abs * (int64_t)(p - 1) < (1LL << 31);
 }
 
+// accumulator mode of the row-split kernel for G lanes per row slice (see launch_spmm_split)
+int acc_mode(const DeviceMatrix& M, int32_t max_len, uint32_t p, int G) {
+    if (use_acc32(M, max_len, p)) return 1;
+    if (M.packed && p > 65536u && G >= 1) {
+        const int64_t per_lane = ((int64_t)max_len + G - 1) / G;
+        if (per_lane * (int64_t)M.max_abs * 65535 < (1LL << 31)) return 2;
+    }
+    return 0;
+}
+
 Error spmm(const DeviceMatrix& M, const Operand& op, int W, ModP mp, const uint32_t* X, const uint32_t* scale,
            uint32_t* Y, hipStream_t st) {
     hipError_t e;
@@ -228,20 +238,20 @@ Error launch_step(const DeviceMatrix& M, const Operand& op1, const Operand& op2,
     const int64_t nb = op2.rows;
     hipError_t e;
     if (pl.G1 > 0) {
-        e = launch_spmm_split(pl.W, pl.G1, false, use_acc32(M, op1.max_len, mp.p), smallp, pl.esize, op1.rows, op1.rp,
+        e = launch_spmm_split(pl.W, pl.G1, false, acc_mode(M, op1.max_len, mp.p, pl.G1), smallp, pl.esize, op1.rows, op1.rp,
                               op1.ent, cur, b.dr, b.Y, nullptr, nullptr, 0, mp, st);
         if (e != hipSuccess) return Error::device(e, "spmm_split (first product)");
     } else {
         BWR_TRY(spmm(M, op1, pl.W, mp, (const uint32_t*)cur, b.dr, (uint32_t*)b.Y, st));
     }
     if (pl.fused) {
-        e = launch_spmm_split(pl.W, pl.G2, true, use_acc32(M, op2.max_len, mp.p), smallp, pl.esize, op2.rows, op2.rp,
+        e = launch_spmm_split(pl.W, pl.G2, true, acc_mode(M, op2.max_len, mp.p, pl.G2), smallp, pl.esize, op2.rows, op2.rp,
                               op2.ent, b.Y, b.dc2, nxt, b.Ut, slot, pl.NB, mp, st);
         if (e != hipSuccess) return Error::device(e, "spmm_split (second product + projection)");
         return {};
     }
     if (pl.G2 > 0) {
-        e = launch_spmm_split(pl.W, pl.G2, false, use_acc32(M, op2.max_len, mp.p), smallp, pl.esize, op2.rows, op2.rp,
+        e = launch_spmm_split(pl.W, pl.G2, false, acc_mode(M, op2.max_len, mp.p, pl.G2), smallp, pl.esize, op2.rows, op2.rp,
                               op2.ent, b.Y, b.dc2, nxt, nullptr, nullptr, 0, mp, st);
         if (e != hipSuccess) return Error::device(e, "spmm_split (second product)");
     } else {
@@ -336,7 +346,7 @@ Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl
             if (!split_supported(W, g, false)) continue;
             double us = 0;
             BWR_TRY(time_launches(3, st, [&]() -> Error {
-                hipError_t e = launch_spmm_split(W, g, false, use_acc32(M, op1.max_len, mp.p), smallp, pl->esize,
+                hipError_t e = launch_spmm_split(W, g, false, acc_mode(M, op1.max_len, mp.p, g), smallp, pl->esize,
                                                  op1.rows, op1.rp, op1.ent, X.as<void>(), nullptr, Y.as<void>(),
                                                  nullptr, nullptr, 0, mp, st);
                 return e == hipSuccess ? Error{} : Error::device(e, "autotune");
@@ -366,7 +376,7 @@ Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl
                 const int nbk = fused ? (int)std::max<int64_t>(1, std::min<int64_t>(tiles, cap)) : pnb;
                 double us = 0;
                 BWR_TRY(time_launches(3, st, [&]() -> Error {
-                    hipError_t e = launch_spmm_split(W, g, fused, use_acc32(M, op2.max_len, mp.p), smallp, pl->esize,
+                    hipError_t e = launch_spmm_split(W, g, fused, acc_mode(M, op2.max_len, mp.p, g), smallp, pl->esize,
                                                      op2.rows, op2.rp, op2.ent, Y.as<void>(), nullptr, Z.as<void>(),
                                                      U.as<void>(), part.as<uint32_t>(), fused ? nbk : 0, mp, st);
                     if (e == hipSuccess && !fused && nb > 0)
@@ -567,7 +577,7 @@ Error time_step_kernels(const DeviceMatrix& M, bool transpose, ModP mp, int32_t 
     // [0] first product, [1] second product (+ projection when fused), [2] separate projection (0 when fused)
     BWR_TRY(time_launches(iters, st, [&]() -> Error {
         if (pl.G1 > 0) {
-            hipError_t e = launch_spmm_split(W, pl.G1, false, use_acc32(M, op1.max_len, mp.p), smallp, pl.esize,
+            hipError_t e = launch_spmm_split(W, pl.G1, false, acc_mode(M, op1.max_len, mp.p, pl.G1), smallp, pl.esize,
                                              op1.rows, op1.rp, op1.ent, X.as<void>(), d1.as<uint32_t>(), Y.as<void>(),
                                              nullptr, nullptr, 0, mp, st);
             return e == hipSuccess ? Error{} : Error::device(e, "spmm_split");
@@ -576,7 +586,7 @@ Error time_step_kernels(const DeviceMatrix& M, bool transpose, ModP mp, int32_t 
     }, &us[0]));
     BWR_TRY(time_launches(iters, st, [&]() -> Error {
         if (pl.G2 > 0) {
-            hipError_t e = launch_spmm_split(W, pl.G2, pl.fused, use_acc32(M, op2.max_len, mp.p), smallp, pl.esize,
+            hipError_t e = launch_spmm_split(W, pl.G2, pl.fused, acc_mode(M, op2.max_len, mp.p, pl.G2), smallp, pl.esize,
                                              op2.rows, op2.rp, op2.ent, Y.as<void>(), d2.as<uint32_t>(), Z.as<void>(),
                                              U.as<void>(), part.as<uint32_t>(), pl.NB, mp, st);
             return e == hipSuccess ? Error{} : Error::device(e, "spmm_split");

@@ -89,8 +89,10 @@ namespace bwr {
 // partials (nblocks blocks in a grid-stride loop).
 bool split_supported(int W, int G, bool proj);
 int split_rows_per_block(int W, int G);
-// X, Y, U hold esize-byte residues (2: p <= 2^16, 4: any p).
-hipError_t launch_spmm_split(int W, int G, bool proj, bool acc32, bool smallp, int esize, int64_t nrows,
+// X, Y, U hold esize-byte residues (2: p <= 2^16, 4: any p).  acc: 1 = int32 sums (p <= 2^16 and
+// max row length * max |a| * (p - 1) < 2^31), 2 = 16-bit halves of the residues summed in two int32
+// (p > 2^16 and ceil(max row length / G) * max |a| * 65535 < 2^31), 0 = int64 sums.
+hipError_t launch_spmm_split(int W, int G, bool proj, int acc, bool smallp, int esize, int64_t nrows,
                              const int32_t* rp, const uint32_t* ent, const void* X, const uint32_t* scale, void* Y,
                              const void* U, uint32_t* partial, int nblocks, ModP mp, hipStream_t st);
 }  // namespace bwr

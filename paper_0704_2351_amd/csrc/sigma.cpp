@@ -41,13 +41,15 @@ class Pool {
         stop();
         start(n);
     }
-    // runs fn(i) for i in [0, n) on all threads; returns when done
+    // runs fn(i) for i in [0, n) on all threads; returns when done.  Calls from several host threads
+    // take turns (one job at a time).
     void run(int64_t n, const std::function<void(int64_t)>& fn) {
         if (n <= 0) return;
         if (workers_.empty() || n == 1) {
             for (int64_t i = 0; i < n; ++i) fn(i);
             return;
         }
+        std::lock_guard<std::mutex> turn(run_mu_);
         std::unique_lock<std::mutex> lk(mu_);
         job_ = &fn;
         total_ = n;
@@ -98,7 +100,7 @@ class Pool {
         workers_.clear();
     }
     std::vector<std::thread> workers_;
-    std::mutex mu_;
+    std::mutex mu_, run_mu_;
     std::condition_variable cv_, done_cv_;
     const std::function<void(int64_t)>* job_ = nullptr;
     int64_t total_ = 0;

@@ -76,7 +76,7 @@ __device__ __forceinline__ void loadn(const E* p, uint32_t (&x)[N]) {
     }
 }
 
-template <int W, int G, bool ACC32, bool SMALLP, bool PROJ, typename E>
+template <int W, int G, int ACC, bool SMALLP, bool PROJ, typename E>
 __global__ __launch_bounds__(TPB) void k_spmm_split(int64_t nrows, const int32_t* __restrict__ rp,
                                                     const uint32_t* __restrict__ ent, const E* __restrict__ X,
                                                     const uint32_t* __restrict__ scale, E* __restrict__ Y,
@@ -89,6 +89,9 @@ __global__ __launch_bounds__(TPB) void k_spmm_split(int64_t nrows, const int32_t
     constexpr int RPB = (TPB / 64) * RPW;
     constexpr int IPL = PROJ ? W / G : 1;
     static_assert(!PROJ || (W % G == 0 && IPL <= 4), "projection needs W / G <= 4");
+    // ACC 1: int32 sums (16-bit primes, bounded rows); 2: residues split into 16-bit halves summed in two
+    // int32 with full-rate 24-bit multiplies (large primes, bounded share of a row per lane); 0: int64
+    constexpr bool ACC32 = ACC == 1;
     using Acc = typename std::conditional<ACC32, int32_t, int64_t>::type;
 
     const int lane = threadIdx.x & 63;
@@ -98,16 +101,20 @@ __global__ __launch_bounds__(TPB) void k_spmm_split(int64_t nrows, const int32_t
     const int j = sub / CG;
     const int slot = lane / LPR;
 
-    uint64_t pacc[IPL][4];
+    uint64_t pacc[IPL][4], phi[SMALLP ? 1 : IPL][4];  // projection sums (low and high product halves)
 #pragma unroll
     for (int u = 0; u < IPL; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) pacc[u][v] = 0;
+        for (int v = 0; v < 4; ++v) {
+            pacc[u][v] = 0;
+            if (!SMALLP) phi[u][v] = 0;
+        }
 
     for (int64_t tile = blockIdx.x; tile * RPB < nrows; tile += gridDim.x) {
         const int64_t row = tile * RPB + wave * RPW + slot;
         const bool active = row < nrows;
         Acc acc[4] = {0, 0, 0, 0};
+        int32_t ah[4] = {0, 0, 0, 0}, al[4] = {0, 0, 0, 0};
         if (active) {
             const int32_t b = rp[row], e = rp[row + 1];
             const E* Xs = X + cg * 4;
@@ -124,8 +131,14 @@ __global__ __launch_bounds__(TPB) void k_spmm_split(int64_t nrows, const int32_t
                     const int32_t a = (int32_t)en[u] >> 24;
 #pragma unroll
                     for (int c = 0; c < 4; ++c) {
-                        if constexpr (ACC32) acc[c] += __mul24(a, (int32_t)x[u][c]);
-                        else acc[c] += (int64_t)a * (int64_t)x[u][c];
+                        if constexpr (ACC == 1) {
+                            acc[c] += __mul24(a, (int32_t)x[u][c]);
+                        } else if constexpr (ACC == 2) {
+                            ah[c] += __mul24(a, (int32_t)(x[u][c] >> 16));
+                            al[c] += __mul24(a, (int32_t)(x[u][c] & 0xffffu));
+                        } else {
+                            acc[c] += (int64_t)a * (int64_t)x[u][c];
+                        }
                     }
                 }
             }
@@ -136,10 +149,20 @@ __global__ __launch_bounds__(TPB) void k_spmm_split(int64_t nrows, const int32_t
                 const int32_t a = (int32_t)en0 >> 24;
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    if constexpr (ACC32) acc[c] += __mul24(a, (int32_t)x[c]);
-                    else acc[c] += (int64_t)a * (int64_t)x[c];
+                    if constexpr (ACC == 1) {
+                        acc[c] += __mul24(a, (int32_t)x[c]);
+                    } else if constexpr (ACC == 2) {
+                        ah[c] += __mul24(a, (int32_t)(x[c] >> 16));
+                        al[c] += __mul24(a, (int32_t)(x[c] & 0xffffu));
+                    } else {
+                        acc[c] += (int64_t)a * (int64_t)x[c];
+                    }
                 }
             }
+        }
+        if constexpr (ACC == 2) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c] = (int64_t)ah[c] * 65536 + al[c];
         }
         // all G slices of the row end with the full sum
 #pragma unroll
@@ -161,12 +184,28 @@ __global__ __launch_bounds__(TPB) void k_spmm_split(int64_t nrows, const int32_t
 #pragma unroll
                 for (int q = 0; q < IPL; ++q)
 #pragma unroll
-                    for (int c = 0; c < 4; ++c)
-                        pacc[q][c] += SMALLP ? (uint64_t)(u[q] * y[c]) : (uint64_t)mulmod(mp, u[q], y[c]);
+                    for (int c = 0; c < 4; ++c) {
+                        if (SMALLP) {
+                            pacc[q][c] += (uint64_t)(u[q] * y[c]);
+                        } else {
+                            const uint64_t pr = (uint64_t)u[q] * y[c];
+                            pacc[q][c] += pr & 0xffffffffu;
+                            phi[SMALLP ? 0 : q][c] += pr >> 32;
+                        }
+                    }
             }
         }
     }
     if constexpr (PROJ) {
+        if constexpr (!SMALLP) {
+            // fold the two halves: sum = hi 2^32 + lo, reduced per lane before the cross-lane sums
+            const uint32_t r32 = red64(mp, (uint64_t)1 << 32);
+#pragma unroll
+            for (int q = 0; q < IPL; ++q)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    pacc[q][c] = addmod(mp, mulmod(mp, red64(mp, phi[q][c]), r32), red64(mp, pacc[q][c]));
+        }
         // sum over the row slots of the wave (lanes with equal sub)
 #pragma unroll
         for (int off = LPR; off < 64; off <<= 1)
@@ -204,49 +243,51 @@ struct Args {
 };
 
 template <int W, int G, bool PROJ, typename E>
-hipError_t launch_wge(bool acc32, bool smallp, unsigned grid, const Args& a, hipStream_t st) {
+hipError_t launch_wge(int acc, bool smallp, unsigned grid, const Args& a, hipStream_t st) {
     const E* X = (const E*)a.X;
     E* Y = (E*)a.Y;
     const E* U = (const E*)a.U;
-    if (acc32)
-        k_spmm_split<W, G, true, true, PROJ, E><<<grid, TPB, 0, st>>>(a.nrows, a.rp, a.ent, X, a.scale, Y, U, a.partial,
-                                                                    a.mp);
+    if (acc == 1)
+        k_spmm_split<W, G, 1, true, PROJ, E><<<grid, TPB, 0, st>>>(a.nrows, a.rp, a.ent, X, a.scale, Y, U, a.partial,
+                                                                 a.mp);
     else if (smallp)
-        k_spmm_split<W, G, false, true, PROJ, E><<<grid, TPB, 0, st>>>(a.nrows, a.rp, a.ent, X, a.scale, Y, U,
-                                                                     a.partial, a.mp);
+        k_spmm_split<W, G, 0, true, PROJ, E><<<grid, TPB, 0, st>>>(a.nrows, a.rp, a.ent, X, a.scale, Y, U, a.partial,
+                                                                 a.mp);
+    else if (acc == 2)
+        k_spmm_split<W, G, 2, false, PROJ, E><<<grid, TPB, 0, st>>>(a.nrows, a.rp, a.ent, X, a.scale, Y, U, a.partial,
+                                                                  a.mp);
     else
-        k_spmm_split<W, G, false, false, PROJ, E><<<grid, TPB, 0, st>>>(a.nrows, a.rp, a.ent, X, a.scale, Y, U,
-                                                                      a.partial, a.mp);
+        k_spmm_split<W, G, 0, false, PROJ, E><<<grid, TPB, 0, st>>>(a.nrows, a.rp, a.ent, X, a.scale, Y, U, a.partial,
+                                                                  a.mp);
     return hipGetLastError();
 }
 
 template <int W, int G, bool PROJ>
-hipError_t launch_wg(bool acc32, bool smallp, int esize, unsigned grid, const Args& a, hipStream_t st) {
-    if (esize == 2) return launch_wge<W, G, PROJ, uint16_t>(acc32, true, grid, a, st);
-    return launch_wge<W, G, PROJ, uint32_t>(acc32, smallp, grid, a, st);
+hipError_t launch_wg(int acc, bool smallp, int esize, unsigned grid, const Args& a, hipStream_t st) {
+    if (esize == 2) return launch_wge<W, G, PROJ, uint16_t>(acc, true, grid, a, st);
+    return launch_wge<W, G, PROJ, uint32_t>(acc, smallp, grid, a, st);
 }
 
 template <int W, int G>
-hipError_t launch_g(bool proj, bool acc32, bool smallp, int esize, unsigned grid, const Args& a, hipStream_t st) {
+hipError_t launch_g(bool proj, int acc, bool smallp, int esize, unsigned grid, const Args& a, hipStream_t st) {
     if constexpr ((W / 4) * G <= 64) {
         if (proj) {
-            if constexpr (W % G == 0 && W / G <= 4) return launch_wg<W, G, true>(acc32, smallp, esize, grid, a, st);
+            if constexpr (W % G == 0 && W / G <= 4) return launch_wg<W, G, true>(acc, smallp, esize, grid, a, st);
             return hipErrorInvalidValue;
         }
-        return launch_wg<W, G, false>(acc32, smallp, esize, grid, a, st);
+        return launch_wg<W, G, false>(acc, smallp, esize, grid, a, st);
     }
     return hipErrorInvalidValue;
 }
 
 template <int W>
-hipError_t launch_w(int G, bool proj, bool acc32, bool smallp, int esize, unsigned grid, const Args& a,
-                    hipStream_t st) {
+hipError_t launch_w(int G, bool proj, int acc, bool smallp, int esize, unsigned grid, const Args& a, hipStream_t st) {
     switch (G) {
-        case 1: return launch_g<W, 1>(proj, acc32, smallp, esize, grid, a, st);
-        case 2: return launch_g<W, 2>(proj, acc32, smallp, esize, grid, a, st);
-        case 4: return launch_g<W, 4>(proj, acc32, smallp, esize, grid, a, st);
-        case 8: return launch_g<W, 8>(proj, acc32, smallp, esize, grid, a, st);
-        case 16: return launch_g<W, 16>(proj, acc32, smallp, esize, grid, a, st);
+        case 1: return launch_g<W, 1>(proj, acc, smallp, esize, grid, a, st);
+        case 2: return launch_g<W, 2>(proj, acc, smallp, esize, grid, a, st);
+        case 4: return launch_g<W, 4>(proj, acc, smallp, esize, grid, a, st);
+        case 8: return launch_g<W, 8>(proj, acc, smallp, esize, grid, a, st);
+        case 16: return launch_g<W, 16>(proj, acc, smallp, esize, grid, a, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -262,10 +303,11 @@ bool split_supported(int W, int G, bool proj) {
 
 int split_rows_per_block(int W, int G) { return (TPB / 64) * (64 / ((W / 4) * G)); }
 
-hipError_t launch_spmm_split(int W, int G, bool proj, bool acc32, bool smallp, int esize, int64_t nrows,
+hipError_t launch_spmm_split(int W, int G, bool proj, int acc, bool smallp, int esize, int64_t nrows,
                              const int32_t* rp, const uint32_t* ent, const void* X, const uint32_t* scale, void* Y,
                              const void* U, uint32_t* partial, int nblocks, ModP mp, hipStream_t st) {
-    if (!split_supported(W, G, proj) || (acc32 && !smallp) || (esize == 2 && !smallp) || (esize != 2 && esize != 4))
+    if (!split_supported(W, G, proj) || (acc == 1 && !smallp) || (acc == 2 && smallp) || acc < 0 || acc > 2 ||
+        (esize == 2 && !smallp) || (esize != 2 && esize != 4))
         return hipErrorInvalidValue;
     const int rpb = split_rows_per_block(W, G);
     int64_t tiles = (nrows + rpb - 1) / rpb;
@@ -274,11 +316,11 @@ hipError_t launch_spmm_split(int W, int G, bool proj, bool acc32, bool smallp, i
     if (grid < 1) grid = 1;
     const Args a{nrows, rp, ent, X, scale, Y, U, partial, mp};
     switch (W) {
-        case 4: return launch_w<4>(G, proj, acc32, smallp, esize, grid, a, st);
-        case 8: return launch_w<8>(G, proj, acc32, smallp, esize, grid, a, st);
-        case 16: return launch_w<16>(G, proj, acc32, smallp, esize, grid, a, st);
-        case 32: return launch_w<32>(G, proj, acc32, smallp, esize, grid, a, st);
-        case 64: return launch_w<64>(G, proj, acc32, smallp, esize, grid, a, st);
+        case 4: return launch_w<4>(G, proj, acc, smallp, esize, grid, a, st);
+        case 8: return launch_w<8>(G, proj, acc, smallp, esize, grid, a, st);
+        case 16: return launch_w<16>(G, proj, acc, smallp, esize, grid, a, st);
+        case 32: return launch_w<32>(G, proj, acc, smallp, esize, grid, a, st);
+        case 64: return launch_w<64>(G, proj, acc, smallp, esize, grid, a, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -99,3 +99,37 @@ def test_rank_config2(p):
     got, info = bw.rank_modp(A, p, 8, 1)
     announce(f"  info {info}")
     assert got == native.rank_csr_c(A, p) == 140_000
+
+
+def test_concurrent_calls_from_host_threads():
+    """Solves issued from several host threads (each on its own library stream) give the ranks and the
+    sequences that the same calls give one after another."""
+    import threading
+
+    need_gpu()
+    announce("concurrent host threads")
+    mats = [planted(3000, 2200, 1900, 9, 70), planted(2500, 2000, 1500, 9, 71)]
+    primes = [65521, 2**31 - 1]
+    want = {(j, p): bw.rank_modp(A, p, 8, 3)[0] for j, A in enumerate(mats) for p in primes}
+    rng = np.random.default_rng(0)
+    A0 = mats[0]
+    U = rng.integers(0, 65521, size=(A0.n, 4))
+    V = rng.integers(0, 65521, size=(A0.n, 4))
+    S_want = bw.sequence(A0, U, V, 65521, 300)
+    got, seqs, errors = {}, [], []
+
+    def solve(j, p):
+        try:
+            got[(j, p)] = bw.rank_modp(mats[j], p, 8, 3)[0]
+            seqs.append(bw.sequence(A0, U, V, 65521, 300))
+        except Exception as e:  # surfaced below
+            errors.append(e)
+
+    threads = [threading.Thread(target=solve, args=key) for key in want]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    assert got == want
+    assert all(np.array_equal(S, S_want) for S in seqs) and len(seqs) == len(want)
