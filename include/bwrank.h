@@ -25,8 +25,12 @@
  *   - Blocks are row-major: an n x s block X has X[r * s + c].
  *   - "_dev" entry points take device pointers (memory of the current HIP
  *     device) and a hipStream_t passed as void* (NULL = the null stream); they
- *     return after the work on that stream has completed.  Every other entry
+ *     wait for the work already queued on that stream, run on a library
+ *     stream and return when their work has completed.  Every other entry
  *     point takes host pointers.
+ *   - The library keeps one non-blocking stream per host thread and device, so
+ *     calls made from different host threads run concurrently on the device
+ *     (bwr_set_threads must not run while another call is in progress).
  *   - p must be a prime with 3 <= p < 2^31 (BWR_EPRIME otherwise).
  *   - Block sizes s are 1 .. 64.
  */
@@ -67,7 +71,7 @@ typedef struct {
     int64_t sum_delta;    /* sum of the generator's row degrees */
     double t_encode;      /* seconds: validation and device encoding of A */
     double t_sequence;    /* seconds: the L + check terms on the device */
-    double t_sigma;       /* seconds: sigma-basis on the host */
+    double t_sigma;       /* seconds: sigma-basis (on the device when its leaf fits in LDS, s <= 32; else host) */
     double t_readout;     /* seconds: check and read-out */
     int32_t sigma_threads;
     int32_t pad;
