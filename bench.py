@@ -176,6 +176,7 @@ def batch_mode(args):
         for t, p in enumerate(primes):
             r, _ = bw.rank_modp(A, p, 8, 1)
             plain_ok &= (r == ranks[j, t])
+        log(f"plain: matrix {j + 1}/{len(mats)} done")
     tp = time.perf_counter() - t0
     log(f"plain {tp:.2f} s, identical ranks: {plain_ok}")
     print(json.dumps({
@@ -188,6 +189,67 @@ def batch_mode(args):
         "config": {"workload": f"{len(mats)} of the 64 batched-configuration matrices (n log-uniform 5e3..2e5, "
                                f"m = 1.2-2.0 n, rank 70-95 % of n) x primes {list(primes)}, block 8",
                    "matrices": [[A.m, A.n, A.nnz] for A in mats]}}), flush=True)
+
+
+def paper_scale_mode(args):
+    """The 2 000 000 x 1 000 000 matrix (37 M non-zeros, block 16, p = 65521): kernel timings and roofline at a
+    size far beyond the caches, the sequence rate over a bounded number of steps, and the device sigma-basis
+    time at the full sequence length (on a random sequence of that length and block size)."""
+    import numpy as np
+    import torch
+
+    import paper_0704_2351_amd as bw
+    from workloads import config3
+
+    s, p = 16, 65521
+    log("generating the planted 2000000 x 1000000 matrix")
+    A = config3()
+    Ad = bw.csr_to_device(A, "cuda:0")
+    torch.cuda.synchronize()
+    m, n, nnz = A.m, A.n, A.nnz
+    log("kernel timing")
+    us, plan = bw.time_step_kernels_dev(Ad, p, s, False, args.kernel_iters, with_plan=True)
+    bytes_second = 4 * (n + 1) + 5 * nnz + 4 * s * (m + n)
+    bytes_first = 4 * (m + 1) + 5 * nnz + 4 * s * (n + m)
+    L = bw.sequence_length(n, s)
+    steps = args.paper_steps
+    log(f"sequence of {steps} terms")
+    rng = np.random.default_rng(0)
+    U = torch.from_numpy(rng.integers(0, p, size=(n, s), dtype=np.int64).astype(np.int32)).cuda()
+    V = torch.from_numpy(rng.integers(0, p, size=(n, s), dtype=np.int64).astype(np.int32)).cuda()
+    dr = torch.from_numpy(rng.integers(1, p, size=m, dtype=np.int64).astype(np.int32)).cuda()
+    dc = torch.from_numpy(rng.integers(1, p, size=n, dtype=np.int64).astype(np.int32)).cuda()
+    bw.sequence_dev(Ad, U, V, p, 600, dr, dc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bw.sequence_dev(Ad, U, V, p, steps, dr, dc)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    per_step = ts / (steps - 1)
+    log(f"device sigma-basis at L = {L}, s = {s} (random sequence)")
+    S = torch.from_numpy(rng.integers(0, p, size=(L, s, s), dtype=np.int64).astype(np.int32)).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bw.min_generator_dev(S, p)
+    tsig = time.perf_counter() - t0
+    work_step = 2.0 * nnz * s
+    print(json.dumps({
+        "metric": METRIC, "mode": "paper_scale", "unit": "Gnnz·vec/s",
+        "value": round(work_step / per_step / 1e9, 3), "steps": steps, "per_step_us": round(per_step * 1e6, 2),
+        "projected_sequence_s": round(per_step * (L + 3), 2), "sigma_basis_s": round(tsig, 2),
+        "projected_rank_s": round(per_step * (L + 3) + tsig, 2),
+        "step_kernel_us": [round(float(x), 3) for x in us], "step_plan": plan,
+        "roofline": {"bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM_GBS,
+                     "second_product": {"achieved": round(bytes_second / (us[1] * 1e-6) / 1e9, 1),
+                                        "frac": round(bytes_second / (us[1] * 1e-6) / 1e9 / PEAK_HBM_GBS, 4),
+                                        "avg_launch_us": round(float(us[1]), 3), "bytes_per_launch": int(bytes_second)},
+                     "first_product": {"achieved": round(bytes_first / (us[0] * 1e-6) / 1e9, 1),
+                                       "frac": round(bytes_first / (us[0] * 1e-6) / 1e9 / PEAK_HBM_GBS, 4),
+                                       "avg_launch_us": round(float(us[0]), 3), "bytes_per_launch": int(bytes_first)}},
+        "higher_is_better": True, "n_gpus": 1, "dtype": "u16" if plan["esize"] == 2 else "u32",
+        "data": "synthetic planted-rank matrix (seeded); random sequence for the sigma-basis timing",
+        "config": {"workload": f"planted {m} x {n}, rank {A.planted_rank}, {nnz / 1e6:.1f} M non-zeros, block {s}, "
+                               f"p = {p}", "m": m, "n": n, "nnz": nnz, "sequence_length": L}}), flush=True)
 
 
 def serve_mode(args):
@@ -255,6 +317,10 @@ def main():
     ap.add_argument("--serve-count", type=int, default=40)
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--serve-nmax", type=float, default=2e4)
+    ap.add_argument("--paper-scale", action="store_true",
+                    help="the 2000000 x 1000000 matrix (37 M non-zeros), block 16: kernel roofline, sequence rate "
+                         "over --paper-steps terms, device sigma-basis time at the full length")
+    ap.add_argument("--paper-steps", type=int, default=3000)
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the per-kernel timing loop at p = 65521 plus a 256 MiB device copy "
                          "(a plain copy kernel of known size, for calibrating memory counters)")
@@ -275,6 +341,8 @@ def main():
         return batch_mode(args)
     if args.serve:
         return serve_mode(args)
+    if args.paper_scale:
+        return paper_scale_mode(args)
     s = 8
     primes = (65521, 2**31 - 1)
     log("generating the planted 200000 x 150000 matrix")

@@ -80,8 +80,9 @@ typedef struct {
 /* Timings of one batched rank computation. */
 typedef struct {
     double t_encode;    /* seconds: upload, validation and encoding of every matrix */
-    double t_sequence;  /* seconds: batched sequence steps */
-    double t_sigma;     /* seconds: sigma-bases (device) of the finished jobs */
+    double t_sequence;  /* wall seconds of the batched phase: sequence steps, with the read-outs of finished
+                           jobs overlapped on a pool of host threads (one stream each) */
+    double t_sigma;     /* read-out seconds (sigma-basis, check, rank) summed over those threads */
     double t_total;     /* seconds: the whole call */
     int64_t steps;      /* batched steps (one launch per product each) */
     int32_t jobs;       /* (matrix, group of primes) jobs */

@@ -14,6 +14,7 @@
 #include "sigma.h"
 #include "sigma_gpu.h"
 #include "batch_runner.h"
+#include "readout.h"
 #include "server.h"
 #include "splitmix.h"
 
@@ -266,29 +267,6 @@ int pow2_at_most(double x, int lo, int hi) {
     int g = lo;
     while (g * 2 <= hi && g * 2 <= x) g *= 2;
     return g;
-}
-
-// Read-out of one finished (job, prime): device sigma-basis, check terms, rank.
-Error rank_of_sequence_dev(const uint32_t* S_dev, int64_t L, int64_t total, int32_t s, uint32_t p, hipStream_t st,
-                           int64_t* rank, double* t_sigma) {
-    const double t0 = now_s();
-    Generator g;
-    Error e;
-    std::vector<uint32_t> Sh((size_t)(total * s * s));
-    if (gpu_leaf_order(s) > 0 && !getenv("BWR_HOST_SIGMA")) {
-        if (!(e = gpu_min_generator(S_dev, L, s, p, st, &g)).ok()) return e;
-        hipError_t he = hipMemcpyAsync(Sh.data(), S_dev, 4 * Sh.size(), hipMemcpyDeviceToHost, st);
-        if (he == hipSuccess) he = hipStreamSynchronize(st);
-        if (he != hipSuccess) return Error::device(he, "sequence download");
-    } else {
-        hipError_t he = hipMemcpyAsync(Sh.data(), S_dev, 4 * Sh.size(), hipMemcpyDeviceToHost, st);
-        if (he == hipSuccess) he = hipStreamSynchronize(st);
-        if (he != hipSuccess) return Error::device(he, "sequence download");
-        if (!(e = min_generator(Sh.data(), L, s, p, &g)).ok()) return e;
-    }
-    *t_sigma += now_s() - t0;
-    if (!(e = check_generator(g, Sh.data(), L, total, p)).ok()) return e;
-    return rank_from_generator(g, p, rank);
 }
 
 struct BatchPlan {
@@ -657,29 +635,53 @@ int bwr_rank_modp_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* p
         }
         const double t1 = now_s();
         double t_sig = 0;
+        // read-outs of finished jobs run on a pool of host threads (one stream each), beside the sequences
+        // of the jobs still running; a job's buffers are released once all its primes are read out
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+        const size_t ntasks = owner.size() * (size_t)bp.per_job;
+        ReadoutPool pool((int)std::min<size_t>(READOUT_THREADS, std::max<size_t>(1, ntasks)), dev);
+        std::vector<int> left(owner.size(), 0);
         size_t finished = 0;
+        Error first;
         while (finished < owner.size()) {
-            std::vector<int> done;
-            if (!(e = R.advance(INT64_MAX, &done)).ok()) return fail(e);
-            if (done.empty() && R.active() == 0) break;
-            for (int id : done) {
-                const Own& o = owner[id];
-                const BatchSpec& sp = R.spec(id);
-                for (size_t t = 0; t < sp.primes.size(); ++t) {
-                    int64_t r = 0;
-                    if (!(e = rank_of_sequence_dev(R.sequence(id, (int)t), o.L, R.length(id), o.s, sp.primes[t], st, &r,
-                                                   &t_sig))
-                             .ok())
-                        return fail(e);
-                    ranks[(size_t)o.j * nprimes + o.t0 + t] = r;
+            if (R.active() > 0 && first.ok()) {
+                std::vector<int> done;
+                if (!(e = R.advance(INT64_MAX, &done)).ok()) {
+                    first = e;
+                    break;
                 }
-                R.release(id);
-                ++finished;
+                for (int id : done) {
+                    const Own& o = owner[id];
+                    const BatchSpec& sp = R.spec(id);
+                    left[id] = (int)sp.primes.size();
+                    for (size_t t = 0; t < sp.primes.size(); ++t) {
+                        hipEvent_t ev = nullptr;
+                        hipError_t he = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+                        if (he == hipSuccess) he = hipEventRecord(ev, st);
+                        if (he != hipSuccess) return fail(Error::device(he, "read-out event"));
+                        pool.submit((uint64_t)id * BATCH_MAX_PRIMES + t, R.sequence(id, (int)t), o.L, R.length(id), o.s,
+                                    sp.primes[t], ev);
+                    }
+                }
+            } else if (pool.outstanding() == 0) {
+                break;
+            }
+            for (const ReadoutPool::Result& r : pool.collect(R.active() == 0 || !first.ok())) {
+                const int id = (int)(r.tag / BATCH_MAX_PRIMES), t = (int)(r.tag % BATCH_MAX_PRIMES);
+                if (!r.err.ok() && first.ok()) first = r.err;
+                ranks[(size_t)owner[id].j * nprimes + owner[id].t0 + t] = r.rank;
+                t_sig += r.seconds;
+                if (--left[id] == 0) {
+                    R.release(id);
+                    ++finished;
+                }
             }
         }
+        if (!first.ok()) return fail(first);
         bi.steps = R.global_step();
         bi.t_sigma += t_sig;
-        bi.t_sequence += now_s() - t1 - t_sig;
+        bi.t_sequence += now_s() - t1;
     }
     std::memcpy(ranks_out, ranks.data(), sizeof(int64_t) * ranks.size());
     bi.t_total = now_s() - t0;

@@ -1,0 +1,68 @@
+// Read-out of finished sequences: sigma-basis, check on the extra terms and
+// rank (Section 2.4 and steps 3-4 of the rank algorithm in Section 2.5).  A
+// pool of host threads, each on its own device stream, runs read-outs
+// concurrently with each other and with sequences still being computed.
+// Internal C++.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "engine.h"
+
+namespace bwr {
+
+// Generator of S_dev[0 .. L) (device sigma-basis when its leaf fits in LDS, else host), checked on the
+// terms L .. total - 1, and the rank it reads out.  Runs on st; adds its seconds to *t_sigma.
+Error rank_of_sequence_dev(const uint32_t* S_dev, int64_t L, int64_t total, int32_t s, uint32_t p, hipStream_t st,
+                           int64_t* rank, double* t_sigma);
+
+// Host threads of a read-out pool: with the stream of the running batch this fills the four hardware
+// queues a process gets by default; more concurrent sigma-bases only slow each other down.
+constexpr int READOUT_THREADS = 3;
+
+class ReadoutPool {
+   public:
+    struct Result {
+        uint64_t tag = 0;
+        int64_t rank = 0;
+        double seconds = 0;
+        Error err;
+    };
+    // threads >= 1; device = the HIP device the workers use
+    ReadoutPool(int threads, int device);
+    ~ReadoutPool();
+    // Waits (on the worker's stream) for `ready` before reading S_dev; the event is owned by the pool
+    // afterwards.  S_dev must stay allocated until the task's result has been collected.
+    void submit(uint64_t tag, const uint32_t* S_dev, int64_t L, int64_t total, int32_t s, uint32_t p,
+                hipEvent_t ready);
+    // Finished tasks; with wait = true blocks until at least one is available (if any is outstanding).
+    std::vector<Result> collect(bool wait);
+    size_t outstanding();
+
+   private:
+    struct Task {
+        uint64_t tag;
+        const uint32_t* S;
+        int64_t L, total;
+        int32_t s;
+        uint32_t p;
+        hipEvent_t ready;
+    };
+    void work();
+    int device_;
+    std::mutex mu_;
+    std::condition_variable cv_, done_cv_;
+    std::deque<Task> queue_;
+    std::vector<Result> results_;
+    size_t outstanding_ = 0;
+    bool quit_ = false;
+    std::vector<std::thread> workers_;
+};
+
+}  // namespace bwr

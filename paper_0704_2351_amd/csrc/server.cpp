@@ -18,6 +18,7 @@
 
 #include "../../include/bwrank.h"
 #include "batch_runner.h"
+#include "readout.h"
 #include "server.h"
 #include "sigma.h"
 #include "sigma_gpu.h"
@@ -80,6 +81,7 @@ void Server::stop() {
         quit_ = true;
     }
     cv_.notify_all();
+    done_cv_.notify_all();
     if (worker_.joinable()) worker_.join();
     runner_.reset();
     reqs_.clear();
@@ -194,17 +196,20 @@ ServerStats Server::stats() {
 
 void Server::loop() {
     (void)hipSetDevice(device_);
-    std::vector<std::shared_ptr<Req>> active;
+    // sigma-bases and read-outs of finished sequences run on a pool of host threads (one stream each),
+    // beside the batch that keeps advancing
+    ReadoutPool pool(READOUT_THREADS, device_);
+    std::vector<std::shared_ptr<Req>> active;       // sequences in the batch
+    std::map<int, std::shared_ptr<Req>> reading;    // job id -> request being read out
     for (;;) {
         // admission at a step boundary
         {
             std::unique_lock<std::mutex> lk(mu_);
-            if (active.empty())
-                cv_.wait(lk, [&] { return quit_ || !queue_.empty(); });
+            if (active.empty() && reading.empty()) cv_.wait(lk, [&] { return quit_ || !queue_.empty(); });
             if (quit_) break;
-            while (!queue_.empty() && (int)active.size() < max_slots_) {
+            while (!queue_.empty() && (int)(active.size() + reading.size()) < max_slots_) {
                 std::shared_ptr<Req> R = reqs_[queue_.front()];
-                if (runner_->bytes_in_use() + R->footprint > budget_ && !active.empty()) break;
+                if (runner_->bytes_in_use() + R->footprint > budget_ && !(active.empty() && reading.empty())) break;
                 queue_.pop_front();
                 lk.unlock();
                 BatchSpec sp;
@@ -227,47 +232,46 @@ void Server::loop() {
                 }
                 active.push_back(R);
             }
-            max_active_ = std::max<int64_t>(max_active_, (int64_t)active.size());
+            max_active_ = std::max<int64_t>(max_active_, (int64_t)(active.size() + reading.size()));
         }
-        if (active.empty()) continue;
         const double t0 = now_s();
-        std::vector<int> fin;
-        Error e = runner_->advance(64, &fin);
-        steps_ = runner_->global_step();
-        for (int id : fin) {
-            auto it = std::find_if(active.begin(), active.end(), [&](const std::shared_ptr<Req>& r) { return r->job == id; });
-            if (it == active.end()) continue;
-            std::shared_ptr<Req> R = *it;
-            active.erase(it);
-            int64_t rank = 0;
-            Error er = e;
-            if (er.ok()) {
-                Generator g;
-                const uint32_t* S = runner_->sequence(id, 0);
-                const int64_t total = runner_->length(id);
-                std::vector<uint32_t> Sh((size_t)total * R->s * R->s);
-                if (gpu_leaf_order(R->s) > 0) er = gpu_min_generator(S, R->L, R->s, R->p, compute_, &g);
-                hipError_t he = hipMemcpyAsync(Sh.data(), S, 4 * Sh.size(), hipMemcpyDeviceToHost, compute_);
-                if (he == hipSuccess) he = hipStreamSynchronize(compute_);
-                if (er.ok() && he != hipSuccess) er = Error::device(he, "server download");
-                if (er.ok() && gpu_leaf_order(R->s) == 0) er = min_generator(Sh.data(), R->L, R->s, R->p, &g);
-                if (er.ok()) er = check_generator(g, Sh.data(), R->L, total, R->p);
-                if (er.ok()) er = rank_from_generator(g, R->p, &rank);
+        Error e;
+        if (!active.empty()) {
+            std::vector<int> fin;
+            e = runner_->advance(64, &fin);
+            steps_ = runner_->global_step();
+            for (int id : fin) {
+                auto it = std::find_if(active.begin(), active.end(),
+                                       [&](const std::shared_ptr<Req>& r) { return r->job == id; });
+                if (it == active.end()) continue;
+                std::shared_ptr<Req> R = *it;
+                active.erase(it);
+                hipEvent_t ev = nullptr;
+                hipError_t he = e.ok() ? hipEventCreateWithFlags(&ev, hipEventDisableTiming) : hipSuccess;
+                if (e.ok() && he == hipSuccess) he = hipEventRecord(ev, compute_);
+                if (!e.ok() || he != hipSuccess) {
+                    if (ev) (void)hipEventDestroy(ev);
+                    (void)hipStreamSynchronize(compute_);
+                    const Error er = e.ok() ? Error::device(he, "read-out event") : e;
+                    runner_->release(id);
+                    std::lock_guard<std::mutex> lk(mu_);
+                    R->done = true;
+                    R->code = er.code;
+                    R->msg = er.msg;
+                    R->finished = now_s();
+                    latencies_.push_back(R->finished - R->arrival);
+                    ++completed_;
+                    last_finish_ = R->finished;
+                    R->M = DeviceMatrix();
+                    done_cv_.notify_all();
+                    continue;
+                }
+                reading[id] = R;
+                pool.submit((uint64_t)id, runner_->sequence(id, 0), R->L, runner_->length(id), R->s, R->p, ev);
             }
-            runner_->release(id);
-            std::lock_guard<std::mutex> lk(mu_);
-            R->done = true;
-            R->rank = rank;
-            R->code = er.code;
-            R->msg = er.msg;
-            R->finished = now_s();
-            latencies_.push_back(R->finished - R->arrival);
-            ++completed_;
-            last_finish_ = R->finished;
-            R->M = DeviceMatrix();
-            done_cv_.notify_all();
         }
         if (!e.ok()) {
+            (void)hipStreamSynchronize(compute_);
             std::lock_guard<std::mutex> lk(mu_);
             for (auto& R : active) {
                 R->done = true;
@@ -275,6 +279,25 @@ void Server::loop() {
                 R->msg = e.msg;
             }
             active.clear();
+            done_cv_.notify_all();
+        }
+        // answer the requests whose read-out finished (wait for one when nothing else is running)
+        for (const ReadoutPool::Result& r : pool.collect(active.empty() && !reading.empty())) {
+            auto it = reading.find((int)r.tag);
+            if (it == reading.end()) continue;
+            std::shared_ptr<Req> R = it->second;
+            reading.erase(it);
+            runner_->release((int)r.tag);
+            std::lock_guard<std::mutex> lk(mu_);
+            R->done = true;
+            R->rank = r.rank;
+            R->code = r.err.code;
+            R->msg = r.err.msg;
+            R->finished = now_s();
+            latencies_.push_back(R->finished - R->arrival);
+            ++completed_;
+            last_finish_ = R->finished;
+            R->M = DeviceMatrix();
             done_cv_.notify_all();
         }
         busy_s_ += now_s() - t0;
