@@ -156,8 +156,9 @@ int bwr_rank_modp_dev(const bwr_csr* A_dev, uint32_t p, int32_t block, uint64_t 
  * the U^T projection (0 when it is fused into the second product).  If
  * plan_out is not NULL it receives the launch plan the sequence would use:
  * {block width W, row split of the first product, row split of the second,
- * projection fused (0/1), projection blocks, bytes per stored residue}
- * (row split 0 = the one-row-per-lane kernel).  For measurement; computes
+ * projection fused (0/1), projection blocks, bytes per stored residue,
+ * column passes of the first product, column passes of the second} (8
+ * int32; row split 0 = the one-row-per-lane kernel).  For measurement; computes
  * nothing the caller keeps. */
 int bwr_time_step_kernels_dev(const bwr_csr* A_dev, uint32_t p, int32_t s, int32_t transpose, int32_t iters,
                               void* stream, double* us_out, int32_t* plan_out);

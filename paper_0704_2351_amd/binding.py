@@ -267,14 +267,14 @@ def rank_modp_dev(Ad, p: int, block: int, seed: int):
 
 def time_step_kernels_dev(Ad, p: int, s: int, transpose: bool = False, iters: int = 20, with_plan: bool = False):
     """Average microseconds of [first product, second product, projection] (HIP events on torch's stream);
-    with_plan=True also returns the launch plan {W, G1, G2, fused, NB, esize}."""
+    with_plan=True also returns the launch plan {W, G1, G2, fused, NB, esize, parts1, parts2}."""
     st = _dev_csr(Ad)
     us = np.zeros(3, dtype=np.float64)
-    plan = np.zeros(6, dtype=np.int32)
+    plan = np.zeros(8, dtype=np.int32)
     _check(lib().bwr_time_step_kernels_dev(ctypes.byref(st), int(p), int(s), int(transpose), int(iters), _stream(),
                                            us.ctypes.data, plan.ctypes.data))
     if with_plan:
-        keys = ("W", "G1", "G2", "fused", "NB", "esize")
+        keys = ("W", "G1", "G2", "fused", "NB", "esize", "parts1", "parts2")
         return us, {k: int(v) for k, v in zip(keys, plan)}
     return us
 

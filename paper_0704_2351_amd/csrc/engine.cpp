@@ -196,6 +196,34 @@ void operands(const DeviceMatrix& M, bool transpose, Operand* first, Operand* se
     *second = transpose ? a : t;
 }
 
+// The two column parts of a packed operand (entries gathering from the first and the second half of
+// the block) and the carry buffer between their passes.
+struct SplitOp {
+    DevBuf rp0, rp1, ent0, ent1, carry;
+    Operand p0{}, p1{};
+    bool on = false;
+};
+
+Error build_split(const Operand& op, int64_t cols, int64_t nnz, int W, hipStream_t st, SplitOp* so) {
+    const int64_t rows = op.rows;
+    DevBuf cnt0, cnt1, tmp;
+    BWR_TRY(so->rp0.alloc(sizeof(int32_t) * (size_t)(rows + 1), st));
+    BWR_TRY(so->rp1.alloc(sizeof(int32_t) * (size_t)(rows + 1), st));
+    BWR_TRY(so->ent0.alloc(sizeof(uint32_t) * (size_t)std::max<int64_t>(nnz, 1), st));
+    BWR_TRY(so->ent1.alloc(sizeof(uint32_t) * (size_t)std::max<int64_t>(nnz, 1), st));
+    BWR_TRY(so->carry.alloc(sizeof(uint32_t) * (size_t)std::max<int64_t>(rows * W, 1), st));
+    BWR_TRY(cnt0.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(rows, 1), st));
+    BWR_TRY(cnt1.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(rows, 1), st));
+    BWR_TRY(tmp.alloc(sizeof(int32_t) * (size_t)scan_tmp_words(rows), st));
+    BWR_HIP(launch_split_operand(rows, op.rp, op.ent, (uint32_t)(cols / 2), cnt0.as<int32_t>(), cnt1.as<int32_t>(),
+                                 tmp.as<int32_t>(), so->rp0.as<int32_t>(), so->rp1.as<int32_t>(),
+                                 so->ent0.as<uint32_t>(), so->ent1.as<uint32_t>(), st));
+    so->p0 = Operand{rows, op.max_len, so->rp0.as<int32_t>(), so->ent0.as<uint32_t>(), nullptr};
+    so->p1 = Operand{rows, op.max_len, so->rp1.as<int32_t>(), so->ent1.as<uint32_t>(), nullptr};
+    so->on = true;
+    return {};
+}
+
 }  // namespace
 
 namespace {
@@ -225,6 +253,42 @@ int heuristic_g(const Operand& op, int64_t nnz, int W, bool proj) {
     return split_supported(W, g, proj) ? g : 0;
 }
 
+// First product of a step: Y = D_r (A X) (row-split kernel, in two column passes when so is set).
+hipError_t first_product(const DeviceMatrix& M, const Operand& op1, const SplitOp* so, int G, const StepPlan& pl,
+                         ModP mp, const void* X, const uint32_t* dr, void* Y, hipStream_t st) {
+    const bool smallp = mp.p <= 65536u;
+    if (so && so->on) {
+        hipError_t e = launch_spmm_split(pl.W, G, false, acc_mode(M, op1.max_len, mp.p, G), smallp, pl.esize,
+                                         op1.rows, so->p0.rp, so->p0.ent, X, nullptr, nullptr, nullptr, nullptr, 0, mp,
+                                         st, 1, so->carry.as<uint32_t>());
+        if (e != hipSuccess) return e;
+        return launch_spmm_split(pl.W, G, false, acc_mode(M, op1.max_len, mp.p, G), smallp, pl.esize, op1.rows,
+                                 so->p1.rp, so->p1.ent, X, dr, Y, nullptr, nullptr, 0, mp, st, 2,
+                                 so->carry.as<uint32_t>());
+    }
+    return launch_spmm_split(pl.W, G, false, acc_mode(M, op1.max_len, mp.p, G), smallp, pl.esize, op1.rows, op1.rp,
+                             op1.ent, X, dr, Y, nullptr, nullptr, 0, mp, st);
+}
+
+// Second product: Z = D_c^2 (A^T Y), with the projection partials when fused (nblocks persistent blocks).
+hipError_t second_product(const DeviceMatrix& M, const Operand& op2, const SplitOp* so, int G, bool fused,
+                          int nblocks, const StepPlan& pl, ModP mp, const void* Yin, const uint32_t* dc2, void* Z,
+                          const void* Ut, uint32_t* partial, hipStream_t st) {
+    const bool smallp = mp.p <= 65536u;
+    if (so && so->on) {
+        hipError_t e = launch_spmm_split(pl.W, G, false, acc_mode(M, op2.max_len, mp.p, G), smallp, pl.esize,
+                                         op2.rows, so->p0.rp, so->p0.ent, Yin, nullptr, nullptr, nullptr, nullptr, 0,
+                                         mp, st, 1, so->carry.as<uint32_t>());
+        if (e != hipSuccess) return e;
+        return launch_spmm_split(pl.W, G, fused, acc_mode(M, op2.max_len, mp.p, G), smallp, pl.esize, op2.rows,
+                                 so->p1.rp, so->p1.ent, Yin, dc2, Z, fused ? Ut : nullptr, fused ? partial : nullptr,
+                                 fused ? nblocks : 0, mp, st, 2, so->carry.as<uint32_t>());
+    }
+    return launch_spmm_split(pl.W, G, fused, acc_mode(M, op2.max_len, mp.p, G), smallp, pl.esize, op2.rows, op2.rp,
+                             op2.ent, Yin, dc2, Z, fused ? Ut : nullptr, fused ? partial : nullptr, fused ? nblocks : 0,
+                             mp, st);
+}
+
 struct Bufs {
     const uint32_t* dr;
     const uint32_t* dc2;
@@ -232,28 +296,22 @@ struct Bufs {
     void* Y;
 };
 
-Error launch_step(const DeviceMatrix& M, const Operand& op1, const Operand& op2, const StepPlan& pl, ModP mp,
-                  const Bufs& b, const void* cur, void* nxt, uint32_t* slot, hipStream_t st) {
+Error launch_step(const DeviceMatrix& M, const Operand& op1, const Operand& op2, const SplitOp* so1,
+                  const SplitOp* so2, const StepPlan& pl, ModP mp, const Bufs& b, const void* cur, void* nxt,
+                  uint32_t* slot, hipStream_t st) {
     const bool smallp = mp.p <= 65536u;
     const int64_t nb = op2.rows;
     hipError_t e;
     if (pl.G1 > 0) {
-        e = launch_spmm_split(pl.W, pl.G1, false, acc_mode(M, op1.max_len, mp.p, pl.G1), smallp, pl.esize, op1.rows, op1.rp,
-                              op1.ent, cur, b.dr, b.Y, nullptr, nullptr, 0, mp, st);
+        e = first_product(M, op1, so1, pl.G1, pl, mp, cur, b.dr, b.Y, st);
         if (e != hipSuccess) return Error::device(e, "spmm_split (first product)");
     } else {
         BWR_TRY(spmm(M, op1, pl.W, mp, (const uint32_t*)cur, b.dr, (uint32_t*)b.Y, st));
     }
-    if (pl.fused) {
-        e = launch_spmm_split(pl.W, pl.G2, true, acc_mode(M, op2.max_len, mp.p, pl.G2), smallp, pl.esize, op2.rows, op2.rp,
-                              op2.ent, b.Y, b.dc2, nxt, b.Ut, slot, pl.NB, mp, st);
-        if (e != hipSuccess) return Error::device(e, "spmm_split (second product + projection)");
-        return {};
-    }
     if (pl.G2 > 0) {
-        e = launch_spmm_split(pl.W, pl.G2, false, acc_mode(M, op2.max_len, mp.p, pl.G2), smallp, pl.esize, op2.rows, op2.rp,
-                              op2.ent, b.Y, b.dc2, nxt, nullptr, nullptr, 0, mp, st);
+        e = second_product(M, op2, so2, pl.G2, pl.fused, pl.NB, pl, mp, b.Y, b.dc2, nxt, b.Ut, slot, st);
         if (e != hipSuccess) return Error::device(e, "spmm_split (second product)");
+        if (pl.fused) return {};
     } else {
         BWR_TRY(spmm(M, op2, pl.W, mp, (const uint32_t*)b.Y, b.dc2, (uint32_t*)nxt, st));
     }
@@ -309,6 +367,11 @@ StepPlan plan_step(const DeviceMatrix& M, bool transpose, int32_t s, uint32_t p)
     }
     // 16-bit storage of the iterated blocks when every kernel of the step can read it
     pl.esize = (p <= 65536u && pl.G1 > 0 && pl.G2 > 0 && env_int("BWR_E32", 0) == 0) ? 2 : 4;
+    // column passes (32-bit residues): BWR_PARTS=2 forces two passes for both products
+    if (pl.esize == 4 && M.packed && env_int("BWR_PARTS", 1) == 2) {
+        pl.parts1 = pl.G1 > 0 && nb >= 2 ? 2 : 1;
+        pl.parts2 = pl.G2 > 0 && op1.rows >= 2 ? 2 : 1;
+    }
     if (pl.fused) {
         const int rpb = split_rows_per_block(pl.W, pl.G2);
         int64_t tiles = (nb + rpb - 1) / rpb;
@@ -396,6 +459,39 @@ Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl
         pl->NB = bestnb;
         pl->fused = bestf;
     }
+    // 32-bit residues: does running each product in two column passes (each gathering from half of the
+    // block, which then fits an XCD's L2) beat one pass?
+    if (pl->esize == 4 && M.packed && env_int("BWR_NO_PARTS", 0) == 0 && getenv("BWR_PARTS") == nullptr) {
+        SplitOp so1, so2;
+        if (pl->G1 > 0 && nb >= 2) {
+            BWR_TRY(build_split(op1, nb, M.nnz, W, st, &so1));
+            double one = 0, two = 0;
+            BWR_TRY(time_launches(3, st, [&]() -> Error {
+                hipError_t e = first_product(M, op1, nullptr, pl->G1, *pl, mp, X.as<void>(), nullptr, Y.as<void>(), st);
+                return e == hipSuccess ? Error{} : Error::device(e, "autotune");
+            }, &one));
+            BWR_TRY(time_launches(3, st, [&]() -> Error {
+                hipError_t e = first_product(M, op1, &so1, pl->G1, *pl, mp, X.as<void>(), nullptr, Y.as<void>(), st);
+                return e == hipSuccess ? Error{} : Error::device(e, "autotune");
+            }, &two));
+            pl->parts1 = two < one ? 2 : 1;
+        }
+        if (pl->G2 > 0 && outer >= 2) {
+            BWR_TRY(build_split(op2, outer, M.nnz, W, st, &so2));
+            double one = 0, two = 0;
+            auto run = [&](const SplitOp* so) -> Error {
+                hipError_t e = second_product(M, op2, so, pl->G2, pl->fused, pl->NB, *pl, mp, Y.as<void>(), nullptr,
+                                              Z.as<void>(), U.as<void>(), part.as<uint32_t>(), st);
+                if (e == hipSuccess && !pl->fused && nb > 0)
+                    e = launch_project(W, smallp, nb, U.as<void>(), Z.as<void>(), pl->esize, part.as<uint32_t>(),
+                                       pl->NB, mp, st);
+                return e == hipSuccess ? Error{} : Error::device(e, "autotune");
+            };
+            BWR_TRY(time_launches(3, st, [&]() -> Error { return run(nullptr); }, &one));
+            BWR_TRY(time_launches(3, st, [&]() -> Error { return run(&so2); }, &two));
+            pl->parts2 = two < one ? 2 : 1;
+        }
+    }
     return {};
 }
 
@@ -419,6 +515,9 @@ Error run_sequence(const SequenceArgs& a, hipStream_t st) {
     if (a.plan_out) *a.plan_out = pl;
 
     const size_t es = (size_t)pl.esize;
+    SplitOp so1, so2;
+    if (pl.parts1 == 2) BWR_TRY(build_split(op1, nb, M.nnz, W, st, &so1));
+    if (pl.parts2 == 2) BWR_TRY(build_split(op2, outer, M.nnz, W, st, &so2));
     DevBuf Ut, X0, X1, Y, dr, dc2, part, flag;
     BWR_TRY(Ut.alloc(es * (size_t)(nb * W), st));
     BWR_TRY(X0.alloc(es * (size_t)(nb * W), st));
@@ -474,7 +573,7 @@ Error run_sequence(const SequenceArgs& a, hipStream_t st) {
                     break;
                 }
                 for (int64_t i = 0; i < CH && err.ok(); ++i) {
-                    err = launch_step(M, op1, op2, pl, mp, bufs, cur, nxt, slots + per_step * (size_t)i, st);
+                    err = launch_step(M, op1, op2, &so1, &so2, pl, mp, bufs, cur, nxt, slots + per_step * (size_t)i, st);
                     std::swap(cur, nxt);
                 }
                 e = hipStreamEndCapture(st, &graph);
@@ -492,7 +591,7 @@ Error run_sequence(const SequenceArgs& a, hipStream_t st) {
             }
         } else {
             for (int64_t i = 0; i < cnt && err.ok(); ++i) {
-                err = launch_step(M, op1, op2, pl, mp, bufs, cur, nxt, slots + per_step * (size_t)i, st);
+                err = launch_step(M, op1, op2, &so1, &so2, pl, mp, bufs, cur, nxt, slots + per_step * (size_t)i, st);
                 std::swap(cur, nxt);
             }
             if (!err.ok()) break;
@@ -574,21 +673,22 @@ Error time_step_kernels(const DeviceMatrix& M, bool transpose, ModP mp, int32_t 
     BWR_HIP(launch_rng_block(12345, 2, outer, 1, 1, mp, 1, d1.as<uint32_t>(), st));
     BWR_HIP(launch_rng_block(12345, 3, nb, 1, 1, mp, 1, d2.as<uint32_t>(), st));
     const bool smallp = mp.p <= 65536u;
-    // [0] first product, [1] second product (+ projection when fused), [2] separate projection (0 when fused)
+    SplitOp so1, so2;
+    if (pl.parts1 == 2) BWR_TRY(build_split(op1, nb, M.nnz, W, st, &so1));
+    if (pl.parts2 == 2) BWR_TRY(build_split(op2, outer, M.nnz, W, st, &so2));
+    // [0] first product, [1] second product (+ projection when fused), [2] separate projection (0 when fused);
+    // a product in two column passes counts both
     BWR_TRY(time_launches(iters, st, [&]() -> Error {
         if (pl.G1 > 0) {
-            hipError_t e = launch_spmm_split(W, pl.G1, false, acc_mode(M, op1.max_len, mp.p, pl.G1), smallp, pl.esize,
-                                             op1.rows, op1.rp, op1.ent, X.as<void>(), d1.as<uint32_t>(), Y.as<void>(),
-                                             nullptr, nullptr, 0, mp, st);
+            hipError_t e = first_product(M, op1, &so1, pl.G1, pl, mp, X.as<void>(), d1.as<uint32_t>(), Y.as<void>(), st);
             return e == hipSuccess ? Error{} : Error::device(e, "spmm_split");
         }
         return spmm(M, op1, W, mp, X.as<uint32_t>(), d1.as<uint32_t>(), Y.as<uint32_t>(), st);
     }, &us[0]));
     BWR_TRY(time_launches(iters, st, [&]() -> Error {
         if (pl.G2 > 0) {
-            hipError_t e = launch_spmm_split(W, pl.G2, pl.fused, acc_mode(M, op2.max_len, mp.p, pl.G2), smallp, pl.esize,
-                                             op2.rows, op2.rp, op2.ent, Y.as<void>(), d2.as<uint32_t>(), Z.as<void>(),
-                                             U.as<void>(), part.as<uint32_t>(), pl.NB, mp, st);
+            hipError_t e = second_product(M, op2, &so2, pl.G2, pl.fused, pl.NB, pl, mp, Y.as<void>(),
+                                          d2.as<uint32_t>(), Z.as<void>(), U.as<void>(), part.as<uint32_t>(), st);
             return e == hipSuccess ? Error{} : Error::device(e, "spmm_split");
         }
         return spmm(M, op2, W, mp, Y.as<uint32_t>(), d2.as<uint32_t>(), Z.as<uint32_t>(), st);

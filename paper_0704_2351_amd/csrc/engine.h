@@ -90,6 +90,9 @@ struct StepPlan {
     bool fused = false;
     int NB = 0;
     int esize = 4;  // bytes per stored residue of the iterated blocks (2 when p <= 2^16)
+    // column parts of each product (1 or 2): with 2, the entries gathering from each half of the block
+    // run as separate passes (32-bit residues only), so that each pass gathers from a half that fits L2
+    int parts1 = 1, parts2 = 1;
 };
 
 struct SequenceArgs {

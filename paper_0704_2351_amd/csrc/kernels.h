@@ -43,6 +43,12 @@ hipError_t launch_col_count(int64_t m, const int64_t* rp64, const int32_t* col, 
 hipError_t launch_exclusive_scan(int64_t count, const int32_t* in, int32_t* out /* count + 1 */,
                                  int32_t* tmp /* >= scan_tmp_words(count) */, hipStream_t st);
 int64_t scan_tmp_words(int64_t count);
+// Column split of a packed operand (rows x cols, int32 row pointers): part 0 = entries with column < mid,
+// part 1 = the rest, each a CSR over the same rows (rp0, rp1: rows + 1 entries; cnt0, cnt1: rows; tmp:
+// scan_tmp_words(rows)).  ent0/ent1 must hold the counts the scans produce (at most nnz in all).
+hipError_t launch_split_operand(int64_t rows, const int32_t* rp, const uint32_t* ent, uint32_t mid, int32_t* cnt0,
+                                int32_t* cnt1, int32_t* tmp, int32_t* rp0, int32_t* rp1, uint32_t* ent0, uint32_t* ent1,
+                                hipStream_t st);
 hipError_t launch_scatter_packed_t(int64_t m, const int64_t* rp64, const int32_t* col, const int32_t* val,
                                    const int32_t* rpT, int32_t* cursor, uint32_t* entT, hipStream_t st);
 hipError_t launch_scatter_wide_t(int64_t m, const int64_t* rp64, const int32_t* col, const int32_t* val,
@@ -92,7 +98,10 @@ int split_rows_per_block(int W, int G);
 // X, Y, U hold esize-byte residues (2: p <= 2^16, 4: any p).  acc: 1 = int32 sums (p <= 2^16 and
 // max row length * max |a| * (p - 1) < 2^31), 2 = 16-bit halves of the residues summed in two int32
 // (p > 2^16 and ceil(max row length / G) * max |a| * 65535 < 2^31), 0 = int64 sums.
+// pass (32-bit residues only): 0 = whole rows; 1 = first column part, reduced sums to carry (nrows x W,
+// no scale, no projection); 2 = second part, carry added before the scale, store and projection.
 hipError_t launch_spmm_split(int W, int G, bool proj, int acc, bool smallp, int esize, int64_t nrows,
                              const int32_t* rp, const uint32_t* ent, const void* X, const uint32_t* scale, void* Y,
-                             const void* U, uint32_t* partial, int nblocks, ModP mp, hipStream_t st);
+                             const void* U, uint32_t* partial, int nblocks, ModP mp, hipStream_t st,
+                             int pass = 0, uint32_t* carry = nullptr);
 }  // namespace bwr

@@ -469,6 +469,33 @@ __global__ __launch_bounds__(RED_TPB) void k_reduce_partials(int W, int32_t s, i
     }
 }
 
+// Column split of a packed operand: entries with column < mid go to part 0, the others to part 1
+// (same order inside each row).
+__global__ __launch_bounds__(TPB) void k_split_count(int64_t rows, const int32_t* __restrict__ rp,
+                                                     const uint32_t* __restrict__ ent, uint32_t mid,
+                                                     int32_t* __restrict__ cnt0, int32_t* __restrict__ cnt1) {
+    const int64_t r = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (r >= rows) return;
+    int32_t c0 = 0;
+    for (int32_t t = rp[r]; t < rp[r + 1]; ++t) c0 += (ent[t] & 0xFFFFFFu) < mid ? 1 : 0;
+    cnt0[r] = c0;
+    cnt1[r] = rp[r + 1] - rp[r] - c0;
+}
+
+__global__ __launch_bounds__(TPB) void k_split_scatter(int64_t rows, const int32_t* __restrict__ rp,
+                                                       const uint32_t* __restrict__ ent, uint32_t mid,
+                                                       const int32_t* __restrict__ rp0, const int32_t* __restrict__ rp1,
+                                                       uint32_t* __restrict__ ent0, uint32_t* __restrict__ ent1) {
+    const int64_t r = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (r >= rows) return;
+    int32_t o0 = rp0[r], o1 = rp1[r];
+    for (int32_t t = rp[r]; t < rp[r + 1]; ++t) {
+        const uint32_t e = ent[t];
+        if ((e & 0xFFFFFFu) < mid) ent0[o0++] = e;
+        else ent1[o1++] = e;
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
@@ -679,6 +706,23 @@ hipError_t launch_reduce_partials(int W, int32_t s, int nblocks, int64_t nsteps,
                                   ModP mp, hipStream_t st) {
     if (nsteps <= 0 || s <= 0) return hipSuccess;
     k_reduce_partials<<<(unsigned)nsteps, RED_TPB, 0, st>>>(W, s, nblocks, partial, S, mp);
+    return hipGetLastError();
+}
+
+}  // namespace bwr
+
+namespace bwr {
+
+hipError_t launch_split_operand(int64_t rows, const int32_t* rp, const uint32_t* ent, uint32_t mid, int32_t* cnt0,
+                                int32_t* cnt1, int32_t* tmp, int32_t* rp0, int32_t* rp1, uint32_t* ent0, uint32_t* ent1,
+                                hipStream_t st) {
+    if (rows <= 0) return hipSuccess;
+    k_split_count<<<grid_for(rows, TPB), TPB, 0, st>>>(rows, rp, ent, mid, cnt0, cnt1);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = launch_exclusive_scan(rows, cnt0, rp0, tmp, st);
+    if (e == hipSuccess) e = launch_exclusive_scan(rows, cnt1, rp1, tmp, st);
+    if (e != hipSuccess) return e;
+    k_split_scatter<<<grid_for(rows, TPB), TPB, 0, st>>>(rows, rp, ent, mid, rp0, rp1, ent0, ent1);
     return hipGetLastError();
 }
 

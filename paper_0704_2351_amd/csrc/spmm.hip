@@ -76,12 +76,27 @@ __device__ __forceinline__ void loadn(const E* p, uint32_t (&x)[N]) {
     }
 }
 
-template <int W, int G, int ACC, bool SMALLP, bool PROJ, typename E>
+// acc += a * x for one residue x: int32 (ACC 1), two int32 over the 16-bit halves of x (ACC 2), or int64 (ACC 0)
+template <int ACC, typename Acc>
+__device__ __forceinline__ void mac(Acc& acc, int32_t& ah, int32_t& al, int32_t a, uint32_t x) {
+    if constexpr (ACC == 1) {
+        acc += __mul24(a, (int32_t)x);
+    } else if constexpr (ACC == 2) {
+        ah += __mul24(a, (int32_t)(x >> 16));
+        al += __mul24(a, (int32_t)(x & 0xffffu));
+    } else {
+        acc += (int64_t)a * (int64_t)x;
+    }
+}
+
+// PASS 0: one pass over the row.  PASS 1: first of two column parts: the reduced sum goes to carry (no scale,
+// no store, no projection).  PASS 2: second part: carry is added before the scale, store and projection.
+template <int W, int G, int ACC, bool SMALLP, bool PROJ, typename E, int PASS>
 __global__ __launch_bounds__(TPB) void k_spmm_split(int64_t nrows, const int32_t* __restrict__ rp,
                                                     const uint32_t* __restrict__ ent, const E* __restrict__ X,
                                                     const uint32_t* __restrict__ scale, E* __restrict__ Y,
                                                     const E* __restrict__ U, uint32_t* __restrict__ partial,
-                                                    ModP mp) {
+                                                    ModP mp, uint32_t* __restrict__ carry) {
     constexpr int CG = W / 4;
     constexpr int LPR = CG * G;
     static_assert(LPR <= 64 && 64 % LPR == 0, "row group must divide a wave");
@@ -118,6 +133,8 @@ __global__ __launch_bounds__(TPB) void k_spmm_split(int64_t nrows, const int32_t
         if (active) {
             const int32_t b = rp[row], e = rp[row + 1];
             const E* Xs = X + cg * 4;
+            // 4 entries per lane in flight, then the rest of the lane's share one by one (measured faster on
+            // the planted matrices than predicated rounds, which cost registers and occupancy)
             int32_t t = b + j;
             for (; t + 3 * G < e; t += 4 * G) {
                 uint32_t en[4];
@@ -130,16 +147,7 @@ __global__ __launch_bounds__(TPB) void k_spmm_split(int64_t nrows, const int32_t
                 for (int u = 0; u < 4; ++u) {
                     const int32_t a = (int32_t)en[u] >> 24;
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        if constexpr (ACC == 1) {
-                            acc[c] += __mul24(a, (int32_t)x[u][c]);
-                        } else if constexpr (ACC == 2) {
-                            ah[c] += __mul24(a, (int32_t)(x[u][c] >> 16));
-                            al[c] += __mul24(a, (int32_t)(x[u][c] & 0xffffu));
-                        } else {
-                            acc[c] += (int64_t)a * (int64_t)x[u][c];
-                        }
-                    }
+                    for (int c = 0; c < 4; ++c) mac<ACC>(acc[c], ah[c], al[c], a, x[u][c]);
                 }
             }
             for (; t < e; t += G) {
@@ -148,16 +156,7 @@ __global__ __launch_bounds__(TPB) void k_spmm_split(int64_t nrows, const int32_t
                 load4(Xs + (size_t)(en0 & 0xFFFFFFu) * W, x);
                 const int32_t a = (int32_t)en0 >> 24;
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    if constexpr (ACC == 1) {
-                        acc[c] += __mul24(a, (int32_t)x[c]);
-                    } else if constexpr (ACC == 2) {
-                        ah[c] += __mul24(a, (int32_t)(x[c] >> 16));
-                        al[c] += __mul24(a, (int32_t)(x[c] & 0xffffu));
-                    } else {
-                        acc[c] += (int64_t)a * (int64_t)x[c];
-                    }
-                }
+                for (int c = 0; c < 4; ++c) mac<ACC>(acc[c], ah[c], al[c], a, x[c]);
             }
         }
         if constexpr (ACC == 2) {
@@ -169,12 +168,23 @@ __global__ __launch_bounds__(TPB) void k_spmm_split(int64_t nrows, const int32_t
         for (int off = CG; off < LPR; off <<= 1)
 #pragma unroll
             for (int c = 0; c < 4; ++c) acc[c] += shfl_xor_acc(acc[c], off);
+        if (PASS == 1) {
+            if (active && j == 0) {
+                uint32_t r[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) r[c] = ACC32 ? reds32(mp, (int32_t)acc[c]) : reds64(mp, (int64_t)acc[c]);
+                store4(carry + (size_t)row * W + cg * 4, r);
+            }
+            continue;
+        }
         if (active) {
             const uint32_t sc = scale ? scale[row] : 1u;
-            uint32_t y[4];
+            uint32_t y[4], cin[4] = {0, 0, 0, 0};
+            if (PASS == 2) load4(carry + (size_t)row * W + cg * 4, cin);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const uint32_t r = ACC32 ? reds32(mp, (int32_t)acc[c]) : reds64(mp, (int64_t)acc[c]);
+                uint32_t r = ACC32 ? reds32(mp, (int32_t)acc[c]) : reds64(mp, (int64_t)acc[c]);
+                if (PASS == 2) r = addmod(mp, r, cin[c]);
                 y[c] = SMALLP ? mulmod16(mp, r, sc) : mulmod(mp, r, sc);
             }
             if (j == 0) store4(Y + (size_t)row * W + cg * 4, y);
@@ -240,54 +250,66 @@ struct Args {
     const void* U;
     uint32_t* partial;
     ModP mp;
+    uint32_t* carry;
 };
 
-template <int W, int G, bool PROJ, typename E>
-hipError_t launch_wge(int acc, bool smallp, unsigned grid, const Args& a, hipStream_t st) {
+template <int W, int G, bool PROJ, typename E, int PASS>
+hipError_t launch_wgep(int acc, bool smallp, unsigned grid, const Args& a, hipStream_t st) {
     const E* X = (const E*)a.X;
     E* Y = (E*)a.Y;
     const E* U = (const E*)a.U;
     if (acc == 1)
-        k_spmm_split<W, G, 1, true, PROJ, E><<<grid, TPB, 0, st>>>(a.nrows, a.rp, a.ent, X, a.scale, Y, U, a.partial,
-                                                                 a.mp);
+        k_spmm_split<W, G, 1, true, PROJ, E, PASS><<<grid, TPB, 0, st>>>(a.nrows, a.rp, a.ent, X, a.scale, Y, U,
+                                                                       a.partial, a.mp, a.carry);
     else if (smallp)
-        k_spmm_split<W, G, 0, true, PROJ, E><<<grid, TPB, 0, st>>>(a.nrows, a.rp, a.ent, X, a.scale, Y, U, a.partial,
-                                                                 a.mp);
+        k_spmm_split<W, G, 0, true, PROJ, E, PASS><<<grid, TPB, 0, st>>>(a.nrows, a.rp, a.ent, X, a.scale, Y, U,
+                                                                       a.partial, a.mp, a.carry);
     else if (acc == 2)
-        k_spmm_split<W, G, 2, false, PROJ, E><<<grid, TPB, 0, st>>>(a.nrows, a.rp, a.ent, X, a.scale, Y, U, a.partial,
-                                                                  a.mp);
+        k_spmm_split<W, G, 2, false, PROJ, E, PASS><<<grid, TPB, 0, st>>>(a.nrows, a.rp, a.ent, X, a.scale, Y, U,
+                                                                        a.partial, a.mp, a.carry);
     else
-        k_spmm_split<W, G, 0, false, PROJ, E><<<grid, TPB, 0, st>>>(a.nrows, a.rp, a.ent, X, a.scale, Y, U, a.partial,
-                                                                  a.mp);
+        k_spmm_split<W, G, 0, false, PROJ, E, PASS><<<grid, TPB, 0, st>>>(a.nrows, a.rp, a.ent, X, a.scale, Y, U,
+                                                                        a.partial, a.mp, a.carry);
     return hipGetLastError();
 }
 
 template <int W, int G, bool PROJ>
-hipError_t launch_wg(int acc, bool smallp, int esize, unsigned grid, const Args& a, hipStream_t st) {
-    if (esize == 2) return launch_wge<W, G, PROJ, uint16_t>(acc, true, grid, a, st);
-    return launch_wge<W, G, PROJ, uint32_t>(acc, smallp, grid, a, st);
+hipError_t launch_wg(int acc, bool smallp, int esize, int pass, unsigned grid, const Args& a, hipStream_t st) {
+    if (esize == 2) {
+        if (pass != 0) return hipErrorInvalidValue;  // column parts are for 32-bit residues only
+        return launch_wgep<W, G, PROJ, uint16_t, 0>(acc, true, grid, a, st);
+    }
+    if (pass == 1) {
+        if constexpr (!PROJ) return launch_wgep<W, G, false, uint32_t, 1>(acc, smallp, grid, a, st);
+        return hipErrorInvalidValue;
+    }
+    if (pass == 2) return launch_wgep<W, G, PROJ, uint32_t, 2>(acc, smallp, grid, a, st);
+    return launch_wgep<W, G, PROJ, uint32_t, 0>(acc, smallp, grid, a, st);
 }
 
 template <int W, int G>
-hipError_t launch_g(bool proj, int acc, bool smallp, int esize, unsigned grid, const Args& a, hipStream_t st) {
+hipError_t launch_g(bool proj, int acc, bool smallp, int esize, int pass, unsigned grid, const Args& a,
+                    hipStream_t st) {
     if constexpr ((W / 4) * G <= 64) {
         if (proj) {
-            if constexpr (W % G == 0 && W / G <= 4) return launch_wg<W, G, true>(acc, smallp, esize, grid, a, st);
+            if constexpr (W % G == 0 && W / G <= 4)
+                return launch_wg<W, G, true>(acc, smallp, esize, pass, grid, a, st);
             return hipErrorInvalidValue;
         }
-        return launch_wg<W, G, false>(acc, smallp, esize, grid, a, st);
+        return launch_wg<W, G, false>(acc, smallp, esize, pass, grid, a, st);
     }
     return hipErrorInvalidValue;
 }
 
 template <int W>
-hipError_t launch_w(int G, bool proj, int acc, bool smallp, int esize, unsigned grid, const Args& a, hipStream_t st) {
+hipError_t launch_w(int G, bool proj, int acc, bool smallp, int esize, int pass, unsigned grid, const Args& a,
+                    hipStream_t st) {
     switch (G) {
-        case 1: return launch_g<W, 1>(proj, acc, smallp, esize, grid, a, st);
-        case 2: return launch_g<W, 2>(proj, acc, smallp, esize, grid, a, st);
-        case 4: return launch_g<W, 4>(proj, acc, smallp, esize, grid, a, st);
-        case 8: return launch_g<W, 8>(proj, acc, smallp, esize, grid, a, st);
-        case 16: return launch_g<W, 16>(proj, acc, smallp, esize, grid, a, st);
+        case 1: return launch_g<W, 1>(proj, acc, smallp, esize, pass, grid, a, st);
+        case 2: return launch_g<W, 2>(proj, acc, smallp, esize, pass, grid, a, st);
+        case 4: return launch_g<W, 4>(proj, acc, smallp, esize, pass, grid, a, st);
+        case 8: return launch_g<W, 8>(proj, acc, smallp, esize, pass, grid, a, st);
+        case 16: return launch_g<W, 16>(proj, acc, smallp, esize, pass, grid, a, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -305,22 +327,24 @@ int split_rows_per_block(int W, int G) { return (TPB / 64) * (64 / ((W / 4) * G)
 
 hipError_t launch_spmm_split(int W, int G, bool proj, int acc, bool smallp, int esize, int64_t nrows,
                              const int32_t* rp, const uint32_t* ent, const void* X, const uint32_t* scale, void* Y,
-                             const void* U, uint32_t* partial, int nblocks, ModP mp, hipStream_t st) {
+                             const void* U, uint32_t* partial, int nblocks, ModP mp, hipStream_t st, int pass,
+                             uint32_t* carry) {
     if (!split_supported(W, G, proj) || (acc == 1 && !smallp) || (acc == 2 && smallp) || acc < 0 || acc > 2 ||
-        (esize == 2 && !smallp) || (esize != 2 && esize != 4))
+        (esize == 2 && !smallp) || (esize != 2 && esize != 4) || pass < 0 || pass > 2 || (pass && !carry) ||
+        (pass == 1 && proj))
         return hipErrorInvalidValue;
     const int rpb = split_rows_per_block(W, G);
     int64_t tiles = (nrows + rpb - 1) / rpb;
     if (tiles < 1) tiles = 1;
     unsigned grid = proj ? (unsigned)nblocks : (unsigned)tiles;
     if (grid < 1) grid = 1;
-    const Args a{nrows, rp, ent, X, scale, Y, U, partial, mp};
+    const Args a{nrows, rp, ent, X, scale, Y, U, partial, mp, carry};
     switch (W) {
-        case 4: return launch_w<4>(G, proj, acc, smallp, esize, grid, a, st);
-        case 8: return launch_w<8>(G, proj, acc, smallp, esize, grid, a, st);
-        case 16: return launch_w<16>(G, proj, acc, smallp, esize, grid, a, st);
-        case 32: return launch_w<32>(G, proj, acc, smallp, esize, grid, a, st);
-        case 64: return launch_w<64>(G, proj, acc, smallp, esize, grid, a, st);
+        case 4: return launch_w<4>(G, proj, acc, smallp, esize, pass, grid, a, st);
+        case 8: return launch_w<8>(G, proj, acc, smallp, esize, pass, grid, a, st);
+        case 16: return launch_w<16>(G, proj, acc, smallp, esize, pass, grid, a, st);
+        case 32: return launch_w<32>(G, proj, acc, smallp, esize, pass, grid, a, st);
+        case 64: return launch_w<64>(G, proj, acc, smallp, esize, pass, grid, a, st);
         default: return hipErrorInvalidValue;
     }
 }

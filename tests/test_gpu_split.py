@@ -68,3 +68,25 @@ def test_graph_and_stream_paths_agree(graph, monkeypatch):
     got = bw.sequence(A, U, V, p, 1100, dr, dc)
     want = oseq.sequence(A, U, V, p, 1100, dr, dc)
     assert np.array_equal(got.astype(np.int64), want)
+
+
+@pytest.mark.parametrize("s,g", [(3, 1), (8, 2), (8, 4), (16, 4), (32, 1)])
+@pytest.mark.parametrize("p,e32", [(2**31 - 1, "0"), (65537, "0"), (65521, "1")])
+def test_two_column_passes(s, g, p, e32, monkeypatch):
+    """Both products in two passes over the column halves (32-bit residues): same terms as the oracle,
+    on rows of very different lengths, wide and tall shapes."""
+    need_gpu()
+    announce(f"column passes s={s} G={g} p={p} e32={e32}")
+    monkeypatch.setenv("BWR_PARTS", "2")
+    monkeypatch.setenv("BWR_G1", str(g))
+    monkeypatch.setenv("BWR_G2", str(g))
+    monkeypatch.setenv("BWR_E32", e32)
+    for (m, n, seed) in ((700, 300, s + g), (301, 500, 7 * s + g)):
+        A = skewed_matrix(m, n, seed)
+        rng = np.random.default_rng(seed)
+        U, V = blocks(rng, A.n, s, p)
+        dr = rng.integers(1, p, size=A.m)
+        dc = rng.integers(1, p, size=A.n)
+        got = bw.sequence(A, U, V, p, 7, dr, dc)
+        want = oseq.sequence(A, U, V, p, 7, dr, dc)
+        assert np.array_equal(got.astype(np.int64), want), (m, n)
