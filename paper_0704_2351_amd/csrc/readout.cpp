@@ -40,6 +40,7 @@ Error rank_of_sequence_dev(const uint32_t* S_dev, int64_t L, int64_t total, int3
 }
 
 ReadoutPool::ReadoutPool(int threads, int device) : device_(device) {
+    if (const char* v = getenv("BWR_READOUT_THREADS")) threads = std::max(1, atoi(v));
     for (int i = 0; i < std::max(1, threads); ++i) workers_.emplace_back([this] { work(); });
 }
 

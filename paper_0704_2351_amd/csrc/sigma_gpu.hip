@@ -240,6 +240,58 @@ __global__ __launch_bounds__(TPB) void k_crt(const uint32_t* __restrict__ C, int
     out[idx] = v;
 }
 
+// Same product with a 4 x 4 tile of (i, l) per thread and transform point: per inner index j the thread
+// loads 4 values of A and 4 of B for 16 products (instead of 9 loads for 8), summed in 64 bits and
+// reduced every 3 terms (3 (q - 1)^2 + q < 2^64 for q < 2^31).
+constexpr int PW_TILE = 4;
+__global__ __launch_bounds__(TPB) void k_pointwise_tiled(const uint32_t* __restrict__ A,
+                                                         const uint32_t* __restrict__ B, uint32_t* __restrict__ C,
+                                                         int r, int k, int c, int64_t N, int T, NttConsts cs) {
+    const int rt = (r + PW_TILE - 1) / PW_TILE, ct = (c + PW_TILE - 1) / PW_TILE;
+    const int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (idx >= (int64_t)T * rt * ct * N) return;
+    const int64_t x = idx % N;
+    int64_t rest = idx / N;
+    const int lt = (int)(rest % ct);
+    rest /= ct;
+    const int it = (int)(rest % rt);
+    const int t = (int)(rest / rt);
+    const ModP mq = cs.mq[t];
+    const uint32_t* At = A + (size_t)t * r * k * N;
+    const uint32_t* Bt = B + (size_t)t * k * c * N;
+    const int i0 = it * PW_TILE, l0 = lt * PW_TILE;
+    uint64_t acc[PW_TILE][PW_TILE];
+#pragma unroll
+    for (int a = 0; a < PW_TILE; ++a)
+#pragma unroll
+        for (int b = 0; b < PW_TILE; ++b) acc[a][b] = 0;
+    int pending = 0;
+    for (int j = 0; j < k; ++j) {
+        uint64_t av[PW_TILE], bv[PW_TILE];
+#pragma unroll
+        for (int a = 0; a < PW_TILE; ++a) av[a] = i0 + a < r ? At[((size_t)(i0 + a) * k + j) * N + x] : 0u;
+#pragma unroll
+        for (int b = 0; b < PW_TILE; ++b) bv[b] = l0 + b < c ? Bt[((size_t)j * c + l0 + b) * N + x] : 0u;
+#pragma unroll
+        for (int a = 0; a < PW_TILE; ++a)
+#pragma unroll
+            for (int b = 0; b < PW_TILE; ++b) acc[a][b] += av[a] * bv[b];
+        if (++pending == 3) {
+            pending = 0;
+#pragma unroll
+            for (int a = 0; a < PW_TILE; ++a)
+#pragma unroll
+                for (int b = 0; b < PW_TILE; ++b) acc[a][b] = red64(mq, acc[a][b]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < PW_TILE; ++a)
+#pragma unroll
+        for (int b = 0; b < PW_TILE; ++b)
+            if (i0 + a < r && l0 + b < c)
+                C[((size_t)t * r * c + (size_t)(i0 + a) * c + l0 + b) * N + x] = red64(mq, acc[a][b]);
+}
+
 // ------------------------------------------------------------------ schoolbook window product mod p
 __global__ __launch_bounds__(TPB) void k_schoolbook(const uint32_t* __restrict__ A, int64_t lenA,
                                                     const uint32_t* __restrict__ B, int64_t lenB, int r, int k, int c,
@@ -263,6 +315,46 @@ __global__ __launch_bounds__(TPB) void k_schoolbook(const uint32_t* __restrict__
         }
     }
     out[idx] = addmod(mp, red64(mp, acc_lo), mulmod(mp, red64(mp, acc_hi), red64(mp, (uint64_t)1 << 32)));
+}
+
+// Schoolbook window product with the operands in LDS: one workgroup per (output row i, group of SB_COLS
+// output columns) loads A[i][.] and B[.][columns] once, then each thread forms output coefficients from LDS.
+constexpr int SB_COLS = 8;
+__global__ __launch_bounds__(TPB) void k_schoolbook_lds(const uint32_t* __restrict__ A, int64_t lenA,
+                                                        const uint32_t* __restrict__ B, int64_t lenB, int r, int k,
+                                                        int c, int64_t lo, int64_t W, ModP mp,
+                                                        uint32_t* __restrict__ out) {
+    extern __shared__ uint32_t lds[];
+    const int groups = (c + SB_COLS - 1) / SB_COLS;
+    const int i = blockIdx.x / groups, l0 = (blockIdx.x % groups) * SB_COLS;
+    const int nl = c - l0 < SB_COLS ? c - l0 : SB_COLS;
+    uint32_t* As = lds;                      // [k][lenA]
+    uint32_t* Bs = lds + (size_t)k * lenA;   // [k][nl][lenB]
+    for (int64_t e = threadIdx.x; e < (int64_t)k * lenA; e += TPB) As[e] = A[(size_t)i * k * lenA + e];
+    for (int64_t e = threadIdx.x; e < (int64_t)k * nl * lenB; e += TPB) {
+        const int64_t j = e / (nl * lenB), rem = e % (nl * lenB);
+        Bs[e] = B[((size_t)j * c + l0) * lenB + rem];
+    }
+    __syncthreads();
+    const uint32_t r32 = red64(mp, (uint64_t)1 << 32);
+    for (int64_t o = threadIdx.x; o < (int64_t)nl * W; o += TPB) {
+        const int l = (int)(o / W);
+        const int64_t x = o % W + lo;
+        int64_t t0 = x - (lenB - 1);
+        if (t0 < 0) t0 = 0;
+        const int64_t t1 = x < lenA - 1 ? x : lenA - 1;
+        uint64_t acc_lo = 0, acc_hi = 0;
+        for (int j = 0; j < k; ++j) {
+            const uint32_t* a = As + (size_t)j * lenA;
+            const uint32_t* b = Bs + ((size_t)j * nl + l) * lenB;
+            for (int64_t t = t0; t <= t1; ++t) {
+                const uint64_t pr = (uint64_t)a[t] * b[x - t];
+                acc_lo += pr & 0xffffffffu;
+                acc_hi += pr >> 32;
+            }
+        }
+        out[((size_t)i * c + l0 + l) * W + (x - lo)] = addmod(mp, red64(mp, acc_lo), mulmod(mp, red64(mp, acc_hi), r32));
+    }
 }
 
 // ------------------------------------------------------------------ M-Basis leaf
@@ -791,8 +883,8 @@ hipError_t gpu_ntt(uint32_t* a, int lg, int nb, int T, const NttConsts& c, const
 
 hipError_t gpu_pointwise(const uint32_t* A, const uint32_t* B, uint32_t* C, int r, int k, int c, int64_t N, int T,
                          const NttConsts& cs, hipStream_t st) {
-    int64_t total = (int64_t)T * r * ((c + PW_COLS - 1) / PW_COLS) * N;
-    k_pointwise<<<grid_for(total, TPB), TPB, 0, st>>>(A, B, C, r, k, c, N, T, cs);
+    const int64_t tiles = (int64_t)T * ((r + PW_TILE - 1) / PW_TILE) * ((c + PW_TILE - 1) / PW_TILE) * N;
+    k_pointwise_tiled<<<grid_for(tiles, TPB), TPB, 0, st>>>(A, B, C, r, k, c, N, T, cs);
     return hipGetLastError();
 }
 
@@ -804,6 +896,13 @@ hipError_t gpu_crt(const uint32_t* C, int npoly, int64_t N, int64_t lo, int64_t 
 
 hipError_t gpu_schoolbook(const uint32_t* A, int64_t lenA, const uint32_t* B, int64_t lenB, int r, int k, int c,
                           int64_t lo, int64_t W, ModP mp, uint32_t* out, hipStream_t st) {
+    const int nl = c < SB_COLS ? c : SB_COLS;
+    const size_t lds = sizeof(uint32_t) * ((size_t)k * lenA + (size_t)k * nl * lenB);
+    if (lds <= 48 * 1024 && r > 0 && c > 0 && W > 0) {
+        const unsigned grid = (unsigned)r * (unsigned)((c + SB_COLS - 1) / SB_COLS);
+        k_schoolbook_lds<<<grid, TPB, lds, st>>>(A, lenA, B, lenB, r, k, c, lo, W, mp, out);
+        return hipGetLastError();
+    }
     k_schoolbook<<<grid_for((int64_t)r * c * W, TPB), TPB, 0, st>>>(A, lenA, B, lenB, r, k, c, lo, W, mp, out);
     return hipGetLastError();
 }
