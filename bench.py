@@ -73,24 +73,28 @@ def cpu_baseline(A, p, s, target_s=15.0):
                       f"block, then U^T W mod {p}) on the same matrix, {el:.1f} s single-threaded"}
 
 
-def kernel_traffic(kernel_name):
-    """HBM bytes per launch of `kernel_name` from the committed counter summary, or None when the
-    summary is missing or was taken on another revision of the kernel source."""
+def kernel_traffic(W, G, esize, fused, kpass=0):
+    """HBM bytes per launch of the row-split kernel instantiation <W, G, *, esize == 2, fused, residue
+    type, kpass> from the committed counter summary, or None when the summary is missing, was taken on
+    another revision of the kernel source, or does not hold that instantiation."""
     import hashlib
+    import re
 
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    src = os.path.join(ROOT, "paper_0704_2351_amd", "csrc", "spmm.hip")
     try:
         with open(path) as f:
             rec = json.load(f)
-        with open(src, "rb") as f:
+        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
             digest = hashlib.sha256(f.read()).hexdigest()
-    except OSError:
+    except (OSError, KeyError, ValueError):
         return None
-    ent = rec.get("kernels", {}).get(kernel_name)
-    if not ent or ent.get("source_sha256") != digest:
+    if rec.get("source_sha256") != digest:
         return None
-    return ent.get("bytes_per_launch")
+    etype = "unsigned short" if esize == 2 else "unsigned int"
+    pat = re.compile(rf"k_spmm_split<{W}, {G}, \d, {str(esize == 2).lower()}, {str(bool(fused)).lower()}, "
+                     rf"{etype}, {kpass}>$")
+    hits = [v for k, v in rec.get("kernels", {}).items() if pat.match(k)]
+    return hits[0].get("bytes_per_launch") if len(hits) == 1 else None
 
 
 def roofline_entry(A, s, p, us, plan):
@@ -101,11 +105,10 @@ def roofline_entry(A, s, p, us, plan):
     m, n, nnz = A.m, A.n, A.nnz
     bytes_second = 4 * (n + 1) + 5 * nnz + 4 * s * (m + n)
     bytes_first = 4 * (m + 1) + 5 * nnz + 4 * s * (n + m)
-    name = "spmm_second_fused" if plan["fused"] else "spmm_second"
     ach = bytes_second / (us[1] * 1e-6) / 1e9
     ach1 = bytes_first / (us[0] * 1e-6) / 1e9
     return {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": kernel_traffic(name),
+            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": kernel_traffic(plan["W"], plan["G2"], plan["esize"], plan["fused"]),
             "kernel": f"k_spmm_split (second product: A^T Y, column scale, projection fused={bool(plan['fused'])}, "
                       f"W={plan['W']}, G={plan['G2']}, {plan['esize']}-byte residues), p = {p}",
             "avg_launch_us": round(us[1], 3), "bytes_per_launch": int(bytes_second),

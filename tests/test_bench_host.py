@@ -37,18 +37,33 @@ def test_result_line_contract():
 
 
 def test_traffic_is_null_without_matching_summary(tmp_path, monkeypatch):
+    import hashlib
+
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.kernel_traffic("spmm_second_fused") is None
+    assert bench.kernel_traffic(8, 4, 2, True) is None
     (tmp_path / "profiles").mkdir()
     (tmp_path / "paper_0704_2351_amd" / "csrc").mkdir(parents=True)
     (tmp_path / "paper_0704_2351_amd" / "csrc" / "spmm.hip").write_text("kernel v2")
-    rec = {"kernels": {"spmm_second_fused": {"source_sha256": "0" * 64, "bytes_per_launch": 123}}}
+    name16 = "k_spmm_split<8, 4, 1, true, true, unsigned short, 0>"
+    name32 = "k_spmm_split<8, 4, 2, false, true, unsigned int, 0>"
+    rec = {"source": "paper_0704_2351_amd/csrc/spmm.hip", "source_sha256": "0" * 64,
+           "kernels": {name16: {"bytes_per_launch": 123}, name32: {"bytes_per_launch": 456}}}
     (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(rec))
-    assert bench.kernel_traffic("spmm_second_fused") is None
-    import hashlib
-    rec["kernels"]["spmm_second_fused"]["source_sha256"] = hashlib.sha256(b"kernel v2").hexdigest()
+    assert bench.kernel_traffic(8, 4, 2, True) is None  # another revision of the source
+    rec["source_sha256"] = hashlib.sha256(b"kernel v2").hexdigest()
     (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(rec))
-    assert bench.kernel_traffic("spmm_second_fused") == 123
+    assert bench.kernel_traffic(8, 4, 2, True) == 123
+    assert bench.kernel_traffic(8, 4, 4, True) == 456
+    assert bench.kernel_traffic(8, 8, 2, True) is None  # instantiation not measured
+    assert bench.kernel_traffic(8, 4, 2, False) is None
+
+
+def test_committed_traffic_record_matches_source():
+    """The committed counter summary belongs to the current kernel source and holds the instantiations
+    the autotuner picks on the 200000 x 150000 workload at p = 65521."""
+    rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+    assert bench.kernel_traffic(8, 4, 2, True) == rec["kernels"][
+        "k_spmm_split<8, 4, 1, true, true, unsigned short, 0>"]["bytes_per_launch"]
 
 
 def test_more_than_one_gpu_is_refused():
