@@ -71,7 +71,11 @@ typedef struct {
     int64_t sum_delta;    /* sum of the generator's row degrees */
     double t_encode;      /* seconds: validation and device encoding of A */
     double t_sequence;    /* seconds: the L + check terms on the device */
-    double t_sigma;       /* seconds: sigma-basis (on the device when its leaf fits in LDS, s <= 32; else host) */
+    double t_sigma;       /* seconds from the end of the sequence to the generator.  On the device when its
+                           * leaf fits in LDS (s <= 32), else on the host.  On the device and for L >= 4096
+                           * the basis of the earlier orders is computed on a second stream while the
+                           * sequence runs (BWR_SIGMA_MIN_CHUNK sets its smallest chunk, 0 disables), so
+                           * only the last chunks count here. */
     double t_readout;     /* seconds: check and read-out */
     int32_t sigma_threads;
     int32_t pad;

@@ -70,10 +70,11 @@ Error check_prime(uint32_t p) {
     return {};
 }
 
-// One library stream per device for the host-pointer entry points.
-// One non-blocking library stream per (host thread, device): calls made from different host threads run
-// concurrently on the device (e.g. one prime's sigma-basis beside another prime's sequence).
-hipStream_t lib_stream(Error* err) {
+// Library streams of the calling host thread on the current device: stream 0 runs an entry point's work,
+// stream 1 the sigma-basis that runs beside a rank computation's sequence.  They are non-blocking and per
+// (host thread, device), so calls made from different host threads run concurrently on the device (e.g.
+// one prime's sigma-basis beside another prime's sequence).
+hipStream_t lib_stream(Error* err, int which = 0) {
     thread_local std::vector<hipStream_t> streams;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -81,10 +82,12 @@ hipStream_t lib_stream(Error* err) {
         *err = Error::device(e, "hipGetDevice");
         return nullptr;
     }
-    if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
-    if (!streams[dev]) {
-        e = hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking);
+    const size_t slot = (size_t)dev * 2 + (which ? 1 : 0);
+    if (streams.size() <= slot) streams.resize(slot + 1, nullptr);
+    if (!streams[slot]) {
+        e = hipStreamCreateWithFlags(&streams[slot], hipStreamNonBlocking);
         if (e != hipSuccess) {
+            streams[slot] = nullptr;
             *err = Error::device(e, "hipStreamCreate");
             return nullptr;
         }
@@ -97,7 +100,14 @@ hipStream_t lib_stream(Error* err) {
             (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
         }
     }
-    return streams[dev];
+    return streams[slot];
+}
+
+// Smallest chunk of the sigma-basis that runs beside the sequence (OnlineGenerator) for a sequence of
+// L terms; 0 runs it after the sequence.  BWR_SIGMA_MIN_CHUNK overrides (0 = after the sequence).
+int64_t online_min_chunk(int64_t L) {
+    if (const char* v = getenv("BWR_SIGMA_MIN_CHUNK")) return std::max<int64_t>(0, atoll(v));
+    return L >= 4096 ? std::max<int64_t>(1024, L / 8) : 0;
 }
 
 // Device entry points run on the library stream (which sequence capture needs:
@@ -179,6 +189,14 @@ struct RankOut {
 
 constexpr int64_t CHECK_TERMS = 4;
 
+// Waits for a stream's work at scope exit (so that buffers it reads outlive it on every return path).
+struct StreamDrain {
+    hipStream_t st = nullptr;
+    ~StreamDrain() {
+        if (st) (void)hipStreamSynchronize(st);
+    }
+};
+
 Error rank_dev_impl(const CsrView& A, uint32_t p, int32_t block, uint64_t seed, hipStream_t st, RankOut* out) {
     Error e = check_prime(p);
     if (!e.ok()) return e;
@@ -202,6 +220,8 @@ Error rank_dev_impl(const CsrView& A, uint32_t p, int32_t block, uint64_t seed, 
     const int32_t s = (int32_t)std::min<int64_t>(block, nb);
     const int64_t L = 2 + (2 * nb + s - 1) / s;
     const int64_t total = L + CHECK_TERMS;
+    const bool on_device = gpu_leaf_order(s) > 0 && !getenv("BWR_HOST_SIGMA");
+    const int64_t min_chunk = on_device ? online_min_chunk(L) : 0;
     info.s = s;
     info.len = L;
     info.check_terms = CHECK_TERMS;
@@ -228,6 +248,28 @@ Error rank_dev_impl(const CsrView& A, uint32_t p, int32_t block, uint64_t seed, 
     a.V = V.as<uint32_t>();
     a.len = total;
     a.S_out = S.as<uint32_t>();
+    // device sigma-basis: its chunks run on stream 1 as the terms they need are reduced
+    StreamDrain drain;  // declared first so that it runs after og's destructor has joined og's thread
+    OnlineGenerator og;
+    if (min_chunk > 0) {
+        hipStream_t sst = lib_stream(&e, 1);
+        if (!e.ok()) return e;
+        drain.st = sst;
+        if (!(e = og.begin(S.as<uint32_t>(), L, s, p, min_chunk, sst)).ok()) return e;
+        a.progress = [&](int64_t t) -> Error {
+            const int64_t next = og.next_boundary();
+            if (next < 0 || t < next) return {};
+            hipEvent_t ev = nullptr;
+            hipError_t r = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (r == hipSuccess) r = hipEventRecord(ev, st);
+            if (r != hipSuccess) {
+                if (ev) (void)hipEventDestroy(ev);
+                return Error::device(r, "hipEventRecord");
+            }
+            og.feed_async(t, ev);
+            return {};
+        };
+    }
     const double t1 = now_s();
     if (!(e = run_sequence(a, st)).ok()) return e;
     he = hipStreamSynchronize(st);
@@ -236,9 +278,14 @@ Error rank_dev_impl(const CsrView& A, uint32_t p, int32_t block, uint64_t seed, 
     info.t_sequence = t2 - t1;
     Generator g;
     SigmaStats ss;
-    const bool on_device = gpu_leaf_order(s) > 0 && !getenv("BWR_HOST_SIGMA");
     std::vector<uint32_t> Sh((size_t)(total * s * s));
-    if (on_device) {
+    if (on_device && min_chunk > 0) {
+        og.feed_async(L, nullptr);
+        if (!(e = og.finish(&g)).ok()) return e;
+        he = hipMemcpyAsync(Sh.data(), S.as<void>(), sizeof(uint32_t) * Sh.size(), hipMemcpyDeviceToHost, st);
+        if (he == hipSuccess) he = hipStreamSynchronize(st);
+        if (he != hipSuccess) return Error::device(he, "sequence download");
+    } else if (on_device) {
         if (!(e = gpu_min_generator(S.as<uint32_t>(), L, s, p, st, &g, &ss)).ok()) return e;
         he = hipMemcpyAsync(Sh.data(), S.as<void>(), sizeof(uint32_t) * Sh.size(), hipMemcpyDeviceToHost, st);
         if (he == hipSuccess) he = hipStreamSynchronize(st);
@@ -700,7 +747,11 @@ int bwr_min_generator_dev(const uint32_t* S_dev, int64_t len, int32_t s, uint32_
     hipStream_t st = work_stream(stream, &e);
     if (!e.ok()) return fail(e);
     Generator g;
-    if (!(e = gpu_min_generator(S_dev, len, s, p, st, &g)).ok()) return fail(e);
+    // the whole sequence is there, so the basis is one PM-Basis call unless BWR_SIGMA_MIN_CHUNK asks for
+    // the chunked order of the online generator (same result)
+    int64_t mc = 0;
+    if (const char* v = getenv("BWR_SIGMA_MIN_CHUNK")) mc = std::max<int64_t>(0, atoll(v));
+    if (!(e = gpu_min_generator(S_dev, len, s, p, st, &g, nullptr, mc)).ok()) return fail(e);
     int64_t maxd = 0;
     for (int64_t x : g.delta) maxd = std::max(maxd, x);
     if (maxd + 1 > P_cap_terms) return fail(BWR_EINVAL, "P_out capacity too small");

@@ -556,6 +556,7 @@ Error run_sequence(const SequenceArgs& a, hipStream_t st) {
         BWR_HIP(hipMemsetAsync(slots, 0, sizeof(uint32_t) * per_step, st));
     }
     BWR_HIP(launch_reduce_partials(W, a.s, pl.NB, 1, slots, a.S_out, mp, st));
+    if (a.progress) BWR_TRY(a.progress(1));
 
     void* cur = X0.as<void>();
     void* nxt = X1.as<void>();
@@ -599,6 +600,7 @@ Error run_sequence(const SequenceArgs& a, hipStream_t st) {
         hipError_t e = launch_reduce_partials(W, a.s, pl.NB, cnt, slots, a.S_out + (size_t)k * a.s * a.s, mp, st);
         if (e != hipSuccess) err = Error::device(e, "reduce launch");
         k += cnt;
+        if (err.ok() && a.progress) err = a.progress(k);
     }
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);

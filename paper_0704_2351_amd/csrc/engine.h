@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -107,6 +108,9 @@ struct SequenceArgs {
     int64_t len = 0;
     uint32_t* S_out = nullptr;  // device, len x s x s
     StepPlan* plan_out = nullptr;  // optional: the plan used
+    // optional: called from the enqueueing thread each time the reductions of the terms
+    // S_0 .. S_{t-1} have been enqueued on the sequence stream (t increasing, last t = len)
+    std::function<Error(int64_t t)> progress;
 };
 
 Error run_sequence(const SequenceArgs& a, hipStream_t st);

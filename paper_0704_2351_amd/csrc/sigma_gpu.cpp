@@ -206,30 +206,137 @@ Error pm(const Recur& R, const DPoly& G, int64_t sigma, DPoly* P, DevBuf* Pbuf) 
 
 }  // namespace
 
-Error gpu_min_generator(const uint32_t* S_dev, int64_t L, int32_t s, uint32_t p, hipStream_t st, Generator* out,
-                        SigmaStats* stats) {
-    auto t0 = std::chrono::steady_clock::now();
-    const int leaf = gpu_leaf_order(s);
-    if (!leaf) return Error::inval("block size too large for the device sigma-basis");
+Error OnlineGenerator::begin(const uint32_t* S_dev, int64_t L, int32_t s, uint32_t p, int64_t min_chunk,
+                             hipStream_t st) {
+    leaf_ = gpu_leaf_order(s);
+    if (!leaf_) return Error::inval("block size too large for the device sigma-basis");
+    if (s > 64) return Error::inval("block size too large for the device sigma-basis");
+    S_ = S_dev;
+    L_ = L;
+    s_ = s;
+    p_ = p;
+    st_ = st;
+    built_ = done_ = 0;
+    next_ = pending_ = 0;
+    cuts_.clear();
+    if (L > 0) {
+        int64_t c = 0;
+        if (min_chunk > 0) {
+            // quarters while at least half of the range is left, then halves of the rest: early chunks
+            // start while most of the sequence is still to come, the last ones leave a short tail
+            while ((L - c) / 2 >= min_chunk) {
+                c += std::max<int64_t>(std::min<int64_t>(L / 4, (L - c) / 2), 1);
+                cuts_.push_back(c);
+            }
+        }
+        cuts_.push_back(L);
+    }
     const int m = 2 * s, n = s;
-    const int64_t len = std::max<int64_t>(L, 1);
-    // G = [S; -I] as an m x n device polynomial matrix
-    DevBuf gb, db;
-    DPoly G;
-    BWR_TRY(alloc_poly(m, n, len, st, &gb, &G));
-    BWR_HIP(gpu_build_G(S_dev, L, s, p, G.ptr, len, st));
+    // G = [S; -I] as an m x n device polynomial matrix, filled as the terms arrive
+    BWR_TRY(alloc_poly(m, n, std::max<int64_t>(L, 1), st, &gb_, &G_));
     std::vector<int64_t> d0(m, 0);
     for (int i = s; i < m; ++i) d0[i] = 1;
-    BWR_TRY(db.alloc(sizeof(int64_t) * m, st));
-    BWR_HIP(hipMemcpyAsync(db.as<void>(), d0.data(), sizeof(int64_t) * m, hipMemcpyHostToDevice, st));
-    BWR_HIP(hipStreamSynchronize(st));  // the host buffers above must outlive their copies
-    Recur R{p, ModP::make(p), m, n, leaf, db.as<int64_t>(), st};
-    DevBuf pb;
-    DPoly P;
-    BWR_TRY(pm(R, G, L, &P, &pb));
+    BWR_TRY(db_.alloc(sizeof(int64_t) * m, st));
+    BWR_HIP(hipMemcpyAsync(db_.as<void>(), d0.data(), sizeof(int64_t) * m, hipMemcpyHostToDevice, st));
+    BWR_HIP(hipStreamSynchronize(st));  // the host buffer above must outlive its copy
+    return {};
+}
+
+OnlineGenerator::~OnlineGenerator() { (void)join_worker(); }
+
+void OnlineGenerator::feed_async(int64_t avail, hipEvent_t ready) {
+    while (pending_ < (int)cuts_.size() && cuts_[pending_] <= avail) ++pending_;
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        queue_.emplace_back(avail, ready);
+    }
+    if (!worker_.joinable()) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        worker_ = std::thread([this, dev] {
+            (void)hipSetDevice(dev);
+            for (;;) {
+                std::pair<int64_t, hipEvent_t> item;
+                {
+                    std::unique_lock<std::mutex> lk(mu_);
+                    cv_.wait(lk, [&] { return closing_ || !queue_.empty(); });
+                    if (queue_.empty()) return;
+                    item = queue_.front();
+                    queue_.pop_front();
+                }
+                Error e = werr_.ok() ? feed(item.first, item.second) : Error{};
+                if (item.second) (void)hipEventDestroy(item.second);  // the wait above is already enqueued
+                if (!e.ok()) {
+                    std::lock_guard<std::mutex> lk(mu_);
+                    werr_ = e;
+                }
+            }
+        });
+    }
+    cv_.notify_one();
+}
+
+Error OnlineGenerator::join_worker() {
+    if (worker_.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            closing_ = true;
+        }
+        cv_.notify_one();
+        worker_.join();
+    }
+    for (auto& it : queue_)
+        if (it.second) (void)hipEventDestroy(it.second);
+    queue_.clear();
+    return werr_;
+}
+
+Error OnlineGenerator::feed(int64_t avail, hipEvent_t ready) {
+    avail = std::min(avail, L_);
+    if (avail <= built_) return {};
+    if (ready) BWR_HIP(hipStreamWaitEvent(st_, ready, 0));
+    BWR_HIP(gpu_build_G(S_, L_, s_, p_, G_.ptr, G_.ld, built_, avail, st_));
+    built_ = avail;
+    const Recur R{p_, ModP::make(p_), 2 * s_, s_, leaf_, db_.as<int64_t>(), st_};
+    while (next_ < (int)cuts_.size() && cuts_[next_] <= built_) {
+        const int64_t c0 = done_, c1 = cuts_[next_];
+        DPoly Gs = G_;
+        Gs.len = c1;
+        if (c0 == 0) {
+            BWR_TRY(pm(R, Gs, c1, &Q_, &qb_));
+        } else {
+            DevBuf rb, pb, nb;
+            DPoly Rc, P, Qn;
+            BWR_TRY(gpu_polymat_mul(Q_, Gs, c0, c1, p_, &Rc, &rb, st_));
+            BWR_TRY(pm(R, Rc, c1 - c0, &P, &pb));
+            BWR_TRY(gpu_polymat_mul(P, Q_, 0, c1 + 1, p_, &Qn, &nb, st_));
+            qb_ = std::move(nb);
+            Q_ = Qn;
+        }
+        done_ = c1;
+        ++next_;
+    }
+    return {};
+}
+
+
+
+Error OnlineGenerator::finish(Generator* out) {
+    BWR_TRY(join_worker());
+    if (done_ != L_) return Error::inval("sigma-basis finished before every term was fed");
+    const int m = 2 * s_, s = s_;
+    DevBuf ib;
+    DPoly P = Q_;
+    if (L_ == 0) {  // the basis of order 0 is the identity
+        BWR_TRY(alloc_poly(m, m, 1, st_, &ib, &P));
+        std::vector<uint32_t> I((size_t)m * m, 0);
+        for (int i = 0; i < m; ++i) I[(size_t)i * m + i] = 1;
+        BWR_HIP(hipMemcpyAsync(P.ptr, I.data(), 4 * I.size(), hipMemcpyHostToDevice, st_));
+        BWR_HIP(hipStreamSynchronize(st_));
+    }
     std::vector<int64_t> d(m);
-    BWR_HIP(hipMemcpyAsync(d.data(), db.as<void>(), sizeof(int64_t) * m, hipMemcpyDeviceToHost, st));
-    BWR_HIP(hipStreamSynchronize(st));
+    BWR_HIP(hipMemcpyAsync(d.data(), db_.as<void>(), sizeof(int64_t) * m, hipMemcpyDeviceToHost, st_));
+    BWR_HIP(hipStreamSynchronize(st_));
     std::vector<int> rows(m);
     for (int r = 0; r < m; ++r) rows[r] = r;
     std::stable_sort(rows.begin(), rows.end(), [&](int a, int b) { return d[a] < d[b]; });
@@ -242,23 +349,32 @@ Error gpu_min_generator(const uint32_t* S_dev, int64_t L, int32_t s, uint32_t p,
     }
     out->P.resize(s, s, maxd + 1);
     // gather the chosen rows on the device (coefficients above each delta zeroed and checked), then one copy
-    if (s > 64) return Error::inval("block size too large for the device sigma-basis");
     GenRows gr{};
     for (int i = 0; i < s; ++i) {
         gr.row[i] = rows[i];
         gr.delta[i] = out->delta[i];
     }
     DevBuf ob, fb;
-    BWR_TRY(ob.alloc(sizeof(uint32_t) * out->P.a.size(), st));
-    BWR_TRY(fb.alloc(sizeof(int32_t), st));
-    BWR_HIP(hipMemsetAsync(fb.as<void>(), 0, sizeof(int32_t), st));
-    BWR_HIP(gpu_extract_rows(P.ptr, P.ld, P.len, m, s, gr, maxd + 1, ob.as<uint32_t>(), fb.as<int32_t>(), st));
+    BWR_TRY(ob.alloc(sizeof(uint32_t) * out->P.a.size(), st_));
+    BWR_TRY(fb.alloc(sizeof(int32_t), st_));
+    BWR_HIP(hipMemsetAsync(fb.as<void>(), 0, sizeof(int32_t), st_));
+    BWR_HIP(gpu_extract_rows(P.ptr, P.ld, P.len, m, s, gr, maxd + 1, ob.as<uint32_t>(), fb.as<int32_t>(), st_));
     int32_t bad = 0;
     BWR_HIP(hipMemcpyAsync(out->P.a.data(), ob.as<void>(), sizeof(uint32_t) * out->P.a.size(), hipMemcpyDeviceToHost,
-                           st));
-    BWR_HIP(hipMemcpyAsync(&bad, fb.as<void>(), sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    BWR_HIP(hipStreamSynchronize(st));
+                           st_));
+    BWR_HIP(hipMemcpyAsync(&bad, fb.as<void>(), sizeof(int32_t), hipMemcpyDeviceToHost, st_));
+    BWR_HIP(hipStreamSynchronize(st_));
     if (bad) return {ESHORT_, "generator row degree exceeds its shifted degree"};
+    return {};
+}
+
+Error gpu_min_generator(const uint32_t* S_dev, int64_t L, int32_t s, uint32_t p, hipStream_t st, Generator* out,
+                        SigmaStats* stats, int64_t min_chunk) {
+    auto t0 = std::chrono::steady_clock::now();
+    OnlineGenerator og;
+    BWR_TRY(og.begin(S_dev, L, s, p, min_chunk, st));
+    BWR_TRY(og.feed(L, nullptr));
+    BWR_TRY(og.finish(out));
     if (stats) {
         stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         stats->threads = 0;

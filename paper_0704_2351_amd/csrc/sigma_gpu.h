@@ -3,6 +3,14 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <utility>
+#include <vector>
+
+#include "engine.h"
 #include "modp.h"
 #include "sigma.h"
 
@@ -35,8 +43,10 @@ size_t mbasis_leaf_lds(int m, int n, int sigma);
 // LDS of the one-transform-per-order leaf (used for m = 2n, n <= LEAF2_MAX_S).
 constexpr int LEAF2_MAX_S = 16;
 size_t mbasis_leaf2_lds(int m, int n, int sigma);
-// G = [S(x); -I_s] as a 2s x s polynomial matrix with entries of length len >= L.
-hipError_t gpu_build_G(const uint32_t* S, int64_t L, int s, uint32_t p, uint32_t* G, int64_t len, hipStream_t st);
+// Coefficients k0 .. k1 - 1 of G = [S(x); -I_s], a 2s x s polynomial matrix with entries of length len
+// (stride len); S holds L terms and coefficients k >= L of the S rows are zero.
+hipError_t gpu_build_G(const uint32_t* S, int64_t L, int s, uint32_t p, uint32_t* G, int64_t len, int64_t k0,
+                       int64_t k1, hipStream_t st);
 
 // Rows chosen for the generator (at most 64): basis row indices and their shifted degrees.
 struct GenRows {
@@ -51,21 +61,73 @@ hipError_t gpu_copy_rows(uint32_t* dst, int64_t dld, const uint32_t* src, int64_
 hipError_t gpu_extract_rows(const uint32_t* P, int64_t ld, int64_t len, int m, int s, const GenRows& gr, int64_t olen,
                             uint32_t* out, int32_t* bad, hipStream_t st);
 
-// Largest leaf order (power of two <= 32) whose M-Basis fits the LDS budget; 0 if none.
-int gpu_leaf_order(int s);
-
-// Minimal generator of the device sequence S (L x s x s) on the device; the
-// chosen rows come back to the host in `out`.
-Error gpu_min_generator(const uint32_t* S_dev, int64_t L, int32_t s, uint32_t p, hipStream_t st, Generator* out,
-                        SigmaStats* stats = nullptr);
-
-// Window [lo, hi) of the product of two device polynomial matrices (exposed for tests).
+// A device polynomial matrix: entry (r, c) holds coefficients ptr[(r * cols + c) * ld + k], k < len.
 struct DPoly {
     int rows = 0, cols = 0;
     int64_t len = 0;  // coefficients in use
     int64_t ld = 0;   // stride between entries (>= len)
     uint32_t* ptr = nullptr;
 };
+
+// Largest leaf order (power of two <= 32) whose M-Basis fits the LDS budget; 0 if none.
+int gpu_leaf_order(int s);
+
+// Minimal generator of the device sequence S (L x s x s) on the device; the
+// chosen rows come back to the host in `out`.  min_chunk > 0 takes the order
+// range in the chunks of OnlineGenerator (same result; used by tests).
+Error gpu_min_generator(const uint32_t* S_dev, int64_t L, int32_t s, uint32_t p, hipStream_t st, Generator* out,
+                        SigmaStats* stats = nullptr, int64_t min_chunk = 0);
+
+// Sigma-basis of order L computed while the sequence is still being produced.
+// The order range [0, L) is cut into chunks [c_{i-1}, c_i) (quarters of L while
+// half of it is left, then halves of the rest down to min_chunk, then the
+// rest); the basis of chunk i is the PM-Basis
+// of the residual (Q_{i-1} G) mod x^{c_i} div x^{c_{i-1}}, with Q_{i-1} the
+// product of the earlier chunks' bases, and Q_i = P_i Q_{i-1}.  Every order's
+// M-Basis transform depends only on its residual coefficient and the shifted
+// degrees, so the result equals the basis of one PM-Basis call over [0, L).
+// Chunk i needs the terms S_0 .. S_{c_i - 1} only, so it can run on its own
+// stream while the sequence computes later terms.
+class OnlineGenerator {
+   public:
+    ~OnlineGenerator();
+    // Work is enqueued on st; S_dev (L x s x s, device) must stay allocated until finish() returns.
+    Error begin(const uint32_t* S_dev, int64_t L, int32_t s, uint32_t p, int64_t min_chunk, hipStream_t st);
+    // The first `avail` terms of S_dev are complete once `ready` (an event recorded on the producer's
+    // stream, or null when they are complete already) has fired: enqueue every chunk they cover.
+    Error feed(int64_t avail, hipEvent_t ready);
+    // Same, from a host thread of the generator's own (started on first use), so that the caller (which
+    // enqueues the sequence) never waits on the basis stream's queue.  Takes ownership of `ready`.
+    void feed_async(int64_t avail, hipEvent_t ready);
+    // Call after feed(L, ...) or feed_async(L, ...): waits for the basis and returns the generator.
+    Error finish(Generator* out);
+    // chunk end the next feed must reach to enqueue more work; -1 when every chunk is enqueued or queued
+    int64_t next_boundary() const { return pending_ < (int64_t)cuts_.size() ? cuts_[pending_] : -1; }
+    int chunks() const { return (int)cuts_.size(); }
+
+   private:
+    Error join_worker();
+    const uint32_t* S_ = nullptr;
+    int64_t L_ = 0, built_ = 0, done_ = 0;
+    int32_t s_ = 0;
+    uint32_t p_ = 0;
+    int leaf_ = 0;
+    hipStream_t st_ = nullptr;
+    std::vector<int64_t> cuts_;  // chunk ends, increasing, last = L
+    int next_ = 0;               // first chunk not enqueued on st_
+    int pending_ = 0;            // first chunk not covered by a feed (caller's view)
+    DevBuf gb_, db_, qb_;
+    DPoly G_, Q_;
+    // feed_async worker
+    std::thread worker_;
+    std::mutex mu_;
+    std::condition_variable cv_;
+    std::deque<std::pair<int64_t, hipEvent_t>> queue_;
+    bool closing_ = false;
+    Error werr_;
+};
+
+// Window [lo, hi) of the product of two device polynomial matrices (exposed for tests).
 Error gpu_polymat_mul(const DPoly& A, const DPoly& B, int64_t lo, int64_t hi, uint32_t p, DPoly* C, DevBuf* Cbuf,
                       hipStream_t st);
 

@@ -783,13 +783,15 @@ __global__ __launch_bounds__(LEAF2_TPB) void k_mbasis_leaf2(const uint32_t* __re
     }
 }
 
-// G[r][c][k] = S[k][r][c] for r < s, k < L; -1 (mod p) at r = s + c, k = 0; 0 elsewhere.
+// G[r][c][k] = S[k][r][c] for r < s, k < L; -1 (mod p) at r = s + c, k = 0; 0 elsewhere;
+// written for the coefficients k0 <= k < k1 of every entry.
 __global__ __launch_bounds__(TPB) void k_build_G(const uint32_t* __restrict__ S, int64_t L, int s, uint32_t p,
-                                                 uint32_t* __restrict__ G, int64_t len) {
+                                                 uint32_t* __restrict__ G, int64_t len, int64_t k0, int64_t k1) {
+    const int64_t span = k1 - k0;
     int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x;
-    if (idx >= (int64_t)2 * s * s * len) return;
-    int64_t k = idx % len;
-    int64_t rc = idx / len;
+    if (idx >= (int64_t)2 * s * s * span) return;
+    int64_t k = k0 + idx % span;
+    int64_t rc = idx / span;
     int r = (int)(rc / s), c = (int)(rc % s);
     uint32_t v = 0;
     if (r < s) {
@@ -797,7 +799,7 @@ __global__ __launch_bounds__(TPB) void k_build_G(const uint32_t* __restrict__ S,
     } else if (k == 0 && r - s == c) {
         v = p - 1;
     }
-    G[idx] = v;
+    G[rc * len + k] = v;
 }
 
 // dst[r * dld + x] = src[r * sld + x] for x < width, r < nrows (strided copies as plain loads and stores)
@@ -845,8 +847,10 @@ namespace {
 
 }  // namespace
 
-hipError_t gpu_build_G(const uint32_t* S, int64_t L, int s, uint32_t p, uint32_t* G, int64_t len, hipStream_t st) {
-    k_build_G<<<grid_for((int64_t)2 * s * s * len, TPB), TPB, 0, st>>>(S, L, s, p, G, len);
+hipError_t gpu_build_G(const uint32_t* S, int64_t L, int s, uint32_t p, uint32_t* G, int64_t len, int64_t k0,
+                       int64_t k1, hipStream_t st) {
+    if (k0 < 0 || k1 > len || k0 >= k1) return k0 == k1 ? hipSuccess : hipErrorInvalidValue;
+    k_build_G<<<grid_for((int64_t)2 * s * s * (k1 - k0), TPB), TPB, 0, st>>>(S, L, s, p, G, len, k0, k1);
     return hipGetLastError();
 }
 

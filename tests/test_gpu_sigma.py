@@ -64,6 +64,22 @@ def test_device_generator_long_random_sequences(L, s, p):
     assert np.array_equal(P_dev, P_host)
 
 
+@pytest.mark.parametrize("L,s,p,min_chunk", [(2000, 8, 65521, 1), (2000, 8, 65521, 300), (701, 4, 2**31 - 1, 7),
+                                             (1500, 16, 65521, 64), (90, 3, 65537, 2)])
+def test_chunked_generator_equals_one_call(L, s, p, min_chunk, monkeypatch):
+    """The online order (chunks [c_{i-1}, c_i) halving down to min_chunk, each chunk's basis composed onto
+    the product of the earlier ones) gives the one-call PM-Basis generator entry for entry."""
+    torch = need_gpu()
+    announce(f"chunked device sigma-basis L={L} s={s} p={p} min_chunk={min_chunk}")
+    rng = np.random.default_rng(L + min_chunk)
+    S = rng.integers(0, p, size=(L, s, s), dtype=np.int64)
+    d_host, P_host = bw.min_generator(S, p)
+    monkeypatch.setenv("BWR_SIGMA_MIN_CHUNK", str(min_chunk))
+    d_dev, P_dev = bw.min_generator_dev(to_dev(torch, S), p)
+    assert np.array_equal(d_dev, d_host)
+    assert np.array_equal(P_dev, P_host)
+
+
 def test_device_generator_zero_sequence():
     torch = need_gpu()
     announce("device sigma-basis zero sequence")
@@ -83,3 +99,16 @@ def test_rank_with_sigma_on_device_or_host(where, p, monkeypatch):
     r, info = bw.rank_modp(A, p, 8, 4)
     assert r == native.rank_csr_c(A, p) == 1900
     assert (info["sigma_threads"] == 0) == (where == "device")
+
+
+@pytest.mark.parametrize("min_chunk", [0, 1, 16, 100])
+@pytest.mark.parametrize("p", [65521, 2**31 - 1])
+def test_rank_with_sigma_beside_sequence(min_chunk, p, monkeypatch):
+    """The sigma-basis chunks that run on a second stream while the sequence is computed (each waits on
+    an event after the terms it needs) give the rank of elimination; min_chunk 0 runs it afterwards."""
+    need_gpu()
+    announce(f"rank with online sigma min_chunk={min_chunk} p={p}")
+    monkeypatch.setenv("BWR_SIGMA_MIN_CHUNK", str(min_chunk))
+    A = planted(3000, 2200, 1900, 9, 809)
+    r, info = bw.rank_modp(A, p, 8, 5)
+    assert r == native.rank_csr_c(A, p) == 1900
