@@ -7,6 +7,10 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <tuple>
+#include <mutex>
+#include <map>
 
 #include "kernels.h"
 
@@ -323,6 +327,9 @@ Error launch_step(const DeviceMatrix& M, const Operand& op1, const Operand& op2,
 }
 
 // Times `iters` launches of fn with HIP events (after one untimed launch).
+// back-to-back launches per autotuner timing (one untimed launch first)
+constexpr int TUNE_ITERS = 4;
+
 template <class Fn>
 Error time_launches(int iters, hipStream_t st, Fn fn, double* us) {
     hipEvent_t ev[2];
@@ -344,12 +351,29 @@ Error time_launches(int iters, hipStream_t st, Fn fn, double* us) {
     return err;
 }
 
+// Index of the fastest candidate: TUNE_ROUNDS rounds, each timing every candidate in turn; a candidate's
+// time is its best round, so work that another stream runs meanwhile inflates the candidates alike
+// instead of deciding the choice.
+constexpr int TUNE_ROUNDS = 3;
+
+Error pick_fastest(const std::vector<std::function<Error()>>& cands, hipStream_t st, int* best) {
+    std::vector<double> t(cands.size(), 1e30);
+    for (int r = 0; r < TUNE_ROUNDS; ++r)
+        for (size_t i = 0; i < cands.size(); ++i) {
+            double us = 0;
+            BWR_TRY(time_launches(TUNE_ITERS, st, cands[i], &us));
+            t[i] = std::min(t[i], us);
+        }
+    *best = (int)(std::min_element(t.begin(), t.end()) - t.begin());
+    return {};
+}
+
 }  // namespace
 
-// Persistent blocks of the fused second product: at most `want`, and at most 2^18 partial words per step.
-constexpr int FUSED_NB_MAX = 2048;
-int64_t fused_nb_cap(int W, int want) {
-    return std::max<int64_t>(1, std::min<int64_t>(want, 262144 / ((int64_t)W * W)));
+// Persistent blocks of the fused second product: at most `want`, and at most 2^19 partial words per step.
+constexpr int64_t FUSED_PARTIAL_WORDS = 524288;
+int64_t fused_nb_cap(int W, int64_t want) {
+    return std::max<int64_t>(1, std::min<int64_t>(want, FUSED_PARTIAL_WORDS / ((int64_t)W * W)));
 }
 
 StepPlan plan_step(const DeviceMatrix& M, bool transpose, int32_t s, uint32_t p) {
@@ -396,49 +420,57 @@ Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl
     BWR_TRY(Z.alloc(es * (size_t)std::max<int64_t>(nb * W, 1), st));
     BWR_TRY(U.alloc(es * (size_t)std::max<int64_t>(nb * W, 1), st));
     BWR_TRY(Y.alloc(es * (size_t)std::max<int64_t>(outer * W, 1), st));
-    const int64_t part_words = std::max<int64_t>((int64_t)FUSED_NB_MAX * W * W, (int64_t)proj_blocks(nb, W) * W * W);
+    const int64_t part_words = std::max<int64_t>(FUSED_PARTIAL_WORDS, (int64_t)proj_blocks(nb, W) * W * W);
     BWR_TRY(part.alloc(sizeof(uint32_t) * (size_t)part_words, st));
     // timing inputs: contents do not change the memory traffic
     BWR_HIP(hipMemsetAsync(X.as<void>(), 0, X.bytes(), st));
     BWR_HIP(hipMemsetAsync(U.as<void>(), 0, U.bytes(), st));
     BWR_HIP(hipMemsetAsync(Y.as<void>(), 0, Y.bytes(), st));
     if (pl->G1 > 0) {
-        double best = 1e30;
-        int bestg = pl->G1;
+        std::vector<int> gs;
+        std::vector<std::function<Error()>> runs;
         for (int g = 1; g <= 16; g <<= 1) {
             if (!split_supported(W, g, false)) continue;
-            double us = 0;
-            BWR_TRY(time_launches(3, st, [&]() -> Error {
+            gs.push_back(g);
+            runs.push_back([&, g]() -> Error {
                 hipError_t e = launch_spmm_split(W, g, false, acc_mode(M, op1.max_len, mp.p, g), smallp, pl->esize,
                                                  op1.rows, op1.rp, op1.ent, X.as<void>(), nullptr, Y.as<void>(),
                                                  nullptr, nullptr, 0, mp, st);
                 return e == hipSuccess ? Error{} : Error::device(e, "autotune");
-            }, &us));
-            if (us < best) {
-                best = us;
-                bestg = g;
-            }
+            });
         }
-        pl->G1 = bestg;
+        int bi = 0;
+        BWR_TRY(pick_fastest(runs, st, &bi));
+        pl->G1 = gs[bi];
     }
     if (pl->G2 > 0) {
-        // second product and projection: fused with 1024 or FUSED_NB_MAX persistent blocks, or the
-        // plain product followed by the projection kernel; the fastest pair wins
-        double best = 1e30;
-        int bestg = pl->G2, bestnb = pl->NB;
-        bool bestf = pl->fused;
+        // second product and projection: fused, with 1024 or 2048 persistent blocks or with the row tiles
+        // split evenly over ceil(tiles / k) blocks (k = 1 .. 4, so no block runs one tile more than the
+        // others), or the plain product followed by the projection kernel; the fastest pair wins
+        struct Cand {
+            int g, nbk;
+            bool fused;
+        };
+        std::vector<Cand> cs;
+        std::vector<std::function<Error()>> runs;
         const int pnb = proj_blocks(nb, W);
         for (int g = 1; g <= 16; g <<= 1) {
             const int rpb = split_rows_per_block(W, g);
             const int64_t tiles = (nb + rpb - 1) / rpb;
-            for (int variant = 0; variant < 3; ++variant) {
-                const bool fused = variant < 2;
-                if (!split_supported(W, g, fused)) continue;
-                const int64_t cap = fused ? fused_nb_cap(W, variant == 0 ? 1024 : FUSED_NB_MAX) : 0;
-                if (fused && variant == 1 && cap <= 1024) continue;
-                const int nbk = fused ? (int)std::max<int64_t>(1, std::min<int64_t>(tiles, cap)) : pnb;
-                double us = 0;
-                BWR_TRY(time_launches(3, st, [&]() -> Error {
+            std::vector<int> nbs;  // fused block counts; 0 = plain product + projection kernel
+            if (split_supported(W, g, true)) {
+                for (int64_t want : {(int64_t)1024, (int64_t)2048, tiles, (tiles + 1) / 2, (tiles + 2) / 3,
+                                     (tiles + 3) / 4}) {
+                    const int c = (int)std::min<int64_t>(std::max<int64_t>(1, tiles), fused_nb_cap(W, want));
+                    if (std::find(nbs.begin(), nbs.end(), c) == nbs.end()) nbs.push_back(c);
+                }
+            }
+            if (split_supported(W, g, false)) nbs.push_back(0);
+            for (int c : nbs) {
+                const bool fused = c > 0;
+                const int nbk = fused ? c : pnb;
+                cs.push_back({g, nbk, fused});
+                runs.push_back([&, g, nbk, fused]() -> Error {
                     hipError_t e = launch_spmm_split(W, g, fused, acc_mode(M, op2.max_len, mp.p, g), smallp, pl->esize,
                                                      op2.rows, op2.rp, op2.ent, Y.as<void>(), nullptr, Z.as<void>(),
                                                      U.as<void>(), part.as<uint32_t>(), fused ? nbk : 0, mp, st);
@@ -446,18 +478,14 @@ Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl
                         e = launch_project(W, smallp, nb, U.as<void>(), Z.as<void>(), pl->esize, part.as<uint32_t>(),
                                            nbk, mp, st);
                     return e == hipSuccess ? Error{} : Error::device(e, "autotune");
-                }, &us));
-                if (us < best) {
-                    best = us;
-                    bestg = g;
-                    bestnb = nbk;
-                    bestf = fused;
-                }
+                });
             }
         }
-        pl->G2 = bestg;
-        pl->NB = bestnb;
-        pl->fused = bestf;
+        int bi = 0;
+        BWR_TRY(pick_fastest(runs, st, &bi));
+        pl->G2 = cs[bi].g;
+        pl->NB = cs[bi].nbk;
+        pl->fused = cs[bi].fused;
     }
     // 32-bit residues: does running each product in two column passes (each gathering from half of the
     // block, which then fits an XCD's L2) beat one pass?
@@ -465,20 +493,16 @@ Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl
         SplitOp so1, so2;
         if (pl->G1 > 0 && nb >= 2) {
             BWR_TRY(build_split(op1, nb, M.nnz, W, st, &so1));
-            double one = 0, two = 0;
-            BWR_TRY(time_launches(3, st, [&]() -> Error {
-                hipError_t e = first_product(M, op1, nullptr, pl->G1, *pl, mp, X.as<void>(), nullptr, Y.as<void>(), st);
+            auto run = [&](const SplitOp* so) -> Error {
+                hipError_t e = first_product(M, op1, so, pl->G1, *pl, mp, X.as<void>(), nullptr, Y.as<void>(), st);
                 return e == hipSuccess ? Error{} : Error::device(e, "autotune");
-            }, &one));
-            BWR_TRY(time_launches(3, st, [&]() -> Error {
-                hipError_t e = first_product(M, op1, &so1, pl->G1, *pl, mp, X.as<void>(), nullptr, Y.as<void>(), st);
-                return e == hipSuccess ? Error{} : Error::device(e, "autotune");
-            }, &two));
-            pl->parts1 = two < one ? 2 : 1;
+            };
+            int bi = 0;
+            BWR_TRY(pick_fastest({[&]() { return run(nullptr); }, [&]() { return run(&so1); }}, st, &bi));
+            pl->parts1 = bi == 1 ? 2 : 1;
         }
         if (pl->G2 > 0 && outer >= 2) {
             BWR_TRY(build_split(op2, outer, M.nnz, W, st, &so2));
-            double one = 0, two = 0;
             auto run = [&](const SplitOp* so) -> Error {
                 hipError_t e = second_product(M, op2, so, pl->G2, pl->fused, pl->NB, *pl, mp, Y.as<void>(), nullptr,
                                               Z.as<void>(), U.as<void>(), part.as<uint32_t>(), st);
@@ -487,13 +511,56 @@ Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl
                                        pl->NB, mp, st);
                 return e == hipSuccess ? Error{} : Error::device(e, "autotune");
             };
-            BWR_TRY(time_launches(3, st, [&]() -> Error { return run(nullptr); }, &one));
-            BWR_TRY(time_launches(3, st, [&]() -> Error { return run(&so2); }, &two));
-            pl->parts2 = two < one ? 2 : 1;
+            int bi = 0;
+            BWR_TRY(pick_fastest({[&]() { return run(nullptr); }, [&]() { return run(&so2); }}, st, &bi));
+            pl->parts2 = bi == 1 ? 2 : 1;
         }
     }
     return {};
 }
+
+namespace {
+
+// Launch plans tuned in this process, by matrix shape, orientation, block width and prime: a plan only
+// changes speed, so a matrix of the same shape reuses it (the second and later solves do not retune,
+// and every solve of a shape runs the same kernels).  BWR_NO_PLAN_CACHE=1 retunes every call.
+struct PlanKey {
+    int dev;
+    int64_t m, n, nnz;
+    int32_t la, lt;
+    bool transpose;
+    int W, esize;
+    uint32_t p;
+    bool operator<(const PlanKey& o) const {
+        return std::tie(dev, m, n, nnz, la, lt, transpose, W, esize, p) <
+               std::tie(o.dev, o.m, o.n, o.nnz, o.la, o.lt, o.transpose, o.W, o.esize, o.p);
+    }
+};
+std::mutex g_plan_mu;
+std::map<PlanKey, StepPlan> g_plans;
+
+Error tuned_plan(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl, hipStream_t st) {
+    int dev = 0;
+    BWR_HIP(hipGetDevice(&dev));
+    const PlanKey key{dev, M.m, M.n, M.nnz, M.max_len_a, M.max_len_t, transpose, pl->W, pl->esize, mp.p};
+    const bool cache = env_int("BWR_NO_PLAN_CACHE", 0) == 0 && getenv("BWR_PARTS") == nullptr;
+    if (cache) {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        auto it = g_plans.find(key);
+        if (it != g_plans.end()) {
+            *pl = it->second;
+            return {};
+        }
+    }
+    BWR_TRY(autotune_step(M, transpose, mp, pl, st));
+    if (cache) {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        g_plans[key] = *pl;
+    }
+    return {};
+}
+
+}  // namespace
 
 Error run_sequence(const SequenceArgs& a, hipStream_t st) {
     const DeviceMatrix& M = *a.M;
@@ -511,7 +578,7 @@ Error run_sequence(const SequenceArgs& a, hipStream_t st) {
     StepPlan pl = plan_step(M, a.transpose, a.s, mp.p);
     if (a.len >= 64 && M.nnz >= 100000 && env_int("BWR_NO_TUNE", 0) == 0 && getenv("BWR_G1") == nullptr &&
         getenv("BWR_G2") == nullptr)
-        BWR_TRY(autotune_step(M, a.transpose, mp, &pl, st));
+        BWR_TRY(tuned_plan(M, a.transpose, mp, &pl, st));
     if (a.plan_out) *a.plan_out = pl;
 
     const size_t es = (size_t)pl.esize;
@@ -654,7 +721,7 @@ Error time_step_kernels(const DeviceMatrix& M, bool transpose, ModP mp, int32_t 
     const int64_t nb = op2.rows, outer = op1.rows;
     StepPlan pl = plan_step(M, transpose, s, mp.p);
     if (M.nnz >= 100000 && env_int("BWR_NO_TUNE", 0) == 0 && getenv("BWR_G1") == nullptr && getenv("BWR_G2") == nullptr)
-        BWR_TRY(autotune_step(M, transpose, mp, &pl, st));
+        BWR_TRY(tuned_plan(M, transpose, mp, &pl, st));
     if (plan_out) *plan_out = pl;
     const size_t es = (size_t)pl.esize;
     DevBuf X, Y, Z, U, d1, d2, part;

@@ -18,7 +18,8 @@
 // loop).  Partials meet through shuffles (row slots of a wave) and LDS (the
 // 4 waves), and one W x W partial per block goes to memory, reduced later by
 // k_reduce_partials.  Sums are exact in 64 bits: products of residues below
-// 2^16 are < 2^32, larger primes reduce each product first.
+// 2^16 are < 2^32 and summed as they are; for larger primes each product is
+// reduced and a lane keeps its sums mod p in 32 bits (fewer registers).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -92,11 +93,11 @@ __device__ __forceinline__ void mac(Acc& acc, int32_t& ah, int32_t& al, int32_t 
 // PASS 0: one pass over the row.  PASS 1: first of two column parts: the reduced sum goes to carry (no scale,
 // no store, no projection).  PASS 2: second part: carry is added before the scale, store and projection.
 template <int W, int G, int ACC, bool SMALLP, bool PROJ, typename E, int PASS>
-__global__ __launch_bounds__(TPB) void k_spmm_split(int64_t nrows, const int32_t* __restrict__ rp,
-                                                    const uint32_t* __restrict__ ent, const E* __restrict__ X,
-                                                    const uint32_t* __restrict__ scale, E* __restrict__ Y,
-                                                    const E* __restrict__ U, uint32_t* __restrict__ partial,
-                                                    ModP mp, uint32_t* __restrict__ carry) {
+__device__ __forceinline__ void spmm_split_body(int64_t nrows, const int32_t* __restrict__ rp,
+                                                const uint32_t* __restrict__ ent, const E* __restrict__ X,
+                                                const uint32_t* __restrict__ scale, E* __restrict__ Y,
+                                                const E* __restrict__ U, uint32_t* __restrict__ partial, ModP mp,
+                                                uint32_t* __restrict__ carry) {
     constexpr int CG = W / 4;
     constexpr int LPR = CG * G;
     static_assert(LPR <= 64 && 64 % LPR == 0, "row group must divide a wave");
@@ -116,14 +117,14 @@ __global__ __launch_bounds__(TPB) void k_spmm_split(int64_t nrows, const int32_t
     const int j = sub / CG;
     const int slot = lane / LPR;
 
-    uint64_t pacc[IPL][4], phi[SMALLP ? 1 : IPL][4];  // projection sums (low and high product halves)
+    // projection sums: 64-bit sums of exact products below 2^32 (16-bit primes), else residues summed mod p
+    // (32 bits, so the kernel keeps the occupancy of the unfused product)
+    using PAcc = typename std::conditional<SMALLP, uint64_t, uint32_t>::type;
+    PAcc pacc[IPL][4];
 #pragma unroll
     for (int u = 0; u < IPL; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            pacc[u][v] = 0;
-            if (!SMALLP) phi[u][v] = 0;
-        }
+        for (int v = 0; v < 4; ++v) pacc[u][v] = 0;
 
     for (int64_t tile = blockIdx.x; tile * RPB < nrows; tile += gridDim.x) {
         const int64_t row = tile * RPB + wave * RPW + slot;
@@ -198,37 +199,31 @@ __global__ __launch_bounds__(TPB) void k_spmm_split(int64_t nrows, const int32_t
                         if (SMALLP) {
                             pacc[q][c] += (uint64_t)(u[q] * y[c]);
                         } else {
-                            const uint64_t pr = (uint64_t)u[q] * y[c];
-                            pacc[q][c] += pr & 0xffffffffu;
-                            phi[SMALLP ? 0 : q][c] += pr >> 32;
+                            pacc[q][c] = addmod(mp, pacc[q][c], mulmod(mp, u[q], y[c]));
                         }
                     }
             }
         }
     }
     if constexpr (PROJ) {
-        if constexpr (!SMALLP) {
-            // fold the two halves: sum = hi 2^32 + lo, reduced per lane before the cross-lane sums
-            const uint32_t r32 = red64(mp, (uint64_t)1 << 32);
+        // sum over the row slots of the wave (lanes with equal sub); at most 64 terms below 2^32 each
+        uint64_t ps[IPL][4];
 #pragma unroll
-            for (int q = 0; q < IPL; ++q)
+        for (int q = 0; q < IPL; ++q)
 #pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    pacc[q][c] = addmod(mp, mulmod(mp, red64(mp, phi[q][c]), r32), red64(mp, pacc[q][c]));
-        }
-        // sum over the row slots of the wave (lanes with equal sub)
+            for (int c = 0; c < 4; ++c) ps[q][c] = pacc[q][c];
 #pragma unroll
         for (int off = LPR; off < 64; off <<= 1)
 #pragma unroll
             for (int q = 0; q < IPL; ++q)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) pacc[q][c] += shfl_xor_u64(pacc[q][c], off);
+                for (int c = 0; c < 4; ++c) ps[q][c] += shfl_xor_u64(ps[q][c], off);
         __shared__ uint64_t sh[TPB / 64][W * W];
         if (lane < LPR) {
 #pragma unroll
             for (int q = 0; q < IPL; ++q)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) sh[wave][(j * IPL + q) * W + cg * 4 + c] = pacc[q][c];
+                for (int c = 0; c < 4; ++c) sh[wave][(j * IPL + q) * W + cg * 4 + c] = ps[q][c];
         }
         __syncthreads();
         for (int e = threadIdx.x; e < W * W; e += TPB) {
@@ -238,6 +233,30 @@ __global__ __launch_bounds__(TPB) void k_spmm_split(int64_t nrows, const int32_t
             partial[(size_t)blockIdx.x * W * W + e] = red64(mp, s);
         }
     }
+}
+
+template <int W, int G, int ACC, bool SMALLP, bool PROJ, typename E, int PASS>
+__global__ __launch_bounds__(TPB) void k_spmm_split(int64_t nrows, const int32_t* __restrict__ rp,
+                                                    const uint32_t* __restrict__ ent, const E* __restrict__ X,
+                                                    const uint32_t* __restrict__ scale, E* __restrict__ Y,
+                                                    const E* __restrict__ U, uint32_t* __restrict__ partial,
+                                                    ModP mp, uint32_t* __restrict__ carry) {
+    spmm_split_body<W, G, ACC, SMALLP, PROJ, E, PASS>(nrows, rp, ent, X, scale, Y, U, partial, mp, carry);
+}
+
+// The same kernel held to 72 registers (7 waves per SIMD instead of 6): used for the 8-wide fused
+// projection with 32-bit residues and G >= 4, which fits 72 registers without spilling.
+template <int W, int G, int ACC, bool SMALLP, bool PROJ, typename E, int PASS>
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(7))) void k_spmm_split_o7(
+    int64_t nrows, const int32_t* __restrict__ rp, const uint32_t* __restrict__ ent, const E* __restrict__ X,
+    const uint32_t* __restrict__ scale, E* __restrict__ Y, const E* __restrict__ U, uint32_t* __restrict__ partial,
+    ModP mp, uint32_t* __restrict__ carry) {
+    spmm_split_body<W, G, ACC, SMALLP, PROJ, E, PASS>(nrows, rp, ent, X, scale, Y, U, partial, mp, carry);
+}
+
+bool use_o7() {
+    static const bool on = getenv("BWR_NO_O7") == nullptr;
+    return on;
 }
 
 struct Args {
@@ -258,18 +277,27 @@ hipError_t launch_wgep(int acc, bool smallp, unsigned grid, const Args& a, hipSt
     const E* X = (const E*)a.X;
     E* Y = (E*)a.Y;
     const E* U = (const E*)a.U;
-    if (acc == 1)
-        k_spmm_split<W, G, 1, true, PROJ, E, PASS><<<grid, TPB, 0, st>>>(a.nrows, a.rp, a.ent, X, a.scale, Y, U,
-                                                                       a.partial, a.mp, a.carry);
-    else if (smallp)
-        k_spmm_split<W, G, 0, true, PROJ, E, PASS><<<grid, TPB, 0, st>>>(a.nrows, a.rp, a.ent, X, a.scale, Y, U,
-                                                                       a.partial, a.mp, a.carry);
-    else if (acc == 2)
-        k_spmm_split<W, G, 2, false, PROJ, E, PASS><<<grid, TPB, 0, st>>>(a.nrows, a.rp, a.ent, X, a.scale, Y, U,
-                                                                        a.partial, a.mp, a.carry);
-    else
-        k_spmm_split<W, G, 0, false, PROJ, E, PASS><<<grid, TPB, 0, st>>>(a.nrows, a.rp, a.ent, X, a.scale, Y, U,
-                                                                        a.partial, a.mp, a.carry);
+#define BWR_SPLIT_ARGS a.nrows, a.rp, a.ent, X, a.scale, Y, U, a.partial, a.mp, a.carry
+    if (acc == 1) {
+        k_spmm_split<W, G, 1, true, PROJ, E, PASS><<<grid, TPB, 0, st>>>(BWR_SPLIT_ARGS);
+    } else if (smallp) {
+        k_spmm_split<W, G, 0, true, PROJ, E, PASS><<<grid, TPB, 0, st>>>(BWR_SPLIT_ARGS);
+    } else {
+        if constexpr (PROJ && W == 8 && G >= 4 && PASS == 0 && std::is_same<E, uint32_t>::value) {
+            if (use_o7()) {
+                if (acc == 2)
+                    k_spmm_split_o7<W, G, 2, false, PROJ, E, PASS><<<grid, TPB, 0, st>>>(BWR_SPLIT_ARGS);
+                else
+                    k_spmm_split_o7<W, G, 0, false, PROJ, E, PASS><<<grid, TPB, 0, st>>>(BWR_SPLIT_ARGS);
+                return hipGetLastError();
+            }
+        }
+        if (acc == 2)
+            k_spmm_split<W, G, 2, false, PROJ, E, PASS><<<grid, TPB, 0, st>>>(BWR_SPLIT_ARGS);
+        else
+            k_spmm_split<W, G, 0, false, PROJ, E, PASS><<<grid, TPB, 0, st>>>(BWR_SPLIT_ARGS);
+    }
+#undef BWR_SPLIT_ARGS
     return hipGetLastError();
 }
 
