@@ -174,7 +174,12 @@ int bwr_time_step_kernels_dev(const bwr_csr* A_dev, uint32_t p, int32_t s, int32
  * primes x block).  Each rank equals bwr_rank_modp(A[j], primes[t], block,
  * seed) exactly: same draws, same sequence, same read-out.
  * ranks_out[j * nprimes + t].  Matrices with entries outside [-127, 127] or
- * a dimension above 2^24 take the single-matrix path.  info may be NULL. */
+ * a dimension above 2^24, and matrices whose side-by-side block (larger
+ * dimension x width x 4 bytes) exceeds 8 MB (BWR_BATCH_BLOCK_BYTES), take the
+ * single-matrix path, on 3 host threads (BWR_BATCH_SOLO_THREADS) that run
+ * beside the batched launches.  The sigma-bases of a job's 16-bit primes run
+ * as one batched sigma-basis, as do those of its larger primes
+ * (BWR_SIGMA_BATCH=0: one per prime).  info may be NULL. */
 int bwr_rank_modp_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* primes, int32_t nprimes,
                         int32_t block, uint64_t seed, int64_t* ranks_out, bwr_batch_info* info);
 
@@ -232,6 +237,18 @@ int bwr_min_generator(const uint32_t* S, int64_t len, int32_t s, uint32_t p, int
  * and M-Basis leaves, s <= 32); delta_out and P_out are host memory. */
 int bwr_min_generator_dev(const uint32_t* S_dev, int64_t len, int32_t s, uint32_t p, void* stream,
                           int64_t* delta_out, uint32_t* P_out, int64_t P_cap_terms, int64_t* max_deg_out);
+
+/* bwr_min_generator_dev for n <= 4 device sequences S_dev[b] of one length
+ * and block size, sequence b mod p[b], the primes all <= 2^16 or all larger
+ * (else BWR_EINVAL): the sigma-bases run as one PM-Basis recursion whose leaf
+ * and product launches serve every sequence (Section 2.4; the sequences of
+ * one matrix at several primes share their length).  Host outputs per
+ * sequence b: delta_out + b s, P_out + b P_cap_terms s s (layout as in
+ * bwr_min_generator), max_deg_out[b].  Each result equals
+ * bwr_min_generator_dev's for that sequence alone. */
+int bwr_min_generators_dev(const uint32_t* const* S_dev, int32_t n, int64_t len, int32_t s, const uint32_t* p,
+                           void* stream, int64_t* delta_out, uint32_t* P_out, int64_t P_cap_terms,
+                           int64_t* max_deg_out);
 
 /* Rank read-out from a host sequence: generator from the first `len` terms,
  * verified on `check` further terms (S holds len + check terms), then

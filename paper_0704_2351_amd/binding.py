@@ -19,7 +19,7 @@ BWR_OK, BWR_EINVAL, BWR_EPRIME, BWR_ENOMEM, BWR_EDEVICE, BWR_EBUSY, BWR_ESHORT =
 EXPORTED = ("bwr_version", "bwr_last_error", "bwr_is_prime", "bwr_sequence_length", "bwr_set_threads",
             "bwr_random_block", "bwr_sequence", "bwr_sequence_dev", "bwr_apply_dev", "bwr_rank_modp",
             "bwr_rank_modp_dev", "bwr_min_generator", "bwr_rank_from_sequence", "bwr_time_step_kernels_dev",
-            "bwr_min_generator_dev", "bwr_rank_modp_batch", "bwr_sequence_batch", "bwr_server_create",
+            "bwr_min_generator_dev", "bwr_min_generators_dev", "bwr_rank_modp_batch", "bwr_sequence_batch", "bwr_server_create",
             "bwr_server_submit", "bwr_server_poll", "bwr_server_wait", "bwr_server_get_stats", "bwr_server_destroy")
 
 
@@ -81,6 +81,7 @@ def lib():
             "bwr_rank_from_sequence": (ctypes.c_int, [vp, i64, i64, i32, u32, vp]),
             "bwr_time_step_kernels_dev": (ctypes.c_int, [vp, u32, i32, i32, i32, vp, vp, vp]),
             "bwr_min_generator_dev": (ctypes.c_int, [vp, i64, i32, u32, vp, vp, vp, i64, vp]),
+            "bwr_min_generators_dev": (ctypes.c_int, [vp, i32, i64, i32, vp, vp, vp, vp, i64, vp]),
             "bwr_rank_modp_batch": (ctypes.c_int, [vp, i32, vp, i32, i32, u64, vp, vp]),
             "bwr_sequence_batch": (ctypes.c_int, [vp, i32, vp, i32, i32, u64, vp, vp]),
             "bwr_server_create": (ctypes.c_int, [u64, i32, i32, vp]),
@@ -288,6 +289,26 @@ def min_generator_dev(S_dev, p: int):
     _check(lib().bwr_min_generator_dev(_dptr(S_dev), int(L), int(s), int(p), _stream(), delta.ctypes.data,
                                        P.ctypes.data, int(L + 2), ctypes.byref(md)))
     return delta, P[: (md.value + 1) * s * s].reshape(md.value + 1, s, s)
+
+
+def min_generators_dev(S_devs, primes):
+    """Batched device sigma-basis of device sequence tensors (len, s, s) of one shape, one prime each:
+    a list of (delta, P) on the host."""
+    n = len(S_devs)
+    L, s, _ = S_devs[0].shape
+    ptrs = (ctypes.c_void_p * n)(*[_dptr(S) for S in S_devs])
+    pr = np.ascontiguousarray(primes, dtype=np.uint32)
+    delta = np.zeros(n * s, dtype=np.int64)
+    cap = L + 2
+    P = np.zeros(n * cap * s * s, dtype=np.uint32)
+    md = np.zeros(n, dtype=np.int64)
+    _check(lib().bwr_min_generators_dev(ptrs, int(n), int(L), int(s), pr.ctypes.data, _stream(), delta.ctypes.data,
+                                        P.ctypes.data, int(cap), md.ctypes.data))
+    out = []
+    for b in range(n):
+        Pb = P[b * cap * s * s:(b + 1) * cap * s * s]
+        out.append((delta[b * s:(b + 1) * s].copy(), Pb[: (md[b] + 1) * s * s].reshape(md[b] + 1, s, s).copy()))
+    return out
 
 
 def _csr_array(mats):

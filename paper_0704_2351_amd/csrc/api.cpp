@@ -2,10 +2,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
+#include <utility>
 #include <vector>
 
 #include "../../include/bwrank.h"
@@ -188,6 +191,17 @@ struct RankOut {
 };
 
 constexpr int64_t CHECK_TERMS = 4;
+
+// Largest block (all of a job's primes side by side, 4-byte residues) a matrix may gather from in the
+// batched launches (measured on the batched configuration: 8 MB batched the smaller half of the
+// matrices and beat both 2 MB and 512 KB), and the host threads of the single-matrix solves beside them.
+constexpr int64_t BATCH_BLOCK_BYTES = 8 << 20;
+constexpr int BATCH_SOLO_THREADS = 3;
+
+int64_t env_i64(const char* name, int64_t dflt) {
+    const char* v = getenv(name);
+    return (v && *v) ? atoll(v) : dflt;
+}
 
 // Waits for a stream's work at scope exit (so that buffers it reads outlive it on every return path).
 struct StreamDrain {
@@ -628,17 +642,67 @@ int bwr_rank_modp_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* p
         batched[j] = Ms[j].packed;
     }
     bi.t_encode = now_s() - t0;
-    // matrices the batch kernels cannot take (wide entries) go through the single-matrix path
+    // Matrices whose block of all primes side by side (outer x W residues of 4 bytes) would exceed
+    // BATCH_BLOCK_BYTES run as single-matrix solves instead: their gathers would miss the L2 of every XCD,
+    // while the single-matrix path keeps one prime per block (16-bit residues for 16-bit primes).  Those
+    // solves, and the matrices the batch kernels cannot take (wide entries), run on host threads of their
+    // own beside the batched launches.  Every rank is the same either way.
+    const int64_t block_bytes_max = env_i64("BWR_BATCH_BLOCK_BYTES", BATCH_BLOCK_BYTES);
+    for (int j = 0; j < nmat; ++j) {
+        if (!batched[j]) continue;
+        const int64_t nb = std::min(A[j]->m, A[j]->n), outer = std::max(A[j]->m, A[j]->n);
+        const int spad = ((int)std::min<int64_t>(block, nb) + 3) & ~3;
+        const int per_job = std::max(1, std::min(nprimes, 32 / std::max(spad, 1)));
+        if (outer * (int64_t)per_job * spad * 4 > block_bytes_max) batched[j] = false;
+    }
+    std::vector<std::pair<int, int>> solo;  // (matrix, prime) pairs for the single-matrix path
     for (int j = 0; j < nmat; ++j) {
         if (batched[j] || A[j]->nnz == 0 || A[j]->m == 0 || A[j]->n == 0) continue;
-        for (int t = 0; t < nprimes; ++t) {
-            RankOut ro;
-            if (!(e = rank_dev_impl(ups[j].dev, primes[t], block, seed, st, &ro)).ok()) return fail(e);
-            ranks[(size_t)j * nprimes + t] = ro.rank;
-            bi.t_sequence += ro.info.t_sequence;
-            bi.t_sigma += ro.info.t_sigma;
-        }
+        for (int t = 0; t < nprimes; ++t) solo.emplace_back(j, t);
     }
+    std::vector<std::thread> solo_threads;
+    std::mutex solo_mu;
+    std::atomic<size_t> solo_next{0};
+    Error solo_err;
+    if (!solo.empty()) {
+        hipError_t he = hipStreamSynchronize(st);  // uploads and encodings are complete
+        if (he != hipSuccess) return fail(Error::device(he, "upload"));
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+        const int nthr = (int)std::min<int64_t>((int64_t)solo.size(), std::max<int64_t>(1, env_i64("BWR_BATCH_SOLO_THREADS", BATCH_SOLO_THREADS)));
+        for (int w = 0; w < nthr; ++w)
+            solo_threads.emplace_back([&, dev] {
+                (void)hipSetDevice(dev);
+                Error le;
+                hipStream_t wst = lib_stream(&le);
+                for (size_t i; le.ok() && (i = solo_next.fetch_add(1)) < solo.size();) {
+                    const int j = solo[i].first, t = solo[i].second;
+                    RankOut ro;
+                    le = rank_dev_impl(ups[j].dev, primes[t], block, seed, wst, &ro);
+                    if (!le.ok()) break;
+                    std::lock_guard<std::mutex> lk(solo_mu);
+                    ranks[(size_t)j * nprimes + t] = ro.rank;
+                    bi.t_sequence += ro.info.t_sequence;
+                    bi.t_sigma += ro.info.t_sigma;
+                }
+                if (!le.ok()) {
+                    std::lock_guard<std::mutex> lk(solo_mu);
+                    if (solo_err.ok()) solo_err = le;
+                    solo_next.store(solo.size());  // the other threads stop too
+                }
+            });
+    }
+    // on every return path below: stop handing out single-matrix solves and join their threads
+    struct Joiner {
+        std::vector<std::thread>* th;
+        std::atomic<size_t>* next;
+        size_t n;
+        ~Joiner() {
+            next->store(n);
+            for (auto& t : *th)
+                if (t.joinable()) t.join();
+        }
+    } joiner{&solo_threads, &solo_next, solo.size()};
     std::vector<int> live_of;
     for (int j = 0; j < nmat; ++j)
         if (batched[j]) live_of.push_back(j);
@@ -702,13 +766,30 @@ int bwr_rank_modp_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* p
                     const Own& o = owner[id];
                     const BatchSpec& sp = R.spec(id);
                     left[id] = (int)sp.primes.size();
-                    for (size_t t = 0; t < sp.primes.size(); ++t) {
-                        hipEvent_t ev = nullptr;
-                        hipError_t he = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-                        if (he == hipSuccess) he = hipEventRecord(ev, st);
-                        if (he != hipSuccess) return fail(Error::device(he, "read-out event"));
-                        pool.submit((uint64_t)id * BATCH_MAX_PRIMES + t, R.sequence(id, (int)t), o.L, R.length(id), o.s,
-                                    sp.primes[t], ev);
+                    // the job's primes share L and s: one read-out (one batched sigma-basis) for its 16-bit
+                    // primes and one for the larger ones; BWR_SIGMA_BATCH=0 reads each prime out alone
+                    for (int cls = 0; cls < 2; ++cls) {
+                        uint64_t tags[BATCH_MAX_PRIMES];
+                        const uint32_t* seqs[BATCH_MAX_PRIMES];
+                        uint32_t ps[BATCH_MAX_PRIMES];
+                        int n = 0;
+                        for (size_t t = 0; t < sp.primes.size(); ++t) {
+                            if ((sp.primes[t] <= 65536u) != (cls == 0)) continue;
+                            tags[n] = (uint64_t)id * BATCH_MAX_PRIMES + t;
+                            seqs[n] = R.sequence(id, (int)t);
+                            ps[n] = sp.primes[t];
+                            ++n;
+                        }
+                        const char* sb = getenv("BWR_SIGMA_BATCH");
+                        const int group = (sb && atoi(sb) == 0) ? 1 : BATCH_MAX_PRIMES;
+                        for (int g0 = 0; g0 < n; g0 += group) {
+                            hipEvent_t ev = nullptr;
+                            hipError_t he = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+                            if (he == hipSuccess) he = hipEventRecord(ev, st);
+                            if (he != hipSuccess) return fail(Error::device(he, "read-out event"));
+                            pool.submit_group(tags + g0, seqs + g0, ps + g0, std::min(group, n - g0), o.L,
+                                              R.length(id), o.s, ev);
+                        }
                     }
                 }
             } else if (pool.outstanding() == 0) {
@@ -727,9 +808,12 @@ int bwr_rank_modp_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* p
         }
         if (!first.ok()) return fail(first);
         bi.steps = R.global_step();
+        std::lock_guard<std::mutex> lk(solo_mu);
         bi.t_sigma += t_sig;
         bi.t_sequence += now_s() - t1;
     }
+    for (auto& t : solo_threads) t.join();
+    if (!solo_err.ok()) return fail(solo_err);
     std::memcpy(ranks_out, ranks.data(), sizeof(int64_t) * ranks.size());
     bi.t_total = now_s() - t0;
     if (info) *info = bi;
@@ -764,6 +848,44 @@ int bwr_min_generator_dev(const uint32_t* S_dev, int64_t len, int32_t s, uint32_
         }
     }
     *max_deg_out = maxd;
+    g_err.clear();
+    return BWR_OK;
+}
+
+int bwr_min_generators_dev(const uint32_t* const* S_dev, int32_t n, int64_t len, int32_t s, const uint32_t* p,
+                           void* stream, int64_t* delta_out, uint32_t* P_out, int64_t P_cap_terms,
+                           int64_t* max_deg_out) {
+    if (n < 1 || n > SIGMA_BATCH_MAX || !S_dev || !p) return fail(BWR_EINVAL, "bad arguments");
+    Error e;
+    for (int b = 0; b < n; ++b)
+        if (!(e = check_prime(p[b])).ok()) return fail(e);
+    if (s < 1 || s > 64 || len < 0 || !delta_out || !P_out || !max_deg_out) return fail(BWR_EINVAL, "bad arguments");
+    for (int b = 0; b < n; ++b)
+        if (len > 0 && !S_dev[b]) return fail(BWR_EINVAL, "bad arguments");
+    if (gpu_leaf_order(s) == 0) return fail(BWR_EINVAL, "block size too large for the device sigma-basis");
+    hipStream_t st = work_stream(stream, &e);
+    if (!e.ok()) return fail(e);
+    std::vector<Generator> g(n);
+    if (!(e = gpu_min_generators(S_dev, n, len, s, p, st, g.data())).ok()) return fail(e);
+    for (int b = 0; b < n; ++b) {
+        int64_t maxd = 0;
+        for (int64_t x : g[b].delta) maxd = std::max(maxd, x);
+        if (maxd + 1 > P_cap_terms) return fail(BWR_EINVAL, "P_out capacity too small");
+    }
+    for (int b = 0; b < n; ++b) {
+        int64_t maxd = 0;
+        for (int64_t x : g[b].delta) maxd = std::max(maxd, x);
+        uint32_t* Pb = P_out + (size_t)b * P_cap_terms * s * s;
+        std::memset(Pb, 0, sizeof(uint32_t) * (size_t)(maxd + 1) * s * s);
+        for (int i = 0; i < s; ++i) {
+            delta_out[(size_t)b * s + i] = g[b].delta[i];
+            for (int j = 0; j < s; ++j) {
+                const uint32_t* src = g[b].P.at(i, j);
+                for (int64_t k = 0; k < g[b].P.len && k <= maxd; ++k) Pb[((size_t)k * s + i) * s + j] = src[k];
+            }
+        }
+        max_deg_out[b] = maxd;
+    }
     g_err.clear();
     return BWR_OK;
 }

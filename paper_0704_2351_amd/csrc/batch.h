@@ -39,12 +39,16 @@ int batch_rows_per_block(int W, int G);
 // Row split G valid for width W (second = the product carrying the projection).
 bool batch_supported(int W, int G, bool second);
 
+// Accumulator mode for a launch over jobs whose rows have at most max_len non-zeros of absolute value at
+// most max_abs: 2 (16-bit halves in int32) when a lane's share of a row keeps those sums below 2^31, else
+// 0 (int64).
+int batch_acc_mode(int64_t max_len, int32_t max_abs, int G);
 // First product for all jobs: block b belongs to the job j with start[j] <= b < start[j+1].
-hipError_t launch_batch_first(int W, int G, const BatchJob* jobs, const int32_t* start, int njobs, int nblocks,
-                              int parity, hipStream_t st);
+hipError_t launch_batch_first(int W, int G, int acc, const BatchJob* jobs, const int32_t* start, int njobs,
+                              int nblocks, int parity, hipStream_t st);
 // Second product + per-prime projection partials into partial + slot_off.
-hipError_t launch_batch_second(int W, int G, const BatchJob* jobs, const int32_t* start, int njobs, int nblocks,
-                               int parity, uint32_t* partial, int64_t slot_off, hipStream_t st);
+hipError_t launch_batch_second(int W, int G, int acc, const BatchJob* jobs, const int32_t* start, int njobs,
+                               int nblocks, int parity, uint32_t* partial, int64_t slot_off, hipStream_t st);
 // S terms of the chunk [g_first, g_first + nsteps) for every job (slot k of the chunk at k * slot_words).
 hipError_t launch_batch_reduce(const BatchJob* jobs, int njobs, int64_t g_first, int nsteps, const uint32_t* partial,
                                int64_t slot_words, int max_entries, hipStream_t st);

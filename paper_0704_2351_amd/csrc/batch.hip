@@ -4,9 +4,14 @@
 // column group belongs to one prime of the job, so a single pass over a
 // matrix serves all its primes and a gathered row of the block is W * 4 bytes
 // (128 bytes for 4 primes x 8 columns: one cache line per non-zero).
-// Accumulators are 64-bit (primes of any size mix in one launch).
+// Accumulators: ACC 2 sums the 16-bit halves of the residues in two int32
+// with full-rate 24-bit multiplies (when every active job's rows are short
+// enough for the sums to stay below 2^31), ACC 0 sums in int64; primes of any
+// size mix in one launch.  Projection sums are kept mod p in 32 bits.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "batch.h"
 #include "kernels.h"
@@ -39,7 +44,7 @@ __device__ __forceinline__ int find_job(const int32_t* __restrict__ start, int n
     return lo;
 }
 
-template <int W, int G, bool SECOND>
+template <int W, int G, bool SECOND, int ACC>
 __global__ __launch_bounds__(TPB) void k_batch(const BatchJob* __restrict__ jobs, const int32_t* __restrict__ start,
                                                int njobs, int parity, uint32_t* __restrict__ partial,
                                                int64_t slot_off) {
@@ -74,7 +79,7 @@ __global__ __launch_bounds__(TPB) void k_batch(const BatchJob* __restrict__ jobs
     const bool live = tp < np;
     const ModP mp = J.mp[live ? tp : 0];
 
-    uint64_t pacc[IPL][4];
+    uint32_t pacc[IPL][4];  // projection sums mod the lane's prime
 #pragma unroll
     for (int u = 0; u < IPL; ++u)
 #pragma unroll
@@ -84,9 +89,22 @@ __global__ __launch_bounds__(TPB) void k_batch(const BatchJob* __restrict__ jobs
         const int64_t row = tile * RPB + wave * RPW + slot;
         const bool active = row < rows;
         int64_t acc[4] = {0, 0, 0, 0};
+        int32_t ah[4] = {0, 0, 0, 0}, al[4] = {0, 0, 0, 0};
         if (active && live) {
             const int32_t b = rp[row], e = rp[row + 1];
             const uint32_t* Xs = X + cg * 4;
+            auto mac = [&](int32_t a, const uint4& x) {
+                const uint32_t xv[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    if constexpr (ACC == 2) {
+                        ah[c] += __mul24(a, (int32_t)(xv[c] >> 16));
+                        al[c] += __mul24(a, (int32_t)(xv[c] & 0xffffu));
+                    } else {
+                        acc[c] += (int64_t)a * (int64_t)xv[c];
+                    }
+                }
+            };
             int32_t t = b + j;
             for (; t + 3 * G < e; t += 4 * G) {
                 uint32_t en[4];
@@ -96,23 +114,17 @@ __global__ __launch_bounds__(TPB) void k_batch(const BatchJob* __restrict__ jobs
 #pragma unroll
                 for (int u = 0; u < 4; ++u) x[u] = *reinterpret_cast<const uint4*>(Xs + (size_t)(en[u] & 0xFFFFFFu) * W);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int64_t a = (int32_t)en[u] >> 24;
-                    acc[0] += a * (int64_t)x[u].x;
-                    acc[1] += a * (int64_t)x[u].y;
-                    acc[2] += a * (int64_t)x[u].z;
-                    acc[3] += a * (int64_t)x[u].w;
-                }
+                for (int u = 0; u < 4; ++u) mac((int32_t)en[u] >> 24, x[u]);
             }
             for (; t < e; t += G) {
                 const uint32_t en0 = ent[t];
                 const uint4 x = *reinterpret_cast<const uint4*>(Xs + (size_t)(en0 & 0xFFFFFFu) * W);
-                const int64_t a = (int32_t)en0 >> 24;
-                acc[0] += a * (int64_t)x.x;
-                acc[1] += a * (int64_t)x.y;
-                acc[2] += a * (int64_t)x.z;
-                acc[3] += a * (int64_t)x.w;
+                mac((int32_t)en0 >> 24, x);
             }
+        }
+        if constexpr (ACC == 2) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c] = (int64_t)ah[c] * 65536 + al[c];
         }
 #pragma unroll
         for (int off = CG; off < LPR; off <<= 1)
@@ -135,25 +147,31 @@ __global__ __launch_bounds__(TPB) void k_batch(const BatchJob* __restrict__ jobs
                         if (i / spad != tp) continue;  // only the diagonal blocks of one prime
                         const uint32_t u = J.Ut[(size_t)row * W + i];
 #pragma unroll
-                        for (int c = 0; c < 4; ++c) pacc[q][c] += mulmod(mp, u, y[c]);
+                        for (int c = 0; c < 4; ++c) pacc[q][c] = addmod(mp, pacc[q][c], mulmod(mp, u, y[c]));
                     }
                 }
             }
         }
     }
     if constexpr (SECOND) {
+        // sums over the row slots of the wave: at most 64 terms below 2^31 each
+        uint64_t ps[IPL][4];
+#pragma unroll
+        for (int q = 0; q < IPL; ++q)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) ps[q][c] = pacc[q][c];
 #pragma unroll
         for (int off = LPR; off < 64; off <<= 1)
 #pragma unroll
             for (int q = 0; q < IPL; ++q)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) pacc[q][c] += shfl_xor_u64(pacc[q][c], off);
+                for (int c = 0; c < 4; ++c) ps[q][c] += shfl_xor_u64(ps[q][c], off);
         __shared__ uint64_t sh[TPB / 64][W * W];
         if (lane < LPR) {
 #pragma unroll
             for (int q = 0; q < IPL; ++q)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) sh[wave][(j * IPL + q) * W + cg * 4 + c] = pacc[q][c];
+                for (int c = 0; c < 4; ++c) sh[wave][(j * IPL + q) * W + cg * 4 + c] = ps[q][c];
         }
         __syncthreads();
         const int per = spad * spad;
@@ -249,46 +267,53 @@ __global__ __launch_bounds__(TPB) void k_place_block(int64_t n, int32_t s, int W
 }
 
 template <int W, int G>
-hipError_t first_wg(const BatchJob* jobs, const int32_t* start, int njobs, int nblocks, int parity, hipStream_t st) {
+hipError_t first_wg(int acc, const BatchJob* jobs, const int32_t* start, int njobs, int nblocks, int parity,
+                    hipStream_t st) {
     if constexpr ((W / 4) * G <= 64) {
-        k_batch<W, G, false><<<nblocks, TPB, 0, st>>>(jobs, start, njobs, parity, nullptr, 0);
+        if (acc == 2)
+            k_batch<W, G, false, 2><<<nblocks, TPB, 0, st>>>(jobs, start, njobs, parity, nullptr, 0);
+        else
+            k_batch<W, G, false, 0><<<nblocks, TPB, 0, st>>>(jobs, start, njobs, parity, nullptr, 0);
         return hipGetLastError();
     }
     return hipErrorInvalidValue;
 }
 
 template <int W, int G>
-hipError_t second_wg(const BatchJob* jobs, const int32_t* start, int njobs, int nblocks, int parity, uint32_t* partial,
-                     int64_t slot_off, hipStream_t st) {
+hipError_t second_wg(int acc, const BatchJob* jobs, const int32_t* start, int njobs, int nblocks, int parity,
+                     uint32_t* partial, int64_t slot_off, hipStream_t st) {
     if constexpr ((W / 4) * G <= 64 && W % G == 0 && W / G <= 4) {
-        k_batch<W, G, true><<<nblocks, TPB, 0, st>>>(jobs, start, njobs, parity, partial, slot_off);
+        if (acc == 2)
+            k_batch<W, G, true, 2><<<nblocks, TPB, 0, st>>>(jobs, start, njobs, parity, partial, slot_off);
+        else
+            k_batch<W, G, true, 0><<<nblocks, TPB, 0, st>>>(jobs, start, njobs, parity, partial, slot_off);
         return hipGetLastError();
     }
     return hipErrorInvalidValue;
 }
 
 template <int W>
-hipError_t first_w(int G, const BatchJob* jobs, const int32_t* start, int njobs, int nblocks, int parity,
+hipError_t first_w(int G, int acc, const BatchJob* jobs, const int32_t* start, int njobs, int nblocks, int parity,
                    hipStream_t st) {
     switch (G) {
-        case 1: return first_wg<W, 1>(jobs, start, njobs, nblocks, parity, st);
-        case 2: return first_wg<W, 2>(jobs, start, njobs, nblocks, parity, st);
-        case 4: return first_wg<W, 4>(jobs, start, njobs, nblocks, parity, st);
-        case 8: return first_wg<W, 8>(jobs, start, njobs, nblocks, parity, st);
-        case 16: return first_wg<W, 16>(jobs, start, njobs, nblocks, parity, st);
+        case 1: return first_wg<W, 1>(acc, jobs, start, njobs, nblocks, parity, st);
+        case 2: return first_wg<W, 2>(acc, jobs, start, njobs, nblocks, parity, st);
+        case 4: return first_wg<W, 4>(acc, jobs, start, njobs, nblocks, parity, st);
+        case 8: return first_wg<W, 8>(acc, jobs, start, njobs, nblocks, parity, st);
+        case 16: return first_wg<W, 16>(acc, jobs, start, njobs, nblocks, parity, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <int W>
-hipError_t second_w(int G, const BatchJob* jobs, const int32_t* start, int njobs, int nblocks, int parity,
+hipError_t second_w(int G, int acc, const BatchJob* jobs, const int32_t* start, int njobs, int nblocks, int parity,
                     uint32_t* partial, int64_t slot_off, hipStream_t st) {
     switch (G) {
-        case 1: return second_wg<W, 1>(jobs, start, njobs, nblocks, parity, partial, slot_off, st);
-        case 2: return second_wg<W, 2>(jobs, start, njobs, nblocks, parity, partial, slot_off, st);
-        case 4: return second_wg<W, 4>(jobs, start, njobs, nblocks, parity, partial, slot_off, st);
-        case 8: return second_wg<W, 8>(jobs, start, njobs, nblocks, parity, partial, slot_off, st);
-        case 16: return second_wg<W, 16>(jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        case 1: return second_wg<W, 1>(acc, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        case 2: return second_wg<W, 2>(acc, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        case 4: return second_wg<W, 4>(acc, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        case 8: return second_wg<W, 8>(acc, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        case 16: return second_wg<W, 16>(acc, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -297,6 +322,11 @@ hipError_t second_w(int G, const BatchJob* jobs, const int32_t* start, int njobs
 
 int batch_rows_per_block(int W, int G) { return (TPB / 64) * (64 / ((W / 4) * G)); }
 
+int batch_acc_mode(int64_t max_len, int32_t max_abs, int G) {
+    const int64_t share = (max_len + G - 1) / G;  // non-zeros of a row one lane sums
+    return share * (int64_t)std::max(max_abs, 1) * 65535 < ((int64_t)1 << 31) ? 2 : 0;
+}
+
 bool batch_supported(int W, int G, bool second) {
     if (W != 4 && W != 8 && W != 16 && W != 32) return false;
     if (G < 1 || G > 16 || (G & (G - 1))) return false;
@@ -304,26 +334,28 @@ bool batch_supported(int W, int G, bool second) {
     return !second || (W % G == 0 && W / G <= 4);
 }
 
-hipError_t launch_batch_first(int W, int G, const BatchJob* jobs, const int32_t* start, int njobs, int nblocks,
-                              int parity, hipStream_t st) {
+hipError_t launch_batch_first(int W, int G, int acc, const BatchJob* jobs, const int32_t* start, int njobs,
+                              int nblocks, int parity, hipStream_t st) {
+    if (acc != 0 && acc != 2) return hipErrorInvalidValue;
     if (nblocks <= 0 || njobs <= 0) return hipSuccess;
     switch (W) {
-        case 4: return first_w<4>(G, jobs, start, njobs, nblocks, parity, st);
-        case 8: return first_w<8>(G, jobs, start, njobs, nblocks, parity, st);
-        case 16: return first_w<16>(G, jobs, start, njobs, nblocks, parity, st);
-        case 32: return first_w<32>(G, jobs, start, njobs, nblocks, parity, st);
+        case 4: return first_w<4>(G, acc, jobs, start, njobs, nblocks, parity, st);
+        case 8: return first_w<8>(G, acc, jobs, start, njobs, nblocks, parity, st);
+        case 16: return first_w<16>(G, acc, jobs, start, njobs, nblocks, parity, st);
+        case 32: return first_w<32>(G, acc, jobs, start, njobs, nblocks, parity, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_batch_second(int W, int G, const BatchJob* jobs, const int32_t* start, int njobs, int nblocks,
-                               int parity, uint32_t* partial, int64_t slot_off, hipStream_t st) {
+hipError_t launch_batch_second(int W, int G, int acc, const BatchJob* jobs, const int32_t* start, int njobs,
+                               int nblocks, int parity, uint32_t* partial, int64_t slot_off, hipStream_t st) {
+    if (acc != 0 && acc != 2) return hipErrorInvalidValue;
     if (nblocks <= 0 || njobs <= 0) return hipSuccess;
     switch (W) {
-        case 4: return second_w<4>(G, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
-        case 8: return second_w<8>(G, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
-        case 16: return second_w<16>(G, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
-        case 32: return second_w<32>(G, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        case 4: return second_w<4>(G, acc, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        case 8: return second_w<8>(G, acc, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        case 16: return second_w<16>(G, acc, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        case 32: return second_w<32>(G, acc, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
         default: return hipErrorInvalidValue;
     }
 }

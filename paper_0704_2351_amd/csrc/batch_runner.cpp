@@ -39,6 +39,16 @@ namespace {
 int round4(int s) { return (s + 3) & ~3; }
 
 constexpr double SECOND_BLOCKS = 2048;
+// BWR_BATCH_ACC=0 forces the int64 accumulators (tests use it to cover both kernels)
+int env_acc(int mode) {
+    const char* v = getenv("BWR_BATCH_ACC");
+    return (v && atoi(v) == 0) ? 0 : mode;
+}
+
+double second_blocks() {
+    static const double v = getenv("BWR_BATCH_BLOCKS") ? std::max(1, atoi(getenv("BWR_BATCH_BLOCKS"))) : SECOND_BLOCKS;
+    return v;
+}
 
 }  // namespace
 
@@ -200,7 +210,7 @@ Error BatchRunner::rebuild() {
     for (int id : active_) {
         BatchJob& dj = jobs_[id]->d;
         const int64_t tiles2 = std::max<int64_t>(1, (dj.rows2 + rpb2 - 1) / rpb2);
-        const int64_t want = (int64_t)(SECOND_BLOCKS * (double)dj.rows2 / std::max(rows_all, 1.0) + 0.5);
+        const int64_t want = (int64_t)(second_blocks() * (double)dj.rows2 / std::max(rows_all, 1.0) + 0.5);
         dj.nblk2 = (int32_t)std::max<int64_t>(1, std::min<int64_t>(tiles2, want));
     }
     for (int id : active_) {
@@ -216,6 +226,18 @@ Error BatchRunner::rebuild() {
     slot_words_ = std::max<int64_t>(off, 1);
     nblocks1_ = s1.back();
     nblocks2_ = s2.back();
+    // accumulators: split 32-bit sums when every active job's rows allow them
+    int64_t len1 = 0, len2 = 0;
+    int32_t vabs = 1;
+    for (int id : active_) {
+        const Job& J = *jobs_[id];
+        const DeviceMatrix& M = *J.spec.M;
+        len1 = std::max<int64_t>(len1, J.spec.transpose ? M.max_len_t : M.max_len_a);
+        len2 = std::max<int64_t>(len2, J.spec.transpose ? M.max_len_a : M.max_len_t);
+        vabs = std::max(vabs, M.max_abs);
+    }
+    acc1_ = env_acc(batch_acc_mode(len1, vabs, G1_));
+    acc2_ = env_acc(batch_acc_mode(len2, vabs, G2_));
     if (exec_) (void)hipGraphExecDestroy(exec_);
     if (graph_) (void)hipGraphDestroy(graph_);
     exec_ = nullptr;
@@ -266,8 +288,9 @@ Error BatchRunner::advance(int64_t max_steps, std::vector<int>* done) {
         auto launch_chunk = [&](int64_t steps, int64_t g_start) -> Error {
             for (int64_t i = 0; i < steps; ++i) {
                 const int par = (int)((g_start + i) & 1);
-                BWR_HIP(launch_batch_first(W_, G1_, dj, st1, nact, nblocks1_, par, st_));
-                BWR_HIP(launch_batch_second(W_, G2_, dj, st2, nact, nblocks2_, par, part, i * slot_words_, st_));
+                BWR_HIP(launch_batch_first(W_, G1_, acc1_, dj, st1, nact, nblocks1_, par, st_));
+                BWR_HIP(launch_batch_second(W_, G2_, acc2_, dj, st2, nact, nblocks2_, par, part, i * slot_words_,
+                                            st_));
             }
             return {};
         };

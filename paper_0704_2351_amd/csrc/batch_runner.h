@@ -59,6 +59,7 @@ class BatchRunner {
     bool dirty_ = true;
     DevBuf djobs_, dstart1_, dstart2_, part_;
     int nblocks1_ = 0, nblocks2_ = 0, max_entries_ = 0;
+    int acc1_ = 0, acc2_ = 0;  // accumulator modes of the active set (batch_acc_mode)
     int64_t slot_words_ = 0;
     int64_t chunk_ = 64;
     hipGraph_t graph_ = nullptr;

@@ -11,6 +11,12 @@ namespace bwr {
 
 namespace {
 
+#define BWR_TRY(expr)              \
+    do {                           \
+        Error er_ = (expr);        \
+        if (!er_.ok()) return er_; \
+    } while (0)
+
 double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -39,6 +45,30 @@ Error rank_of_sequence_dev(const uint32_t* S_dev, int64_t L, int64_t total, int3
     return rank_from_generator(g, p, rank);
 }
 
+Error rank_of_sequences_dev(const uint32_t* const* S_dev, int n, int64_t L, int64_t total, int32_t s,
+                            const uint32_t* p, hipStream_t st, int64_t* ranks, double* t_sigma) {
+    if (n < 1 || n > SIGMA_BATCH_MAX) return Error::inval("read-out batch must hold 1 to 4 sequences");
+    bool same_class = true;
+    for (int b = 1; b < n; ++b) same_class = same_class && ((p[b] <= 65536u) == (p[0] <= 65536u));
+    if (n == 1 || !same_class || gpu_leaf_order(s) == 0 || getenv("BWR_HOST_SIGMA")) {
+        for (int b = 0; b < n; ++b) BWR_TRY(rank_of_sequence_dev(S_dev[b], L, total, s, p[b], st, &ranks[b], t_sigma));
+        return {};
+    }
+    const double t0 = now_s();
+    std::vector<Generator> g(n);
+    BWR_TRY(gpu_min_generators(S_dev, n, L, s, p, st, g.data()));
+    *t_sigma += now_s() - t0;
+    std::vector<uint32_t> Sh((size_t)(total * s * s));
+    for (int b = 0; b < n; ++b) {
+        hipError_t he = hipMemcpyAsync(Sh.data(), S_dev[b], 4 * Sh.size(), hipMemcpyDeviceToHost, st);
+        if (he == hipSuccess) he = hipStreamSynchronize(st);
+        if (he != hipSuccess) return Error::device(he, "sequence download");
+        BWR_TRY(check_generator(g[b], Sh.data(), L, total, p[b]));
+        BWR_TRY(rank_from_generator(g[b], p[b], &ranks[b]));
+    }
+    return {};
+}
+
 ReadoutPool::ReadoutPool(int threads, int device) : device_(device) {
     if (const char* v = getenv("BWR_READOUT_THREADS")) threads = std::max(1, atoi(v));
     for (int i = 0; i < std::max(1, threads); ++i) workers_.emplace_back([this] { work(); });
@@ -55,12 +85,23 @@ ReadoutPool::~ReadoutPool() {
         if (t.ready) (void)hipEventDestroy(t.ready);
 }
 
-void ReadoutPool::submit(uint64_t tag, const uint32_t* S_dev, int64_t L, int64_t total, int32_t s, uint32_t p,
-                         hipEvent_t ready) {
+void ReadoutPool::submit_group(const uint64_t* tags, const uint32_t* const* S_dev, const uint32_t* p, int n,
+                               int64_t L, int64_t total, int32_t s, hipEvent_t ready) {
+    Task t{};
+    t.n = std::max(1, std::min(n, 4));
+    for (int b = 0; b < t.n; ++b) {
+        t.tag[b] = tags[b];
+        t.S[b] = S_dev[b];
+        t.p[b] = p[b];
+    }
+    t.L = L;
+    t.total = total;
+    t.s = s;
+    t.ready = ready;
     {
         std::lock_guard<std::mutex> lk(mu_);
-        queue_.push_back(Task{tag, S_dev, L, total, s, p, ready});
-        ++outstanding_;
+        queue_.push_back(t);
+        outstanding_ += (size_t)t.n;
     }
     cv_.notify_one();
 }
@@ -91,22 +132,30 @@ void ReadoutPool::work() {
             t = queue_.front();
             queue_.pop_front();
         }
-        Result r;
-        r.tag = t.tag;
+        int64_t ranks[4] = {0, 0, 0, 0};
+        double seconds = 0;
+        Error err;
         if (se != hipSuccess) {
-            r.err = Error::device(se, "read-out stream");
+            err = Error::device(se, "read-out stream");
         } else {
             hipError_t he = t.ready ? hipStreamWaitEvent(st, t.ready, 0) : hipSuccess;
-            if (he != hipSuccess) r.err = Error::device(he, "hipStreamWaitEvent");
-            else r.err = rank_of_sequence_dev(t.S, t.L, t.total, t.s, t.p, st, &r.rank, &r.seconds);
+            if (he != hipSuccess) err = Error::device(he, "hipStreamWaitEvent");
+            else err = rank_of_sequences_dev(t.S, t.n, t.L, t.total, t.s, t.p, st, ranks, &seconds);
             // the stream has been synchronized by the read-out (or nothing was queued after the wait)
-            if (!r.err.ok()) (void)hipStreamSynchronize(st);
+            if (!err.ok()) (void)hipStreamSynchronize(st);
         }
         if (t.ready) (void)hipEventDestroy(t.ready);
         {
             std::lock_guard<std::mutex> lk(mu_);
-            results_.push_back(r);
-            --outstanding_;
+            for (int b = 0; b < t.n; ++b) {
+                Result r;
+                r.tag = t.tag[b];
+                r.rank = ranks[b];
+                r.seconds = b == 0 ? seconds : 0.0;  // the group's time, counted once
+                r.err = err;
+                results_.push_back(r);
+            }
+            outstanding_ -= (size_t)t.n;
         }
         done_cv_.notify_all();
     }

@@ -21,6 +21,10 @@ namespace bwr {
 // terms L .. total - 1, and the rank it reads out.  Runs on st; adds its seconds to *t_sigma.
 Error rank_of_sequence_dev(const uint32_t* S_dev, int64_t L, int64_t total, int32_t s, uint32_t p, hipStream_t st,
                            int64_t* rank, double* t_sigma);
+// Same for n <= 4 sequences of one length and block size, one prime each: on the device the generators
+// come from one batched sigma-basis when the primes are all <= 2^16 or all larger.
+Error rank_of_sequences_dev(const uint32_t* const* S_dev, int n, int64_t L, int64_t total, int32_t s,
+                            const uint32_t* p, hipStream_t st, int64_t* ranks, double* t_sigma);
 
 // Host threads of a read-out pool: with the stream of the running batch this fills the four hardware
 // queues a process gets by default; more concurrent sigma-bases only slow each other down.
@@ -40,18 +44,25 @@ class ReadoutPool {
     // Waits (on the worker's stream) for `ready` before reading S_dev; the event is owned by the pool
     // afterwards.  S_dev must stay allocated until the task's result has been collected.
     void submit(uint64_t tag, const uint32_t* S_dev, int64_t L, int64_t total, int32_t s, uint32_t p,
-                hipEvent_t ready);
+                hipEvent_t ready) {
+        submit_group(&tag, &S_dev, &p, 1, L, total, s, ready);
+    }
+    // n <= 4 sequences of one length and block size read out together (rank_of_sequences_dev); one
+    // result per tag.
+    void submit_group(const uint64_t* tags, const uint32_t* const* S_dev, const uint32_t* p, int n, int64_t L,
+                      int64_t total, int32_t s, hipEvent_t ready);
     // Finished tasks; with wait = true blocks until at least one is available (if any is outstanding).
     std::vector<Result> collect(bool wait);
     size_t outstanding();
 
    private:
     struct Task {
-        uint64_t tag;
-        const uint32_t* S;
+        int n;
+        uint64_t tag[4];
+        const uint32_t* S[4];
+        uint32_t p[4];
         int64_t L, total;
         int32_t s;
-        uint32_t p;
         hipEvent_t ready;
     };
     void work();

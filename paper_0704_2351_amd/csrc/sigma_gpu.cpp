@@ -72,9 +72,8 @@ Error device_tables(DevTables* out) {
 
 uint32_t shoup(uint32_t w, uint32_t q) { return (uint32_t)(((uint64_t)w << 32) / q); }
 
-NttConsts make_consts(const DevTables& T, int lg, uint32_t p) {
+NttConsts make_consts(const DevTables& T, int lg, const PrimeBatch& pb) {
     NttConsts c{};
-    const ModP mp = ModP::make(p);
     for (int t = 0; t < 3; ++t) {
         c.q[t] = T.q[t];
         c.mq[t] = ModP::make(T.q[t]);
@@ -84,8 +83,11 @@ NttConsts make_consts(const DevTables& T, int lg, uint32_t p) {
     }
     c.inv01 = invmod(c.mq[1], T.q[0] % T.q[1]);
     c.inv012 = invmod(c.mq[2], mulmod(c.mq[2], T.q[0] % T.q[2], T.q[1] % T.q[2]));
-    c.q0p = red64(mp, T.q[0]);
-    c.q01p = mulmod(mp, red64(mp, T.q[0]), red64(mp, T.q[1]));
+    for (int b = 0; b < pb.n; ++b) {
+        const ModP& mp = pb.mp[b];
+        c.q0p[b] = red64(mp, T.q[0]);
+        c.q01p[b] = mulmod(mp, red64(mp, T.q[0]), red64(mp, T.q[1]));
+    }
     c.tw_stride = (int64_t)1 << MAX_LG;
     return c;
 }
@@ -96,14 +98,22 @@ int ceil_log2(int64_t x) {
     return l;
 }
 
-Error alloc_poly(int rows, int cols, int64_t len, hipStream_t st, DevBuf* buf, DPoly* P) {
-    BWR_TRY(buf->alloc(sizeof(uint32_t) * (size_t)rows * cols * (size_t)std::max<int64_t>(len, 1), st));
+Error alloc_poly(int rows, int cols, int64_t len, int batch, hipStream_t st, DevBuf* buf, DPoly* P) {
+    BWR_TRY(buf->alloc(sizeof(uint32_t) * (size_t)batch * rows * cols * (size_t)std::max<int64_t>(len, 1), st));
     P->rows = rows;
     P->cols = cols;
     P->len = len;
     P->ld = len;
     P->ptr = buf->as<uint32_t>();
+    P->batch = batch;
     return {};
+}
+
+PrimeBatch make_batch(const uint32_t* p, int nb) {
+    PrimeBatch pb;
+    pb.n = nb;
+    for (int b = 0; b < nb; ++b) pb.mp[b] = ModP::make(p[b]);
+    return pb;
 }
 
 }  // namespace
@@ -128,30 +138,32 @@ int gpu_leaf_order(int s) {
     return 0;
 }
 
-Error gpu_polymat_mul(const DPoly& A, const DPoly& B, int64_t lo, int64_t hi, uint32_t p, DPoly* C, DevBuf* Cbuf,
-                      hipStream_t st) {
-    const int r = A.rows, k = A.cols, c = B.cols;
+Error gpu_polymat_mul(const DPoly& A, const DPoly& B, int64_t lo, int64_t hi, const PrimeBatch& pb, DPoly* C,
+                      DevBuf* Cbuf, hipStream_t st) {
+    const int r = A.rows, k = A.cols, c = B.cols, nbt = A.batch;
+    if (A.cols != B.rows || A.batch != B.batch || A.batch != pb.n || pb.n < 1 || pb.n > SIGMA_BATCH_MAX)
+        return Error::inval("polynomial matrix product: shapes or batch do not match");
     const int64_t W = hi - lo;
-    BWR_TRY(alloc_poly(r, c, W, st, Cbuf, C));
-    const ModP mp = ModP::make(p);
+    BWR_TRY(alloc_poly(r, c, W, nbt, st, Cbuf, C));
     const int64_t minlen = std::min(A.len, B.len);
     if (minlen <= 32) {
         if (A.ld != A.len || B.ld != B.len) {
             // compact copies so the schoolbook kernel can assume dense rows
             DevBuf ab, bb;
             DPoly Ac, Bc;
-            BWR_TRY(alloc_poly(A.rows, A.cols, A.len, st, &ab, &Ac));
-            BWR_TRY(alloc_poly(B.rows, B.cols, B.len, st, &bb, &Bc));
-            BWR_HIP(gpu_copy_rows(Ac.ptr, A.len, A.ptr, A.ld, A.len, (int64_t)A.rows * A.cols, st));
-            BWR_HIP(gpu_copy_rows(Bc.ptr, B.len, B.ptr, B.ld, B.len, (int64_t)B.rows * B.cols, st));
-            BWR_HIP(gpu_schoolbook(Ac.ptr, A.len, Bc.ptr, B.len, r, k, c, lo, W, mp, C->ptr, st));
+            BWR_TRY(alloc_poly(A.rows, A.cols, A.len, nbt, st, &ab, &Ac));
+            BWR_TRY(alloc_poly(B.rows, B.cols, B.len, nbt, st, &bb, &Bc));
+            BWR_HIP(gpu_copy_rows(Ac.ptr, A.len, A.ptr, A.ld, A.len, (int64_t)nbt * A.rows * A.cols, st));
+            BWR_HIP(gpu_copy_rows(Bc.ptr, B.len, B.ptr, B.ld, B.len, (int64_t)nbt * B.rows * B.cols, st));
+            BWR_HIP(gpu_schoolbook(Ac.ptr, A.len, Bc.ptr, B.len, r, k, c, lo, W, pb, C->ptr, st));
             return {};
         }
-        BWR_HIP(gpu_schoolbook(A.ptr, A.len, B.ptr, B.len, r, k, c, lo, W, mp, C->ptr, st));
+        BWR_HIP(gpu_schoolbook(A.ptr, A.len, B.ptr, B.len, r, k, c, lo, W, pb, C->ptr, st));
         return {};
     }
     DevTables T;
     BWR_TRY(device_tables(&T));
+    const uint32_t p = pb.max_p();
     const double bound = (double)k * (double)minlen * (double)(p - 1) * (double)(p - 1);
     int np = 1;
     double prod = (double)T.q[0];
@@ -160,36 +172,38 @@ Error gpu_polymat_mul(const DPoly& A, const DPoly& B, int64_t lo, int64_t hi, ui
     const int lg = ceil_log2(std::max<int64_t>(hi, A.len + B.len - 1 - lo));
     if (lg > MAX_LG) return Error::inval("polynomial product too long for the transform tables");
     const int64_t N = (int64_t)1 << lg;
-    const NttConsts cs = make_consts(T, lg, p);
+    const NttConsts cs = make_consts(T, lg, pb);
     DevBuf fa, fb, fc;
-    BWR_TRY(fa.alloc(sizeof(uint32_t) * (size_t)np * r * k * N, st));
-    BWR_TRY(fb.alloc(sizeof(uint32_t) * (size_t)np * k * c * N, st));
-    BWR_TRY(fc.alloc(sizeof(uint32_t) * (size_t)np * r * c * N, st));
-    BWR_HIP(gpu_load_polys(A.ptr, A.ld, A.len, 0, r * k, N, np, cs, fa.as<uint32_t>(), st));
-    BWR_HIP(gpu_load_polys(B.ptr, B.ld, B.len, 0, k * c, N, np, cs, fb.as<uint32_t>(), st));
-    BWR_HIP(gpu_ntt(fa.as<uint32_t>(), lg, r * k, np, cs, T.tw, T.itw, true, st));
-    BWR_HIP(gpu_ntt(fb.as<uint32_t>(), lg, k * c, np, cs, T.tw, T.itw, true, st));
-    BWR_HIP(gpu_pointwise(fa.as<uint32_t>(), fb.as<uint32_t>(), fc.as<uint32_t>(), r, k, c, N, np, cs, st));
-    BWR_HIP(gpu_ntt(fc.as<uint32_t>(), lg, r * c, np, cs, T.tw, T.itw, false, st));
-    BWR_HIP(gpu_crt(fc.as<uint32_t>(), r * c, N, lo, W, np, cs, mp, C->ptr, st));
+    const int na = nbt * r * k, nbb = nbt * k * c, nc = nbt * r * c;
+    BWR_TRY(fa.alloc(sizeof(uint32_t) * (size_t)np * na * N, st));
+    BWR_TRY(fb.alloc(sizeof(uint32_t) * (size_t)np * nbb * N, st));
+    BWR_TRY(fc.alloc(sizeof(uint32_t) * (size_t)np * nc * N, st));
+    BWR_HIP(gpu_load_polys(A.ptr, A.ld, A.len, 0, na, N, np, cs, fa.as<uint32_t>(), st));
+    BWR_HIP(gpu_load_polys(B.ptr, B.ld, B.len, 0, nbb, N, np, cs, fb.as<uint32_t>(), st));
+    BWR_HIP(gpu_ntt(fa.as<uint32_t>(), lg, na, np, cs, T.tw, T.itw, true, st));
+    BWR_HIP(gpu_ntt(fb.as<uint32_t>(), lg, nbb, np, cs, T.tw, T.itw, true, st));
+    BWR_HIP(gpu_pointwise(fa.as<uint32_t>(), fb.as<uint32_t>(), fc.as<uint32_t>(), r, k, c, nbt, N, np, cs, st));
+    BWR_HIP(gpu_ntt(fc.as<uint32_t>(), lg, nc, np, cs, T.tw, T.itw, false, st));
+    BWR_HIP(gpu_crt(fc.as<uint32_t>(), nc, r * c, N, lo, W, np, cs, pb, C->ptr, st));
     return {};
 }
 
 namespace {
 
 struct Recur {
-    uint32_t p;
-    ModP mp;
+    PrimeBatch pb;
     int m, n, leaf;
-    int64_t* d;  // device shifted degrees
+    int64_t* d;  // device shifted degrees, m per batch element
     hipStream_t st;
 };
 
-// P (m x m, len sigma + 1) = order-sigma basis of G (m x n, coefficients 0 .. sigma - 1, stride G.ld)
+// P (m x m, len sigma + 1) = order-sigma basis of G (m x n, coefficients 0 .. sigma - 1, stride G.ld), for
+// every batch element
 Error pm(const Recur& R, const DPoly& G, int64_t sigma, DPoly* P, DevBuf* Pbuf) {
     if (sigma <= R.leaf) {
-        BWR_TRY(alloc_poly(R.m, R.m, sigma + 1, R.st, Pbuf, P));
-        BWR_HIP(gpu_mbasis_leaf(G.ptr, G.ld, R.m, R.n, (int)sigma, R.d, P->ptr, P->ld, R.mp, R.st));
+        BWR_TRY(alloc_poly(R.m, R.m, sigma + 1, G.batch, R.st, Pbuf, P));
+        BWR_HIP(gpu_mbasis_leaf(G.ptr, G.ld, (int64_t)G.rows * G.cols * G.ld, R.m, R.n, (int)sigma, R.d, P->ptr, P->ld,
+                                (int64_t)P->rows * P->cols * P->ld, R.pb, R.st));
         return {};
     }
     const int64_t s1 = sigma / 2, s2 = sigma - s1;
@@ -198,23 +212,25 @@ Error pm(const Recur& R, const DPoly& G, int64_t sigma, DPoly* P, DevBuf* Pbuf) 
     BWR_TRY(pm(R, G, s1, &P1, &b1));
     DPoly Gs = G;
     Gs.len = sigma;
-    BWR_TRY(gpu_polymat_mul(P1, Gs, s1, sigma, R.p, &G2, &bg2, R.st));
+    BWR_TRY(gpu_polymat_mul(P1, Gs, s1, sigma, R.pb, &G2, &bg2, R.st));
     BWR_TRY(pm(R, G2, s2, &P2, &b2));
-    BWR_TRY(gpu_polymat_mul(P2, P1, 0, sigma + 1, R.p, P, Pbuf, R.st));
+    BWR_TRY(gpu_polymat_mul(P2, P1, 0, sigma + 1, R.pb, P, Pbuf, R.st));
     return {};
 }
 
 }  // namespace
 
-Error OnlineGenerator::begin(const uint32_t* S_dev, int64_t L, int32_t s, uint32_t p, int64_t min_chunk,
-                             hipStream_t st) {
+Error OnlineGenerator::begin(const uint32_t* const* S_dev, int nb, int64_t L, int32_t s, const uint32_t* p,
+                             int64_t min_chunk, hipStream_t st) {
     leaf_ = gpu_leaf_order(s);
     if (!leaf_) return Error::inval("block size too large for the device sigma-basis");
     if (s > 64) return Error::inval("block size too large for the device sigma-basis");
-    S_ = S_dev;
+    if (nb < 1 || nb > SIGMA_BATCH_MAX) return Error::inval("sigma-basis batch must hold 1 to 4 sequences");
+    pb_ = make_batch(p, nb);
+    if (!pb_.small() && !pb_.large()) return Error::inval("a sigma-basis batch mixes 16-bit and larger primes");
+    for (int b = 0; b < nb; ++b) S_[b] = S_dev[b];
     L_ = L;
     s_ = s;
-    p_ = p;
     st_ = st;
     built_ = done_ = 0;
     next_ = pending_ = 0;
@@ -232,12 +248,13 @@ Error OnlineGenerator::begin(const uint32_t* S_dev, int64_t L, int32_t s, uint32
         cuts_.push_back(L);
     }
     const int m = 2 * s, n = s;
-    // G = [S; -I] as an m x n device polynomial matrix, filled as the terms arrive
-    BWR_TRY(alloc_poly(m, n, std::max<int64_t>(L, 1), st, &gb_, &G_));
-    std::vector<int64_t> d0(m, 0);
-    for (int i = s; i < m; ++i) d0[i] = 1;
-    BWR_TRY(db_.alloc(sizeof(int64_t) * m, st));
-    BWR_HIP(hipMemcpyAsync(db_.as<void>(), d0.data(), sizeof(int64_t) * m, hipMemcpyHostToDevice, st));
+    // G_b = [S_b; -I] as m x n device polynomial matrices, filled as the terms arrive
+    BWR_TRY(alloc_poly(m, n, std::max<int64_t>(L, 1), nb, st, &gb_, &G_));
+    std::vector<int64_t> d0((size_t)nb * m, 0);
+    for (int b = 0; b < nb; ++b)
+        for (int i = s; i < m; ++i) d0[(size_t)b * m + i] = 1;
+    BWR_TRY(db_.alloc(sizeof(int64_t) * d0.size(), st));
+    BWR_HIP(hipMemcpyAsync(db_.as<void>(), d0.data(), sizeof(int64_t) * d0.size(), hipMemcpyHostToDevice, st));
     BWR_HIP(hipStreamSynchronize(st));  // the host buffer above must outlive its copy
     return {};
 }
@@ -295,9 +312,11 @@ Error OnlineGenerator::feed(int64_t avail, hipEvent_t ready) {
     avail = std::min(avail, L_);
     if (avail <= built_) return {};
     if (ready) BWR_HIP(hipStreamWaitEvent(st_, ready, 0));
-    BWR_HIP(gpu_build_G(S_, L_, s_, p_, G_.ptr, G_.ld, built_, avail, st_));
+    const int64_t gbs = (int64_t)G_.rows * G_.cols * G_.ld;
+    for (int b = 0; b < pb_.n; ++b)
+        BWR_HIP(gpu_build_G(S_[b], L_, s_, pb_.mp[b].p, G_.ptr + b * gbs, G_.ld, built_, avail, st_));
     built_ = avail;
-    const Recur R{p_, ModP::make(p_), 2 * s_, s_, leaf_, db_.as<int64_t>(), st_};
+    const Recur R{pb_, 2 * s_, s_, leaf_, db_.as<int64_t>(), st_};
     while (next_ < (int)cuts_.size() && cuts_[next_] <= built_) {
         const int64_t c0 = done_, c1 = cuts_[next_];
         DPoly Gs = G_;
@@ -307,9 +326,9 @@ Error OnlineGenerator::feed(int64_t avail, hipEvent_t ready) {
         } else {
             DevBuf rb, pb, nb;
             DPoly Rc, P, Qn;
-            BWR_TRY(gpu_polymat_mul(Q_, Gs, c0, c1, p_, &Rc, &rb, st_));
+            BWR_TRY(gpu_polymat_mul(Q_, Gs, c0, c1, pb_, &Rc, &rb, st_));
             BWR_TRY(pm(R, Rc, c1 - c0, &P, &pb));
-            BWR_TRY(gpu_polymat_mul(P, Q_, 0, c1 + 1, p_, &Qn, &nb, st_));
+            BWR_TRY(gpu_polymat_mul(P, Q_, 0, c1 + 1, pb_, &Qn, &nb, st_));
             qb_ = std::move(nb);
             Q_ = Qn;
         }
@@ -324,47 +343,57 @@ Error OnlineGenerator::feed(int64_t avail, hipEvent_t ready) {
 Error OnlineGenerator::finish(Generator* out) {
     BWR_TRY(join_worker());
     if (done_ != L_) return Error::inval("sigma-basis finished before every term was fed");
-    const int m = 2 * s_, s = s_;
+    const int m = 2 * s_, s = s_, nbt = pb_.n;
     DevBuf ib;
     DPoly P = Q_;
     if (L_ == 0) {  // the basis of order 0 is the identity
-        BWR_TRY(alloc_poly(m, m, 1, st_, &ib, &P));
-        std::vector<uint32_t> I((size_t)m * m, 0);
-        for (int i = 0; i < m; ++i) I[(size_t)i * m + i] = 1;
+        BWR_TRY(alloc_poly(m, m, 1, nbt, st_, &ib, &P));
+        std::vector<uint32_t> I((size_t)nbt * m * m, 0);
+        for (int b = 0; b < nbt; ++b)
+            for (int i = 0; i < m; ++i) I[((size_t)b * m + i) * m + i] = 1;
         BWR_HIP(hipMemcpyAsync(P.ptr, I.data(), 4 * I.size(), hipMemcpyHostToDevice, st_));
         BWR_HIP(hipStreamSynchronize(st_));
     }
-    std::vector<int64_t> d(m);
-    BWR_HIP(hipMemcpyAsync(d.data(), db_.as<void>(), sizeof(int64_t) * m, hipMemcpyDeviceToHost, st_));
+    std::vector<int64_t> d((size_t)nbt * m);
+    BWR_HIP(hipMemcpyAsync(d.data(), db_.as<void>(), sizeof(int64_t) * d.size(), hipMemcpyDeviceToHost, st_));
     BWR_HIP(hipStreamSynchronize(st_));
-    std::vector<int> rows(m);
-    for (int r = 0; r < m; ++r) rows[r] = r;
-    std::stable_sort(rows.begin(), rows.end(), [&](int a, int b) { return d[a] < d[b]; });
-    out->s = s;
-    out->delta.assign(s, 0);
-    int64_t maxd = 0;
-    for (int i = 0; i < s; ++i) {
-        out->delta[i] = d[rows[i]];
-        maxd = std::max(maxd, out->delta[i]);
+    // per batch element: the s rows of smallest shifted degree (ties: row index), gathered on the device
+    // (coefficients above each degree zeroed and checked), then one copy each
+    std::vector<DevBuf> obs(nbt);
+    DevBuf fb;
+    BWR_TRY(fb.alloc(sizeof(int32_t) * nbt, st_));
+    BWR_HIP(hipMemsetAsync(fb.as<void>(), 0, sizeof(int32_t) * nbt, st_));
+    const int64_t pbs = (int64_t)P.rows * P.cols * P.ld;
+    for (int b = 0; b < nbt; ++b) {
+        const int64_t* db = d.data() + (size_t)b * m;
+        std::vector<int> rows(m);
+        for (int r = 0; r < m; ++r) rows[r] = r;
+        std::stable_sort(rows.begin(), rows.end(), [&](int a, int c) { return db[a] < db[c]; });
+        Generator& g = out[b];
+        g.s = s;
+        g.delta.assign(s, 0);
+        int64_t maxd = 0;
+        for (int i = 0; i < s; ++i) {
+            g.delta[i] = db[rows[i]];
+            maxd = std::max(maxd, g.delta[i]);
+        }
+        g.P.resize(s, s, maxd + 1);
+        GenRows gr{};
+        for (int i = 0; i < s; ++i) {
+            gr.row[i] = rows[i];
+            gr.delta[i] = g.delta[i];
+        }
+        BWR_TRY(obs[b].alloc(sizeof(uint32_t) * g.P.a.size(), st_));
+        BWR_HIP(gpu_extract_rows(P.ptr + b * pbs, P.ld, P.len, m, s, gr, maxd + 1, obs[b].as<uint32_t>(),
+                                 fb.as<int32_t>() + b, st_));
+        BWR_HIP(hipMemcpyAsync(g.P.a.data(), obs[b].as<void>(), sizeof(uint32_t) * g.P.a.size(),
+                               hipMemcpyDeviceToHost, st_));
     }
-    out->P.resize(s, s, maxd + 1);
-    // gather the chosen rows on the device (coefficients above each delta zeroed and checked), then one copy
-    GenRows gr{};
-    for (int i = 0; i < s; ++i) {
-        gr.row[i] = rows[i];
-        gr.delta[i] = out->delta[i];
-    }
-    DevBuf ob, fb;
-    BWR_TRY(ob.alloc(sizeof(uint32_t) * out->P.a.size(), st_));
-    BWR_TRY(fb.alloc(sizeof(int32_t), st_));
-    BWR_HIP(hipMemsetAsync(fb.as<void>(), 0, sizeof(int32_t), st_));
-    BWR_HIP(gpu_extract_rows(P.ptr, P.ld, P.len, m, s, gr, maxd + 1, ob.as<uint32_t>(), fb.as<int32_t>(), st_));
-    int32_t bad = 0;
-    BWR_HIP(hipMemcpyAsync(out->P.a.data(), ob.as<void>(), sizeof(uint32_t) * out->P.a.size(), hipMemcpyDeviceToHost,
-                           st_));
-    BWR_HIP(hipMemcpyAsync(&bad, fb.as<void>(), sizeof(int32_t), hipMemcpyDeviceToHost, st_));
+    std::vector<int32_t> bad(nbt, 0);
+    BWR_HIP(hipMemcpyAsync(bad.data(), fb.as<void>(), sizeof(int32_t) * nbt, hipMemcpyDeviceToHost, st_));
     BWR_HIP(hipStreamSynchronize(st_));
-    if (bad) return {ESHORT_, "generator row degree exceeds its shifted degree"};
+    for (int b = 0; b < nbt; ++b)
+        if (bad[b]) return {ESHORT_, "generator row degree exceeds its shifted degree"};
     return {};
 }
 
@@ -372,7 +401,7 @@ Error gpu_min_generator(const uint32_t* S_dev, int64_t L, int32_t s, uint32_t p,
                         SigmaStats* stats, int64_t min_chunk) {
     auto t0 = std::chrono::steady_clock::now();
     OnlineGenerator og;
-    BWR_TRY(og.begin(S_dev, L, s, p, min_chunk, st));
+    BWR_TRY(og.begin(&S_dev, 1, L, s, &p, min_chunk, st));
     BWR_TRY(og.feed(L, nullptr));
     BWR_TRY(og.finish(out));
     if (stats) {
@@ -380,6 +409,14 @@ Error gpu_min_generator(const uint32_t* S_dev, int64_t L, int32_t s, uint32_t p,
         stats->threads = 0;
     }
     return {};
+}
+
+Error gpu_min_generators(const uint32_t* const* S_dev, int nb, int64_t L, int32_t s, const uint32_t* p,
+                         hipStream_t st, Generator* out) {
+    OnlineGenerator og;
+    BWR_TRY(og.begin(S_dev, nb, L, s, p, 0, st));
+    BWR_TRY(og.feed(L, nullptr));
+    return og.finish(out);
 }
 
 }  // namespace bwr

@@ -5,7 +5,9 @@
 // the host.
 //
 // Layouts: a polynomial matrix is [row][col][coef] (each entry contiguous),
-// residues uint32.  Transform buffers are [prime][poly][N].
+// residues uint32; a batch of matrices (one per target prime, same shape) is
+// [batch][row][col][coef].  Transform buffers are [FFT prime][poly][N], the
+// polys of a batch in batch order.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -211,12 +213,16 @@ __global__ __launch_bounds__(TPB) void k_pointwise(const uint32_t* __restrict__ 
 }
 
 // ------------------------------------------------------------------ CRT
-// out[e][x - lo] for x in [lo, hi): residues scaled by N^-1 mod q_t, Garner, then mod p.
-__global__ __launch_bounds__(TPB) void k_crt(const uint32_t* __restrict__ C, int npoly, int64_t N, int64_t lo,
-                                             int64_t W, int T, NttConsts cs, ModP mp, uint32_t* __restrict__ out) {
+// out[e][x - lo] for x in [lo, hi): residues scaled by N^-1 mod q_t, Garner, then mod the prime of
+// poly e's batch (per_batch polys each).
+__global__ __launch_bounds__(TPB) void k_crt(const uint32_t* __restrict__ C, int npoly, int per_batch, int64_t N,
+                                             int64_t lo, int64_t W, int T, NttConsts cs, PrimeBatch pb,
+                                             uint32_t* __restrict__ out) {
     int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x;
     if (idx >= (int64_t)npoly * W) return;
     int64_t e = idx / W, x = idx % W + lo;
+    const int b = (int)(e / per_batch);
+    const ModP mp = pb.mp[b];
     uint32_t a[3];
     for (int t = 0; t < T; ++t) {
         uint32_t v = C[((size_t)t * npoly + e) * N + x];
@@ -229,12 +235,12 @@ __global__ __launch_bounds__(TPB) void k_crt(const uint32_t* __restrict__ C, int
         const uint32_t q0 = cs.q[0], q1 = cs.q[1];
         uint32_t a0m1 = a[0] >= q1 ? a[0] - q1 : a[0];
         uint32_t t1 = mulmod(cs.mq[1], subq(a[1], a0m1, q1), cs.inv01);
-        v = addmod(mp, red32(mp, a[0]), mulmod(mp, cs.q0p, red32(mp, t1)));
+        v = addmod(mp, red32(mp, a[0]), mulmod(mp, cs.q0p[b], red32(mp, t1)));
         if (T == 3) {
             const uint32_t q2 = cs.q[2];
             uint32_t x01 = addq(a[0] >= q2 ? a[0] - q2 : a[0], mulmod(cs.mq[2], q0 >= q2 ? q0 - q2 : q0, t1), q2);
             uint32_t t2 = mulmod(cs.mq[2], subq(a[2], x01, q2), cs.inv012);
-            v = addmod(mp, v, mulmod(mp, cs.q01p, red32(mp, t2)));
+            v = addmod(mp, v, mulmod(mp, cs.q01p[b], red32(mp, t2)));
         }
     }
     out[idx] = v;
@@ -246,19 +252,23 @@ __global__ __launch_bounds__(TPB) void k_crt(const uint32_t* __restrict__ C, int
 constexpr int PW_TILE = 4;
 __global__ __launch_bounds__(TPB) void k_pointwise_tiled(const uint32_t* __restrict__ A,
                                                          const uint32_t* __restrict__ B, uint32_t* __restrict__ C,
-                                                         int r, int k, int c, int64_t N, int T, NttConsts cs) {
+                                                         int r, int k, int c, int nbatch, int64_t N, int T,
+                                                         NttConsts cs) {
     const int rt = (r + PW_TILE - 1) / PW_TILE, ct = (c + PW_TILE - 1) / PW_TILE;
     const int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x;
-    if (idx >= (int64_t)T * rt * ct * N) return;
+    if (idx >= (int64_t)T * nbatch * rt * ct * N) return;
     const int64_t x = idx % N;
     int64_t rest = idx / N;
     const int lt = (int)(rest % ct);
     rest /= ct;
     const int it = (int)(rest % rt);
-    const int t = (int)(rest / rt);
+    rest /= rt;
+    const int b = (int)(rest % nbatch);
+    const int t = (int)(rest / nbatch);
     const ModP mq = cs.mq[t];
-    const uint32_t* At = A + (size_t)t * r * k * N;
-    const uint32_t* Bt = B + (size_t)t * k * c * N;
+    const uint32_t* At = A + ((size_t)t * nbatch + b) * r * k * N;
+    const uint32_t* Bt = B + ((size_t)t * nbatch + b) * k * c * N;
+    C += (size_t)b * r * c * N;
     const int i0 = it * PW_TILE, l0 = lt * PW_TILE;
     uint64_t acc[PW_TILE][PW_TILE];
 #pragma unroll
@@ -289,17 +299,23 @@ __global__ __launch_bounds__(TPB) void k_pointwise_tiled(const uint32_t* __restr
 #pragma unroll
         for (int b = 0; b < PW_TILE; ++b)
             if (i0 + a < r && l0 + b < c)
-                C[((size_t)t * r * c + (size_t)(i0 + a) * c + l0 + b) * N + x] = red64(mq, acc[a][b]);
+                C[((size_t)t * nbatch * r * c + (size_t)(i0 + a) * c + l0 + b) * N + x] = red64(mq, acc[a][b]);
 }
 
 // ------------------------------------------------------------------ schoolbook window product mod p
 __global__ __launch_bounds__(TPB) void k_schoolbook(const uint32_t* __restrict__ A, int64_t lenA,
                                                     const uint32_t* __restrict__ B, int64_t lenB, int r, int k, int c,
-                                                    int64_t lo, int64_t W, ModP mp, uint32_t* __restrict__ out) {
+                                                    int64_t lo, int64_t W, PrimeBatch pb,
+                                                    uint32_t* __restrict__ out) {
     int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x;
-    if (idx >= (int64_t)r * c * W) return;
+    if (idx >= (int64_t)pb.n * r * c * W) return;
     int64_t x = idx % W + lo;
     int64_t e = idx / W;
+    const int bt = (int)(e / ((int64_t)r * c));
+    e %= (int64_t)r * c;
+    const ModP mp = pb.mp[bt];
+    A += (size_t)bt * r * k * lenA;
+    B += (size_t)bt * k * c * lenB;
     int i = (int)(e / c), l = (int)(e % c);
     uint64_t acc_lo = 0, acc_hi = 0;
     for (int j = 0; j < k; ++j) {
@@ -322,11 +338,17 @@ __global__ __launch_bounds__(TPB) void k_schoolbook(const uint32_t* __restrict__
 constexpr int SB_COLS = 8;
 __global__ __launch_bounds__(TPB) void k_schoolbook_lds(const uint32_t* __restrict__ A, int64_t lenA,
                                                         const uint32_t* __restrict__ B, int64_t lenB, int r, int k,
-                                                        int c, int64_t lo, int64_t W, ModP mp,
+                                                        int c, int64_t lo, int64_t W, PrimeBatch pb,
                                                         uint32_t* __restrict__ out) {
     extern __shared__ uint32_t lds[];
     const int groups = (c + SB_COLS - 1) / SB_COLS;
-    const int i = blockIdx.x / groups, l0 = (blockIdx.x % groups) * SB_COLS;
+    const int bt = (int)(blockIdx.x / ((unsigned)r * groups));
+    const int blk = (int)(blockIdx.x % ((unsigned)r * groups));
+    const ModP mp = pb.mp[bt];
+    A += (size_t)bt * r * k * lenA;
+    B += (size_t)bt * k * c * lenB;
+    out += (size_t)bt * r * c * W;
+    const int i = blk / groups, l0 = (blk % groups) * SB_COLS;
     const int nl = c - l0 < SB_COLS ? c - l0 : SB_COLS;
     uint32_t* As = lds;                      // [k][lenA]
     uint32_t* Bs = lds + (size_t)k * lenA;   // [k][nl][lenB]
@@ -370,10 +392,25 @@ __global__ __launch_bounds__(TPB) void k_schoolbook_lds(const uint32_t* __restri
 // processing the rows one by one); then the pivot rows are multiplied by x.
 constexpr int LEAF_TPB = 512;
 
-__global__ __launch_bounds__(LEAF_TPB) void k_mbasis_leaf(const uint32_t* __restrict__ G, int64_t ldG, int m, int n,
-                                                          int sigma, int64_t* __restrict__ d,
-                                                          uint32_t* __restrict__ P, int64_t ldP, ModP mp, Mont mt) {
+__global__ __launch_bounds__(LEAF_TPB) void k_mbasis_leaf(const uint32_t* __restrict__ G, int64_t ldG, int64_t gbs,
+                                                          int m, int n, int sigma, int64_t* __restrict__ d,
+                                                          uint32_t* __restrict__ P, int64_t ldP, int64_t pbs,
+                                                          PrimeBatch pb) {
     extern __shared__ uint32_t smem[];
+    // batch element of this workgroup: its matrices, degrees and prime
+    const ModP mp = pb.mp[blockIdx.x];
+    G += blockIdx.x * gbs;
+    P += blockIdx.x * pbs;
+    d += (int64_t)blockIdx.x * m;
+    Mont mt;
+    mt.p = mp.p;
+    {
+        uint32_t inv = 1;  // p^-1 mod 2^32 by Newton iteration (p odd)
+        for (int i = 0; i < 5; ++i) inv *= 2u - mp.p * inv;
+        mt.pinv_neg = 0u - inv;
+        const uint32_t r1 = (uint32_t)((((uint64_t)1) << 32) % mp.p);
+        mt.r2 = mulmod(mp, r1, r1);
+    }
     const int sp = sigma + 1;
     uint32_t* R = smem;                        // [m][n][sigma]
     uint32_t* Pl = R + m * n * sigma;          // [m][m][sp]
@@ -581,10 +618,16 @@ __device__ __forceinline__ uint32_t group_bcast(uint32_t v, int sp) {
 }
 
 template <int S, bool SMALLP>
-__global__ __launch_bounds__(LEAF2_TPB) void k_mbasis_leaf2(const uint32_t* __restrict__ G, int64_t ldG, int sigma,
-                                                           int64_t* __restrict__ d, uint32_t* __restrict__ P,
-                                                           int64_t ldP, ModP mp) {
+__global__ __launch_bounds__(LEAF2_TPB) void k_mbasis_leaf2(const uint32_t* __restrict__ G, int64_t ldG, int64_t gbs,
+                                                           int sigma, int64_t* __restrict__ d,
+                                                           uint32_t* __restrict__ P, int64_t ldP, int64_t pbs,
+                                                           PrimeBatch pb) {
     constexpr int M = 2 * S, N = S;
+    // batch element of this workgroup: its matrices, degrees and prime
+    const ModP mp = pb.mp[blockIdx.x];
+    G += blockIdx.x * gbs;
+    P += blockIdx.x * pbs;
+    d += (int64_t)blockIdx.x * M;
     constexpr int LPRW = LeafLanes<M>::LPRW;
     constexpr int EC = (N + LPRW - 1) / LPRW;       // E columns per lane
     constexpr int TS = (M + LPRW - 1) / LPRW;       // T column slots per row
@@ -885,29 +928,32 @@ hipError_t gpu_ntt(uint32_t* a, int lg, int nb, int T, const NttConsts& c, const
     return hipGetLastError();
 }
 
-hipError_t gpu_pointwise(const uint32_t* A, const uint32_t* B, uint32_t* C, int r, int k, int c, int64_t N, int T,
-                         const NttConsts& cs, hipStream_t st) {
-    const int64_t tiles = (int64_t)T * ((r + PW_TILE - 1) / PW_TILE) * ((c + PW_TILE - 1) / PW_TILE) * N;
-    k_pointwise_tiled<<<grid_for(tiles, TPB), TPB, 0, st>>>(A, B, C, r, k, c, N, T, cs);
+hipError_t gpu_pointwise(const uint32_t* A, const uint32_t* B, uint32_t* C, int r, int k, int c, int nbatch,
+                         int64_t N, int T, const NttConsts& cs, hipStream_t st) {
+    const int64_t tiles =
+        (int64_t)T * nbatch * ((r + PW_TILE - 1) / PW_TILE) * ((c + PW_TILE - 1) / PW_TILE) * N;
+    k_pointwise_tiled<<<grid_for(tiles, TPB), TPB, 0, st>>>(A, B, C, r, k, c, nbatch, N, T, cs);
     return hipGetLastError();
 }
 
-hipError_t gpu_crt(const uint32_t* C, int npoly, int64_t N, int64_t lo, int64_t W, int T, const NttConsts& cs,
-                   ModP mp, uint32_t* out, hipStream_t st) {
-    k_crt<<<grid_for((int64_t)npoly * W, TPB), TPB, 0, st>>>(C, npoly, N, lo, W, T, cs, mp, out);
+hipError_t gpu_crt(const uint32_t* C, int npoly, int per_batch, int64_t N, int64_t lo, int64_t W, int T,
+                   const NttConsts& cs, const PrimeBatch& pb, uint32_t* out, hipStream_t st) {
+    if (per_batch < 1 || npoly > per_batch * pb.n) return hipErrorInvalidValue;
+    k_crt<<<grid_for((int64_t)npoly * W, TPB), TPB, 0, st>>>(C, npoly, per_batch, N, lo, W, T, cs, pb, out);
     return hipGetLastError();
 }
 
 hipError_t gpu_schoolbook(const uint32_t* A, int64_t lenA, const uint32_t* B, int64_t lenB, int r, int k, int c,
-                          int64_t lo, int64_t W, ModP mp, uint32_t* out, hipStream_t st) {
+                          int64_t lo, int64_t W, const PrimeBatch& pb, uint32_t* out, hipStream_t st) {
+    if (pb.n < 1 || pb.n > SIGMA_BATCH_MAX) return hipErrorInvalidValue;
     const int nl = c < SB_COLS ? c : SB_COLS;
     const size_t lds = sizeof(uint32_t) * ((size_t)k * lenA + (size_t)k * nl * lenB);
     if (lds <= 48 * 1024 && r > 0 && c > 0 && W > 0) {
-        const unsigned grid = (unsigned)r * (unsigned)((c + SB_COLS - 1) / SB_COLS);
-        k_schoolbook_lds<<<grid, TPB, lds, st>>>(A, lenA, B, lenB, r, k, c, lo, W, mp, out);
+        const unsigned grid = (unsigned)pb.n * (unsigned)r * (unsigned)((c + SB_COLS - 1) / SB_COLS);
+        k_schoolbook_lds<<<grid, TPB, lds, st>>>(A, lenA, B, lenB, r, k, c, lo, W, pb, out);
         return hipGetLastError();
     }
-    k_schoolbook<<<grid_for((int64_t)r * c * W, TPB), TPB, 0, st>>>(A, lenA, B, lenB, r, k, c, lo, W, mp, out);
+    k_schoolbook<<<grid_for((int64_t)pb.n * r * c * W, TPB), TPB, 0, st>>>(A, lenA, B, lenB, r, k, c, lo, W, pb, out);
     return hipGetLastError();
 }
 
@@ -918,59 +964,54 @@ size_t mbasis_leaf2_lds(int m, int n, int sigma) {
 namespace {
 
 template <int S, bool SMALLP>
-hipError_t leaf2_launch(const uint32_t* G, int64_t ldG, int sigma, int64_t* d, uint32_t* P, int64_t ldP, ModP mp,
-                        hipStream_t st) {
+hipError_t leaf2_launch(const uint32_t* G, int64_t ldG, int64_t gbs, int sigma, int64_t* d, uint32_t* P, int64_t ldP,
+                        int64_t pbs, const PrimeBatch& pb, hipStream_t st) {
     const size_t lds = mbasis_leaf2_lds(2 * S, S, sigma);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mbasis_leaf2<S, SMALLP>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    k_mbasis_leaf2<S, SMALLP><<<1, LEAF2_TPB, lds, st>>>(G, ldG, sigma, d, P, ldP, mp);
+    k_mbasis_leaf2<S, SMALLP><<<(unsigned)pb.n, LEAF2_TPB, lds, st>>>(G, ldG, gbs, sigma, d, P, ldP, pbs, pb);
     return hipGetLastError();
 }
 
 template <int S>
-hipError_t leaf2_s(const uint32_t* G, int64_t ldG, int sigma, int64_t* d, uint32_t* P, int64_t ldP, ModP mp,
-                   hipStream_t st) {
-    if (mp.p <= 65536u) return leaf2_launch<S, true>(G, ldG, sigma, d, P, ldP, mp, st);
-    return leaf2_launch<S, false>(G, ldG, sigma, d, P, ldP, mp, st);
+hipError_t leaf2_s(const uint32_t* G, int64_t ldG, int64_t gbs, int sigma, int64_t* d, uint32_t* P, int64_t ldP,
+                   int64_t pbs, const PrimeBatch& pb, hipStream_t st) {
+    if (pb.small()) return leaf2_launch<S, true>(G, ldG, gbs, sigma, d, P, ldP, pbs, pb, st);
+    if (pb.large()) return leaf2_launch<S, false>(G, ldG, gbs, sigma, d, P, ldP, pbs, pb, st);
+    return hipErrorInvalidValue;  // a batch is all 16-bit primes or all larger ones
 }
 
 }  // namespace
 
-hipError_t gpu_mbasis_leaf(const uint32_t* G, int64_t ldG, int m, int n, int sigma, int64_t* d, uint32_t* P,
-                           int64_t ldP, ModP mp, hipStream_t st) {
+hipError_t gpu_mbasis_leaf(const uint32_t* G, int64_t ldG, int64_t gbs, int m, int n, int sigma, int64_t* d,
+                           uint32_t* P, int64_t ldP, int64_t pbs, const PrimeBatch& pb, hipStream_t st) {
+    if (pb.n < 1 || pb.n > SIGMA_BATCH_MAX) return hipErrorInvalidValue;
     if (m == 2 * n && n >= 1 && n <= LEAF2_MAX_S) {
         switch (n) {
-            case 1: return leaf2_s<1>(G, ldG, sigma, d, P, ldP, mp, st);
-            case 2: return leaf2_s<2>(G, ldG, sigma, d, P, ldP, mp, st);
-            case 3: return leaf2_s<3>(G, ldG, sigma, d, P, ldP, mp, st);
-            case 4: return leaf2_s<4>(G, ldG, sigma, d, P, ldP, mp, st);
-            case 5: return leaf2_s<5>(G, ldG, sigma, d, P, ldP, mp, st);
-            case 6: return leaf2_s<6>(G, ldG, sigma, d, P, ldP, mp, st);
-            case 7: return leaf2_s<7>(G, ldG, sigma, d, P, ldP, mp, st);
-            case 8: return leaf2_s<8>(G, ldG, sigma, d, P, ldP, mp, st);
-            case 9: return leaf2_s<9>(G, ldG, sigma, d, P, ldP, mp, st);
-            case 10: return leaf2_s<10>(G, ldG, sigma, d, P, ldP, mp, st);
-            case 11: return leaf2_s<11>(G, ldG, sigma, d, P, ldP, mp, st);
-            case 12: return leaf2_s<12>(G, ldG, sigma, d, P, ldP, mp, st);
-            case 13: return leaf2_s<13>(G, ldG, sigma, d, P, ldP, mp, st);
-            case 14: return leaf2_s<14>(G, ldG, sigma, d, P, ldP, mp, st);
-            case 15: return leaf2_s<15>(G, ldG, sigma, d, P, ldP, mp, st);
-            case 16: return leaf2_s<16>(G, ldG, sigma, d, P, ldP, mp, st);
+            case 1: return leaf2_s<1>(G, ldG, gbs, sigma, d, P, ldP, pbs, pb, st);
+            case 2: return leaf2_s<2>(G, ldG, gbs, sigma, d, P, ldP, pbs, pb, st);
+            case 3: return leaf2_s<3>(G, ldG, gbs, sigma, d, P, ldP, pbs, pb, st);
+            case 4: return leaf2_s<4>(G, ldG, gbs, sigma, d, P, ldP, pbs, pb, st);
+            case 5: return leaf2_s<5>(G, ldG, gbs, sigma, d, P, ldP, pbs, pb, st);
+            case 6: return leaf2_s<6>(G, ldG, gbs, sigma, d, P, ldP, pbs, pb, st);
+            case 7: return leaf2_s<7>(G, ldG, gbs, sigma, d, P, ldP, pbs, pb, st);
+            case 8: return leaf2_s<8>(G, ldG, gbs, sigma, d, P, ldP, pbs, pb, st);
+            case 9: return leaf2_s<9>(G, ldG, gbs, sigma, d, P, ldP, pbs, pb, st);
+            case 10: return leaf2_s<10>(G, ldG, gbs, sigma, d, P, ldP, pbs, pb, st);
+            case 11: return leaf2_s<11>(G, ldG, gbs, sigma, d, P, ldP, pbs, pb, st);
+            case 12: return leaf2_s<12>(G, ldG, gbs, sigma, d, P, ldP, pbs, pb, st);
+            case 13: return leaf2_s<13>(G, ldG, gbs, sigma, d, P, ldP, pbs, pb, st);
+            case 14: return leaf2_s<14>(G, ldG, gbs, sigma, d, P, ldP, pbs, pb, st);
+            case 15: return leaf2_s<15>(G, ldG, gbs, sigma, d, P, ldP, pbs, pb, st);
+            case 16: return leaf2_s<16>(G, ldG, gbs, sigma, d, P, ldP, pbs, pb, st);
             default: break;
         }
     }
     size_t lds = mbasis_leaf_lds(m, n, sigma);
-    Mont mt;
-    mt.p = mp.p;
-    uint32_t inv = 1;  // p^-1 mod 2^32 by Newton iteration (p odd)
-    for (int i = 0; i < 5; ++i) inv *= 2u - mp.p * inv;
-    mt.pinv_neg = 0u - inv;
-    const uint64_t r1 = ((uint64_t)1 << 32) % mp.p;
-    mt.r2 = (uint32_t)((r1 * r1) % mp.p);
-    k_mbasis_leaf<<<1, LEAF_TPB, lds, st>>>(G, ldG, m, n, sigma, d, P, ldP, mp, mt);
+    k_mbasis_leaf<<<(unsigned)pb.n, LEAF_TPB, lds, st>>>(G, ldG, gbs, m, n, sigma, d, P, ldP, pbs, pb);
     return hipGetLastError();
 }
 

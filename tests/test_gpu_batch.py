@@ -88,6 +88,29 @@ def test_batched_ranks_equal_single_ranks():
             assert bw.rank_modp(mats[j], p, 8, 1)[0] == ranks[j, t]
 
 
+@pytest.mark.parametrize("limit", ["1", "150000"])
+def test_batched_ranks_with_single_matrix_share(limit, monkeypatch):
+    """Matrices whose block of all primes exceeds the batched launches' budget (BWR_BATCH_BLOCK_BYTES) run
+    as single-matrix solves on host threads beside the batched launches (all of them with limit 1, the
+    larger ones with 150000): the ranks are those of the all-batched run and the planted ones."""
+    need_gpu()
+    announce(f"batched ranks with single-matrix share, limit {limit}")
+    rng = np.random.default_rng(5)
+    mats = []
+    for j in range(6):
+        n = int(rng.integers(300, 2500))
+        mats.append(planted(int(n * rng.uniform(1.2, 2.0)), n, int(n * rng.uniform(0.7, 0.95)), 9, 4200 + j))
+    want, _ = bw.rank_modp_batch(mats, PRIMES4, 8, 1)
+    monkeypatch.setenv("BWR_BATCH_BLOCK_BYTES", limit)
+    got, info = bw.rank_modp_batch(mats, PRIMES4, 8, 1)
+    announce(f"  info {info}")
+    assert np.array_equal(got, want)
+    for j, A in enumerate(mats):
+        assert (got[j] == A.planted_rank).all(), j
+    if limit == "1":
+        assert info["jobs"] == 0
+
+
 def test_batched_ranks_with_wide_entries_and_empty():
     need_gpu()
     announce("batched ranks, wide entries and empty matrix")

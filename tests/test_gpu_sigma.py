@@ -80,6 +80,32 @@ def test_chunked_generator_equals_one_call(L, s, p, min_chunk, monkeypatch):
     assert np.array_equal(P_dev, P_host)
 
 
+@pytest.mark.parametrize("primes,L,s", [((65521, 65519, 65497), 900, 8), ((2**31 - 1, 2147483629), 700, 4),
+                                         ((65521, 65519, 65497, 40009), 300, 3), ((2**31 - 1,), 260, 8),
+                                         ((40009, 3), 150, 16), ((65537, 1000003), 120, 16)])
+def test_batched_generators_equal_single(primes, L, s):
+    """Several sequences of one shape, one prime each, through one batched recursion: each generator equals
+    the one the single-sequence device sigma-basis gives, entry for entry."""
+    torch = need_gpu()
+    announce(f"batched device sigma-basis primes={primes} L={L} s={s}")
+    rng = np.random.default_rng(L + s)
+    seqs = [rng.integers(0, p, size=(L, s, s), dtype=np.int64) for p in primes]
+    devs = [to_dev(torch, S) for S in seqs]
+    got = bw.min_generators_dev(devs, primes)
+    for (d, P), S_dev, p in zip(got, devs, primes):
+        d1, P1 = bw.min_generator_dev(S_dev, p)
+        assert np.array_equal(d, d1)
+        assert np.array_equal(P, P1)
+
+
+def test_batched_generators_refuse_mixed_classes():
+    torch = need_gpu()
+    announce("batched device sigma-basis mixed prime classes")
+    S = to_dev(torch, np.ones((40, 2, 2), dtype=np.int64))
+    with pytest.raises(bw.BwrError):
+        bw.min_generators_dev([S, S], (65521, 2**31 - 1))
+
+
 def test_device_generator_zero_sequence():
     torch = need_gpu()
     announce("device sigma-basis zero sequence")
