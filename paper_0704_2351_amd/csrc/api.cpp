@@ -170,7 +170,7 @@ Error sequence_dev_impl(const CsrView& A, const uint32_t* d_row, const uint32_t*
     if (len > 0 && (!S_out || (A.n > 0 && (!U || !V)))) return Error::inval("NULL output or block");
     if (len == 0) return {};
     DeviceMatrix M;
-    if (!(e = encode_matrix(A, p, st, &M)).ok()) return e;
+    if (!(e = encode_matrix(A, p, st, &M, true)).ok()) return e;
     SequenceArgs a;
     a.M = &M;
     a.transpose = false;
@@ -224,7 +224,7 @@ Error rank_dev_impl(const CsrView& A, uint32_t p, int32_t block, uint64_t seed, 
     info.nb = nb;
     info.transposed = transpose ? 1 : 0;
     DeviceMatrix M;
-    if (!(e = encode_matrix(A, p, st, &M)).ok()) return e;
+    if (!(e = encode_matrix(A, p, st, &M, true)).ok()) return e;
     info.t_encode = now_s() - t0;
     if (nb == 0 || A.nnz == 0) {
         out->rank = 0;
@@ -513,7 +513,7 @@ int bwr_time_step_kernels_dev(const bwr_csr* A_dev, uint32_t p, int32_t s, int32
     hipStream_t st = work_stream(stream, &e);
     if (!e.ok()) return fail(e);
     DeviceMatrix M;
-    if (!(e = encode_matrix(view(A_dev), p, st, &M)).ok()) return fail(e);
+    if (!(e = encode_matrix(view(A_dev), p, st, &M, true)).ok()) return fail(e);
     StepPlan pl;
     if (!(e = time_step_kernels(M, transpose != 0, ModP::make(p), s, iters, st, us_out, &pl)).ok()) return fail(e);
     if (plan_out) {

@@ -86,7 +86,9 @@ Error check_host_csr(const CsrView& A) {
     return {};
 }
 
-Error encode_matrix(const CsrView& A, uint32_t p, hipStream_t st, DeviceMatrix* M) {
+namespace {
+
+Error encode_plain(const CsrView& A, uint32_t p, hipStream_t st, DeviceMatrix* M) {
     if (A.m < 0 || A.n < 0 || A.nnz < 0) return Error::inval("negative size");
     if (A.m >= (1LL << 31) - 1 || A.n >= (1LL << 31) - 1) return Error::inval("dimension must be below 2^31 - 1");
     if (A.nnz >= (1LL << 31)) return Error::inval("nnz must be below 2^31");
@@ -161,6 +163,59 @@ Error encode_matrix(const CsrView& A, uint32_t p, hipStream_t st, DeviceMatrix* 
     BWR_HIP(hipMemcpyAsync(&mlt, mx.as<int32_t>(), sizeof(mlt), hipMemcpyDeviceToHost, st));
     BWR_HIP(hipStreamSynchronize(st));
     M->max_len_t = mlt;
+    return {};
+}
+
+// Indices 0 .. count-1 in order of decreasing length (stable; lengths above 4095 count as 4095).
+std::vector<int32_t> by_decreasing_length(const std::vector<int32_t>& len) {
+    constexpr int KMAX = 4095;
+    std::vector<int64_t> start(KMAX + 2, 0);
+    for (int32_t l : len) ++start[KMAX - std::min(std::max(l, 0), KMAX) + 1];
+    for (int k = 0; k <= KMAX; ++k) start[k + 1] += start[k];
+    std::vector<int32_t> order(len.size());
+    for (size_t i = 0; i < len.size(); ++i) order[start[KMAX - std::min(std::max(len[i], 0), KMAX)]++] = (int32_t)i;
+    return order;
+}
+
+}  // namespace
+
+Error encode_matrix(const CsrView& A, uint32_t p, hipStream_t st, DeviceMatrix* M, bool sort) {
+    BWR_TRY(encode_plain(A, p, st, M));
+    const char* ns = getenv("BWR_NO_SORT");
+    if (!sort || (ns && atoi(ns) != 0) || A.m < 2 || A.n < 1 || A.nnz == 0) return {};
+    // row lengths of A and of A^T from the encoding just built
+    std::vector<int32_t> rpa((size_t)A.m + 1), rpt((size_t)A.n + 1);
+    BWR_HIP(hipMemcpyAsync(rpa.data(), M->rp_a.as<void>(), sizeof(int32_t) * rpa.size(), hipMemcpyDeviceToHost, st));
+    BWR_HIP(hipMemcpyAsync(rpt.data(), M->rp_t.as<void>(), sizeof(int32_t) * rpt.size(), hipMemcpyDeviceToHost, st));
+    BWR_HIP(hipStreamSynchronize(st));
+    std::vector<int32_t> lr((size_t)A.m), lc((size_t)A.n);
+    for (int64_t i = 0; i < A.m; ++i) lr[i] = rpa[i + 1] - rpa[i];
+    for (int64_t j = 0; j < A.n; ++j) lc[j] = rpt[j + 1] - rpt[j];
+    const std::vector<int32_t> perm_r = by_decreasing_length(lr), perm_c = by_decreasing_length(lc);
+    std::vector<int32_t> inv_c((size_t)A.n);
+    for (int64_t j = 0; j < A.n; ++j) inv_c[perm_c[j]] = (int32_t)j;
+    std::vector<int64_t> rp_new((size_t)A.m + 1, 0);
+    for (int64_t i = 0; i < A.m; ++i) rp_new[i + 1] = rp_new[i] + lr[perm_r[i]];
+    DevBuf d_pr, d_pc, d_ic, d_rp, d_col, d_val;
+    BWR_TRY(d_pr.alloc(sizeof(int32_t) * perm_r.size(), st));
+    BWR_TRY(d_pc.alloc(sizeof(int32_t) * perm_c.size(), st));
+    BWR_TRY(d_ic.alloc(sizeof(int32_t) * inv_c.size(), st));
+    BWR_TRY(d_rp.alloc(sizeof(int64_t) * rp_new.size(), st));
+    BWR_TRY(d_col.alloc(sizeof(int32_t) * (size_t)A.nnz, st));
+    BWR_TRY(d_val.alloc(sizeof(int32_t) * (size_t)A.nnz, st));
+    BWR_HIP(hipMemcpyAsync(d_pr.as<void>(), perm_r.data(), sizeof(int32_t) * perm_r.size(), hipMemcpyHostToDevice, st));
+    BWR_HIP(hipMemcpyAsync(d_pc.as<void>(), perm_c.data(), sizeof(int32_t) * perm_c.size(), hipMemcpyHostToDevice, st));
+    BWR_HIP(hipMemcpyAsync(d_ic.as<void>(), inv_c.data(), sizeof(int32_t) * inv_c.size(), hipMemcpyHostToDevice, st));
+    BWR_HIP(hipMemcpyAsync(d_rp.as<void>(), rp_new.data(), sizeof(int64_t) * rp_new.size(), hipMemcpyHostToDevice, st));
+    BWR_HIP(launch_permute_csr(A.m, d_rp.as<int64_t>(), d_pr.as<int32_t>(), A.row_ptr, A.col_idx, A.val,
+                               d_ic.as<int32_t>(), d_col.as<int32_t>(), d_val.as<int32_t>(), st));
+    const CsrView B{A.m, A.n, A.nnz, d_rp.as<int64_t>(), d_col.as<int32_t>(), d_val.as<int32_t>()};
+    DeviceMatrix S;
+    BWR_TRY(encode_plain(B, p, st, &S));  // synchronizes st, so the host vectors above have been read
+    S.sorted = true;
+    S.perm_r = std::move(d_pr);
+    S.perm_c = std::move(d_pc);
+    *M = std::move(S);
     return {};
 }
 
@@ -528,12 +583,12 @@ struct PlanKey {
     int dev;
     int64_t m, n, nnz;
     int32_t la, lt;
-    bool transpose;
+    bool transpose, sorted;
     int W, esize;
     uint32_t p;
     bool operator<(const PlanKey& o) const {
-        return std::tie(dev, m, n, nnz, la, lt, transpose, W, esize, p) <
-               std::tie(o.dev, o.m, o.n, o.nnz, o.la, o.lt, o.transpose, o.W, o.esize, o.p);
+        return std::tie(dev, m, n, nnz, la, lt, transpose, sorted, W, esize, p) <
+               std::tie(o.dev, o.m, o.n, o.nnz, o.la, o.lt, o.transpose, o.sorted, o.W, o.esize, o.p);
     }
 };
 std::mutex g_plan_mu;
@@ -542,7 +597,7 @@ std::map<PlanKey, StepPlan> g_plans;
 Error tuned_plan(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl, hipStream_t st) {
     int dev = 0;
     BWR_HIP(hipGetDevice(&dev));
-    const PlanKey key{dev, M.m, M.n, M.nnz, M.max_len_a, M.max_len_t, transpose, pl->W, pl->esize, mp.p};
+    const PlanKey key{dev, M.m, M.n, M.nnz, M.max_len_a, M.max_len_t, transpose, M.sorted, pl->W, pl->esize, mp.p};
     const bool cache = env_int("BWR_NO_PLAN_CACHE", 0) == 0 && getenv("BWR_PARTS") == nullptr;
     if (cache) {
         std::lock_guard<std::mutex> lk(g_plan_mu);
@@ -585,6 +640,35 @@ Error run_sequence(const SequenceArgs& a, hipStream_t st) {
     SplitOp so1, so2;
     if (pl.parts1 == 2) BWR_TRY(build_split(op1, nb, M.nnz, W, st, &so1));
     if (pl.parts2 == 2) BWR_TRY(build_split(op2, outer, M.nnz, W, st, &so2));
+    // a length-sorted encoding works in relabelled coordinates: U, V, D_c (iterated side) and D_r (other
+    // side) are gathered into that order, which leaves every S_k unchanged
+    const uint32_t* aU = a.U;
+    const uint32_t* aV = a.V;
+    const uint32_t* aDr = a.d_row;
+    const uint32_t* aDc = a.d_col;
+    DevBuf gU, gV, gDr, gDc;
+    if (M.sorted) {
+        const int32_t* pn = (a.transpose ? M.perm_r : M.perm_c).as<int32_t>();  // iterated side
+        const int32_t* po = (a.transpose ? M.perm_c : M.perm_r).as<int32_t>();  // other side
+        if (nb > 0) {
+            BWR_TRY(gU.alloc(sizeof(uint32_t) * (size_t)(nb * a.s), st));
+            BWR_TRY(gV.alloc(sizeof(uint32_t) * (size_t)(nb * a.s), st));
+            BWR_HIP(launch_gather_rows(nb, a.s, pn, a.U, gU.as<uint32_t>(), st));
+            BWR_HIP(launch_gather_rows(nb, a.s, pn, a.V, gV.as<uint32_t>(), st));
+            aU = gU.as<uint32_t>();
+            aV = gV.as<uint32_t>();
+            if (a.d_col) {
+                BWR_TRY(gDc.alloc(sizeof(uint32_t) * (size_t)nb, st));
+                BWR_HIP(launch_gather_rows(nb, 1, pn, a.d_col, gDc.as<uint32_t>(), st));
+                aDc = gDc.as<uint32_t>();
+            }
+        }
+        if (a.d_row && outer > 0) {
+            BWR_TRY(gDr.alloc(sizeof(uint32_t) * (size_t)outer, st));
+            BWR_HIP(launch_gather_rows(outer, 1, po, a.d_row, gDr.as<uint32_t>(), st));
+            aDr = gDr.as<uint32_t>();
+        }
+    }
     DevBuf Ut, X0, X1, Y, dr, dc2, part, flag;
     BWR_TRY(Ut.alloc(es * (size_t)(nb * W), st));
     BWR_TRY(X0.alloc(es * (size_t)(nb * W), st));
@@ -594,19 +678,19 @@ Error run_sequence(const SequenceArgs& a, hipStream_t st) {
     BWR_HIP(hipMemsetAsync(flag.as<int32_t>(), 0, sizeof(int32_t), st));
     const uint32_t* drp = nullptr;
     const uint32_t* dc2p = nullptr;
-    if (a.d_row && outer > 0) {
+    if (aDr && outer > 0) {
         BWR_TRY(dr.alloc(sizeof(uint32_t) * (size_t)outer, st));
-        BWR_HIP(launch_reduce_vec(outer, a.d_row, mp, dr.as<uint32_t>(), st));
+        BWR_HIP(launch_reduce_vec(outer, aDr, mp, dr.as<uint32_t>(), st));
         drp = dr.as<uint32_t>();
     }
-    if (a.d_col && nb > 0) {
+    if (aDc && nb > 0) {
         BWR_TRY(dc2.alloc(sizeof(uint32_t) * (size_t)nb, st));
-        BWR_HIP(launch_square_diag(nb, a.d_col, mp, dc2.as<uint32_t>(), flag.as<int32_t>(), st));
+        BWR_HIP(launch_square_diag(nb, aDc, mp, dc2.as<uint32_t>(), flag.as<int32_t>(), st));
         dc2p = dc2.as<uint32_t>();
     }
     // X_0 = D_c V and U~ = D_c^{-1} U, so that S_k = U~^T X_k with X_{k+1} = D_c^2 A^T D_r A X_k
-    BWR_HIP(launch_pad_scale(nb, a.s, W, a.U, a.d_col, a.d_col ? 2 : 0, mp, Ut.as<void>(), pl.esize, st));
-    BWR_HIP(launch_pad_scale(nb, a.s, W, a.V, a.d_col, a.d_col ? 1 : 0, mp, X0.as<void>(), pl.esize, st));
+    BWR_HIP(launch_pad_scale(nb, a.s, W, aU, aDc, aDc ? 2 : 0, mp, Ut.as<void>(), pl.esize, st));
+    BWR_HIP(launch_pad_scale(nb, a.s, W, aV, aDc, aDc ? 1 : 0, mp, X0.as<void>(), pl.esize, st));
 
     const size_t per_step = (size_t)pl.NB * W * W;
     int64_t CH = 256;
@@ -681,6 +765,7 @@ Error run_sequence(const SequenceArgs& a, hipStream_t st) {
 
 Error apply_once(const DeviceMatrix& M, bool transpose, ModP mp, int32_t s, const uint32_t* d_row,
                  const uint32_t* d_col, const uint32_t* X, uint32_t* Z, hipStream_t st) {
+    if (M.sorted) return Error::inval("one application of B needs the plain (unsorted) encoding");
     if (!M.packed && M.wide_p != mp.p) return Error::inval("matrix was encoded for another prime");
     const int W = padded_width(s);
     if (!W) return Error::inval("block size must be in 1..64");

@@ -55,6 +55,10 @@ struct DeviceMatrix {
     uint32_t wide_p = 0;  // prime the wide values are reduced for
     DevBuf rp_a, ent_a, rp_t, ent_t;     // packed (ent) or wide columns (ent as int32)
     DevBuf val_a, val_t;                 // wide residues
+    // Length-sorted encoding: row i of the encoded A is row perm_r[i] of the input and column j is input
+    // column perm_c[j] (int32, device), so that rows of A and of A^T come in order of decreasing length
+    bool sorted = false;
+    DevBuf perm_r, perm_c;
 };
 
 struct CsrView {  // caller-owned CSR (host or device pointers)
@@ -65,8 +69,14 @@ struct CsrView {  // caller-owned CSR (host or device pointers)
 };
 
 // Validate and encode a device-resident CSR.  p is used only by the wide form
-// (values beyond int8 or dimensions beyond 2^24).
-Error encode_matrix(const CsrView& A_dev, uint32_t p, hipStream_t st, DeviceMatrix* out);
+// (values beyond int8 or dimensions beyond 2^24).  With sort, the rows and the
+// columns are relabelled in order of decreasing length (a wave of the row-split
+// kernels then holds rows of similar length, so its dependent load chains are
+// about as long as its rows need, not as long as the longest row of a random
+// mix); run_sequence permutes the draws to match, so every S_k is unchanged
+// (S_k = U^T B^k V is invariant under a simultaneous relabelling).
+// BWR_NO_SORT=1 turns the relabelling off.
+Error encode_matrix(const CsrView& A_dev, uint32_t p, hipStream_t st, DeviceMatrix* out, bool sort = false);
 
 // Host CSR checks (row pointers, column range) before any upload.
 Error check_host_csr(const CsrView& A);

@@ -43,6 +43,13 @@ hipError_t launch_col_count(int64_t m, const int64_t* rp64, const int32_t* col, 
 hipError_t launch_exclusive_scan(int64_t count, const int32_t* in, int32_t* out /* count + 1 */,
                                  int32_t* tmp /* >= scan_tmp_words(count) */, hipStream_t st);
 int64_t scan_tmp_words(int64_t count);
+// Relabelled CSR: row i = input row perm_r[i], columns mapped through inv_c; rp_out (m + 1) given.
+hipError_t launch_permute_csr(int64_t m, const int64_t* rp_out, const int32_t* perm_r, const int64_t* rp64,
+                              const int32_t* col, const int32_t* val, const int32_t* inv_c, int32_t* col_out,
+                              int32_t* val_out, hipStream_t st);
+// dst[i][c] = src[perm[i]][c], c < width (uint32 rows)
+hipError_t launch_gather_rows(int64_t rows, int width, const int32_t* perm, const uint32_t* src, uint32_t* dst,
+                              hipStream_t st);
 // Column split of a packed operand (rows x cols, int32 row pointers): part 0 = entries with column < mid,
 // part 1 = the rest, each a CSR over the same rows (rp0, rp1: rows + 1 entries; cnt0, cnt1: rows; tmp:
 // scan_tmp_words(rows)).  ent0/ent1 must hold the counts the scans produce (at most nnz in all).

@@ -116,6 +116,34 @@ __global__ __launch_bounds__(TPB) void k_col_count(int64_t m, const int64_t* __r
     for (int64_t t = rp64[i]; t < rp64[i + 1]; ++t) atomicAdd(&cnt[col[t]], 1);
 }
 
+// Row i of the relabelled CSR is row perm_r[i] of the input with its columns mapped through inv_c
+// (rp_out from the host: the scan of the permuted row lengths).
+__global__ __launch_bounds__(TPB) void k_permute_csr(int64_t m, const int64_t* __restrict__ rp_out,
+                                                     const int32_t* __restrict__ perm_r,
+                                                     const int64_t* __restrict__ rp64, const int32_t* __restrict__ col,
+                                                     const int32_t* __restrict__ val,
+                                                     const int32_t* __restrict__ inv_c, int32_t* __restrict__ col_out,
+                                                     int32_t* __restrict__ val_out) {
+    int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (i >= m) return;
+    const int64_t o = perm_r[i];
+    const int64_t b = rp64[o], e = rp64[o + 1], d = rp_out[i];
+    for (int64_t t = b; t < e; ++t) {
+        col_out[d + t - b] = inv_c[col[t]];
+        val_out[d + t - b] = val[t];
+    }
+}
+
+// dst[i][c] = src[perm[i]][c] for c < width
+__global__ __launch_bounds__(TPB) void k_gather_rows(int64_t rows, int width, const int32_t* __restrict__ perm,
+                                                     const uint32_t* __restrict__ src, uint32_t* __restrict__ dst) {
+    int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x;
+    if (idx >= rows * width) return;
+    const int64_t i = idx / width;
+    const int c = (int)(idx % width);
+    dst[idx] = src[(int64_t)perm[i] * width + c];
+}
+
 // Three-phase exclusive scan of int32 counts (totals < 2^31).
 constexpr int SCAN_TILE = 1024;
 
@@ -540,6 +568,21 @@ hipError_t launch_col_count(int64_t m, const int64_t* rp64, const int32_t* col, 
 }
 
 int64_t scan_tmp_words(int64_t count) { return (count + SCAN_TILE - 1) / SCAN_TILE + 1; }
+
+hipError_t launch_permute_csr(int64_t m, const int64_t* rp_out, const int32_t* perm_r, const int64_t* rp64,
+                              const int32_t* col, const int32_t* val, const int32_t* inv_c, int32_t* col_out,
+                              int32_t* val_out, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    k_permute_csr<<<grid_for(m, TPB), TPB, 0, st>>>(m, rp_out, perm_r, rp64, col, val, inv_c, col_out, val_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(int64_t rows, int width, const int32_t* perm, const uint32_t* src, uint32_t* dst,
+                              hipStream_t st) {
+    if (rows <= 0 || width <= 0) return hipSuccess;
+    k_gather_rows<<<grid_for(rows * width, TPB), TPB, 0, st>>>(rows, width, perm, src, dst);
+    return hipGetLastError();
+}
 
 hipError_t launch_exclusive_scan(int64_t count, const int32_t* in, int32_t* out, int32_t* tmp, hipStream_t st) {
     int64_t ntiles = (count + SCAN_TILE - 1) / SCAN_TILE;
