@@ -566,7 +566,7 @@ int bwr_sequence_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* pr
     std::vector<bool> tr(nmat);
     for (int j = 0; j < nmat; ++j) {
         if (!(e = upload(A[j], st, &ups[j])).ok()) return fail(e);
-        if (!(e = encode_matrix(ups[j].dev, primes[0], st, &Ms[j])).ok()) return fail(e);
+        if (!(e = encode_matrix(ups[j].dev, primes[0], st, &Ms[j], true)).ok()) return fail(e);
         if (!Ms[j].packed) return fail(BWR_EINVAL, "batched sequences need entries in [-127, 127] and sizes <= 2^24");
         tr[j] = A[j]->m < A[j]->n;
     }
@@ -638,7 +638,7 @@ int bwr_rank_modp_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* p
         tr[j] = A[j]->m < A[j]->n;
         if (A[j]->nnz == 0 || A[j]->m == 0 || A[j]->n == 0) continue;
         if (!(e = upload(A[j], st, &ups[j])).ok()) return fail(e);
-        if (!(e = encode_matrix(ups[j].dev, primes[0], st, &Ms[j])).ok()) return fail(e);
+        if (!(e = encode_matrix(ups[j].dev, primes[0], st, &Ms[j], true)).ok()) return fail(e);
         batched[j] = Ms[j].packed;
     }
     bi.t_encode = now_s() - t0;

@@ -136,15 +136,34 @@ Error BatchRunner::add(const BatchSpec& sp, int* id) {
     BWR_TRY(tdc.alloc(4 * (size_t)std::max<int64_t>(nb, 1), st_));
     BWR_TRY(flag.alloc(4, st_));
     BatchJob& d = J->d;
-    // the same draws as the single-matrix rank, prime by prime
+    // the same draws as the single-matrix rank, prime by prime; a length-sorted encoding gets them in its
+    // relabelled order (gathered from the draws in the input order), which leaves every S_k unchanged
+    DevBuf gtmp;
+    const int32_t* pn = nullptr;  // iterated side
+    const int32_t* po = nullptr;  // other side
+    if (M.sorted) {
+        pn = (tr ? M.perm_r : M.perm_c).as<int32_t>();
+        po = (tr ? M.perm_c : M.perm_r).as<int32_t>();
+        BWR_TRY(gtmp.alloc(4 * (size_t)std::max<int64_t>(std::max(nb * sp.s, outer), 1), st_));
+    }
+    auto draw = [&](uint64_t stream, int64_t rows, int width, int diag, const ModP& mp, const int32_t* perm,
+                    uint32_t* out) -> Error {
+        if (!perm) {
+            BWR_HIP(launch_rng_block(sp.seed, stream, rows, width, width, mp, diag, out, st_));
+            return {};
+        }
+        BWR_HIP(launch_rng_block(sp.seed, stream, rows, width, width, mp, diag, gtmp.as<uint32_t>(), st_));
+        BWR_HIP(launch_gather_rows(rows, width, perm, gtmp.as<uint32_t>(), out, st_));
+        return {};
+    };
     for (int t = 0; t < np; ++t) {
         const uint32_t p = sp.primes[t];
         const ModP mp = ModP::make(p);
         d.mp[t] = mp;
-        BWR_HIP(launch_rng_block(sp.seed, STREAM_V, nb, sp.s, sp.s, mp, 0, tv.as<uint32_t>(), st_));
-        BWR_HIP(launch_rng_block(sp.seed, STREAM_U, nb, sp.s, sp.s, mp, 0, tu.as<uint32_t>(), st_));
-        BWR_HIP(launch_rng_block(sp.seed, STREAM_DROW, outer, 1, 1, mp, 1, J->dr.as<uint32_t>() + (size_t)t * outer, st_));
-        BWR_HIP(launch_rng_block(sp.seed, STREAM_DCOL, nb, 1, 1, mp, 1, tdc.as<uint32_t>(), st_));
+        BWR_TRY(draw(STREAM_V, nb, sp.s, 0, mp, pn, tv.as<uint32_t>()));
+        BWR_TRY(draw(STREAM_U, nb, sp.s, 0, mp, pn, tu.as<uint32_t>()));
+        BWR_TRY(draw(STREAM_DROW, outer, 1, 1, mp, po, J->dr.as<uint32_t>() + (size_t)t * outer));
+        BWR_TRY(draw(STREAM_DCOL, nb, 1, 1, mp, pn, tdc.as<uint32_t>()));
         BWR_HIP(launch_place_block(nb, sp.s, W_, t * spad, tv.as<uint32_t>(), tdc.as<uint32_t>(), 1, mp,
                                    J->X0.as<uint32_t>(), st_));
         BWR_HIP(launch_place_block(nb, sp.s, W_, t * spad, tu.as<uint32_t>(), tdc.as<uint32_t>(), 2, mp,

@@ -111,7 +111,7 @@ Error Server::submit(const CsrView& A, uint32_t p, uint64_t seed, uint64_t* tick
         if (he == hipSuccess && nnz) he = hipMemcpyAsync(R->val.as<void>(), A.val, 4 * nnz, hipMemcpyHostToDevice, upload_);
         if (he != hipSuccess) return Error::device(he, "server upload");
         CsrView dv{A.m, A.n, A.nnz, R->rp.as<int64_t>(), R->col.as<int32_t>(), R->val.as<int32_t>()};
-        if (!(e = encode_matrix(dv, p, upload_, &R->M)).ok()) return e;
+        if (!(e = encode_matrix(dv, p, upload_, &R->M, true)).ok()) return e;
         he = hipStreamSynchronize(upload_);
         if (he != hipSuccess) return Error::device(he, "server upload");
         // the encoded copy is all the request needs from here on
