@@ -29,6 +29,27 @@ def test_sequence_block_widths(s, p):
     assert np.array_equal(got.astype(np.int64), want)
 
 
+@pytest.mark.parametrize("sorted_enc", ["1", "0"])
+@pytest.mark.parametrize("shape", [(700, 500, 420), (500, 700, 420)])
+def test_sequence_with_and_without_length_sort(shape, sorted_enc, monkeypatch):
+    """The rank path relabels rows and columns by length (and permutes the draws to match); the terms equal
+    the oracle's either way, and so does the rank in both orientations."""
+    need_gpu()
+    announce(f"sequence length-sorted={sorted_enc} shape={shape}")
+    if sorted_enc == "0":
+        monkeypatch.setenv("BWR_NO_SORT", "1")
+    p = 2**31 - 1
+    m, n, r = shape
+    A = planted(m, n, r, 9, 9100 + m)
+    rng = np.random.default_rng(m)
+    U, V = blocks(rng, A.n, 8, p)
+    dr = rng.integers(1, p, size=A.m)
+    dc = rng.integers(1, p, size=A.n)
+    got = bw.sequence(A, U, V, p, 9, dr, dc)
+    assert np.array_equal(got.astype(np.int64), oseq.sequence(A, U, V, p, 9, dr, dc))
+    assert bw.rank_modp(A, p, 8, 3)[0] == r
+
+
 @pytest.mark.parametrize("diag", ["none", "row", "col", "both"])
 def test_sequence_diagonal_options(diag):
     need_gpu()
