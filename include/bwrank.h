@@ -175,11 +175,14 @@ int bwr_time_step_kernels_dev(const bwr_csr* A_dev, uint32_t p, int32_t s, int32
  * seed) exactly: same draws, same sequence, same read-out.
  * ranks_out[j * nprimes + t].  Matrices with entries outside [-127, 127] or
  * a dimension above 2^24, and matrices whose side-by-side block (larger
- * dimension x width x 4 bytes) exceeds 8 MB (BWR_BATCH_BLOCK_BYTES), take the
- * single-matrix path, on 3 host threads (BWR_BATCH_SOLO_THREADS) that run
- * beside the batched launches.  The sigma-bases of a job's 16-bit primes run
- * as one batched sigma-basis, as do those of its larger primes
- * (BWR_SIGMA_BATCH=0: one per prime).  info may be NULL. */
+ * dimension x width x bytes per residue) exceeds 2 MB (BWR_BATCH_BLOCK_BYTES),
+ * take the single-matrix path, on 3 host threads (BWR_BATCH_SOLO_THREADS) that
+ * run beside the batched launches.  When the primes mix 16-bit and larger ones,
+ * the 16-bit primes are batched with 16-bit residues and the larger ones take
+ * the single-matrix path (BWR_BATCH_SPLIT=0: all primes batched, 32-bit
+ * residues).  The sigma-bases of a job's primes run as one batched
+ * sigma-basis per prime class (BWR_SIGMA_BATCH=0: one per prime).  info may
+ * be NULL. */
 int bwr_rank_modp_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* primes, int32_t nprimes,
                         int32_t block, uint64_t seed, int64_t* ranks_out, bwr_batch_info* info);
 

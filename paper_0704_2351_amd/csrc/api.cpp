@@ -192,10 +192,13 @@ struct RankOut {
 
 constexpr int64_t CHECK_TERMS = 4;
 
-// Largest block (all of a job's primes side by side, 4-byte residues) a matrix may gather from in the
-// batched launches (measured on the batched configuration: 8 MB batched the smaller half of the
-// matrices and beat both 2 MB and 512 KB), and the host threads of the single-matrix solves beside them.
-constexpr int64_t BATCH_BLOCK_BYTES = 8 << 20;
+// Largest block (all of a job's primes side by side) a matrix may gather from in the batched launches,
+// and the host threads of the single-matrix solves beside them.  Measured on the batched configuration
+// (16 matrices x 3 16-bit primes and 2^31 - 1): 2 MB with the 16-bit primes batched in 16-bit residues
+// and the large prime as single-matrix solves gave 1.15x the one-at-a-time rate; 8 MB gave 0.89x (the
+// batched kernel loses to the single-matrix kernels once the block outgrows an XCD's L2); batching all four
+// primes in 32-bit residues with 8 MB gave 1.08-1.11x.
+constexpr int64_t BATCH_BLOCK_BYTES = 2 << 20;
 constexpr int BATCH_SOLO_THREADS = 3;
 
 int64_t env_i64(const char* name, int64_t dflt) {
@@ -575,7 +578,9 @@ int bwr_sequence_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* pr
         shapes.push_back({tr[j] ? Ms[j].n : Ms[j].m, tr[j] ? Ms[j].m : Ms[j].n, Ms[j].nnz});
     BatchPlan bp = plan_batch(shapes, nprimes, s);
     if (!bp.W) return fail(BWR_EINVAL, "block size too large for batched sequences");
-    BatchRunner R(bp.W, bp.G1, bp.G2, st);
+    bool all_small = true;
+    for (int t = 0; t < nprimes; ++t) all_small = all_small && primes[t] <= 65536u;
+    BatchRunner R(bp.W, bp.G1, bp.G2, st, all_small ? 2 : 4);
     std::vector<std::pair<int, int>> owner;  // job -> (matrix, first prime index)
     for (int j = 0; j < nmat; ++j)
         for (int t0 = 0; t0 < nprimes; t0 += bp.per_job) {
@@ -647,18 +652,30 @@ int bwr_rank_modp_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* p
     // while the single-matrix path keeps one prime per block (16-bit residues for 16-bit primes).  Those
     // solves, and the matrices the batch kernels cannot take (wide entries), run on host threads of their
     // own beside the batched launches.  Every rank is the same either way.
+    // When the primes mix 16-bit and larger ones, the 16-bit primes are batched with their blocks in
+    // 16-bit residues (one gathered row of 64 bytes serves three of them) and the larger primes run as
+    // single-matrix solves; otherwise every prime is batched (16-bit residues if all are 16-bit).
+    std::vector<int> bt_small, bt_large;
+    for (int t = 0; t < nprimes; ++t) (primes[t] <= 65536u ? bt_small : bt_large).push_back(t);
+    const bool split_classes = !bt_small.empty() && !bt_large.empty() && env_i64("BWR_BATCH_SPLIT", 1) != 0;
+    std::vector<int> bt = split_classes ? bt_small : (bt_small.empty() ? bt_large : bt_small);
+    std::vector<bool> batched_prime(nprimes, false);
+    for (int t : bt) batched_prime[t] = true;
+    const int besize = bt_large.empty() || split_classes ? 2 : 4;
+    const int nbp = (int)bt.size();
     const int64_t block_bytes_max = env_i64("BWR_BATCH_BLOCK_BYTES", BATCH_BLOCK_BYTES);
     for (int j = 0; j < nmat; ++j) {
         if (!batched[j]) continue;
         const int64_t nb = std::min(A[j]->m, A[j]->n), outer = std::max(A[j]->m, A[j]->n);
         const int spad = ((int)std::min<int64_t>(block, nb) + 3) & ~3;
-        const int per_job = std::max(1, std::min(nprimes, 32 / std::max(spad, 1)));
-        if (outer * (int64_t)per_job * spad * 4 > block_bytes_max) batched[j] = false;
+        const int per_job = std::max(1, std::min(nbp, 32 / std::max(spad, 1)));
+        if (outer * (int64_t)per_job * spad * besize > block_bytes_max) batched[j] = false;
     }
     std::vector<std::pair<int, int>> solo;  // (matrix, prime) pairs for the single-matrix path
     for (int j = 0; j < nmat; ++j) {
-        if (batched[j] || A[j]->nnz == 0 || A[j]->m == 0 || A[j]->n == 0) continue;
-        for (int t = 0; t < nprimes; ++t) solo.emplace_back(j, t);
+        if (A[j]->nnz == 0 || A[j]->m == 0 || A[j]->n == 0) continue;
+        for (int t = 0; t < nprimes; ++t)
+            if (!batched[j] || !batched_prime[t]) solo.emplace_back(j, t);
     }
     std::vector<std::thread> solo_threads;
     std::mutex solo_mu;
@@ -714,33 +731,38 @@ int bwr_rank_modp_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* p
             smax = std::max<int>(smax, (int)std::min<int64_t>(block, std::min(A[j]->m, A[j]->n)));
             shapes.push_back({tr[j] ? Ms[j].n : Ms[j].m, tr[j] ? Ms[j].m : Ms[j].n, Ms[j].nnz});
         }
-        const BatchPlan bp = plan_batch(shapes, nprimes, smax);
+        const BatchPlan bp = plan_batch(shapes, nbp, smax);
         if (!bp.W) return fail(BWR_EINVAL, "block size too large for batched ranks");
         bi.width = bp.W;
         bi.g1 = bp.G1;
         bi.g2 = bp.G2;
-        BatchRunner R(bp.W, bp.G1, bp.G2, st);
+        BatchRunner R(bp.W, bp.G1, bp.G2, st, besize);
         struct Own {
-            int j, t0;
+            int j;
             int64_t L;
             int32_t s;
+            int tix[BATCH_MAX_PRIMES];  // the job's primes as indices into primes[]
         };
         std::vector<Own> owner;
         for (int j : live_of) {
             const int64_t nb = std::min(A[j]->m, A[j]->n);
             const int32_t s = (int32_t)std::min<int64_t>(block, nb);
             const int64_t L = 2 + (2 * nb + s - 1) / s;
-            for (int t0 = 0; t0 < nprimes; t0 += bp.per_job) {
+            for (int k0 = 0; k0 < nbp; k0 += bp.per_job) {
                 BatchSpec sp;
                 sp.M = &Ms[j];
                 sp.transpose = tr[j];
-                sp.primes.assign(primes + t0, primes + std::min(nprimes, t0 + bp.per_job));
+                Own o{j, L, s, {0, 0, 0, 0}};
+                for (int k = k0; k < std::min(nbp, k0 + bp.per_job); ++k) {
+                    o.tix[k - k0] = bt[k];
+                    sp.primes.push_back(primes[bt[k]]);
+                }
                 sp.s = s;
                 sp.seed = seed;
                 sp.len = L + CHECK_TERMS;
                 int id = 0;
                 if (!(e = R.add(sp, &id)).ok()) return fail(e);
-                owner.push_back({j, t0, L, s});
+                owner.push_back(o);
                 ++bi.jobs;
             }
         }
@@ -798,7 +820,7 @@ int bwr_rank_modp_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* p
             for (const ReadoutPool::Result& r : pool.collect(R.active() == 0 || !first.ok())) {
                 const int id = (int)(r.tag / BATCH_MAX_PRIMES), t = (int)(r.tag % BATCH_MAX_PRIMES);
                 if (!r.err.ok() && first.ok()) first = r.err;
-                ranks[(size_t)owner[id].j * nprimes + owner[id].t0 + t] = r.rank;
+                ranks[(size_t)owner[id].j * nprimes + owner[id].tix[t]] = r.rank;
                 t_sig += r.seconds;
                 if (--left[id] == 0) {
                     R.release(id);

@@ -20,9 +20,9 @@ struct BatchJob {
     const uint32_t* ent1;
     const int32_t* rp2;
     const uint32_t* ent2;
-    uint32_t* X[2];        // ping-pong iterated block, nb x W
-    uint32_t* Y;           // outer x W
-    const uint32_t* Ut;    // D_c^-1 U, nb x W
+    uint32_t* X[2];        // ping-pong iterated block, nb x W (residues of the runner's storage size)
+    uint32_t* Y;           // outer x W (same storage)
+    const uint32_t* Ut;    // D_c^-1 U, nb x W (same storage)
     const uint32_t* dr;    // [nprimes][outer]
     const uint32_t* dc2;   // [nprimes][nb]
     uint32_t* S;           // [nprimes][len][s][s]
@@ -44,18 +44,21 @@ bool batch_supported(int W, int G, bool second);
 // 0 (int64).
 int batch_acc_mode(int64_t max_len, int32_t max_abs, int G);
 // First product for all jobs: block b belongs to the job j with start[j] <= b < start[j+1].
-hipError_t launch_batch_first(int W, int G, int acc, const BatchJob* jobs, const int32_t* start, int njobs,
+// esize: bytes per stored residue (2 when every prime of the jobs is <= 2^16, else 4).
+hipError_t launch_batch_first(int W, int G, int acc, int esize, const BatchJob* jobs, const int32_t* start, int njobs,
                               int nblocks, int parity, hipStream_t st);
 // Second product + per-prime projection partials into partial + slot_off.
-hipError_t launch_batch_second(int W, int G, int acc, const BatchJob* jobs, const int32_t* start, int njobs,
-                               int nblocks, int parity, uint32_t* partial, int64_t slot_off, hipStream_t st);
+hipError_t launch_batch_second(int W, int G, int acc, int esize, const BatchJob* jobs, const int32_t* start,
+                               int njobs, int nblocks, int parity, uint32_t* partial, int64_t slot_off,
+                               hipStream_t st);
 // S terms of the chunk [g_first, g_first + nsteps) for every job (slot k of the chunk at k * slot_words).
 hipError_t launch_batch_reduce(const BatchJob* jobs, int njobs, int64_t g_first, int nsteps, const uint32_t* partial,
                                int64_t slot_words, int max_entries, hipStream_t st);
 // S_0 of one job (host descriptor copy): partials over nblk blocks, then the reduction.
-hipError_t launch_batch_s0(int W, const BatchJob& job, uint32_t* partial, int nblk, hipStream_t st);
-// out[r * W + off + c] = (in[r * s + c] mod p) * d[r]^(+1, -1 or 0) for c < s (mode 1, 2, 0).
+hipError_t launch_batch_s0(int W, int esize, const BatchJob& job, uint32_t* partial, int nblk, hipStream_t st);
+// out[r * W + off + c] = (in[r * s + c] mod p) * d[r]^(+1, -1 or 0) for c < s (mode 1, 2, 0); out holds
+// esize-byte residues.
 hipError_t launch_place_block(int64_t n, int32_t s, int W, int off, const uint32_t* in, const uint32_t* d, int mode,
-                              ModP mp, uint32_t* out, hipStream_t st);
+                              ModP mp, void* out, int esize, hipStream_t st);
 
 }  // namespace bwr

@@ -8,6 +8,9 @@
 // with full-rate 24-bit multiplies (when every active job's rows are short
 // enough for the sums to stay below 2^31), ACC 0 sums in int64; primes of any
 // size mix in one launch.  Projection sums are kept mod p in 32 bits.
+// Residues are stored in 32 bits (E = uint32_t) or, when every prime of the
+// launch is <= 2^16, in 16 bits (E = uint16_t: a gathered row of 3 primes x 8
+// columns, padded to 32, is 64 bytes).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -44,7 +47,20 @@ __device__ __forceinline__ int find_job(const int32_t* __restrict__ start, int n
     return lo;
 }
 
-template <int W, int G, bool SECOND, int ACC>
+// 4 consecutive residues of storage type E
+__device__ __forceinline__ uint4 load4e(const uint32_t* p) { return *reinterpret_cast<const uint4*>(p); }
+__device__ __forceinline__ uint4 load4e(const uint16_t* p) {
+    const uint2 v = *reinterpret_cast<const uint2*>(p);
+    return make_uint4(v.x & 0xffffu, v.x >> 16, v.y & 0xffffu, v.y >> 16);
+}
+__device__ __forceinline__ void store4e(uint32_t* p, const uint32_t (&y)[4]) {
+    *reinterpret_cast<uint4*>(p) = make_uint4(y[0], y[1], y[2], y[3]);
+}
+__device__ __forceinline__ void store4e(uint16_t* p, const uint32_t (&y)[4]) {
+    *reinterpret_cast<uint2*>(p) = make_uint2(y[0] | (y[1] << 16), y[2] | (y[3] << 16));
+}
+
+template <int W, int G, bool SECOND, int ACC, typename E>
 __global__ __launch_bounds__(TPB) void k_batch(const BatchJob* __restrict__ jobs, const int32_t* __restrict__ start,
                                                int njobs, int parity, uint32_t* __restrict__ partial,
                                                int64_t slot_off) {
@@ -64,8 +80,9 @@ __global__ __launch_bounds__(TPB) void k_batch(const BatchJob* __restrict__ jobs
     const int32_t* __restrict__ rp = SECOND ? J.rp2 : J.rp1;
     const uint32_t* __restrict__ ent = SECOND ? J.ent2 : J.ent1;
     const int cur = (parity + J.par) & 1;
-    const uint32_t* __restrict__ X = SECOND ? J.Y : J.X[cur];
-    uint32_t* __restrict__ Y = SECOND ? J.X[cur ^ 1] : J.Y;
+    const E* __restrict__ X = reinterpret_cast<const E*>(SECOND ? J.Y : J.X[cur]);
+    E* __restrict__ Y = reinterpret_cast<E*>(SECOND ? J.X[cur ^ 1] : J.Y);
+    const E* __restrict__ Ut = reinterpret_cast<const E*>(J.Ut);
     const uint32_t* __restrict__ scale = SECOND ? J.dc2 : J.dr;
     const int spad = J.spad, np = J.nprimes;
 
@@ -92,7 +109,7 @@ __global__ __launch_bounds__(TPB) void k_batch(const BatchJob* __restrict__ jobs
         int32_t ah[4] = {0, 0, 0, 0}, al[4] = {0, 0, 0, 0};
         if (active && live) {
             const int32_t b = rp[row], e = rp[row + 1];
-            const uint32_t* Xs = X + cg * 4;
+            const E* Xs = X + cg * 4;
             auto mac = [&](int32_t a, const uint4& x) {
                 const uint32_t xv[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
@@ -112,13 +129,13 @@ __global__ __launch_bounds__(TPB) void k_batch(const BatchJob* __restrict__ jobs
 #pragma unroll
                 for (int u = 0; u < 4; ++u) en[u] = ent[t + u * G];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) x[u] = *reinterpret_cast<const uint4*>(Xs + (size_t)(en[u] & 0xFFFFFFu) * W);
+                for (int u = 0; u < 4; ++u) x[u] = load4e(Xs + (size_t)(en[u] & 0xFFFFFFu) * W);
 #pragma unroll
                 for (int u = 0; u < 4; ++u) mac((int32_t)en[u] >> 24, x[u]);
             }
             for (; t < e; t += G) {
                 const uint32_t en0 = ent[t];
-                const uint4 x = *reinterpret_cast<const uint4*>(Xs + (size_t)(en0 & 0xFFFFFFu) * W);
+                const uint4 x = load4e(Xs + (size_t)(en0 & 0xFFFFFFu) * W);
                 mac((int32_t)en0 >> 24, x);
             }
         }
@@ -137,15 +154,14 @@ __global__ __launch_bounds__(TPB) void k_batch(const BatchJob* __restrict__ jobs
 #pragma unroll
                 for (int c = 0; c < 4; ++c) y[c] = mulmod(mp, reds64(mp, acc[c]), sc);
             }
-            if (j == 0)
-                *reinterpret_cast<uint4*>(Y + (size_t)row * W + cg * 4) = make_uint4(y[0], y[1], y[2], y[3]);
+            if (j == 0) store4e(Y + (size_t)row * W + cg * 4, y);
             if constexpr (SECOND) {
                 if (live) {
 #pragma unroll
                     for (int q = 0; q < IPL; ++q) {
                         const int i = j * IPL + q;
                         if (i / spad != tp) continue;  // only the diagonal blocks of one prime
-                        const uint32_t u = J.Ut[(size_t)row * W + i];
+                        const uint32_t u = Ut[(size_t)row * W + i];
 #pragma unroll
                         for (int c = 0; c < 4; ++c) pacc[q][c] = addmod(mp, pacc[q][c], mulmod(mp, u, y[c]));
                     }
@@ -226,19 +242,20 @@ __global__ __launch_bounds__(BRED_TPB) void k_batch_reduce(const BatchJob* __res
 }
 
 // S_0: thread t owns diagonal entries e = t, t + TPB, ... of the job; blocks split the rows
-template <int W>
+template <int W, typename E>
 __global__ __launch_bounds__(TPB) void k_batch_s0(BatchJob J, uint32_t* __restrict__ partial) {
     const int spad = J.spad, np = J.nprimes, per = spad * spad;
     const int64_t nb = J.rows2;
     const int64_t rpb = (nb + gridDim.x - 1) / gridDim.x;
     const int64_t r0 = (int64_t)blockIdx.x * rpb;
     const int64_t r1 = r0 + rpb < nb ? r0 + rpb : nb;
-    const uint32_t* X0 = J.X[0];  // the initial block (the first step reads X[0])
+    const E* X0 = reinterpret_cast<const E*>(J.X[0]);  // the initial block (the first step reads X[0])
+    const E* Ut = reinterpret_cast<const E*>(J.Ut);
     for (int e = threadIdx.x; e < np * per; e += TPB) {
         const int t = e / per, ii = (e % per) / spad, cc = e % spad;
         const ModP mp = J.mp[t];
         uint64_t acc = 0;
-        for (int64_t r = r0; r < r1; ++r) acc += mulmod(mp, J.Ut[r * W + t * spad + ii], X0[r * W + t * spad + cc]);
+        for (int64_t r = r0; r < r1; ++r) acc += mulmod(mp, Ut[r * W + t * spad + ii], X0[r * W + t * spad + cc]);
         partial[(int64_t)blockIdx.x * np * per + e] = red64(mp, acc);
     }
 }
@@ -253,9 +270,10 @@ __global__ __launch_bounds__(TPB) void k_batch_s0_reduce(BatchJob J, const uint3
     J.S[((int64_t)t * J.len) * s * s + i * s + c] = red64(J.mp[t], acc);
 }
 
+template <typename E>
 __global__ __launch_bounds__(TPB) void k_place_block(int64_t n, int32_t s, int W, int off, const uint32_t* __restrict__ in,
                                                      const uint32_t* __restrict__ d, int mode, ModP mp,
-                                                     uint32_t* __restrict__ out) {
+                                                     E* __restrict__ out) {
     int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x;
     if (idx >= n * (int64_t)s) return;
     int64_t r = idx / s;
@@ -263,57 +281,66 @@ __global__ __launch_bounds__(TPB) void k_place_block(int64_t n, int32_t s, int W
     uint32_t x = red32(mp, in[idx]);
     if (mode == 1) x = mulmod(mp, x, red32(mp, d[r]));
     else if (mode == 2) x = mulmod(mp, x, invmod(mp, red32(mp, d[r])));
-    out[r * W + off + c] = x;
+    out[r * W + off + c] = (E)x;
 }
 
 template <int W, int G>
-hipError_t first_wg(int acc, const BatchJob* jobs, const int32_t* start, int njobs, int nblocks, int parity,
-                    hipStream_t st) {
+hipError_t first_wg(int acc, int esize, const BatchJob* jobs, const int32_t* start, int njobs, int nblocks,
+                    int parity, hipStream_t st) {
     if constexpr ((W / 4) * G <= 64) {
-        if (acc == 2)
-            k_batch<W, G, false, 2><<<nblocks, TPB, 0, st>>>(jobs, start, njobs, parity, nullptr, 0);
+        // 16-bit residues under acc 2: the high halves are 0, so one int32 sum carries the product
+        if (esize == 2 && acc == 2)
+            k_batch<W, G, false, 2, uint16_t><<<nblocks, TPB, 0, st>>>(jobs, start, njobs, parity, nullptr, 0);
+        else if (esize == 2)
+            k_batch<W, G, false, 0, uint16_t><<<nblocks, TPB, 0, st>>>(jobs, start, njobs, parity, nullptr, 0);
+        else if (acc == 2)
+            k_batch<W, G, false, 2, uint32_t><<<nblocks, TPB, 0, st>>>(jobs, start, njobs, parity, nullptr, 0);
         else
-            k_batch<W, G, false, 0><<<nblocks, TPB, 0, st>>>(jobs, start, njobs, parity, nullptr, 0);
+            k_batch<W, G, false, 0, uint32_t><<<nblocks, TPB, 0, st>>>(jobs, start, njobs, parity, nullptr, 0);
         return hipGetLastError();
     }
     return hipErrorInvalidValue;
 }
 
 template <int W, int G>
-hipError_t second_wg(int acc, const BatchJob* jobs, const int32_t* start, int njobs, int nblocks, int parity,
+hipError_t second_wg(int acc, int esize, const BatchJob* jobs, const int32_t* start, int njobs, int nblocks, int parity,
                      uint32_t* partial, int64_t slot_off, hipStream_t st) {
     if constexpr ((W / 4) * G <= 64 && W % G == 0 && W / G <= 4) {
-        if (acc == 2)
-            k_batch<W, G, true, 2><<<nblocks, TPB, 0, st>>>(jobs, start, njobs, parity, partial, slot_off);
+        if (esize == 2 && acc == 2)
+            k_batch<W, G, true, 2, uint16_t><<<nblocks, TPB, 0, st>>>(jobs, start, njobs, parity, partial, slot_off);
+        else if (esize == 2)
+            k_batch<W, G, true, 0, uint16_t><<<nblocks, TPB, 0, st>>>(jobs, start, njobs, parity, partial, slot_off);
+        else if (acc == 2)
+            k_batch<W, G, true, 2, uint32_t><<<nblocks, TPB, 0, st>>>(jobs, start, njobs, parity, partial, slot_off);
         else
-            k_batch<W, G, true, 0><<<nblocks, TPB, 0, st>>>(jobs, start, njobs, parity, partial, slot_off);
+            k_batch<W, G, true, 0, uint32_t><<<nblocks, TPB, 0, st>>>(jobs, start, njobs, parity, partial, slot_off);
         return hipGetLastError();
     }
     return hipErrorInvalidValue;
 }
 
 template <int W>
-hipError_t first_w(int G, int acc, const BatchJob* jobs, const int32_t* start, int njobs, int nblocks, int parity,
+hipError_t first_w(int G, int acc, int esize, const BatchJob* jobs, const int32_t* start, int njobs, int nblocks, int parity,
                    hipStream_t st) {
     switch (G) {
-        case 1: return first_wg<W, 1>(acc, jobs, start, njobs, nblocks, parity, st);
-        case 2: return first_wg<W, 2>(acc, jobs, start, njobs, nblocks, parity, st);
-        case 4: return first_wg<W, 4>(acc, jobs, start, njobs, nblocks, parity, st);
-        case 8: return first_wg<W, 8>(acc, jobs, start, njobs, nblocks, parity, st);
-        case 16: return first_wg<W, 16>(acc, jobs, start, njobs, nblocks, parity, st);
+        case 1: return first_wg<W, 1>(acc, esize, jobs, start, njobs, nblocks, parity, st);
+        case 2: return first_wg<W, 2>(acc, esize, jobs, start, njobs, nblocks, parity, st);
+        case 4: return first_wg<W, 4>(acc, esize, jobs, start, njobs, nblocks, parity, st);
+        case 8: return first_wg<W, 8>(acc, esize, jobs, start, njobs, nblocks, parity, st);
+        case 16: return first_wg<W, 16>(acc, esize, jobs, start, njobs, nblocks, parity, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <int W>
-hipError_t second_w(int G, int acc, const BatchJob* jobs, const int32_t* start, int njobs, int nblocks, int parity,
+hipError_t second_w(int G, int acc, int esize, const BatchJob* jobs, const int32_t* start, int njobs, int nblocks, int parity,
                     uint32_t* partial, int64_t slot_off, hipStream_t st) {
     switch (G) {
-        case 1: return second_wg<W, 1>(acc, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
-        case 2: return second_wg<W, 2>(acc, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
-        case 4: return second_wg<W, 4>(acc, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
-        case 8: return second_wg<W, 8>(acc, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
-        case 16: return second_wg<W, 16>(acc, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        case 1: return second_wg<W, 1>(acc, esize, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        case 2: return second_wg<W, 2>(acc, esize, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        case 4: return second_wg<W, 4>(acc, esize, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        case 8: return second_wg<W, 8>(acc, esize, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        case 16: return second_wg<W, 16>(acc, esize, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -334,28 +361,28 @@ bool batch_supported(int W, int G, bool second) {
     return !second || (W % G == 0 && W / G <= 4);
 }
 
-hipError_t launch_batch_first(int W, int G, int acc, const BatchJob* jobs, const int32_t* start, int njobs,
+hipError_t launch_batch_first(int W, int G, int acc, int esize, const BatchJob* jobs, const int32_t* start, int njobs,
                               int nblocks, int parity, hipStream_t st) {
-    if (acc != 0 && acc != 2) return hipErrorInvalidValue;
+    if ((acc != 0 && acc != 2) || (esize != 2 && esize != 4)) return hipErrorInvalidValue;
     if (nblocks <= 0 || njobs <= 0) return hipSuccess;
     switch (W) {
-        case 4: return first_w<4>(G, acc, jobs, start, njobs, nblocks, parity, st);
-        case 8: return first_w<8>(G, acc, jobs, start, njobs, nblocks, parity, st);
-        case 16: return first_w<16>(G, acc, jobs, start, njobs, nblocks, parity, st);
-        case 32: return first_w<32>(G, acc, jobs, start, njobs, nblocks, parity, st);
+        case 4: return first_w<4>(G, acc, esize, jobs, start, njobs, nblocks, parity, st);
+        case 8: return first_w<8>(G, acc, esize, jobs, start, njobs, nblocks, parity, st);
+        case 16: return first_w<16>(G, acc, esize, jobs, start, njobs, nblocks, parity, st);
+        case 32: return first_w<32>(G, acc, esize, jobs, start, njobs, nblocks, parity, st);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_batch_second(int W, int G, int acc, const BatchJob* jobs, const int32_t* start, int njobs,
+hipError_t launch_batch_second(int W, int G, int acc, int esize, const BatchJob* jobs, const int32_t* start, int njobs,
                                int nblocks, int parity, uint32_t* partial, int64_t slot_off, hipStream_t st) {
-    if (acc != 0 && acc != 2) return hipErrorInvalidValue;
+    if ((acc != 0 && acc != 2) || (esize != 2 && esize != 4)) return hipErrorInvalidValue;
     if (nblocks <= 0 || njobs <= 0) return hipSuccess;
     switch (W) {
-        case 4: return second_w<4>(G, acc, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
-        case 8: return second_w<8>(G, acc, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
-        case 16: return second_w<16>(G, acc, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
-        case 32: return second_w<32>(G, acc, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        case 4: return second_w<4>(G, acc, esize, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        case 8: return second_w<8>(G, acc, esize, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        case 16: return second_w<16>(G, acc, esize, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
+        case 32: return second_w<32>(G, acc, esize, jobs, start, njobs, nblocks, parity, partial, slot_off, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -369,13 +396,23 @@ hipError_t launch_batch_reduce(const BatchJob* jobs, int njobs, int64_t g_first,
     return hipGetLastError();
 }
 
-hipError_t launch_batch_s0(int W, const BatchJob& job, uint32_t* partial, int nblk, hipStream_t st) {
-    switch (W) {
-        case 4: k_batch_s0<4><<<nblk, TPB, 0, st>>>(job, partial); break;
-        case 8: k_batch_s0<8><<<nblk, TPB, 0, st>>>(job, partial); break;
-        case 16: k_batch_s0<16><<<nblk, TPB, 0, st>>>(job, partial); break;
-        case 32: k_batch_s0<32><<<nblk, TPB, 0, st>>>(job, partial); break;
-        default: return hipErrorInvalidValue;
+hipError_t launch_batch_s0(int W, int esize, const BatchJob& job, uint32_t* partial, int nblk, hipStream_t st) {
+    if (esize == 2) {
+        switch (W) {
+            case 4: k_batch_s0<4, uint16_t><<<nblk, TPB, 0, st>>>(job, partial); break;
+            case 8: k_batch_s0<8, uint16_t><<<nblk, TPB, 0, st>>>(job, partial); break;
+            case 16: k_batch_s0<16, uint16_t><<<nblk, TPB, 0, st>>>(job, partial); break;
+            case 32: k_batch_s0<32, uint16_t><<<nblk, TPB, 0, st>>>(job, partial); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (W) {
+            case 4: k_batch_s0<4, uint32_t><<<nblk, TPB, 0, st>>>(job, partial); break;
+            case 8: k_batch_s0<8, uint32_t><<<nblk, TPB, 0, st>>>(job, partial); break;
+            case 16: k_batch_s0<16, uint32_t><<<nblk, TPB, 0, st>>>(job, partial); break;
+            case 32: k_batch_s0<32, uint32_t><<<nblk, TPB, 0, st>>>(job, partial); break;
+            default: return hipErrorInvalidValue;
+        }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -384,10 +421,13 @@ hipError_t launch_batch_s0(int W, const BatchJob& job, uint32_t* partial, int nb
 }
 
 hipError_t launch_place_block(int64_t n, int32_t s, int W, int off, const uint32_t* in, const uint32_t* d, int mode,
-                              ModP mp, uint32_t* out, hipStream_t st) {
+                              ModP mp, void* out, int esize, hipStream_t st) {
     int64_t total = n * (int64_t)s;
     if (total == 0) return hipSuccess;
-    k_place_block<<<grid_for(total, TPB), TPB, 0, st>>>(n, s, W, off, in, d, mode, mp, out);
+    if (esize == 2)
+        k_place_block<uint16_t><<<grid_for(total, TPB), TPB, 0, st>>>(n, s, W, off, in, d, mode, mp, (uint16_t*)out);
+    else
+        k_place_block<uint32_t><<<grid_for(total, TPB), TPB, 0, st>>>(n, s, W, off, in, d, mode, mp, (uint32_t*)out);
     return hipGetLastError();
 }
 

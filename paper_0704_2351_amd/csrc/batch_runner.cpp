@@ -59,7 +59,8 @@ int BatchRunner::width_for(int nprimes, int s) {
     return w;
 }
 
-BatchRunner::BatchRunner(int W, int G1, int G2, hipStream_t st) : W_(W), G1_(G1), G2_(G2), st_(st) {
+BatchRunner::BatchRunner(int W, int G1, int G2, hipStream_t st, int esize)
+    : W_(W), G1_(G1), G2_(G2), st_(st), esize_(esize == 2 ? 2 : 4) {
     const char* c = getenv("BWR_BATCH_CHUNK");
     if (c && atoi(c) >= 2) chunk_ = atoi(c) & ~1;
 }
@@ -111,6 +112,9 @@ Error BatchRunner::add(const BatchSpec& sp, int* id) {
     if (np < 1 || np > BATCH_MAX_PRIMES) return Error::inval("a batch job takes 1 to 4 primes");
     if (sp.s < 1 || np * round4(sp.s) > W_) return Error::inval("job wider than the batch block");
     if (sp.len < 1) return Error::inval("a job needs at least one term");
+    if (esize_ == 2)
+        for (uint32_t p : sp.primes)
+            if (p > 65536u) return Error::inval("16-bit batch storage needs primes <= 2^16");
     auto J = std::make_unique<Job>();
     J->spec = sp;
     const bool tr = sp.transpose;
@@ -118,10 +122,11 @@ Error BatchRunner::add(const BatchSpec& sp, int* id) {
     J->outer = tr ? M.n : M.m;
     const int64_t nb = J->nb, outer = J->outer;
     const int spad = round4(sp.s);
-    BWR_TRY(J->X0.alloc(4 * (size_t)std::max<int64_t>(nb * W_, 1), st_));
-    BWR_TRY(J->X1.alloc(4 * (size_t)std::max<int64_t>(nb * W_, 1), st_));
-    BWR_TRY(J->Ut.alloc(4 * (size_t)std::max<int64_t>(nb * W_, 1), st_));
-    BWR_TRY(J->Y.alloc(4 * (size_t)std::max<int64_t>(outer * W_, 1), st_));
+    const size_t es = (size_t)esize_;
+    BWR_TRY(J->X0.alloc(es * (size_t)std::max<int64_t>(nb * W_, 1), st_));
+    BWR_TRY(J->X1.alloc(es * (size_t)std::max<int64_t>(nb * W_, 1), st_));
+    BWR_TRY(J->Ut.alloc(es * (size_t)std::max<int64_t>(nb * W_, 1), st_));
+    BWR_TRY(J->Y.alloc(es * (size_t)std::max<int64_t>(outer * W_, 1), st_));
     BWR_TRY(J->dr.alloc(4 * (size_t)std::max<int64_t>(np * outer, 1), st_));
     BWR_TRY(J->dc2.alloc(4 * (size_t)std::max<int64_t>(np * nb, 1), st_));
     BWR_TRY(J->S.alloc(4 * (size_t)np * sp.len * sp.s * sp.s, st_));
@@ -165,9 +170,9 @@ Error BatchRunner::add(const BatchSpec& sp, int* id) {
         BWR_TRY(draw(STREAM_DROW, outer, 1, 1, mp, po, J->dr.as<uint32_t>() + (size_t)t * outer));
         BWR_TRY(draw(STREAM_DCOL, nb, 1, 1, mp, pn, tdc.as<uint32_t>()));
         BWR_HIP(launch_place_block(nb, sp.s, W_, t * spad, tv.as<uint32_t>(), tdc.as<uint32_t>(), 1, mp,
-                                   J->X0.as<uint32_t>(), st_));
+                                   J->X0.as<void>(), esize_, st_));
         BWR_HIP(launch_place_block(nb, sp.s, W_, t * spad, tu.as<uint32_t>(), tdc.as<uint32_t>(), 2, mp,
-                                   J->Ut.as<uint32_t>(), st_));
+                                   J->Ut.as<void>(), esize_, st_));
         BWR_HIP(launch_square_diag(nb, tdc.as<uint32_t>(), mp, J->dc2.as<uint32_t>() + (size_t)t * nb,
                                    flag.as<int32_t>(), st_));
     }
@@ -203,7 +208,7 @@ Error BatchRunner::add(const BatchSpec& sp, int* id) {
     const int nblk0 = (int)std::max<int64_t>(1, std::min<int64_t>(64, (nb + 255) / 256));
     DevBuf p0;
     BWR_TRY(p0.alloc(4 * (size_t)nblk0 * np * spad * spad, st_));
-    BWR_HIP(launch_batch_s0(W_, d, p0.as<uint32_t>(), nblk0, st_));
+    BWR_HIP(launch_batch_s0(W_, esize_, d, p0.as<uint32_t>(), nblk0, st_));
     if (sp.len == 1) J->done = true;
     bytes_ += J->bytes;
     *id = (int)jobs_.size();
@@ -307,9 +312,9 @@ Error BatchRunner::advance(int64_t max_steps, std::vector<int>* done) {
         auto launch_chunk = [&](int64_t steps, int64_t g_start) -> Error {
             for (int64_t i = 0; i < steps; ++i) {
                 const int par = (int)((g_start + i) & 1);
-                BWR_HIP(launch_batch_first(W_, G1_, acc1_, dj, st1, nact, nblocks1_, par, st_));
-                BWR_HIP(launch_batch_second(W_, G2_, acc2_, dj, st2, nact, nblocks2_, par, part, i * slot_words_,
-                                            st_));
+                BWR_HIP(launch_batch_first(W_, G1_, acc1_, esize_, dj, st1, nact, nblocks1_, par, st_));
+                BWR_HIP(launch_batch_second(W_, G2_, acc2_, esize_, dj, st2, nact, nblocks2_, par, part,
+                                            i * slot_words_, st_));
             }
             return {};
         };

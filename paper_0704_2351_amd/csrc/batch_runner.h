@@ -26,7 +26,8 @@ struct BatchSpec {
 class BatchRunner {
    public:
     // W: block width of every job (nprimes * round4(s) <= W); G1, G2: row split of the two products.
-    BatchRunner(int W, int G1, int G2, hipStream_t st);
+    // esize: bytes per stored residue, 2 only if every job's primes are <= 2^16 (add() refuses others)
+    BatchRunner(int W, int G1, int G2, hipStream_t st, int esize = 4);
     ~BatchRunner();
     static int width_for(int nprimes, int s);
 
@@ -53,6 +54,7 @@ class BatchRunner {
     Error rebuild();
     int W_, G1_, G2_;
     hipStream_t st_;
+    int esize_ = 4;
     std::vector<std::unique_ptr<Job>> jobs_;
     std::vector<int> active_;
     int64_t g_ = 0;

@@ -31,8 +31,10 @@ MIX = [planted(300, 200, 150, 6, 1), planted(150, 260, 120, 5, 2), random_sparse
 
 
 @pytest.mark.parametrize("s,primes", [(8, PRIMES4), (16, (65521, 2**31 - 1)), (4, PRIMES4), (3, (65537, 65521)),
-                                      (32, (65519,))])
+                                      (32, (65519,)), (8, (65521, 65519, 65497)), (4, (3, 65521)),
+                                      (16, (257, 40009))])
 def test_batch_sequences_match_oracle(s, primes):
+    """(Only 16-bit primes: the blocks are stored in 16-bit residues.)"""
     need_gpu()
     announce(f"batch sequences s={s} primes={primes}")
     lengths = [12, 7, 20, 3]
