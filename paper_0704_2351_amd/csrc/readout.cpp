@@ -138,8 +138,11 @@ void ReadoutPool::work() {
         if (se != hipSuccess) {
             err = Error::device(se, "read-out stream");
         } else {
-            hipError_t he = t.ready ? hipStreamWaitEvent(st, t.ready, 0) : hipSuccess;
-            if (he != hipSuccess) err = Error::device(he, "hipStreamWaitEvent");
+            // wait on the host, not with a stream wait: the producer's stream may be capturing its next
+            // graph by now, and a stream wait on an event of a capturing stream would pull this stream's
+            // read-out into that capture
+            hipError_t he = t.ready ? hipEventSynchronize(t.ready) : hipSuccess;
+            if (he != hipSuccess) err = Error::device(he, "hipEventSynchronize");
             else err = rank_of_sequences_dev(t.S, t.n, t.L, t.total, t.s, t.p, st, ranks, &seconds);
             // the stream has been synchronized by the read-out (or nothing was queued after the wait)
             if (!err.ok()) (void)hipStreamSynchronize(st);

@@ -41,7 +41,7 @@ class ReadoutPool {
     // threads >= 1; device = the HIP device the workers use
     ReadoutPool(int threads, int device);
     ~ReadoutPool();
-    // Waits (on the worker's stream) for `ready` before reading S_dev; the event is owned by the pool
+    // Waits (on the worker's host thread) for `ready` before reading S_dev; the event is owned by the pool
     // afterwards.  S_dev must stay allocated until the task's result has been collected.
     void submit(uint64_t tag, const uint32_t* S_dev, int64_t L, int64_t total, int32_t s, uint32_t p,
                 hipEvent_t ready) {

@@ -311,7 +311,9 @@ Error OnlineGenerator::join_worker() {
 Error OnlineGenerator::feed(int64_t avail, hipEvent_t ready) {
     avail = std::min(avail, L_);
     if (avail <= built_) return {};
-    if (ready) BWR_HIP(hipStreamWaitEvent(st_, ready, 0));
+    // a host wait (feed_async runs this on the generator's own thread): a stream wait on an event of the
+    // producer's stream would join a graph capture that stream may have begun since the event was recorded
+    if (ready) BWR_HIP(hipEventSynchronize(ready));
     const int64_t gbs = (int64_t)G_.rows * G_.cols * G_.ld;
     for (int b = 0; b < pb_.n; ++b)
         BWR_HIP(gpu_build_G(S_[b], L_, s_, pb_.mp[b].p, G_.ptr + b * gbs, G_.ld, built_, avail, st_));

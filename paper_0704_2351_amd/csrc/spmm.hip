@@ -134,8 +134,8 @@ __device__ __forceinline__ void spmm_split_body(int64_t nrows, const int32_t* __
         if (active) {
             const int32_t b = rp[row], e = rp[row + 1];
             const E* Xs = X + cg * 4;
-            // 4 entries per lane in flight, then the rest of the lane's share one by one (measured faster on
-            // the planted matrices than predicated rounds, which cost registers and occupancy)
+            // 4 entries per lane in flight, then 2, then the rest of the lane's share one by one (measured
+            // faster on the planted matrices than predicated rounds, which cost registers and occupancy)
             int32_t t = b + j;
             for (; t + 3 * G < e; t += 4 * G) {
                 uint32_t en[4];
@@ -150,6 +150,18 @@ __device__ __forceinline__ void spmm_split_body(int64_t nrows, const int32_t* __
 #pragma unroll
                     for (int c = 0; c < 4; ++c) mac<ACC>(acc[c], ah[c], al[c], a, x[u][c]);
                 }
+            }
+            if (t + G < e) {  // two more entries in flight together
+                const uint32_t en0 = ent[t], en1 = ent[t + G];
+                uint32_t x0[4], x1[4];
+                load4(Xs + (size_t)(en0 & 0xFFFFFFu) * W, x0);
+                load4(Xs + (size_t)(en1 & 0xFFFFFFu) * W, x1);
+                const int32_t a0 = (int32_t)en0 >> 24, a1 = (int32_t)en1 >> 24;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) mac<ACC>(acc[c], ah[c], al[c], a0, x0[c]);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) mac<ACC>(acc[c], ah[c], al[c], a1, x1[c]);
+                t += 2 * G;
             }
             for (; t < e; t += G) {
                 const uint32_t en0 = ent[t];
