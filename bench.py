@@ -255,6 +255,34 @@ def paper_scale_mode(args):
                                f"p = {p}", "m": m, "n": n, "nnz": nnz, "sequence_length": L}}), flush=True)
 
 
+def paper_rank_mode(args):
+    """The whole rank of the 2 000 000 x 1 000 000 matrix (37 M non-zeros, block 16, p = 65521) from a CSR in
+    device memory: encoding, all 2 + 2n/16 + 4 terms, the device sigma-basis beside the sequence, read-out."""
+    import torch
+
+    import paper_0704_2351_amd as bw
+    from workloads import config3
+
+    s, p = 16, 65521
+    log("generating the planted 2000000 x 1000000 matrix")
+    A = config3()
+    Ad = bw.csr_to_device(A, "cuda:0")
+    torch.cuda.synchronize()
+    log(f"rank mod {p}, block {s}: {bw.sequence_length(min(A.m, A.n), s) + 4} terms (one call, about 2.5 min)")
+    t0 = time.perf_counter()
+    r, info = bw.rank_modp_dev(Ad, p, s, 1)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    work = 2.0 * A.nnz * info["s"] * (info["len"] + info["check_terms"] - 1)
+    print(json.dumps({
+        "metric": METRIC, "mode": "paper_rank", "unit": "Gnnz·vec/s", "value": round(work / el / 1e9, 3),
+        "rank": int(r), "planted_rank": int(A.planted_rank), "rank_equals_planted": bool(r == A.planted_rank),
+        "seconds": round(el, 2), "info": info, "higher_is_better": True, "n_gpus": 1, "dtype": "u16",
+        "data": "synthetic planted-rank matrix (seeded)",
+        "config": {"workload": f"planted {A.m} x {A.n}, rank {A.planted_rank}, {A.nnz / 1e6:.1f} M non-zeros, "
+                               f"block {s}, p = {p}", "m": A.m, "n": A.n, "nnz": A.nnz}}), flush=True)
+
+
 def serve_mode(args):
     """Seeded Poisson trace of rank requests through the continuous-batching server."""
     import math
@@ -324,6 +352,8 @@ def main():
                     help="the 2000000 x 1000000 matrix (37 M non-zeros), block 16: kernel roofline, sequence rate "
                          "over --paper-steps terms, device sigma-basis time at the full length")
     ap.add_argument("--paper-steps", type=int, default=3000)
+    ap.add_argument("--paper-rank", action="store_true",
+                    help="the whole rank of the 2000000 x 1000000 matrix (about 2.5 minutes of GPU time)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the per-kernel timing loop at p = 65521 plus a 256 MiB device copy "
                          "(a plain copy kernel of known size, for calibrating memory counters)")
@@ -344,6 +374,8 @@ def main():
         return batch_mode(args)
     if args.serve:
         return serve_mode(args)
+    if args.paper_rank:
+        return paper_rank_mode(args)
     if args.paper_scale:
         return paper_scale_mode(args)
     s = 8
