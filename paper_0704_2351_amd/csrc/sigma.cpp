@@ -614,26 +614,39 @@ Error min_generator_mbasis(const uint32_t* S, int64_t L, int32_t s, uint32_t p, 
 Error check_generator(const Generator& g, const uint32_t* S, int64_t L, int64_t L_total, uint32_t p) {
     const ModP mp = ModP::make(p);
     const int s = g.s;
-    for (int i = 0; i < s; ++i) {
+    const uint32_t r32 = red64(mp, (uint64_t)1 << 32);
+    std::atomic<bool> bad{false};
+    // coefficient c of p_i S, sum_j P_i[j] S[c - j], must vanish for max(L, delta_i) <= c < L_total.  Rows
+    // run on the pool; per coefficient j the s x s term S[c - j] is read contiguously (columns b innermost),
+    // and the 64-bit sums of low and high product halves stay exact (at most (delta_i + 1) s terms each).
+    auto row = [&](int64_t i) {
         const int64_t di = g.delta[i];
-        for (int64_t c = std::max(L, di); c < L_total; ++c) {
-            // coefficient c of p_i S: sum_j P_i[j] S[c - j]
-            for (int b = 0; b < s; ++b) {
-                uint64_t lo = 0, hi = 0;
+        std::vector<uint64_t> lo(s), hi(s);
+        std::vector<const uint32_t*> pa(s);
+        for (int a = 0; a < s; ++a) pa[a] = g.P.at((int)i, a);
+        for (int64_t c = std::max(L, di); c < L_total && !bad.load(std::memory_order_relaxed); ++c) {
+            std::fill(lo.begin(), lo.end(), 0);
+            std::fill(hi.begin(), hi.end(), 0);
+            const int64_t jmax = std::min<int64_t>(std::min(di, c), g.P.len - 1);
+            for (int64_t j = 0; j <= jmax; ++j) {
+                const uint32_t* St = S + (size_t)(c - j) * s * s;
                 for (int a = 0; a < s; ++a) {
-                    const uint32_t* pa = g.P.at(i, a);
-                    for (int64_t j = 0; j <= std::min<int64_t>(di, c) && j < g.P.len; ++j) {
-                        if (!pa[j]) continue;
-                        uint64_t pr = (uint64_t)pa[j] * S[((size_t)(c - j) * s + a) * s + b];
-                        lo += pr & 0xffffffffu;
-                        hi += pr >> 32;
+                    const uint64_t w = pa[a][j];
+                    if (!w) continue;
+                    const uint32_t* srow = St + (size_t)a * s;
+                    for (int b2 = 0; b2 < s; ++b2) {
+                        const uint64_t pr = w * srow[b2];
+                        lo[b2] += pr & 0xffffffffu;
+                        hi[b2] += pr >> 32;
                     }
                 }
-                uint32_t v = addmod(mp, red64(mp, lo), mulmod(mp, red64(mp, hi), red64(mp, (uint64_t)1 << 32)));
-                if (v) return {ESHORT_, "generator fails on the check terms: the sequence is too short"};
             }
+            for (int b2 = 0; b2 < s; ++b2)
+                if (addmod(mp, red64(mp, lo[b2]), mulmod(mp, red64(mp, hi[b2]), r32))) bad.store(true);
         }
-    }
+    };
+    pool().run(s, row);
+    if (bad.load()) return {ESHORT_, "generator fails on the check terms: the sequence is too short"};
     return {};
 }
 
