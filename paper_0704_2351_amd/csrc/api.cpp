@@ -77,8 +77,23 @@ Error check_prime(uint32_t p) {
 // stream 1 the sigma-basis that runs beside a rank computation's sequence.  They are non-blocking and per
 // (host thread, device), so calls made from different host threads run concurrently on the device (e.g.
 // one prime's sigma-basis beside another prime's sequence).
+// The thread that loaded the library (normally the process's main thread): its streams are left to the
+// runtime at process exit, when destroying them could outlive the runtime itself.
+const std::thread::id g_load_thread = std::this_thread::get_id();
+
+// A host thread's library streams, destroyed when the thread ends (pending work finishes first).
+struct ThreadStreams {
+    std::vector<hipStream_t> v;
+    ~ThreadStreams() {
+        if (std::this_thread::get_id() == g_load_thread) return;
+        for (hipStream_t s : v)
+            if (s) (void)hipStreamDestroy(s);
+    }
+};
+
 hipStream_t lib_stream(Error* err, int which = 0) {
-    thread_local std::vector<hipStream_t> streams;
+    thread_local ThreadStreams tls;
+    std::vector<hipStream_t>& streams = tls.v;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) {
