@@ -46,6 +46,7 @@ struct Server::Req {
     int64_t L = 0;
     int64_t footprint = 0;
     double arrival = 0, admitted = 0, finished = 0;
+    int cls = 1;  // runner: 0 for primes <= 2^16, 1 otherwise
     int job = -1;
     bool done = false;
     int64_t rank = 0;
@@ -70,7 +71,8 @@ Error Server::start() {
     G2_ = std::max(W_ / 4, std::min(4, 64 / (W_ / 4)));
     if (!batch_supported(W_, G1_, false)) G1_ = 1;
     if (!batch_supported(W_, G2_, true)) G2_ = W_ / 4;
-    runner_ = std::make_unique<BatchRunner>(W_, G1_, G2_, compute_);
+    runners_[0] = std::make_unique<BatchRunner>(W_, G1_, G2_, compute_, 2);
+    runners_[1] = std::make_unique<BatchRunner>(W_, G1_, G2_, compute_, 4);
     worker_ = std::thread([this] { loop(); });
     return {};
 }
@@ -83,7 +85,8 @@ void Server::stop() {
     cv_.notify_all();
     done_cv_.notify_all();
     if (worker_.joinable()) worker_.join();
-    runner_.reset();
+    runners_[0].reset();
+    runners_[1].reset();
     reqs_.clear();
     if (compute_) (void)hipStreamDestroy(compute_);
     if (upload_) (void)hipStreamDestroy(upload_);
@@ -200,7 +203,7 @@ void Server::loop() {
     // beside the batch that keeps advancing
     ReadoutPool pool(READOUT_THREADS, device_);
     std::vector<std::shared_ptr<Req>> active;       // sequences in the batch
-    std::map<int, std::shared_ptr<Req>> reading;    // job id -> request being read out
+    std::map<uint64_t, std::shared_ptr<Req>> reading;  // (runner << 32 | job id) -> request being read out
     for (;;) {
         // admission at a step boundary
         {
@@ -209,7 +212,8 @@ void Server::loop() {
             if (quit_) break;
             while (!queue_.empty() && (int)(active.size() + reading.size()) < max_slots_) {
                 std::shared_ptr<Req> R = reqs_[queue_.front()];
-                if (runner_->bytes_in_use() + R->footprint > budget_ && !(active.empty() && reading.empty())) break;
+                const int64_t in_use = runners_[0]->bytes_in_use() + runners_[1]->bytes_in_use();
+                if (in_use + R->footprint > budget_ && !(active.empty() && reading.empty())) break;
                 queue_.pop_front();
                 lk.unlock();
                 BatchSpec sp;
@@ -219,7 +223,8 @@ void Server::loop() {
                 sp.s = R->s;
                 sp.seed = R->seed;
                 sp.len = R->L + CHECK_TERMS;
-                Error e = runner_->add(sp, &R->job);
+                R->cls = R->p <= 65536u ? 0 : 1;
+                Error e = runners_[R->cls]->add(sp, &R->job);
                 lk.lock();
                 R->admitted = now_s();
                 if (!e.ok()) {
@@ -236,13 +241,16 @@ void Server::loop() {
         }
         const double t0 = now_s();
         Error e;
-        if (!active.empty()) {
+        for (int cls = 0; cls < 2 && e.ok(); ++cls) {
+            if (std::none_of(active.begin(), active.end(), [&](const std::shared_ptr<Req>& r) { return r->cls == cls; }))
+                continue;
+            BatchRunner& run = *runners_[cls];
             std::vector<int> fin;
-            e = runner_->advance(64, &fin);
-            steps_ = runner_->global_step();
+            e = run.advance(64, &fin);
+            steps_ = runners_[0]->global_step() + runners_[1]->global_step();
             for (int id : fin) {
                 auto it = std::find_if(active.begin(), active.end(),
-                                       [&](const std::shared_ptr<Req>& r) { return r->job == id; });
+                                       [&](const std::shared_ptr<Req>& r) { return r->cls == cls && r->job == id; });
                 if (it == active.end()) continue;
                 std::shared_ptr<Req> R = *it;
                 active.erase(it);
@@ -253,7 +261,7 @@ void Server::loop() {
                     if (ev) (void)hipEventDestroy(ev);
                     (void)hipStreamSynchronize(compute_);
                     const Error er = e.ok() ? Error::device(he, "read-out event") : e;
-                    runner_->release(id);
+                    run.release(id);
                     std::lock_guard<std::mutex> lk(mu_);
                     R->done = true;
                     R->code = er.code;
@@ -266,8 +274,9 @@ void Server::loop() {
                     done_cv_.notify_all();
                     continue;
                 }
-                reading[id] = R;
-                pool.submit((uint64_t)id, runner_->sequence(id, 0), R->L, runner_->length(id), R->s, R->p, ev);
+                const uint64_t tag = ((uint64_t)cls << 32) | (uint32_t)id;
+                reading[tag] = R;
+                pool.submit(tag, run.sequence(id, 0), R->L, run.length(id), R->s, R->p, ev);
             }
         }
         if (!e.ok()) {
@@ -283,11 +292,11 @@ void Server::loop() {
         }
         // answer the requests whose read-out finished (wait for one when nothing else is running)
         for (const ReadoutPool::Result& r : pool.collect(active.empty() && !reading.empty())) {
-            auto it = reading.find((int)r.tag);
+            auto it = reading.find(r.tag);
             if (it == reading.end()) continue;
             std::shared_ptr<Req> R = it->second;
             reading.erase(it);
-            runner_->release((int)r.tag);
+            runners_[r.tag >> 32]->release((int)(r.tag & 0xffffffffu));
             std::lock_guard<std::mutex> lk(mu_);
             R->done = true;
             R->rank = r.rank;

@@ -45,7 +45,8 @@ class Server {
     int device_ = 0;
     int W_ = 0, G1_ = 0, G2_ = 0;
     hipStream_t compute_ = nullptr, upload_ = nullptr;
-    std::unique_ptr<BatchRunner> runner_;
+    // batches of requests at primes <= 2^16 (16-bit residues) and at larger primes (32-bit residues)
+    std::unique_ptr<BatchRunner> runners_[2];
     std::thread worker_;
     std::mutex mu_, upload_mu_;
     std::condition_variable cv_, done_cv_;
