@@ -186,6 +186,15 @@ int bwr_time_step_kernels_dev(const bwr_csr* A_dev, uint32_t p, int32_t s, int32
 int bwr_rank_modp_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* primes, int32_t nprimes,
                         int32_t block, uint64_t seed, int64_t* ranks_out, bwr_batch_info* info);
 
+/* Rank of A over the integers, probabilistically (Section 2.5): the largest of
+ * its ranks modulo the nprimes primes (each in [3, 2^31)), computed as one
+ * bwr_rank_modp_batch call.  Each modular rank is at most the rank over Q
+ * (Monte Carlo errors are one-sided too), so *rank_out is a lower bound that
+ * equals it unless every prime divides every non-zero maximal minor or every
+ * solve fails.  ranks_out (nprimes, may be NULL) receives the modular ranks. */
+int bwr_rank_integer(const bwr_csr* A, const uint32_t* primes, int32_t nprimes, int32_t block, uint64_t seed,
+                     int64_t* rank_out, int64_t* ranks_out);
+
 /* The sequences bwr_rank_modp_batch computes, returned instead of ranked:
  * for matrix j (B on its smaller side, as in bwr_rank_modp) and prime t,
  * S_out[j][(t * len[j] + k) * s * s + i * s + c] = S_k[i][c] for k < len[j],

@@ -10,6 +10,8 @@ returns with high probability.
 * ``rank_bareiss``: fraction-free Bareiss elimination over Z (exact big
   integers), giving the rank over Q.  rank_Q >= rank_p, with equality unless p
   divides every non-zero maximal minor.
+* ``rank_over_integers``: the largest rank modulo several primes (Section 2.5:
+  the rank over the integers, probabilistically, from a few random primes).
 
 Parity pinned by: Bareiss vs dense vs sparse on random tiny matrices at two
 primes, planted ranks, rank A = rank A^T <= min(m, n), invariance under
@@ -130,3 +132,10 @@ def rank_bareiss(M) -> int:
 def rank_csr(A, p: int) -> int:
     """Sparse elimination on a ``workloads.CSR``-like object (attributes m, n, row_ptr, col_idx, val)."""
     return rank_sparse_modp(A.m, A.n, A.row_ptr, A.col_idx, A.val, p)
+
+
+def rank_over_integers(A, primes) -> int:
+    """Largest rank of the CSR-like ``A`` over GF(p) for p in ``primes`` (Section 2.5).  Every modular rank is at
+    most the rank over Q, so the maximum is a lower bound that equals it unless every prime divides every
+    non-zero maximal minor."""
+    return max(rank_csr(A, int(p)) for p in primes)

@@ -19,7 +19,7 @@ BWR_OK, BWR_EINVAL, BWR_EPRIME, BWR_ENOMEM, BWR_EDEVICE, BWR_EBUSY, BWR_ESHORT =
 EXPORTED = ("bwr_version", "bwr_last_error", "bwr_is_prime", "bwr_sequence_length", "bwr_set_threads",
             "bwr_random_block", "bwr_sequence", "bwr_sequence_dev", "bwr_apply_dev", "bwr_rank_modp",
             "bwr_rank_modp_dev", "bwr_min_generator", "bwr_rank_from_sequence", "bwr_time_step_kernels_dev",
-            "bwr_min_generator_dev", "bwr_min_generators_dev", "bwr_rank_modp_batch", "bwr_sequence_batch", "bwr_server_create",
+            "bwr_min_generator_dev", "bwr_min_generators_dev", "bwr_rank_modp_batch", "bwr_rank_integer", "bwr_sequence_batch", "bwr_server_create",
             "bwr_server_submit", "bwr_server_poll", "bwr_server_wait", "bwr_server_get_stats", "bwr_server_destroy")
 
 
@@ -82,6 +82,7 @@ def lib():
             "bwr_time_step_kernels_dev": (ctypes.c_int, [vp, u32, i32, i32, i32, vp, vp, vp]),
             "bwr_min_generator_dev": (ctypes.c_int, [vp, i64, i32, u32, vp, vp, vp, i64, vp]),
             "bwr_min_generators_dev": (ctypes.c_int, [vp, i32, i64, i32, vp, vp, vp, vp, i64, vp]),
+            "bwr_rank_integer": (ctypes.c_int, [vp, vp, i32, i32, u64, vp, vp]),
             "bwr_rank_modp_batch": (ctypes.c_int, [vp, i32, vp, i32, i32, u64, vp, vp]),
             "bwr_sequence_batch": (ctypes.c_int, [vp, i32, vp, i32, i32, u64, vp, vp]),
             "bwr_server_create": (ctypes.c_int, [u64, i32, i32, vp]),
@@ -309,6 +310,18 @@ def min_generators_dev(S_devs, primes):
         Pb = P[b * cap * s * s:(b + 1) * cap * s * s]
         out.append((delta[b * s:(b + 1) * s].copy(), Pb[: (md[b] + 1) * s * s].reshape(md[b] + 1, s, s).copy()))
     return out
+
+
+def rank_integer(A, primes, block: int, seed: int):
+    """(rank over the integers = the largest modular rank, ranks per prime) (Section 2.5)."""
+    st, keep = _host_csr(A)
+    pr = np.ascontiguousarray(primes, dtype=np.uint32)
+    ranks = np.zeros(len(pr), dtype=np.int64)
+    r = ctypes.c_int64(0)
+    _check(lib().bwr_rank_integer(ctypes.byref(st), pr.ctypes.data, int(len(pr)), int(block), int(seed),
+                                  ctypes.byref(r), ranks.ctypes.data))
+    del keep
+    return r.value, ranks
 
 
 def _csr_array(mats):

@@ -858,6 +858,19 @@ int bwr_rank_modp_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* p
     return BWR_OK;
 }
 
+int bwr_rank_integer(const bwr_csr* A, const uint32_t* primes, int32_t nprimes, int32_t block, uint64_t seed,
+                     int64_t* rank_out, int64_t* ranks_out) {
+    if (!A || !primes || nprimes < 1 || !rank_out) return fail(BWR_EINVAL, "bad arguments");
+    std::vector<int64_t> r((size_t)nprimes, 0);
+    const bwr_csr* one[1] = {A};
+    const int rc = bwr_rank_modp_batch(one, 1, primes, nprimes, block, seed, r.data(), nullptr);
+    if (rc != BWR_OK) return rc;
+    *rank_out = *std::max_element(r.begin(), r.end());
+    if (ranks_out) std::memcpy(ranks_out, r.data(), sizeof(int64_t) * r.size());
+    g_err.clear();
+    return BWR_OK;
+}
+
 int bwr_min_generator_dev(const uint32_t* S_dev, int64_t len, int32_t s, uint32_t p, void* stream,
                           int64_t* delta_out, uint32_t* P_out, int64_t P_cap_terms, int64_t* max_deg_out) {
     Error e = check_prime(p);

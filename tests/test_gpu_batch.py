@@ -6,10 +6,10 @@ import numpy as np
 import pytest
 
 import paper_0704_2351_amd as bw
-from oracle import native, splitmix
+from oracle import ge, native, splitmix
 from oracle import sequence as oseq
 from tests.gpu_util import announce, need_gpu
-from workloads import planted, random_sparse
+from workloads import from_dense, planted, random_sparse
 
 pytestmark = pytest.mark.gpu
 PRIMES4 = (65521, 65519, 65497, 2**31 - 1)
@@ -125,3 +125,21 @@ def test_batched_ranks_with_wide_entries_and_empty():
     assert ranks[2].tolist() == [90, 90]
     for t, p in enumerate((65521, 2**31 - 1)):
         assert ranks[0, t] == native.rank_csr_c(A, p)
+
+
+def test_rank_over_integers():
+    """Section 2.5: the rank over the integers as the largest rank modulo several primes equals the oracle's
+    and Bareiss's over Q on a 3 x 3 matrix of determinant -78 (rank 2 mod 3 and mod 13), and the planted rank
+    of a planted matrix; no modular rank exceeds it."""
+    need_gpu()
+    announce("rank over the integers")
+    M = np.array([[2, 3, 5], [7, 11, 13], [17, 19, 23]])
+    A = from_dense(M)
+    r, per = bw.rank_integer(A, (3, 13, 65521), 2, 4)
+    assert r == ge.rank_bareiss(M) == 3
+    assert per.max() == 3 and (per <= 3).all()
+    B = planted(300, 220, 180, 7, 4300)
+    primes = (3, 13, 65521, 2**31 - 1)
+    r, per = bw.rank_integer(B, primes, 8, 2)
+    assert r == ge.rank_over_integers(B, primes) == B.planted_rank
+    assert (per <= B.planted_rank).all()

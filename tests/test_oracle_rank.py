@@ -111,3 +111,21 @@ def test_config2_planted_rank_both_primes():
     assert 2_500_000 < A.nnz < 2_700_000
     assert native.rank_csr_c(A, 65521) == 140_000
     assert native.rank_csr_c(A, 2**31 - 1) == 140_000
+
+
+def test_rank_over_integers_is_the_largest_modular_rank():
+    """Section 2.5: the rank over the integers from several primes.  Pins: each modular rank is at most the
+    Bareiss rank over Q; a matrix whose determinant is -78 = -2*3*13 has rank 2 mod 3 and mod 13 and rank 3 over
+    Q, recovered once a prime not dividing 78 is among the primes; random integer matrices agree with Bareiss."""
+    M = np.array([[2, 3, 5], [7, 11, 13], [17, 19, 23]])
+    A = from_dense(M)
+    assert ge.rank_over_integers(A, (3, 13)) == 2
+    assert ge.rank_over_integers(A, (3, 13, 65521)) == 3 == ge.rank_bareiss(M)
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        m, n = int(rng.integers(2, 9)), int(rng.integers(2, 9))
+        M = rng.integers(-6, 7, size=(m, n)) * (rng.random((m, n)) < 0.6)
+        A = from_dense(M)
+        r = ge.rank_bareiss(M.tolist())
+        assert all(ge.rank_csr(A, p) <= r for p in (3, 5, 7))
+        assert ge.rank_over_integers(A, (3, 5, 65521, 2**31 - 1)) == r
