@@ -176,7 +176,7 @@ int bwr_time_step_kernels_dev(const bwr_csr* A_dev, uint32_t p, int32_t s, int32
  * ranks_out[j * nprimes + t].  Matrices with entries outside [-127, 127] or
  * a dimension above 2^24, and matrices whose side-by-side block (larger
  * dimension x width x bytes per residue) exceeds 2 MB (BWR_BATCH_BLOCK_BYTES),
- * take the single-matrix path, on 3 host threads (BWR_BATCH_SOLO_THREADS) that
+ * take the single-matrix path, on 2 host threads (BWR_BATCH_SOLO_THREADS) that
  * run beside the batched launches.  When the primes mix 16-bit and larger ones,
  * the 16-bit primes are batched with 16-bit residues and the larger ones take
  * the single-matrix path (BWR_BATCH_SPLIT=0: all primes batched, 32-bit

@@ -214,7 +214,7 @@ constexpr int64_t CHECK_TERMS = 4;
 // batched kernel loses to the single-matrix kernels once the block outgrows an XCD's L2); batching all four
 // primes in 32-bit residues with 8 MB gave 1.08-1.11x.
 constexpr int64_t BATCH_BLOCK_BYTES = 2 << 20;
-constexpr int BATCH_SOLO_THREADS = 3;
+constexpr int BATCH_SOLO_THREADS = 2;  // all 64 matrices x 4 primes: 2 threads 1.06x, 3 threads 1.02x
 
 int64_t env_i64(const char* name, int64_t dflt) {
     const char* v = getenv(name);
