@@ -203,8 +203,10 @@ int bwr_sequence_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* pr
                        uint64_t seed, const int64_t* len, uint32_t* const* S_out);
 
 /* ---- serving: a continuous-batching rank server ---------------------------
- * A worker thread keeps one batch of sequences running on the current device.
- * Submitted requests queue up and join the running batch at the next step
+ * A worker thread keeps two batches of sequences running on the current
+ * device, each on a stream of its own: requests at primes <= 2^16 (16-bit
+ * residues) and the others (32-bit residues).  Submitted requests queue up
+ * and join their running batch at the next step
  * boundary while the HBM budget (estimated footprint of encoded matrix,
  * blocks and sequence) and the slot count allow.  A finished sequence gets
  * its sigma-basis and read-out and the request is answered; results are

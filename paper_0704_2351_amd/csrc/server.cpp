@@ -1,8 +1,10 @@
 // Rank server: requests (matrix, prime, seed) arrive at any time; a worker
-// thread keeps one batch of sequences running on the device and admits
-// queued requests at step boundaries whenever the HBM budget and the slot
-// count allow (continuous batching).  A request whose sequence is complete
-// gets its sigma-basis and read-out, frees its memory and is answered.
+// thread keeps two batches of sequences running on the device (requests at
+// 16-bit primes in 16-bit residues, the others in 32-bit residues, each batch
+// on a stream of its own) and admits queued requests at step boundaries
+// whenever the HBM budget and the slot count allow (continuous batching).  A
+// request whose sequence is complete gets its sigma-basis and read-out, frees
+// its memory and is answered.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -60,7 +62,7 @@ Server::~Server() { stop(); }
 
 Error Server::start() {
     hipError_t e = hipGetDevice(&device_);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&compute_, hipStreamNonBlocking);
+    for (int c = 0; c < 2 && e == hipSuccess; ++c) e = hipStreamCreateWithFlags(&compute_[c], hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&upload_, hipStreamNonBlocking);
     if (e != hipSuccess) return Error::device(e, "server streams");
     const int spad = (block_ + 3) & ~3;
@@ -71,8 +73,8 @@ Error Server::start() {
     G2_ = std::max(W_ / 4, std::min(4, 64 / (W_ / 4)));
     if (!batch_supported(W_, G1_, false)) G1_ = 1;
     if (!batch_supported(W_, G2_, true)) G2_ = W_ / 4;
-    runners_[0] = std::make_unique<BatchRunner>(W_, G1_, G2_, compute_, 2);
-    runners_[1] = std::make_unique<BatchRunner>(W_, G1_, G2_, compute_, 4);
+    runners_[0] = std::make_unique<BatchRunner>(W_, G1_, G2_, compute_[0], 2);
+    runners_[1] = std::make_unique<BatchRunner>(W_, G1_, G2_, compute_[1], 4);
     worker_ = std::thread([this] { loop(); });
     return {};
 }
@@ -88,9 +90,12 @@ void Server::stop() {
     runners_[0].reset();
     runners_[1].reset();
     reqs_.clear();
-    if (compute_) (void)hipStreamDestroy(compute_);
+    for (hipStream_t& c : compute_) {
+        if (c) (void)hipStreamDestroy(c);
+        c = nullptr;
+    }
     if (upload_) (void)hipStreamDestroy(upload_);
-    compute_ = upload_ = nullptr;
+    upload_ = nullptr;
 }
 
 Error Server::submit(const CsrView& A, uint32_t p, uint64_t seed, uint64_t* ticket) {
@@ -256,10 +261,10 @@ void Server::loop() {
                 active.erase(it);
                 hipEvent_t ev = nullptr;
                 hipError_t he = e.ok() ? hipEventCreateWithFlags(&ev, hipEventDisableTiming) : hipSuccess;
-                if (e.ok() && he == hipSuccess) he = hipEventRecord(ev, compute_);
+                if (e.ok() && he == hipSuccess) he = hipEventRecord(ev, compute_[cls]);
                 if (!e.ok() || he != hipSuccess) {
                     if (ev) (void)hipEventDestroy(ev);
-                    (void)hipStreamSynchronize(compute_);
+                    (void)hipStreamSynchronize(compute_[cls]);
                     const Error er = e.ok() ? Error::device(he, "read-out event") : e;
                     run.release(id);
                     std::lock_guard<std::mutex> lk(mu_);
@@ -280,7 +285,7 @@ void Server::loop() {
             }
         }
         if (!e.ok()) {
-            (void)hipStreamSynchronize(compute_);
+            for (hipStream_t c : compute_) (void)hipStreamSynchronize(c);
             std::lock_guard<std::mutex> lk(mu_);
             for (auto& R : active) {
                 R->done = true;

@@ -44,8 +44,10 @@ class Server {
     int32_t block_;
     int device_ = 0;
     int W_ = 0, G1_ = 0, G2_ = 0;
-    hipStream_t compute_ = nullptr, upload_ = nullptr;
-    // batches of requests at primes <= 2^16 (16-bit residues) and at larger primes (32-bit residues)
+    hipStream_t upload_ = nullptr;
+    // batches of requests at primes <= 2^16 (16-bit residues) and at larger primes (32-bit residues), each
+    // on a stream of its own so that the two batches' steps run side by side
+    hipStream_t compute_[2] = {nullptr, nullptr};
     std::unique_ptr<BatchRunner> runners_[2];
     std::thread worker_;
     std::mutex mu_, upload_mu_;
