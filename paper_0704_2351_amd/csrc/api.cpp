@@ -288,6 +288,10 @@ Error rank_dev_impl(const CsrView& A, uint32_t p, int32_t block, uint64_t seed, 
         if (!e.ok()) return e;
         drain.st = sst;
         if (!(e = og.begin(S.as<uint32_t>(), L, s, p, min_chunk, sst)).ok()) return e;
+        // The generator's thread waits on the host for an event of st.  st captures a graph only for the
+        // sequence's first chunk of steps (at least 32; graphs need two chunks' worth of terms, so L >= 61),
+        // progress is called with t = 1 before that chunk and with t > 32 after it, and the first boundary
+        // (a quarter of L, >= 15 when a graph is used) exceeds 1: st is never capturing during such a wait.
         a.progress = [&](int64_t t) -> Error {
             const int64_t next = og.next_boundary();
             if (next < 0 || t < next) return {};

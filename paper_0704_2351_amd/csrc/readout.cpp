@@ -71,6 +71,8 @@ Error rank_of_sequences_dev(const uint32_t* const* S_dev, int n, int64_t L, int6
 
 ReadoutPool::ReadoutPool(int threads, int device) : device_(device) {
     if (const char* v = getenv("BWR_READOUT_THREADS")) threads = std::max(1, atoi(v));
+    relay_init_ = hipStreamCreateWithFlags(&relay_, hipStreamNonBlocking);
+    if (relay_init_ != hipSuccess) relay_ = nullptr;
     for (int i = 0; i < std::max(1, threads); ++i) workers_.emplace_back([this] { work(); });
 }
 
@@ -83,6 +85,7 @@ ReadoutPool::~ReadoutPool() {
     for (auto& w : workers_) w.join();
     for (Task& t : queue_)
         if (t.ready) (void)hipEventDestroy(t.ready);
+    if (relay_) (void)hipStreamDestroy(relay_);
 }
 
 void ReadoutPool::submit_group(const uint64_t* tags, const uint32_t* const* S_dev, const uint32_t* p, int n,
@@ -98,6 +101,11 @@ void ReadoutPool::submit_group(const uint64_t* tags, const uint32_t* const* S_de
     t.total = total;
     t.s = s;
     t.ready = ready;
+    t.relay_err = relay_init_;
+    if (ready && t.relay_err == hipSuccess) {
+        t.relay_err = hipStreamWaitEvent(relay_, ready, 0);
+        if (t.relay_err == hipSuccess) t.relay_err = hipEventRecord(ready, relay_);
+    }
     {
         std::lock_guard<std::mutex> lk(mu_);
         queue_.push_back(t);
@@ -138,12 +146,13 @@ void ReadoutPool::work() {
         if (se != hipSuccess) {
             err = Error::device(se, "read-out stream");
         } else {
-            // wait on the host, not with a stream wait: the producer's stream may be capturing its next
-            // graph by now, and a stream wait on an event of a capturing stream would pull this stream's
-            // read-out into that capture
-            hipError_t he = t.ready ? hipEventSynchronize(t.ready) : hipSuccess;
-            if (he != hipSuccess) err = Error::device(he, "hipEventSynchronize");
-            else err = rank_of_sequences_dev(t.S, t.n, t.L, t.total, t.s, t.p, st, ranks, &seconds);
+            // wait on the host for the event as re-recorded on the relay stream (never capturing); the
+            // producer's own stream may be capturing its next graph by now
+            hipError_t he = t.relay_err;
+            if (he != hipSuccess) err = Error::device(he, "read-out relay");
+            else if (t.ready && (he = hipEventSynchronize(t.ready)) != hipSuccess)
+                err = Error::device(he, "hipEventSynchronize");
+            if (err.ok()) err = rank_of_sequences_dev(t.S, t.n, t.L, t.total, t.s, t.p, st, ranks, &seconds);
             // the stream has been synchronized by the read-out (or nothing was queued after the wait)
             if (!err.ok()) (void)hipStreamSynchronize(st);
         }

@@ -42,7 +42,11 @@ class ReadoutPool {
     ReadoutPool(int threads, int device);
     ~ReadoutPool();
     // Waits (on the worker's host thread) for `ready` before reading S_dev; the event is owned by the pool
-    // afterwards.  S_dev must stay allocated until the task's result has been collected.
+    // afterwards.  S_dev must stay allocated until the task's result has been collected.  Called on the
+    // producer's thread while no capture is open on the stream `ready` was recorded on: the event is
+    // re-recorded on the pool's relay stream, which never captures, so that a worker's wait cannot meet a
+    // capture the producer begins later on its own stream (HIP refuses a host wait on an event whose
+    // stream is capturing, and invalidates that capture).
     void submit(uint64_t tag, const uint32_t* S_dev, int64_t L, int64_t total, int32_t s, uint32_t p,
                 hipEvent_t ready) {
         submit_group(&tag, &S_dev, &p, 1, L, total, s, ready);
@@ -64,9 +68,12 @@ class ReadoutPool {
         int64_t L, total;
         int32_t s;
         hipEvent_t ready;
+        hipError_t relay_err;  // failure to hand `ready` over to the relay stream
     };
     void work();
     int device_;
+    hipStream_t relay_ = nullptr;
+    hipError_t relay_init_ = hipSuccess;
     std::mutex mu_;
     std::condition_variable cv_, done_cv_;
     std::deque<Task> queue_;
