@@ -205,8 +205,12 @@ int bwr_sequence_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* pr
 /* ---- serving: a continuous-batching rank server ---------------------------
  * A worker thread keeps two batches of sequences running on the current
  * device, each on a stream of its own: requests at primes <= 2^16 (16-bit
- * residues) and the others (32-bit residues).  Submitted requests queue up
- * and join their running batch at the next step
+ * residues) and the others (32-bit residues).  Each batch advances 64 steps
+ * at a time; before queueing an advance the worker waits until the one it
+ * queued before has run (BWR_SERVER_AHEAD = K waits for the one queued K
+ * advances before, 0 never waits), so a request admitted now starts after at
+ * most one advance already on the device.  Submitted requests queue up and
+ * join their running batch at the next step
  * boundary while the HBM budget (estimated footprint of encoded matrix,
  * blocks and sequence) and the slot count allow.  A finished sequence gets
  * its sigma-basis and read-out and the request is answered; results are

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -63,6 +64,10 @@ Server::~Server() { stop(); }
 Error Server::start() {
     hipError_t e = hipGetDevice(&device_);
     for (int c = 0; c < 2 && e == hipSuccess; ++c) e = hipStreamCreateWithFlags(&compute_[c], hipStreamNonBlocking);
+    if (const char* a = getenv("BWR_SERVER_AHEAD")) ahead_ = std::max(0, std::min(MAX_AHEAD, atoi(a)));
+    for (int c = 0; c < 2 && e == hipSuccess; ++c)
+        for (int i = 0; i < ahead_ && e == hipSuccess; ++i)
+            e = hipEventCreateWithFlags(&ahead_ev_[c][i], hipEventDisableTiming);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&upload_, hipStreamNonBlocking);
     if (e != hipSuccess) return Error::device(e, "server streams");
     const int spad = (block_ + 3) & ~3;
@@ -90,6 +95,12 @@ void Server::stop() {
     runners_[0].reset();
     runners_[1].reset();
     reqs_.clear();
+    for (int c = 0; c < 2; ++c)
+        for (int i = 0; i < MAX_AHEAD; ++i) {
+            if (ahead_ev_[c][i]) (void)hipEventDestroy(ahead_ev_[c][i]);
+            ahead_ev_[c][i] = nullptr;
+            ahead_rec_[c][i] = false;
+        }
     for (hipStream_t& c : compute_) {
         if (c) (void)hipStreamDestroy(c);
         c = nullptr;
@@ -251,7 +262,19 @@ void Server::loop() {
                 continue;
             BatchRunner& run = *runners_[cls];
             std::vector<int> fin;
-            e = run.advance(64, &fin);
+            // wait until the advance queued ahead_ advances ago has run (no capture is open on this thread)
+            const int slot = ahead_pos_[cls];
+            if (ahead_ > 0 && ahead_rec_[cls][slot]) {
+                const hipError_t he = hipEventSynchronize(ahead_ev_[cls][slot]);
+                if (he != hipSuccess) e = Error::device(he, "server advance wait");
+            }
+            if (e.ok()) e = run.advance(64, &fin);
+            if (e.ok() && ahead_ > 0) {
+                const hipError_t he = hipEventRecord(ahead_ev_[cls][slot], compute_[cls]);
+                if (he != hipSuccess) e = Error::device(he, "server advance event");
+                ahead_rec_[cls][slot] = he == hipSuccess;
+                ahead_pos_[cls] = (slot + 1) % ahead_;
+            }
             steps_ = runners_[0]->global_step() + runners_[1]->global_step();
             for (int id : fin) {
                 auto it = std::find_if(active.begin(), active.end(),

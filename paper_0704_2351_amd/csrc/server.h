@@ -49,6 +49,14 @@ class Server {
     // on a stream of its own so that the two batches' steps run side by side
     hipStream_t compute_[2] = {nullptr, nullptr};
     std::unique_ptr<BatchRunner> runners_[2];
+    // advances a batch may have on the device (0: no bound): before queueing an advance the worker waits
+    // for the event recorded after the advance queued ahead_ advances before, so that requests admitted
+    // now start after at most ahead_ advances already queued
+    static constexpr int MAX_AHEAD = 8;
+    int ahead_ = 1;
+    hipEvent_t ahead_ev_[2][MAX_AHEAD] = {};
+    bool ahead_rec_[2][MAX_AHEAD] = {};
+    int ahead_pos_[2] = {0, 0};
     std::thread worker_;
     std::mutex mu_, upload_mu_;
     std::condition_variable cv_, done_cv_;
