@@ -92,3 +92,32 @@ def test_server_admission_by_budget():
         srv.submit(planted(30000, 20000, 15000, 9, 5), 65521, 1)
     assert ei.value.code == -3
     srv.close()
+
+
+@pytest.mark.parametrize("ahead", ["0", "1"])
+def test_server_readouts_beside_captures(monkeypatch, ahead):
+    """Many requests of staggered lengths: the active sets change often, so each batch captures new graphs
+    while read-outs of finished requests wait for their sequences on other threads.  A read-out's wait must
+    never meet a capture (HIP would refuse it and invalidate the capture); every answer is the planted rank,
+    with and without the bound on queued advances."""
+    need_gpu()
+    announce(f"server read-outs beside captures, BWR_SERVER_AHEAD={ahead}")
+    monkeypatch.setenv("BWR_SERVER_AHEAD", ahead)
+    rng = np.random.default_rng(40 + int(ahead))
+    reqs = []
+    for j in range(40):
+        n = int(rng.integers(600, 4000))
+        r = int(n * rng.uniform(0.7, 0.95))
+        p = int(CONFIG4_PRIMES[j % 4])
+        reqs.append((planted(int(1.5 * n), n, r, 9, 9100 + j), p, 21 + j))
+    srv = bw.Server(4 << 30, 24, 8)
+    tickets = []
+    for w in range(4):
+        tickets += [srv.submit(A, p, sd) for A, p, sd in reqs[10 * w:10 * w + 10]]
+        time.sleep(0.015)
+    ranks = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    announce(f"  stats {st}")
+    srv.close()
+    assert ranks == [A.planted_rank for A, _, _ in reqs]
+    assert st["completed"] == 40 and st["max_active"] > 4
