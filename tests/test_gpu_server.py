@@ -94,7 +94,7 @@ def test_server_admission_by_budget():
     srv.close()
 
 
-@pytest.mark.parametrize("ahead", ["0", "1"])
+@pytest.mark.parametrize("ahead", ["0", "1", "2"])
 def test_server_readouts_beside_captures(monkeypatch, ahead):
     """Many requests of staggered lengths: the active sets change often, so each batch captures new graphs
     while read-outs of finished requests wait for their sequences on other threads.  A read-out's wait must
