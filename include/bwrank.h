@@ -274,6 +274,33 @@ int bwr_min_generators_dev(const uint32_t* const* S_dev, int32_t n, int64_t len,
 int bwr_rank_from_sequence(const uint32_t* S, int64_t len, int64_t check, int32_t s, uint32_t p,
                            int64_t* rank_out);
 
+/* ---- environment settings ------------------------------------------------
+ * Every result is the same under any of these; they select launch plans or
+ * turn features off, for measurement and for tests.
+ *   BWR_NO_TUNE=1          heuristic launch plans, no autotuner trials
+ *   BWR_NO_PLAN_CACHE=1    tune again on every call (plans are otherwise
+ *                          kept per matrix shape, width and prime class)
+ *   BWR_G1, BWR_G2         lanes per row slice of the first / second product
+ *                          (single-matrix path; either one skips tuning)
+ *   BWR_E32=1              32-bit residues also for primes <= 2^16
+ *   BWR_PARTS=2            two column passes for 32-bit residues;
+ *                          BWR_NO_PARTS=1 keeps the tuner from trying them
+ *   BWR_NO_O7=1            no 7-wave variant of the fused 8-wide product
+ *   BWR_NO_SORT=1          no length-sorted relabelling of rows and columns
+ *   BWR_NO_GRAPH=1         launch every step instead of replaying HIP graphs
+ *   BWR_HOST_SIGMA=1       sigma-basis on the host instead of the device
+ *   BWR_SIGMA_MIN_CHUNK    see bwr_rank_info.t_sigma
+ *   BWR_SIGMA_BATCH, BWR_BATCH_SPLIT, BWR_BATCH_BLOCK_BYTES,
+ *   BWR_BATCH_SOLO_THREADS see bwr_rank_modp_batch
+ *   BWR_BATCH_G1, BWR_BATCH_G2  lanes per row slice of the batched products
+ *   BWR_BATCH_ACC=0        64-bit accumulators in the batched products
+ *   BWR_BATCH_BLOCKS       persistent blocks of the batched second product
+ *                          (default 2048)
+ *   BWR_BATCH_CHUNK        steps per batched graph (even, default 64)
+ *   BWR_READOUT_THREADS    host threads reading out finished batched or
+ *                          served sequences (default 3)
+ *   BWR_SERVER_AHEAD       see the serving section */
+
 #ifdef __cplusplus
 }
 #endif
