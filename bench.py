@@ -284,7 +284,8 @@ def paper_rank_mode(args):
 
 
 def serve_mode(args):
-    """Seeded Poisson trace of rank requests through the continuous-batching server."""
+    """Seeded Poisson trace of rank requests through the continuous-batching server, then the same trace
+    answered one request at a time by the single-matrix path (solves/s and latencies of both)."""
     import math
 
     import numpy as np
@@ -321,10 +322,30 @@ def serve_mode(args):
     st = srv.stats()
     srv.close()
     ok = all(rk == A.planted_rank for rk, A in zip(ranks, mats))
+    log(f"served {st['completed']} requests: {st['solves_per_s']:.2f} solves/s, p50 {st['p50_ms']:.0f} ms")
+    # the same trace answered one request at a time by the single-matrix path, in arrival order: a request
+    # waits for its arrival and for the one before it; rate and latencies are taken as the server takes them
+    bw.rank_modp(mats[0], trace[0][4], 8, 1)
+    plain_ranks, lat = [], []
+    t0 = time.perf_counter()
+    for (at, m, n, r, p, sd), A in zip(trace, mats):
+        delay = at - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        plain_ranks.append(bw.rank_modp(A, p, 8, 1)[0])
+        lat.append(time.perf_counter() - t0 - at)
+    plain_span = (time.perf_counter() - t0) - trace[0][0]
+    lat.sort()
+    q = lambda f: 1000.0 * lat[min(len(lat) - 1, int(f * len(lat)))]
+    plain_rate = len(trace) / plain_span
+    log(f"plain: {plain_rate:.2f} solves/s, p50 {q(0.5):.0f} ms")
     print(json.dumps({
         "metric": METRIC, "mode": "serving", "value": round(st["solves_per_s"], 4), "unit": "solves/s",
         "p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2), "wall_s": round(wall, 2),
         "completed": st["completed"], "max_queue": st["max_queue"], "max_active": st["max_active"],
+        "plain_solves_per_s": round(plain_rate, 4), "plain_p50_ms": round(q(0.5), 2),
+        "plain_p99_ms": round(q(0.99), 2), "speedup_vs_plain": round(st["solves_per_s"] / plain_rate, 3),
+        "ranks_equal_plain": plain_ranks == ranks,
         "ranks_equal_planted": bool(ok), "higher_is_better": True, "n_gpus": 1, "dtype": "u32",
         "data": "synthetic planted-rank matrices (seeded), seeded Poisson arrivals",
         "config": {"workload": f"{args.serve_count} requests, Poisson {args.serve_rate}/s, n log-uniform "
@@ -344,7 +365,8 @@ def main():
                          "solves/s of one batched call against the same ranks one call at a time")
     ap.add_argument("--batch-count", type=int, default=16, help="matrices of the batched configuration to use")
     ap.add_argument("--serve", action="store_true",
-                    help="serving workload: a seeded Poisson trace of rank requests through the server")
+                    help="serving workload: a seeded Poisson trace of rank requests through the server, and the "
+                         "same trace one request at a time through the single-matrix path")
     ap.add_argument("--serve-count", type=int, default=40)
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--serve-nmax", type=float, default=2e4)
