@@ -25,6 +25,7 @@
 #include <cstring>
 #include <functional>
 #include <mutex>
+#include <shared_mutex>
 #include <thread>
 
 namespace bwr {
@@ -176,7 +177,10 @@ NttPrime make_prime(uint32_t q) {
 // 2013265921 = 15 * 2^27 + 1, 1811939329 = 27 * 2^26 + 1, 2113929217 = 63 * 2^25 + 1
 NttPrime g_primes[3];
 std::once_flag g_primes_once;
-std::mutex g_tw_mu;
+// Growing a table reallocates it: growth takes this lock exclusively, and every use of the tables (the
+// transforms of a product, a copy) holds it shared, so that read-out threads running sigma-bases side by
+// side never read a table that another thread is replacing.
+std::shared_mutex g_tw_rw;
 
 void init_primes() {
     std::call_once(g_primes_once, [] {
@@ -187,7 +191,7 @@ void init_primes() {
 }
 
 void ensure_tables(NttPrime& P, int lg) {
-    std::lock_guard<std::mutex> lk(g_tw_mu);
+    std::unique_lock<std::shared_mutex> lk(g_tw_rw);
     if (P.table_log >= lg) return;
     const size_t N = (size_t)1 << lg;
     P.tw.assign(N, 0);
@@ -288,16 +292,17 @@ void mul_naive(const PolyMat& A, const PolyMat& B, int64_t lo, int64_t hi, const
 
 }  // namespace
 
-void ntt_tables(int t, int lg, uint32_t* q, const uint32_t** tw, const uint32_t** tws, const uint32_t** itw,
-                const uint32_t** itws) {
+void ntt_tables(int t, int lg, uint32_t* q, uint32_t* tw, uint32_t* tws, uint32_t* itw, uint32_t* itws) {
     init_primes();
     NttPrime& P = g_primes[t];
     ensure_tables(P, lg);
+    std::shared_lock<std::shared_mutex> lk(g_tw_rw);
+    const size_t n = (size_t)1 << lg;
     *q = P.q;
-    *tw = P.tw.data();
-    *tws = P.tws.data();
-    *itw = P.itw.data();
-    *itws = P.itws.data();
+    std::memcpy(tw, P.tw.data(), n * 4);
+    std::memcpy(tws, P.tws.data(), n * 4);
+    std::memcpy(itw, P.itw.data(), n * 4);
+    std::memcpy(itws, P.itws.data(), n * 4);
 }
 
 void set_sigma_threads(int n) {
@@ -329,6 +334,8 @@ void polymat_mul(const PolyMat& A, const PolyMat& B, int64_t lo, int64_t hi, uin
     const int lg = ceil_log2(need);
     const size_t N = (size_t)1 << lg;
     for (int t = 0; t < np; ++t) ensure_tables(g_primes[t], lg);
+    // tables only grow, so they still cover 2^lg points; no table is replaced while this is held
+    std::shared_lock<std::shared_mutex> tables(g_tw_rw);
     const int64_t W = hi - lo;
     // residues of the window for each prime: res[t][(i*c+l)*W + x]
     std::vector<std::vector<uint32_t>> res(np, std::vector<uint32_t>((size_t)r * c * W));
@@ -383,6 +390,7 @@ void polymat_mul(const PolyMat& A, const PolyMat& B, int64_t lo, int64_t hi, uin
             for (int64_t x = 0; x < W; ++x) dst[x] = mul_shoup(out[lo + x], ninv, nip, q);
         });
     }
+    tables.unlock();
     // CRT (Garner) and reduction mod p
     C->resize(r, c, W);
     const size_t total = (size_t)r * c * W;

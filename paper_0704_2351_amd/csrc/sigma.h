@@ -53,11 +53,10 @@ Error min_generator_mbasis(const uint32_t* S, int64_t L, int32_t s, uint32_t p, 
 void polymat_mul(const PolyMat& A, const PolyMat& B, int64_t lo, int64_t hi, uint32_t p, PolyMat* C);
 
 // Twiddle tables of FFT prime t (0: 2013265921, 1: 1811939329, 2: 2113929217)
-// for transforms up to 2^lg points: tw[half + j] = w_{2 half}^j, with Shoup
-// constants, and the same for the inverse roots.  Pointers stay valid until a
-// larger lg is requested.
-void ntt_tables(int t, int lg, uint32_t* q, const uint32_t** tw, const uint32_t** tws, const uint32_t** itw,
-                const uint32_t** itws);
+// for transforms up to 2^lg points, copied into the caller's arrays of 2^lg
+// entries each: tw[half + j] = w_{2 half}^j, with Shoup constants, and the
+// same for the inverse roots.  Safe beside concurrent products.
+void ntt_tables(int t, int lg, uint32_t* q, uint32_t* tw, uint32_t* tws, uint32_t* itw, uint32_t* itws);
 
 void set_sigma_threads(int n);
 int sigma_threads();

@@ -50,14 +50,9 @@ Error device_tables(DevTables* out) {
     if (!T.tw) {
         const size_t N = (size_t)1 << MAX_LG;
         std::vector<uint32_t> h_tw(3 * 2 * N), h_itw(3 * 2 * N);
-        for (int t = 0; t < 3; ++t) {
-            const uint32_t *tw, *tws, *itw, *itws;
-            ntt_tables(t, MAX_LG, &T.q[t], &tw, &tws, &itw, &itws);
-            std::memcpy(&h_tw[(2 * t) * N], tw, N * 4);
-            std::memcpy(&h_tw[(2 * t + 1) * N], tws, N * 4);
-            std::memcpy(&h_itw[(2 * t) * N], itw, N * 4);
-            std::memcpy(&h_itw[(2 * t + 1) * N], itws, N * 4);
-        }
+        for (int t = 0; t < 3; ++t)
+            ntt_tables(t, MAX_LG, &T.q[t], &h_tw[(2 * t) * N], &h_tw[(2 * t + 1) * N], &h_itw[(2 * t) * N],
+                       &h_itw[(2 * t + 1) * N]);
         uint32_t *a = nullptr, *b = nullptr;
         BWR_HIP(hipMalloc(&a, h_tw.size() * 4));
         BWR_HIP(hipMalloc(&b, h_itw.size() * 4));

@@ -146,3 +146,39 @@ def test_zero_sequence_generator():
     delta, P = bw.min_generator(S, p)
     assert delta.tolist() == [0, 0, 0]
     assert bw.rank_from_sequence(S, 6, 4, p) == 0
+
+
+_THREADS_SCRIPT = r"""
+import sys, threading
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+import paper_0704_2351_amd as bw
+p, s = 2147483647, 8
+rng = np.random.default_rng(7)
+seqs = [rng.integers(0, p, size=(L, s, s), dtype=np.uint64).astype(np.uint32) for L in (300, 700, 1500, 3100, 6300)]
+out, errs = [None] * len(seqs), []
+def run(i):
+    try:
+        out[i] = bw.min_generator(seqs[i], p)
+    except Exception as e:
+        errs.append(repr(e))
+ths = [threading.Thread(target=run, args=(i,)) for i in range(len(seqs))]
+for t in ths: t.start()
+for t in ths: t.join()
+bad = sum(out[i] is None or not all(np.array_equal(a, b) for a, b in zip(out[i], bw.min_generator(S, p)))
+          for i, S in enumerate(seqs))
+print("errors", errs, "mismatches", bad)
+"""
+
+
+def test_host_sigma_bases_on_threads():
+    """Host sigma-bases on several threads at once (read-out threads do this for blocks beyond the device
+    leaf): each equals the same computation run alone.  Run in a fresh process so that the shared transform
+    tables grow while other threads transform; growing them under a concurrent transform once gave wrong
+    generators and spurious degree errors."""
+    import subprocess
+    import sys
+
+    r = subprocess.run([sys.executable, "-c", _THREADS_SCRIPT, ROOT], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert r.stdout.strip().endswith("errors [] mismatches 0"), r.stdout + r.stderr[-2000:]
