@@ -12,6 +12,8 @@
 #include <stdint.h>
 
 #include <climits>
+#include <mutex>
+#include <vector>
 
 #include "sigma_gpu.h"
 
@@ -963,15 +965,32 @@ size_t mbasis_leaf2_lds(int m, int n, int sigma) {
 
 namespace {
 
+// Raises the kernel's dynamic-LDS limit to at least lds on the current device.  The limit only grows, under a
+// lock, so that threads launching leaves of different orders side by side never lower it below what another
+// thread's launch needs.
+template <int S, bool SMALLP>
+hipError_t leaf2_allow_lds(size_t lds) {
+    if (lds <= 64 * 1024) return hipSuccess;
+    static std::mutex mu;
+    static std::vector<size_t> allowed;  // per device
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)allowed.size() <= dev) allowed.resize(dev + 1, 0);
+    if (lds <= allowed[dev]) return hipSuccess;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mbasis_leaf2<S, SMALLP>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess) allowed[dev] = lds;
+    return e;
+}
+
 template <int S, bool SMALLP>
 hipError_t leaf2_launch(const uint32_t* G, int64_t ldG, int64_t gbs, int sigma, int64_t* d, uint32_t* P, int64_t ldP,
                         int64_t pbs, const PrimeBatch& pb, hipStream_t st) {
     const size_t lds = mbasis_leaf2_lds(2 * S, S, sigma);
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mbasis_leaf2<S, SMALLP>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    }
+    hipError_t e = leaf2_allow_lds<S, SMALLP>(lds);
+    if (e != hipSuccess) return e;
     k_mbasis_leaf2<S, SMALLP><<<(unsigned)pb.n, LEAF2_TPB, lds, st>>>(G, ldG, gbs, sigma, d, P, ldP, pbs, pb);
     return hipGetLastError();
 }
