@@ -1,30 +1,39 @@
-"""Benchmark: block Wiedemann rank mod p on one MI355X.
+"""Benchmark: the block Wiedemann sequence mod p on one MI355X.
 
-Workload (one "step"): the rank of the planted 200 000 x 150 000 integer matrix
-(planted rank 140 000, ~2.6 M non-zeros) with block size 8, once at
-p = 65521 and once at p = 2^31 - 1, from a CSR already resident in device
-memory: encoding of A and A^T, the 2 + ceil(2n/s) + 4 sequence terms on the
-GPU, the sigma-basis and the read-out on the host.  Every rank is checked
-against the planted rank.
+Workload (the default, one "step"): 512 applications of B = D_c A^T D_r A D_c
+(513 sequence terms S_k = U^T B^k V mod p, projections included) on the
+planted 2 000 000 x 1 000 000 integer matrix (planted rank 900 000, 37.2 M
+non-zeros, 85 % +-1), block size 16, p = 65521, the paper-scale shape.  The
+matrix is encoded once on the device (bwr_matrix_create_dev) and the
+autotuner has picked the launch plan before the timed region; every step is one
+bwr_matrix_sequence_dev call from the same U, V and diagonals, inputs resident
+in HBM.  After the timed steps the whole rank of the same matrix is computed
+once (bwr_rank_modp_dev: encoding, 2 + 2n/16 + 4 terms, sigma-basis, read-out)
+and checked against the planted rank.
 
 value = whole-job throughput in Gnnz.vec/s: the sparse multiply-adds of the
-two products of every sequence step (2 nnz s per step), summed over the step's
-solves, divided by the step's wall time.  The two primes are solved from two
-host threads (one library stream each), so one prime's sigma-basis overlaps
-the other prime's sequence on the device.
+two products of every application of B (2 nnz s per application), summed over
+the timed steps, divided by their wall time.
 
-roofline: the dominant kernel is the second sparse product of a step (A^T
-times the block, column scale and the fused U^T projection); its average
-device time comes from HIP events around back-to-back launches on the stream
-the kernel runs on (bwr_time_step_kernels_dev), its algorithmic bytes per
-launch from the plain encoding (4 B index + 1 B value per non-zero, 4 B row
-pointers, 4 B residues): B_launch = 4(n+1) + 5 nnz + 4 s (n + m).  traffic is
-the measured memory traffic per launch from the committed counter summary
-(profiles/traffic.json), null when that summary belongs to another revision
-of the kernel source.
+roofline: the kernel with the most device time per step (of the first product
+A X with the row scale, and the second product A^T Y with the column scale and
+the fused U^T projection); its average duration comes from HIP events around
+back-to-back launches on the stream the kernel runs on
+(bwr_time_step_kernels_dev), its algorithmic bytes per launch from the plain
+encoding (4 B index + 1 B value per non-zero, 4 B row pointers, 4 B residues):
+B_launch = 4 (rows + 1) + 5 nnz + 4 s (n + m).  traffic is the measured memory
+traffic per launch from the committed counter summary (profiles/traffic.json),
+null when that summary belongs to another revision of the kernel source.
 
 cpu_baseline: the oracle's plain sequence (scipy CSR products and numpy
-reductions mod p) for a bounded number of steps of the same workload.
+reductions mod p) on a bounded number of applications of B of the same
+matrix, on all host cores (the block's columns split over threads, as the
+paper splits them over processes) and on one core; plus the oracle's plain-C
+elimination rank of the 2000 x 1500 and 200000 x 150000 planted matrices.
+
+Other modes: --rank-c2 (ranks of the 200000 x 150000 matrix at p = 65521 and
+2^31 - 1), --paper-rank (the whole rank only), --batch, --serve, and
+--profile-kernels / --traffic-from for the counter summaries.
 """
 from __future__ import annotations
 
@@ -45,111 +54,154 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(A, p, s, target_s=15.0):
-    """The oracle's sequence loop, timed on a bounded number of steps."""
+def cpu_info():
+    """CPU model (from /proc/cpuinfo) and the threads this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except AttributeError:
+        threads = os.cpu_count() or 1
+    return model, threads
+
+
+def cpu_baseline(A, p, s, target_s=12.0, ge_mats=()):
+    """The oracle's sequence loop on a bounded number of applications of B of A: on all host threads (the
+    block's columns split over a thread pool, each thread running the oracle's apply on its columns; scipy's
+    sparse products release the interpreter lock) and on one thread; plus the oracle's plain-C elimination rank
+    of each matrix in ge_mats (name, CSR)."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import numpy as np
 
+    from oracle import native
     from oracle import sequence as oseq
 
+    model, threads = cpu_info()
     rng = np.random.default_rng(0)
     U = rng.integers(0, p, size=(A.n, s), dtype=np.int64)
     V = rng.integers(0, p, size=(A.n, s), dtype=np.int64)
     dr = rng.integers(1, p, size=A.m)
     dc = rng.integers(1, p, size=A.n)
     orc = oseq.Oracle(A.m, A.n, A.row_ptr, A.col_idx, A.val, p, dr, dc)
-    W = V % p
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        W = orc.apply(W)
-        oseq.project(U, W, p)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= target_s or steps >= 400:
-            break
-    rate = 2.0 * A.nnz * s * steps / el / 1e9
-    return {"value": rate, "unit": "Gnnz·vec/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} steps of the oracle's plain sequence (B = D_c A^T D_r A D_c applied to an n x {s} "
-                      f"block, then U^T W mod {p}) on the same matrix, {el:.1f} s single-threaded"}
+
+    def run(nthreads):
+        groups = [list(range(c, s, nthreads)) for c in range(min(nthreads, s))]
+        W = V % p
+        steps = 0
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=len(groups)) as ex:
+            while True:
+                parts = list(ex.map(lambda g: orc.apply(W[:, g]), groups))
+                for g, part in zip(groups, parts):
+                    W[:, g] = part
+                oseq.project(U, W, p)
+                steps += 1
+                el = time.perf_counter() - t0
+                if el >= target_s or steps >= 400:
+                    break
+        return 2.0 * A.nnz * s * steps / el / 1e9, steps, el
+
+    use = max(1, min(threads, s))
+    log(f"cpu baseline: oracle sequence on {use} threads")
+    rate_all, st_all, el_all = run(use)
+    log("cpu baseline: oracle sequence on 1 thread")
+    rate_one, st_one, el_one = run(1)
+    ge = {}
+    for name, M in ge_mats:
+        log(f"cpu baseline: elimination rank of {name}")
+        t0 = time.perf_counter()
+        r = native.rank_csr_c(M, p)
+        ge[name] = {"rank": int(r), "seconds": round(time.perf_counter() - t0, 3), "p": p}
+    return {"value": round(rate_all, 4), "unit": "Gnnz·vec/s", "cores": use, "kind": "oracle",
+            "sample": f"{st_all} applications of B = D_c A^T D_r A D_c to the n x {s} block (then U^T W mod {p}) "
+                      f"of the same {A.m} x {A.n} matrix by the oracle's plain sequence, the block's columns split "
+                      f"over {use} threads, {el_all:.1f} s",
+            "one_core": {"value": round(rate_one, 4), "cores": 1,
+                         "sample": f"{st_one} applications on one thread, {el_one:.1f} s"},
+            "cpu_model": model, "host_threads": threads,
+            "elimination_rank": ge}
 
 
-def kernel_traffic(W, G, esize, fused, kpass=0):
-    """HBM bytes per launch of the row-split kernel instantiation <W, G, *, esize == 2, fused, residue
-    type, kpass> from the committed counter summary, or None when the summary is missing, was taken on
-    another revision of the kernel source, or does not hold that instantiation."""
+def _source_digest(rel):
     import hashlib
+
+    with open(os.path.join(ROOT, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def kernel_traffic(name):
+    """Memory traffic per launch (bytes) of the kernel instantiation `name` (as rocprofv3 prints it, without
+    the namespace; "ACC" stands for any accumulator digit) from the committed counter summary, or None when
+    the summary is missing, was taken on another revision of the kernel's source, or does not hold exactly
+    one matching instantiation."""
     import re
 
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
-        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
-            digest = hashlib.sha256(f.read()).hexdigest()
-    except (OSError, KeyError, ValueError):
+        pat = re.compile(re.escape(name).replace("ACC", r"\d"))
+        hits = [v for k, v in rec["kernels"].items() if pat.fullmatch(k)]
+        if len(hits) != 1:
+            return None
+        ent = hits[0]
+        src = ent["source"]
+        if rec["sources"][src] != _source_digest(src):
+            return None
+    except (OSError, KeyError, ValueError, TypeError):
         return None
-    if rec.get("source_sha256") != digest:
-        return None
+    return ent.get("bytes_per_launch")
+
+
+def product_kernel(plan, which, s, p):
+    """rocprofv3 name (without namespace) and source of the kernel that runs product `which` (1 or 2)."""
+    esize = plan["esize"]
     etype = "unsigned short" if esize == 2 else "unsigned int"
-    pat = re.compile(rf"k_spmm_split<{W}, {G}, \d, {str(esize == 2).lower()}, {str(bool(fused)).lower()}, "
-                     rf"{etype}, {kpass}>$")
-    hits = [v for k, v in rec.get("kernels", {}).items() if pat.match(k)]
-    return hits[0].get("bytes_per_launch") if len(hits) == 1 else None
+    W = plan["W"]
+    split = "true" if p > 65536 else "false"
+    if plan[f"T{which}R"] > 0:
+        proj = "true" if which == 2 else "false"
+        return (f"k_spmm_tiled<{W}, {etype}, {split}, {proj}>", "paper_0704_2351_amd/csrc/spmm_tiled.hip",
+                f"tiled: row blocks of {plan[f'T{which}R']} rows, slabs of 2^{plan[f'T{which}cb']} block rows, "
+                f"{plan[f'T{which}grid']} workgroups")
+    G = plan[f"G{which}"]
+    fused = "true" if (which == 2 and plan["fused"]) else "false"
+    return (f"k_spmm_split<{W}, {G}, ACC, {'true' if p <= 65536 else 'false'}, {fused}, {etype}, 0>",
+            "paper_0704_2351_amd/csrc/spmm.hip", f"row split G = {G}")
 
 
 def roofline_entry(A, s, p, us, plan):
-    """Roofline of the dominant kernel of a step: the second sparse product (A^T times the
-    n_outer x s block, column scale, fused U^T projection).  Algorithmic bytes per launch with the
-    plain encoding: 4 B row pointers, 4 B index + 1 B value per non-zero, 4 B per residue read and
-    written (U and the diagonals are regenerable and not counted)."""
+    """Roofline of the kernel with the most device time per step: algorithmic bytes per launch with the plain
+    encoding (4 B row pointers, 4 B index + 1 B value per non-zero, 4 B per residue read and written; U and
+    the diagonals are regenerable and not counted) over its average launch time."""
     m, n, nnz = A.m, A.n, A.nnz
-    bytes_second = 4 * (n + 1) + 5 * nnz + 4 * s * (m + n)
-    bytes_first = 4 * (m + 1) + 5 * nnz + 4 * s * (n + m)
-    ach = bytes_second / (us[1] * 1e-6) / 1e9
-    ach1 = bytes_first / (us[0] * 1e-6) / 1e9
+    b = {1: 4 * (m + 1) + 5 * nnz + 4 * s * (n + m), 2: 4 * (n + 1) + 5 * nnz + 4 * s * (m + n)}
+    t = {1: float(us[0]), 2: float(us[1]) + float(us[2])}
+    dom = 1 if t[1] > t[2] else 2
+    other = 3 - dom
+    ach = b[dom] / (t[dom] * 1e-6) / 1e9
+    ach_o = b[other] / (t[other] * 1e-6) / 1e9
+    name, src, how = product_kernel(plan, dom, s, p)
+    oname, _, ohow = product_kernel(plan, other, s, p)
+    what = {1: "first product: A X, row scale", 2: "second product: A^T Y, column scale, fused U^T projection"}
     return {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": kernel_traffic(plan["W"], plan["G2"], plan["esize"], plan["fused"]),
-            "kernel": f"k_spmm_split (second product: A^T Y, column scale, projection fused={bool(plan['fused'])}, "
-                      f"W={plan['W']}, G={plan['G2']}, {plan['esize']}-byte residues), p = {p}",
-            "avg_launch_us": round(us[1], 3), "bytes_per_launch": int(bytes_second),
-            "first_product": {"achieved": round(ach1, 1), "frac": round(ach1 / PEAK_HBM_GBS, 4),
-                              "avg_launch_us": round(us[0], 3), "bytes_per_launch": int(bytes_first),
-                              "G": plan["G1"]}}
-
-
-def result_line(A, s, primes, steps, warmup, elapsed, infos, us, plans):
-    """The JSON record of a timed run: `infos` are the rank_modp infos of the timed solves, `us` and
-    `plans` the per-prime kernel timings and launch plans."""
-    nnz = A.nnz
-    work = sum(2.0 * nnz * i["s"] * (i["len"] + i["check_terms"] - 1) for i in infos)
-    seq_time = sum(i["t_sequence"] for i in infos)
-    sigma_time = sum(i["t_sigma"] for i in infos)
-    return {
-        "metric": METRIC,
-        "value": round(work / elapsed / 1e9, 3),
-        "unit": "Gnnz·vec/s",
-        "n_gpus": 1,
-        "steps": steps,
-        "warmup": warmup,
-        "ms_per_step": round(1000.0 * elapsed / steps, 2),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic planted-rank matrix (seeded); no dataset",
-        "config": {"workload": f"rank mod p of a planted {A.m} x {A.n} sparse integer matrix "
-                               f"(rank {A.planted_rank}, {nnz / 1e6:.1f} M non-zeros), block {s}, "
-                               f"p = {' and '.join(str(p) for p in primes)}",
-                   "m": A.m, "n": A.n, "nnz": nnz, "block": s, "primes": list(primes), "parallelism": "single GPU"},
-        "solves_per_s": round(len(infos) / elapsed, 4),
-        "sequence_gnnzvec_per_s": round(work / seq_time / 1e9, 3),
-        "sequence_s_per_solve": round(seq_time / len(infos), 4),
-        "sigma_basis_s_per_solve": round(sigma_time / len(infos), 4),
-        "sigma_threads": infos[0]["sigma_threads"],
-        "step_kernel_us": {str(p): [round(float(x), 3) for x in us[p]] for p in primes},
-        "step_plan": {str(p): plans[p] for p in primes},
-        "roofline": roofline_entry(A, s, primes[0], us[primes[0]], plans[primes[0]]),
-    }
+            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": kernel_traffic(name),
+            "kernel": f"{name} ({what[dom]}; {how}; {plan['esize']}-byte residues), p = {p}",
+            "avg_launch_us": round(t[dom], 3), "bytes_per_launch": int(b[dom]),
+            "other_product": {"kernel": f"{oname} ({what[other]}; {ohow})", "achieved": round(ach_o, 1),
+                              "frac": round(ach_o / PEAK_HBM_GBS, 4), "avg_launch_us": round(t[other], 3),
+                              "bytes_per_launch": int(b[other]), "traffic": kernel_traffic(oname)},
+            "step": {"achieved": round((b[1] + b[2]) / ((t[1] + t[2]) * 1e-6) / 1e9, 1),
+                     "frac": round((b[1] + b[2]) / ((t[1] + t[2]) * 1e-6) / 1e9 / PEAK_HBM_GBS, 4),
+                     "kernel_us": round(t[1] + t[2], 3), "bytes": int(b[1] + b[2])}}
 
 
 def batch_mode(args):
@@ -194,65 +246,169 @@ def batch_mode(args):
                    "matrices": [[A.m, A.n, A.nnz] for A in mats]}}), flush=True)
 
 
-def paper_scale_mode(args):
-    """The 2 000 000 x 1 000 000 matrix (37 M non-zeros, block 16, p = 65521): kernel timings and roofline at a
-    size far beyond the caches, the sequence rate over a bounded number of steps, and the device sigma-basis
-    time at the full sequence length (on a random sequence of that length and block size)."""
+def draws(p, s, m, n, torch):
+    """U, V (n x s) and the diagonals D_r (m), D_c (n) from the library's counter-based generator, on cuda:0."""
     import numpy as np
+
+    import paper_0704_2351_amd as bw
+
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).cuda()
+    return (t(bw.random_block(11, 1, n, s, p)), t(bw.random_block(11, 0, n, s, p)),
+            t(bw.random_block(11, 2, m, 1, p, True).reshape(m)), t(bw.random_block(11, 3, n, 1, p, True).reshape(n)))
+
+
+def sequence_mode(args):
+    """The default workload: blocks of sequence terms of the 2 000 000 x 1 000 000 matrix (see the module
+    docstring), then the whole rank once."""
+    import torch
+
+    import paper_0704_2351_amd as bw
+    from workloads import config1, config2, config3
+
+    s, p = 16, 65521
+    log("generating the planted 2000000 x 1000000 matrix")
+    A = config3()
+    m, n, nnz = A.m, A.n, A.nnz
+    Ad = bw.csr_to_device(A, "cuda:0")
+    torch.cuda.synchronize()
+    log("kernel timing (the autotuner picks the launch plan on its first call)")
+    us, plan = bw.time_step_kernels_dev(Ad, p, s, False, args.kernel_iters, with_plan=True)
+    log(f"plan {plan}, kernels {[round(x, 1) for x in us]} us")
+    t0 = time.perf_counter()
+    M = bw.Matrix(Ad, p)
+    torch.cuda.synchronize()
+    t_encode = time.perf_counter() - t0
+    U, V, dr, dc = draws(p, s, m, n, torch)
+    terms = args.terms
+    for w in range(args.warmup):
+        M.sequence_dev(U, V, p, terms, dr, dc)
+        log(f"warmup {w + 1}/{args.warmup}")
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps of {terms - 1} applications of B")
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        S = M.sequence_dev(U, V, p, terms, dr, dc)
+        if (k + 1) % 5 == 0 or k + 1 == args.steps:
+            log(f"step {k + 1}/{args.steps} queued")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    work = 2.0 * nnz * s * (terms - 1) * args.steps
+    # live kernel timing for the roofline (HIP events on the stream the kernels run on), with the plan the
+    # timed steps used
+    us, plan = bw.time_step_kernels_dev(Ad, p, s, False, args.kernel_iters, with_plan=True)
+    M.close()
+    out = {
+        "metric": METRIC,
+        "value": round(work / elapsed / 1e9, 3),
+        "unit": "Gnnz·vec/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1000.0 * elapsed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u16" if plan["esize"] == 2 else "u32",
+        "data": "synthetic planted-rank matrix (seeded); no dataset",
+        "config": {"workload": f"block Wiedemann sequence mod {p} of a planted {m} x {n} sparse integer matrix "
+                               f"(rank {A.planted_rank}, {nnz / 1e6:.1f} M non-zeros), block {s}, "
+                               f"{terms - 1} applications of B per step",
+                   "m": m, "n": n, "nnz": nnz, "block": s, "p": p, "applications_per_step": terms - 1,
+                   "parallelism": "single GPU"},
+        "us_per_application": round(1e6 * elapsed / ((terms - 1) * args.steps), 2),
+        "encode_s": round(t_encode, 3),
+        "step_kernel_us": [round(float(x), 3) for x in us],
+        "step_plan": plan,
+        "roofline": roofline_entry(A, s, p, us, plan),
+    }
+    if not args.no_rank:
+        log(f"rank mod {p} of the same matrix, block {s} ({bw.sequence_length(n, s) + 4} terms)")
+        t0 = time.perf_counter()
+        r, info = bw.rank_modp_dev(Ad, p, s, 1)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out["rank"] = {"rank": int(r), "planted_rank": int(A.planted_rank), "equals_planted": bool(r == A.planted_rank),
+                       "seconds": round(el, 2), "t_sequence": round(info["t_sequence"], 2),
+                       "t_sigma_after_sequence": round(info["t_sigma"], 3), "t_encode": round(info["t_encode"], 3),
+                       "gnnzvec_per_s": round(2.0 * nnz * info["s"] * (info["len"] + info["check_terms"] - 1) / el / 1e9,
+                                              3)}
+    del Ad
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(A, p, s, ge_mats=(("2000x1500", config1()), ("200000x150000", config2())))
+    print(json.dumps(out), flush=True)
+
+
+def profile_kernels_mode(args):
+    """The kernels of one step of the default workload launched back to back (bwr_time_step_kernels_dev, after
+    the autotuner), then a 256 MiB device copy: the command the counter summaries are taken on (the copy
+    calibrates FETCH_SIZE and WRITE_SIZE)."""
     import torch
 
     import paper_0704_2351_amd as bw
     from workloads import config3
 
     s, p = 16, 65521
-    log("generating the planted 2000000 x 1000000 matrix")
     A = config3()
     Ad = bw.csr_to_device(A, "cuda:0")
     torch.cuda.synchronize()
-    m, n, nnz = A.m, A.n, A.nnz
-    log("kernel timing")
     us, plan = bw.time_step_kernels_dev(Ad, p, s, False, args.kernel_iters, with_plan=True)
-    bytes_second = 4 * (n + 1) + 5 * nnz + 4 * s * (m + n)
-    bytes_first = 4 * (m + 1) + 5 * nnz + 4 * s * (n + m)
-    L = bw.sequence_length(n, s)
-    steps = args.paper_steps
-    log(f"sequence of {steps} terms")
-    rng = np.random.default_rng(0)
-    U = torch.from_numpy(rng.integers(0, p, size=(n, s), dtype=np.int64).astype(np.int32)).cuda()
-    V = torch.from_numpy(rng.integers(0, p, size=(n, s), dtype=np.int64).astype(np.int32)).cuda()
-    dr = torch.from_numpy(rng.integers(1, p, size=m, dtype=np.int64).astype(np.int32)).cuda()
-    dc = torch.from_numpy(rng.integers(1, p, size=n, dtype=np.int64).astype(np.int32)).cuda()
-    bw.sequence_dev(Ad, U, V, p, 600, dr, dc)
+    src = torch.empty(64 << 20, dtype=torch.int32, device="cuda:0").fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    bw.sequence_dev(Ad, U, V, p, steps, dr, dc)
-    torch.cuda.synchronize()
-    ts = time.perf_counter() - t0
-    per_step = ts / (steps - 1)
-    log(f"device sigma-basis at L = {L}, s = {s} (random sequence)")
-    S = torch.from_numpy(rng.integers(0, p, size=(L, s, s), dtype=np.int64).astype(np.int32)).cuda()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    bw.min_generator_dev(S, p)
-    tsig = time.perf_counter() - t0
-    work_step = 2.0 * nnz * s
-    print(json.dumps({
-        "metric": METRIC, "mode": "paper_scale", "unit": "Gnnz·vec/s",
-        "value": round(work_step / per_step / 1e9, 3), "steps": steps, "per_step_us": round(per_step * 1e6, 2),
-        "projected_sequence_s": round(per_step * (L + 3), 2), "sigma_basis_s": round(tsig, 2),
-        "projected_rank_s": round(per_step * (L + 3) + tsig, 2),
-        "step_kernel_us": [round(float(x), 3) for x in us], "step_plan": plan,
-        "roofline": {"bound": "hbm", "unit": "GB/s", "peak": PEAK_HBM_GBS,
-                     "second_product": {"achieved": round(bytes_second / (us[1] * 1e-6) / 1e9, 1),
-                                        "frac": round(bytes_second / (us[1] * 1e-6) / 1e9 / PEAK_HBM_GBS, 4),
-                                        "avg_launch_us": round(float(us[1]), 3), "bytes_per_launch": int(bytes_second)},
-                     "first_product": {"achieved": round(bytes_first / (us[0] * 1e-6) / 1e9, 1),
-                                       "frac": round(bytes_first / (us[0] * 1e-6) / 1e9 / PEAK_HBM_GBS, 4),
-                                       "avg_launch_us": round(float(us[0]), 3), "bytes_per_launch": int(bytes_first)}},
-        "higher_is_better": True, "n_gpus": 1, "dtype": "u16" if plan["esize"] == 2 else "u32",
-        "data": "synthetic planted-rank matrix (seeded); random sequence for the sigma-basis timing",
-        "config": {"workload": f"planted {m} x {n}, rank {A.planted_rank}, {nnz / 1e6:.1f} M non-zeros, block {s}, "
-                               f"p = {p}", "m": m, "n": n, "nnz": nnz, "sequence_length": L}}), flush=True)
+    print(json.dumps({"kernels_us": [round(x, 3) for x in us], "plan": plan, "copy_bytes": 256 << 20,
+                      "first": product_kernel(plan, 1, s, p)[0], "second": product_kernel(plan, 2, s, p)[0]}),
+          flush=True)
+
+
+def traffic_from(fetch_dir, write_dir, out_path):
+    """profiles/traffic.json from two rocprofv3 --pmc runs of --profile-kernels (FETCH_SIZE, then WRITE_SIZE):
+    per dispatch KiB of every sparse-product kernel, scaled by what the same counter reads for the 256 MiB
+    device copy of that run (reads 256 MiB, writes 256 MiB)."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        vals = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for row in csv.DictReader(open(f)):
+                if row.get("Counter_Name") != counter:
+                    continue
+                k = row["Kernel_Name"]
+                vals.setdefault(k, []).append(float(row["Counter_Value"]))
+        return vals
+
+    fetch, write = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    copy = [k for k in fetch if "copy" in k.lower() or "elementwise" in k.lower()]
+    big = 256 << 10  # KiB
+    cf = max((v for k in copy for v in fetch[k]), default=0.0)
+    cw = max((v for k in copy for v in write.get(k, [])), default=0.0)
+    ff = big / cf if cf > 0 else 1.0
+    fw = big / cw if cw > 0 else 1.0
+    srcs = {"k_spmm_tiled": "paper_0704_2351_amd/csrc/spmm_tiled.hip",
+            "k_spmm_split": "paper_0704_2351_amd/csrc/spmm.hip"}
+    kernels = {}
+    for k, v in fetch.items():
+        short = k.replace("(anonymous namespace)::", "")
+        short = short[5:] if short.startswith("void ") else short
+        short = short.split("(")[0].split("::")[-1].strip()
+        src = next((srcs[x] for x in srcs if short.startswith(x)), None)
+        if src is None or k not in write:
+            continue
+        fk = sum(v) / len(v)
+        wk = sum(write[k]) / len(write[k])
+        kernels[short] = {"source": src, "dispatches": len(v), "fetch_kib": round(fk, 1), "write_kib": round(wk, 1),
+                          "bytes_per_launch": int(round(1024 * (fk * ff + wk * fw)))}
+    rec = {"sources": {s: _source_digest(s) for s in sorted(set(srcs.values()))},
+           "workload": "2000000 x 1000000 planted (37.2 M non-zeros), block 16, p = 65521",
+           "command": "rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -- python3 bench.py --profile-kernels",
+           "fetch_factor": round(ff, 4), "write_factor": round(fw, 4),
+           "note": "average over every dispatch of the kernel in the run (autotuner trials and timing loop)",
+           "kernels": dict(sorted(kernels.items()))}
+    with open(out_path, "w") as f:
+        json.dump(rec, f, indent=1)
+    return rec
 
 
 def paper_rank_mode(args):
@@ -353,12 +509,63 @@ def serve_mode(args):
                                f"block 8"}}), flush=True)
 
 
+def rank_c2_mode(args):
+    """Ranks of the 200 000 x 150 000 matrix (planted rank 140 000, block 8) at p = 65521 and p = 2^31 - 1 from a
+    CSR in device memory, the two primes from two host threads; one step = both ranks."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import torch
+
+    import paper_0704_2351_amd as bw
+    from workloads import config2
+
+    s = 8
+    primes = (65521, 2**31 - 1)
+    log("generating the planted 200000 x 150000 matrix")
+    A = config2()
+    Ad = bw.csr_to_device(A, "cuda:0")
+    torch.cuda.synchronize()
+    pool = ThreadPoolExecutor(max_workers=len(primes))
+
+    def solve(p):
+        r, info = bw.rank_modp_dev(Ad, p, s, 1)
+        if r != A.planted_rank:
+            raise RuntimeError(f"rank {r} != planted {A.planted_rank} at p = {p}")
+        return info
+
+    for w in range(args.warmup):
+        log(f"warmup {w + 1}/{args.warmup}")
+        list(pool.map(solve, primes))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for k in range(args.steps):
+        infos += list(pool.map(solve, primes))
+        log(f"step {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    work = sum(2.0 * A.nnz * i["s"] * (i["len"] + i["check_terms"] - 1) for i in infos)
+    rl = {}
+    for p in primes:
+        us, plan = bw.time_step_kernels_dev(Ad, p, s, False, args.kernel_iters, with_plan=True)
+        rl[str(p)] = roofline_entry(A, s, p, us, plan)
+    print(json.dumps({"metric": METRIC, "mode": "rank_c2", "value": round(work / elapsed / 1e9, 3),
+                      "unit": "Gnnz·vec/s", "solves_per_s": round(len(infos) / elapsed, 4), "steps": args.steps,
+                      "ms_per_step": round(1000.0 * elapsed / args.steps, 2), "roofline": rl,
+                      "config": {"workload": f"ranks of a planted {A.m} x {A.n} matrix (rank {A.planted_rank}, "
+                                             f"{A.nnz / 1e6:.1f} M non-zeros), block {s}, p = 65521 and 2^31 - 1"}}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--terms", type=int, default=513,
+                    help="sequence terms per step of the default workload (terms - 1 applications of B)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-rank", action="store_true", help="default workload: skip the whole rank after the steps")
     ap.add_argument("--kernel-iters", type=int, default=50)
     ap.add_argument("--batch", action="store_true",
                     help="batched workload: planted matrices of the batched configuration, 4 primes, block 8; "
@@ -370,26 +577,27 @@ def main():
     ap.add_argument("--serve-count", type=int, default=40)
     ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--serve-nmax", type=float, default=2e4)
-    ap.add_argument("--paper-scale", action="store_true",
-                    help="the 2000000 x 1000000 matrix (37 M non-zeros), block 16: kernel roofline, sequence rate "
-                         "over --paper-steps terms, device sigma-basis time at the full length")
-    ap.add_argument("--paper-steps", type=int, default=3000)
     ap.add_argument("--paper-rank", action="store_true",
-                    help="the whole rank of the 2000000 x 1000000 matrix (about 2.5 minutes of GPU time)")
-    ap.add_argument("--kernels-only", action="store_true",
-                    help="only the per-kernel timing loop at p = 65521 plus a 256 MiB device copy "
-                         "(a plain copy kernel of known size, for calibrating memory counters)")
+                    help="only the whole rank of the 2000000 x 1000000 matrix")
+    ap.add_argument("--rank-c2", action="store_true",
+                    help="ranks of the 200000 x 150000 matrix at p = 65521 and 2^31 - 1 (one step = both)")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="the default workload's step kernels back to back, then a 256 MiB device copy (the "
+                         "command the counter summaries are taken on)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/traffic.json from two rocprofv3 --pmc output folders of --profile-kernels "
+                         "(FETCH_SIZE, then WRITE_SIZE); needs no GPU")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described, "
               f"not built", file=sys.stderr)
         sys.exit(2)
+    if args.traffic_from:
+        rec = traffic_from(args.traffic_from[0], args.traffic_from[1], os.path.join(ROOT, "profiles", "traffic.json"))
+        print(json.dumps({k: v for k, v in rec.items() if k != "kernels"}), flush=True)
+        return
 
-    import numpy as np
     import torch
-
-    import paper_0704_2351_amd as bw
-    from workloads import config2
 
     torch.cuda.set_device(0)
     if args.batch:
@@ -398,67 +606,11 @@ def main():
         return serve_mode(args)
     if args.paper_rank:
         return paper_rank_mode(args)
-    if args.paper_scale:
-        return paper_scale_mode(args)
-    s = 8
-    primes = (65521, 2**31 - 1)
-    log("generating the planted 200000 x 150000 matrix")
-    A = config2()
-    nnz = A.nnz
-    Ad = bw.csr_to_device(A, "cuda:0")
-    torch.cuda.synchronize()
-    planted = A.planted_rank
-
-    if args.kernels_only:
-        out = {}
-        for p in primes:
-            us, plan = bw.time_step_kernels_dev(Ad, p, s, False, args.kernel_iters, with_plan=True)
-            out[str(p)] = {"kernels_us": [round(x, 3) for x in us], "plan": plan}
-        src = torch.empty(64 << 20, dtype=torch.int32, device="cuda:0").fill_(1)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        out["copy_bytes"] = 256 << 20
-        print(json.dumps(out), flush=True)
-        return
-
-    from concurrent.futures import ThreadPoolExecutor
-
-    pool = ThreadPoolExecutor(max_workers=len(primes))
-
-    def solve(p):
-        r, info = bw.rank_modp_dev(Ad, p, s, 1)
-        if r != planted:
-            raise RuntimeError(f"rank {r} != planted {planted} at p = {p}")
-        return info
-
-    def one_step():
-        # one host thread per prime: each runs on its own library stream, so one prime's
-        # sigma-basis overlaps the other prime's sequence on the device
-        return list(pool.map(solve, primes))
-
-    for w in range(args.warmup):
-        log(f"warmup {w + 1}/{args.warmup}")
-        one_step()
-    torch.cuda.synchronize()
-    log(f"timing {args.steps} steps")
-    t0 = time.perf_counter()
-    all_infos = []
-    for k in range(args.steps):
-        all_infos += one_step()
-        log(f"step {k + 1}/{args.steps} done")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    # live kernel timing for the roofline (HIP events on the stream the kernels run on)
-    us, plans = {}, {}
-    for p in primes:
-        us[p], plans[p] = bw.time_step_kernels_dev(Ad, p, s, False, args.kernel_iters, with_plan=True)
-    torch.cuda.synchronize()
-    out = result_line(A, s, primes, args.steps, args.warmup, elapsed, all_infos, us, plans)
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle sequence)")
-        out["cpu_baseline"] = cpu_baseline(A, primes[0], s)
-    print(json.dumps(out), flush=True)
+    if args.rank_c2:
+        return rank_c2_mode(args)
+    if args.profile_kernels:
+        return profile_kernels_mode(args)
+    return sequence_mode(args)
 
 
 if __name__ == "__main__":

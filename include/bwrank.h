@@ -138,6 +138,25 @@ int bwr_sequence_dev(const bwr_csr* A_dev, const uint32_t* d_row, const uint32_t
 int bwr_apply_dev(const bwr_csr* A_dev, const uint32_t* d_row, const uint32_t* d_col, const uint32_t* X,
                   uint32_t p, int32_t s, uint32_t* Z, void* stream);
 
+/* ---- a matrix encoded once, for several sequences ------------------------
+ * The blackbox of Section 2.3 (B = D_c A^T D_r A D_c) applied many times to
+ * one A: bwr_matrix_create_dev validates and encodes the device CSR A once
+ * (CSR of A and A^T, rows and columns relabelled by length; the CSR arrays
+ * are not retained), and each bwr_matrix_sequence_dev computes
+ * S_k = U^T B^k V exactly as bwr_sequence_dev does, without encoding again;
+ * the tiled forms of the products that the autotuner picks are built on first
+ * use and kept with the matrix.  p: prime the matrix will be used with (only
+ * matters when an entry is outside [-127, 127] or a dimension exceeds 2^24:
+ * then residues mod p are stored and other primes are refused, BWR_EINVAL).
+ * Ownership: the handle owns its device memory until bwr_matrix_destroy,
+ * which waits for the device to be idle first.  Sequence calls on one
+ * handle may run from several threads at once. */
+typedef struct bwr_matrix bwr_matrix;
+int bwr_matrix_create_dev(const bwr_csr* A_dev, uint32_t p, void* stream, bwr_matrix** out);
+int bwr_matrix_sequence_dev(bwr_matrix* M, const uint32_t* d_row, const uint32_t* d_col, const uint32_t* U,
+                            const uint32_t* V, uint32_t p, int32_t s, int64_t len, uint32_t* S_out, void* stream);
+void bwr_matrix_destroy(bwr_matrix* M);
+
 /* Rank of A over GF(p) by the block Wiedemann rank algorithm (Section 2.5):
  * B = D_c A^T D_r A D_c on the smaller side (A and A^T swap when m < n),
  * D_r, D_c, U, V drawn from `seed`, 2 + ceil(2 nb / s) terms plus 4 check
@@ -161,9 +180,11 @@ int bwr_rank_modp_dev(const bwr_csr* A_dev, uint32_t p, int32_t block, uint64_t 
  * plan_out is not NULL it receives the launch plan the sequence would use:
  * {block width W, row split of the first product, row split of the second,
  * projection fused (0/1), projection blocks, bytes per stored residue,
- * column passes of the first product, column passes of the second} (8
- * int32; row split 0 = the one-row-per-lane kernel).  For measurement; computes
- * nothing the caller keeps. */
+ * column passes of the first product, column passes of the second, then for
+ * each product its two-dimensional tiling: rows per row block (0 = not
+ * tiled), log2 of the block rows per slab, workgroups} (14 int32; row split
+ * 0 = the one-row-per-lane kernel).  For measurement; computes nothing the
+ * caller keeps. */
 int bwr_time_step_kernels_dev(const bwr_csr* A_dev, uint32_t p, int32_t s, int32_t transpose, int32_t iters,
                               void* stream, double* us_out, int32_t* plan_out);
 
@@ -286,6 +307,13 @@ int bwr_rank_from_sequence(const uint32_t* S, int64_t len, int64_t check, int32_
  *   BWR_PARTS=2            two column passes for 32-bit residues;
  *                          BWR_NO_PARTS=1 keeps the tuner from trying them
  *   BWR_NO_O7=1            no 7-wave variant of the fused 8-wide product
+ *   BWR_TILED=1            both products in the two-dimensional tiled form
+ *                          wherever it applies (no tuning; also used by
+ *                          bwr_apply_dev); BWR_TILED=0 keeps the tuner from
+ *                          trying it.  BWR_TILED_WGS (workgroups per CU),
+ *                          BWR_TILED_SLAB (bytes of the block per slab),
+ *                          BWR_TILED_R (row block cap) and BWR_TILED_GRID
+ *                          (workgroup cap) pin its geometry
  *   BWR_NO_SORT=1          no length-sorted relabelling of rows and columns
  *   BWR_NO_GRAPH=1         launch every step instead of replaying HIP graphs
  *   BWR_HOST_SIGMA=1       sigma-basis on the host instead of the device

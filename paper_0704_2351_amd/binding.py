@@ -20,7 +20,8 @@ EXPORTED = ("bwr_version", "bwr_last_error", "bwr_is_prime", "bwr_sequence_lengt
             "bwr_random_block", "bwr_sequence", "bwr_sequence_dev", "bwr_apply_dev", "bwr_rank_modp",
             "bwr_rank_modp_dev", "bwr_min_generator", "bwr_rank_from_sequence", "bwr_time_step_kernels_dev",
             "bwr_min_generator_dev", "bwr_min_generators_dev", "bwr_rank_modp_batch", "bwr_rank_integer", "bwr_sequence_batch", "bwr_server_create",
-            "bwr_server_submit", "bwr_server_poll", "bwr_server_wait", "bwr_server_get_stats", "bwr_server_destroy")
+            "bwr_server_submit", "bwr_server_poll", "bwr_server_wait", "bwr_server_get_stats", "bwr_server_destroy",
+            "bwr_matrix_create_dev", "bwr_matrix_sequence_dev", "bwr_matrix_destroy")
 
 
 class BwrError(RuntimeError):
@@ -91,6 +92,9 @@ def lib():
             "bwr_server_wait": (ctypes.c_int, [vp, u64, vp]),
             "bwr_server_get_stats": (ctypes.c_int, [vp, vp]),
             "bwr_server_destroy": (None, [vp]),
+            "bwr_matrix_create_dev": (ctypes.c_int, [vp, u32, vp, vp]),
+            "bwr_matrix_sequence_dev": (ctypes.c_int, [vp, vp, vp, vp, vp, u32, i32, i64, vp, vp]),
+            "bwr_matrix_destroy": (None, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -247,6 +251,36 @@ def sequence_dev(Ad, U, V, p: int, length: int, d_row=None, d_col=None, out=None
     return out[:length]
 
 
+class Matrix:
+    """A device CSR encoded once (bwr_matrix_create_dev) for several sequences (bwr_matrix_sequence_dev)."""
+
+    def __init__(self, Ad, p: int):
+        st = _dev_csr(Ad)
+        h = ctypes.c_void_p()
+        _check(lib().bwr_matrix_create_dev(ctypes.byref(st), int(p), _stream(), ctypes.byref(h)))
+        self._h = h
+
+    def sequence_dev(self, U, V, p: int, length: int, d_row=None, d_col=None, out=None):
+        torch = _torch()
+        s = U.shape[1]
+        if out is None:
+            out = torch.empty((max(length, 1), s, s), dtype=torch.int32, device=U.device)
+        _check(lib().bwr_matrix_sequence_dev(self._h, _dptr(d_row), _dptr(d_col), _dptr(U), _dptr(V), int(p), int(s),
+                                             int(length), _dptr(out), _stream()))
+        return out[:length]
+
+    def close(self):
+        if self._h:
+            lib().bwr_matrix_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def apply_dev(Ad, X, p: int, d_row=None, d_col=None, out=None):
     torch = _torch()
     st = _dev_csr(Ad)
@@ -269,14 +303,17 @@ def rank_modp_dev(Ad, p: int, block: int, seed: int):
 
 def time_step_kernels_dev(Ad, p: int, s: int, transpose: bool = False, iters: int = 20, with_plan: bool = False):
     """Average microseconds of [first product, second product, projection] (HIP events on torch's stream);
-    with_plan=True also returns the launch plan {W, G1, G2, fused, NB, esize, parts1, parts2}."""
+    with_plan=True also returns the launch plan {W, G1, G2, fused, NB, esize, parts1, parts2, and the tiling of
+    each product: T1R, T1cb, T1grid, T2R, T2cb, T2grid (rows per row block, 0 = not tiled; log2 slab rows;
+    workgroups)}."""
     st = _dev_csr(Ad)
     us = np.zeros(3, dtype=np.float64)
-    plan = np.zeros(8, dtype=np.int32)
+    plan = np.zeros(14, dtype=np.int32)
     _check(lib().bwr_time_step_kernels_dev(ctypes.byref(st), int(p), int(s), int(transpose), int(iters), _stream(),
                                            us.ctypes.data, plan.ctypes.data))
     if with_plan:
-        keys = ("W", "G1", "G2", "fused", "NB", "esize", "parts1", "parts2")
+        keys = ("W", "G1", "G2", "fused", "NB", "esize", "parts1", "parts2", "T1R", "T1cb", "T1grid", "T2R",
+                "T2cb", "T2grid")
         return us, {k: int(v) for k, v in zip(keys, plan)}
     return us
 

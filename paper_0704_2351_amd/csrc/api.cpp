@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <memory>
 #include <atomic>
 #include <chrono>
 #include <cstring>
@@ -484,6 +485,89 @@ int bwr_apply_dev(const bwr_csr* A_dev, const uint32_t* d_row, const uint32_t* d
     return BWR_OK;
 }
 
+// ---- a matrix encoded once for several sequences ----
+
+}  // extern "C"
+
+struct bwr_matrix {
+    DeviceMatrix M;
+    int dev = 0;
+    hipStream_t home = nullptr;  // where the matrix's buffers are released
+};
+
+extern "C" {
+
+int bwr_matrix_create_dev(const bwr_csr* A_dev, uint32_t p, void* stream, bwr_matrix** out) {
+    if (!A_dev || !out) return fail(BWR_EINVAL, "NULL argument");
+    *out = nullptr;
+    Error e = check_prime(p);
+    if (!e.ok()) return fail(e);
+    hipStream_t st = work_stream(stream, &e);
+    if (!e.ok()) return fail(e);
+    auto h = std::make_unique<bwr_matrix>();
+    hipError_t he = hipGetDevice(&h->dev);
+    if (he == hipSuccess) he = hipStreamCreateWithFlags(&h->home, hipStreamNonBlocking);
+    if (he != hipSuccess) return fail(Error::device(he, "bwr_matrix_create_dev"));
+    e = encode_matrix(view(A_dev), p, st, &h->M, true);
+    he = hipStreamSynchronize(st);
+    if (e.ok() && he != hipSuccess) e = Error::device(he, "encode");
+    rehome(h->M, h->home);
+    h->M.tiled = make_tiled_store(h->home);
+    if (!e.ok()) {
+        bwr_matrix_destroy(h.release());
+        return fail(e);
+    }
+    *out = h.release();
+    g_err.clear();
+    return BWR_OK;
+}
+
+int bwr_matrix_sequence_dev(bwr_matrix* M, const uint32_t* d_row, const uint32_t* d_col, const uint32_t* U,
+                            const uint32_t* V, uint32_t p, int32_t s, int64_t len, uint32_t* S_out, void* stream) {
+    if (!M) return fail(BWR_EINVAL, "NULL matrix");
+    Error e = check_prime(p);
+    if (!e.ok()) return fail(e);
+    if (s < 1 || s > 64) return fail(BWR_EINVAL, "block size must be in 1..64");
+    if (len < 0) return fail(BWR_EINVAL, "len must be >= 0");
+    if (len > 0 && (!S_out || (M->M.n > 0 && (!U || !V)))) return fail(BWR_EINVAL, "NULL output or block");
+    if (!M->M.packed && M->M.wide_p != p) return fail(BWR_EINVAL, "matrix was encoded for another prime");
+    if (len == 0) return BWR_OK;
+    hipStream_t st = work_stream(stream, &e);
+    if (!e.ok()) return fail(e);
+    SequenceArgs a;
+    a.M = &M->M;
+    a.transpose = false;
+    a.mp = ModP::make(p);
+    a.s = s;
+    a.d_row = d_row;
+    a.d_col = d_col;
+    a.U = U;
+    a.V = V;
+    a.len = len;
+    a.S_out = S_out;
+    e = run_sequence(a, st);
+    hipError_t he = hipStreamSynchronize(st);
+    if (e.ok() && he != hipSuccess) e = Error::device(he, "sequence");
+    if (!e.ok()) return fail(e);
+    g_err.clear();
+    return BWR_OK;
+}
+
+void bwr_matrix_destroy(bwr_matrix* M) {
+    if (!M) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(M->dev);
+    (void)hipDeviceSynchronize();  // no kernel of any stream still reads the matrix
+    hipStream_t home = M->home;
+    delete M;  // buffers released on home
+    if (home) {
+        (void)hipStreamSynchronize(home);
+        (void)hipStreamDestroy(home);
+    }
+    (void)hipSetDevice(cur);
+}
+
 int bwr_rank_modp(const bwr_csr* A, uint32_t p, int32_t block, uint64_t seed, int64_t* rank_out,
                   bwr_rank_info* info) {
     if (!A || !rank_out) return fail(BWR_EINVAL, "NULL argument");
@@ -539,7 +623,8 @@ int bwr_time_step_kernels_dev(const bwr_csr* A_dev, uint32_t p, int32_t s, int32
     StepPlan pl;
     if (!(e = time_step_kernels(M, transpose != 0, ModP::make(p), s, iters, st, us_out, &pl)).ok()) return fail(e);
     if (plan_out) {
-        const int32_t v[8] = {pl.W, pl.G1, pl.G2, pl.fused ? 1 : 0, pl.NB, pl.esize, pl.parts1, pl.parts2};
+        const int32_t v[14] = {pl.W,      pl.G1,     pl.G2,       pl.fused ? 1 : 0, pl.NB,     pl.esize,  pl.parts1,
+                               pl.parts2, pl.t1.R,   pl.t1.cb,    pl.t1.grid,       pl.t2.R,   pl.t2.cb,  pl.t2.grid};
         std::memcpy(plan_out, v, sizeof(v));
     }
     g_err.clear();

@@ -5,6 +5,7 @@
 #include "engine.h"
 
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <functional>
@@ -283,6 +284,201 @@ Error build_split(const Operand& op, int64_t cols, int64_t nnz, int W, hipStream
     return {};
 }
 
+// ---- two-dimensional tiled products ----
+
+int device_attr(hipDeviceAttribute_t a, int dflt) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&v, a, dev) != hipSuccess || v <= 0) return dflt;
+    return v;
+}
+
+// bits of the two's-complement value field holding -max_abs .. max_abs
+int value_bits(int32_t max_abs) {
+    int b = 1;
+    while (b < 31 && (1LL << (b - 1)) <= (int64_t)max_abs) ++b;
+    return std::max(b, 2);
+}
+
+int bit_length(int64_t x) {
+    int b = 0;
+    while (x > 0) {
+        ++b;
+        x >>= 1;
+    }
+    return b;
+}
+
+// int32 accumulation over a whole row (all its slabs): see launch_spmm_tiled
+bool tiled_acc_ok(const DeviceMatrix& M, int32_t max_len, uint32_t p) {
+    if (!M.packed) return false;
+    const int64_t f = p <= 65536u ? (int64_t)(p - 1) : 65535;
+    return (int64_t)max_len * (int64_t)std::max(M.max_abs, 1) * f < (1LL << 31);
+}
+
+TiledOperand tiled_view(int64_t rows, int64_t cols, const StepPlan::Tile& t, int32_t max_abs) {
+    TiledOperand v;
+    v.rows = rows;
+    v.R = t.R;
+    v.cb = t.cb;
+    v.vb = value_bits(max_abs);
+    v.rb = bit_length(t.R - 1);
+    v.nrb = t.nrb;
+    v.K = (int)std::max<int64_t>(1, (cols + (1LL << t.cb) - 1) >> t.cb);
+    return v;
+}
+
+// Row blocks for at most Rmax rows each and `slots` resident workgroups: whole rounds of grid blocks
+// (grid = min(blocks, slots)), each block as small as that count allows.
+void finish_tile(int64_t rows, int64_t Rmax, int64_t slots, StepPlan::Tile* t) {
+    const int64_t nrb0 = (rows + Rmax - 1) / Rmax;
+    const int64_t grid = std::max<int64_t>(1, std::min(nrb0, slots));
+    t->nrb = grid * ((nrb0 + grid - 1) / grid);
+    t->R = (int)((rows + t->nrb - 1) / t->nrb);
+    t->grid = (int)grid;
+}
+
+// Geometry of a tiled product with `rows` outputs gathering from `cols` block rows: slabs of about
+// slab_bytes of the block (fewer when the 32-bit entry needs the bits), row blocks as large as wgs
+// workgroups per CU leave LDS for, one persistent workgroup per (CU, wgs) slot.
+bool tile_geometry(int64_t rows, int64_t cols, int W, int esize, bool split, bool proj, int32_t max_abs,
+                   size_t slab_bytes, int wgs, StepPlan::Tile* t) {
+    if (rows < 1 || cols < 1 || W < 4) return false;
+    wgs = std::min(std::max(wgs, 1), 2);
+    const int lds = device_attr(hipDeviceAttributeMaxSharedMemoryPerBlock, 65536) / wgs;
+    const int nacc = split ? 2 * W : W;
+    const int vb = value_bits(max_abs);
+    int cb = std::min(24, bit_length((int64_t)(slab_bytes / ((size_t)W * esize))) - 1);
+    cb = std::max(4, std::min<int>(cb, std::max(4, bit_length(cols - 1))));
+    for (; cb >= 4; --cb) {
+        const int64_t K = (cols + (1LL << cb) - 1) >> cb;
+        if (K > 8192) return false;
+        int64_t R = ((int64_t)lds / 4 - K - 2) / nacc - 1;
+        R = std::min<int64_t>(R, rows);
+        if (R < 1) return false;
+        if (bit_length(R - 1) + cb + vb > 32) continue;
+        if (tiled_lds_bytes(W, split, proj, (int)R, (int)K) > (size_t)lds) continue;
+        const int cus = device_attr(hipDeviceAttributeMultiprocessorCount, 256);
+        t->cb = cb;
+        finish_tile(rows, R, (int64_t)cus * wgs, t);
+        return true;
+    }
+    return false;
+}
+
+// Tiled geometries the autotuner tries: row blocks for one or two workgroups per CU, slabs of 128 to 512 KB of
+// the block (measured at the 2M x 1M size: larger slabs lose, 256 and 128 KB are within a few per cent).
+// BWR_TILED_WGS, BWR_TILED_SLAB (bytes), BWR_TILED_R (cap on the row block) and BWR_TILED_GRID (cap on the
+// workgroups) pin one geometry.
+std::vector<StepPlan::Tile> tile_candidates(int64_t rows, int64_t cols, int W, int esize, bool split, bool proj,
+                                            int32_t max_abs) {
+    std::vector<StepPlan::Tile> out;
+    const char* ew = getenv("BWR_TILED_WGS");
+    const char* es = getenv("BWR_TILED_SLAB");
+    const char* er = getenv("BWR_TILED_R");
+    std::vector<int> wgs = ew ? std::vector<int>{atoi(ew)} : std::vector<int>{1, 2};
+    std::vector<size_t> slabs = es ? std::vector<size_t>{(size_t)atoll(es)}
+                                   : std::vector<size_t>{(size_t)128 << 10, (size_t)256 << 10, (size_t)512 << 10};
+    for (int w : wgs)
+        for (size_t sl : slabs) {
+            StepPlan::Tile t;
+            if (!tile_geometry(rows, cols, W, esize, split, proj, max_abs, sl, w, &t)) continue;
+            const int64_t slots = (int64_t)device_attr(hipDeviceAttributeMultiprocessorCount, 256) * std::min(2, std::max(1, w));
+            if (er && atoi(er) >= 1 && t.R > atoi(er)) finish_tile(rows, atoi(er), slots, &t);
+            if (const char* eg = getenv("BWR_TILED_GRID")) {
+                if (atoi(eg) >= 1) t.grid = (int)std::min<int64_t>(t.grid, atoi(eg));
+                if (atoi(eg) == -1) t.grid = (int)t.nrb;  // one workgroup per row block
+            }
+            bool dup = false;
+            for (const auto& o : out) dup |= (o.R == t.R && o.cb == t.cb && o.grid == t.grid && o.nrb == t.nrb);
+            if (!dup) out.push_back(t);
+        }
+    return out;
+}
+
+struct TiledOp {
+    DevBuf tp, ent;
+    TiledOperand v;
+    bool on = false;
+};
+
+// Tiled encoding of a packed operand for the geometry cfg (see launch_tiled_build).
+Error build_tiled(const Operand& op, int64_t cols, int64_t nnz, int32_t max_abs, const StepPlan::Tile& cfg,
+                  hipStream_t st, TiledOp* to) {
+    to->v = tiled_view(op.rows, cols, cfg, max_abs);
+    const int64_t ntiles = to->v.nrb * to->v.K;
+    const int64_t count = ntiles * cfg.R;
+    if (count >= (1LL << 31)) return Error::inval("tiled encoding too large");
+    DevBuf cnt, pos, tmp;
+    BWR_TRY(cnt.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(count, 1), st));
+    BWR_TRY(pos.alloc(sizeof(int32_t) * (size_t)(count + 1), st));
+    BWR_TRY(tmp.alloc(sizeof(int32_t) * (size_t)scan_tmp_words(count), st));
+    BWR_TRY(to->tp.alloc(sizeof(uint32_t) * (size_t)(ntiles + 1), st));
+    BWR_TRY(to->ent.alloc(sizeof(uint32_t) * (size_t)std::max<int64_t>(nnz, 1), st));
+    BWR_HIP(launch_tiled_build(op.rows, to->v.nrb, op.rp, op.ent, to->v.K, cfg.R, cfg.cb, to->v.vb, cnt.as<int32_t>(),
+                               pos.as<int32_t>(), tmp.as<int32_t>(), to->tp.as<uint32_t>(), to->ent.as<uint32_t>(),
+                               st));
+    to->v.tile_ptr = to->tp.as<uint32_t>();
+    to->v.ent = to->ent.as<uint32_t>();
+    to->on = true;
+    return {};
+}
+
+}  // namespace
+
+struct TiledStore {
+    hipStream_t home = nullptr;
+    std::mutex mu;
+    struct Ent {
+        int which;  // 0: rows of A, 1: rows of A^T
+        StepPlan::Tile cfg;
+        TiledOp op;
+    };
+    std::vector<std::unique_ptr<Ent>> v;
+};
+
+std::shared_ptr<TiledStore> make_tiled_store(hipStream_t home) {
+    auto s = std::make_shared<TiledStore>();
+    s->home = home;
+    return s;
+}
+
+void rehome(DeviceMatrix& M, hipStream_t home) {
+    for (DevBuf* b : {&M.rp_a, &M.ent_a, &M.rp_t, &M.ent_t, &M.val_a, &M.val_t, &M.perm_r, &M.perm_c})
+        b->set_stream(home);
+}
+
+namespace {
+
+// The tiled encoding of operand op (rows of A or of A^T) for geometry cfg: from the matrix's store when it
+// has one (built there on first use), else built into *scratch.
+Error get_tiled(const DeviceMatrix& M, const Operand& op, int64_t cols, const StepPlan::Tile& cfg, hipStream_t st,
+                TiledOp* scratch, const TiledOp** out) {
+    if (!M.tiled) {
+        BWR_TRY(build_tiled(op, cols, M.nnz, M.max_abs, cfg, st, scratch));
+        *out = scratch;
+        return {};
+    }
+    const int which = op.rp == M.rp_a.as<int32_t>() ? 0 : 1;
+    TiledStore& S = *M.tiled;
+    std::lock_guard<std::mutex> lk(S.mu);
+    for (auto& e : S.v)
+        if (e->which == which && e->cfg.R == cfg.R && e->cfg.cb == cfg.cb && e->cfg.nrb == cfg.nrb) {
+            e->op.v.rows = op.rows;
+            *out = &e->op;
+            return {};
+        }
+    auto e = std::make_unique<TiledStore::Ent>();
+    e->which = which;
+    e->cfg = cfg;
+    BWR_TRY(build_tiled(op, cols, M.nnz, M.max_abs, cfg, st, &e->op));
+    BWR_HIP(hipStreamSynchronize(st));  // built before its buffers change owner stream
+    e->op.tp.set_stream(S.home);
+    e->op.ent.set_stream(S.home);
+    *out = &e->op;
+    S.v.push_back(std::move(e));
+    return {};
+}
+
 }  // namespace
 
 namespace {
@@ -314,8 +510,12 @@ int heuristic_g(const Operand& op, int64_t nnz, int W, bool proj) {
 
 // First product of a step: Y = D_r (A X) (row-split kernel, in two column passes when so is set).
 hipError_t first_product(const DeviceMatrix& M, const Operand& op1, const SplitOp* so, int G, const StepPlan& pl,
-                         ModP mp, const void* X, const uint32_t* dr, void* Y, hipStream_t st) {
+                         ModP mp, const void* X, const uint32_t* dr, void* Y, hipStream_t st,
+                         const TiledOp* to = nullptr) {
     const bool smallp = mp.p <= 65536u;
+    if (to && to->on)
+        return launch_spmm_tiled(to->v, pl.W, false, !smallp, pl.esize, X, dr, Y, nullptr, nullptr, pl.t1.grid, mp,
+                                 st);
     if (so && so->on) {
         hipError_t e = launch_spmm_split(pl.W, G, false, acc_mode(M, op1.max_len, mp.p, G), smallp, pl.esize,
                                          op1.rows, so->p0.rp, so->p0.ent, X, nullptr, nullptr, nullptr, nullptr, 0, mp,
@@ -332,8 +532,10 @@ hipError_t first_product(const DeviceMatrix& M, const Operand& op1, const SplitO
 // Second product: Z = D_c^2 (A^T Y), with the projection partials when fused (nblocks persistent blocks).
 hipError_t second_product(const DeviceMatrix& M, const Operand& op2, const SplitOp* so, int G, bool fused,
                           int nblocks, const StepPlan& pl, ModP mp, const void* Yin, const uint32_t* dc2, void* Z,
-                          const void* Ut, uint32_t* partial, hipStream_t st) {
+                          const void* Ut, uint32_t* partial, hipStream_t st, const TiledOp* to = nullptr) {
     const bool smallp = mp.p <= 65536u;
+    if (to && to->on)
+        return launch_spmm_tiled(to->v, pl.W, true, !smallp, pl.esize, Yin, dc2, Z, Ut, partial, pl.t2.grid, mp, st);
     if (so && so->on) {
         hipError_t e = launch_spmm_split(pl.W, G, false, acc_mode(M, op2.max_len, mp.p, G), smallp, pl.esize,
                                          op2.rows, so->p0.rp, so->p0.ent, Yin, nullptr, nullptr, nullptr, nullptr, 0,
@@ -357,19 +559,19 @@ struct Bufs {
 
 Error launch_step(const DeviceMatrix& M, const Operand& op1, const Operand& op2, const SplitOp* so1,
                   const SplitOp* so2, const StepPlan& pl, ModP mp, const Bufs& b, const void* cur, void* nxt,
-                  uint32_t* slot, hipStream_t st) {
+                  uint32_t* slot, hipStream_t st, const TiledOp* to1 = nullptr, const TiledOp* to2 = nullptr) {
     const bool smallp = mp.p <= 65536u;
     const int64_t nb = op2.rows;
     hipError_t e;
-    if (pl.G1 > 0) {
-        e = first_product(M, op1, so1, pl.G1, pl, mp, cur, b.dr, b.Y, st);
-        if (e != hipSuccess) return Error::device(e, "spmm_split (first product)");
+    if (pl.G1 > 0 || (to1 && to1->on)) {
+        e = first_product(M, op1, so1, pl.G1, pl, mp, cur, b.dr, b.Y, st, to1);
+        if (e != hipSuccess) return Error::device(e, "sparse product (first)");
     } else {
         BWR_TRY(spmm(M, op1, pl.W, mp, (const uint32_t*)cur, b.dr, (uint32_t*)b.Y, st));
     }
-    if (pl.G2 > 0) {
-        e = second_product(M, op2, so2, pl.G2, pl.fused, pl.NB, pl, mp, b.Y, b.dc2, nxt, b.Ut, slot, st);
-        if (e != hipSuccess) return Error::device(e, "spmm_split (second product)");
+    if (pl.G2 > 0 || (to2 && to2->on)) {
+        e = second_product(M, op2, so2, pl.G2, pl.fused, pl.NB, pl, mp, b.Y, b.dc2, nxt, b.Ut, slot, st, to2);
+        if (e != hipSuccess) return Error::device(e, "sparse product (second)");
         if (pl.fused) return {};
     } else {
         BWR_TRY(spmm(M, op2, pl.W, mp, (const uint32_t*)b.Y, b.dc2, (uint32_t*)nxt, st));
@@ -411,7 +613,8 @@ Error time_launches(int iters, hipStream_t st, Fn fn, double* us) {
 // instead of deciding the choice.
 constexpr int TUNE_ROUNDS = 3;
 
-Error pick_fastest(const std::vector<std::function<Error()>>& cands, hipStream_t st, int* best) {
+Error pick_fastest(const std::vector<std::function<Error()>>& cands, hipStream_t st, int* best,
+                   std::vector<double>* times = nullptr) {
     std::vector<double> t(cands.size(), 1e30);
     for (int r = 0; r < TUNE_ROUNDS; ++r)
         for (size_t i = 0; i < cands.size(); ++i) {
@@ -420,8 +623,12 @@ Error pick_fastest(const std::vector<std::function<Error()>>& cands, hipStream_t
             t[i] = std::min(t[i], us);
         }
     *best = (int)(std::min_element(t.begin(), t.end()) - t.begin());
+    if (times) *times = t;
     return {};
 }
+
+// BWR_TUNE_LOG=1: the autotuner prints every candidate's time to stderr
+bool tune_log() { return getenv("BWR_TUNE_LOG") != nullptr; }
 
 }  // namespace
 
@@ -458,7 +665,23 @@ StepPlan plan_step(const DeviceMatrix& M, bool transpose, int32_t s, uint32_t p)
     } else {
         pl.NB = proj_blocks(nb, pl.W);
     }
-    (void)p;
+    // BWR_TILED=1: both products tiled (first geometry of tile_candidates) wherever the encoding allows it
+    if (env_int("BWR_TILED", -1) == 1 && pl.G1 > 0 && pl.G2 > 0) {
+        const bool split = p > 65536u;
+        if (tiled_acc_ok(M, op1.max_len, p)) {
+            auto c = tile_candidates(op1.rows, nb, pl.W, pl.esize, split, false, M.max_abs);
+            if (!c.empty()) pl.t1 = c[0];
+        }
+        if (tiled_acc_ok(M, op2.max_len, p)) {
+            auto c = tile_candidates(op2.rows, op1.rows, pl.W, pl.esize, split, true, M.max_abs);
+            if (!c.empty()) {
+                pl.t2 = c[0];
+                pl.fused = true;
+                pl.NB = pl.t2.grid;
+            }
+        }
+        pl.parts1 = pl.parts2 = 1;
+    }
     return pl;
 }
 
@@ -475,14 +698,31 @@ Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl
     BWR_TRY(Z.alloc(es * (size_t)std::max<int64_t>(nb * W, 1), st));
     BWR_TRY(U.alloc(es * (size_t)std::max<int64_t>(nb * W, 1), st));
     BWR_TRY(Y.alloc(es * (size_t)std::max<int64_t>(outer * W, 1), st));
-    const int64_t part_words = std::max<int64_t>(FUSED_PARTIAL_WORDS, (int64_t)proj_blocks(nb, W) * W * W);
+    const int cus = device_attr(hipDeviceAttributeMultiprocessorCount, 256);
+    const int64_t part_words = std::max<int64_t>(std::max<int64_t>(FUSED_PARTIAL_WORDS, 2LL * cus * W * W),
+                                                 (int64_t)proj_blocks(nb, W) * W * W);
     BWR_TRY(part.alloc(sizeof(uint32_t) * (size_t)part_words, st));
     // timing inputs: contents do not change the memory traffic
     BWR_HIP(hipMemsetAsync(X.as<void>(), 0, X.bytes(), st));
     BWR_HIP(hipMemsetAsync(U.as<void>(), 0, U.bytes(), st));
     BWR_HIP(hipMemsetAsync(Y.as<void>(), 0, Y.bytes(), st));
+    // two-dimensional tiled candidates for matrices of at least 2^20 non-zeros (BWR_TILED=0: none)
+    const bool split = !smallp;
+    const bool tiles_on = M.packed && M.nnz >= (1 << 20) && env_int("BWR_TILED", -1) != 0;
+    std::vector<StepPlan::Tile> tc1, tc2;
+    std::vector<TiledOp> to1, to2;
+    if (tiles_on && pl->G1 > 0 && tiled_acc_ok(M, op1.max_len, mp.p))
+        tc1 = tile_candidates(op1.rows, nb, W, pl->esize, split, false, M.max_abs);
+    if (tiles_on && pl->G2 > 0 && tiled_acc_ok(M, op2.max_len, mp.p))
+        tc2 = tile_candidates(op2.rows, outer, W, pl->esize, split, true, M.max_abs);
+    to1.resize(tc1.size());
+    to2.resize(tc2.size());
+    for (size_t i = 0; i < tc1.size(); ++i) BWR_TRY(build_tiled(op1, nb, M.nnz, M.max_abs, tc1[i], st, &to1[i]));
+    for (size_t i = 0; i < tc2.size(); ++i) BWR_TRY(build_tiled(op2, outer, M.nnz, M.max_abs, tc2[i], st, &to2[i]));
+    pl->t1 = StepPlan::Tile{};
+    pl->t2 = StepPlan::Tile{};
     if (pl->G1 > 0) {
-        std::vector<int> gs;
+        std::vector<int> gs;  // row split G, or -(1 + index) of a tiled candidate
         std::vector<std::function<Error()>> runs;
         for (int g = 1; g <= 16; g <<= 1) {
             if (!split_supported(W, g, false)) continue;
@@ -494,9 +734,31 @@ Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl
                 return e == hipSuccess ? Error{} : Error::device(e, "autotune");
             });
         }
+        for (size_t i = 0; i < tc1.size(); ++i) {
+            gs.push_back(-1 - (int)i);
+            runs.push_back([&, i]() -> Error {
+                hipError_t e = launch_spmm_tiled(to1[i].v, W, false, split, pl->esize, X.as<void>(), nullptr,
+                                                 Y.as<void>(), nullptr, nullptr, tc1[i].grid, mp, st);
+                return e == hipSuccess ? Error{} : Error::device(e, "autotune (tiled)");
+            });
+        }
         int bi = 0;
-        BWR_TRY(pick_fastest(runs, st, &bi));
-        pl->G1 = gs[bi];
+        std::vector<double> tt;
+        BWR_TRY(pick_fastest(runs, st, &bi, &tt));
+        if (tune_log())
+            for (size_t i = 0; i < gs.size(); ++i) {
+                if (gs[i] > 0)
+                    fprintf(stderr, "[bwr tune] first product  row split G=%d: %.2f us\n", gs[i], tt[i]);
+                else {
+                    const auto& c = tc1[-1 - gs[i]];
+                    fprintf(stderr, "[bwr tune] first product  tiled R=%d cb=%d grid=%d: %.2f us\n", c.R, c.cb,
+                            c.grid, tt[i]);
+                }
+            }
+        if (gs[bi] > 0)
+            pl->G1 = gs[bi];
+        else
+            pl->t1 = tc1[-1 - gs[bi]];
     }
     if (pl->G2 > 0) {
         // second product and projection: fused, with 1024 or 2048 persistent blocks or with the row tiles
@@ -536,17 +798,43 @@ Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl
                 });
             }
         }
+        for (size_t i = 0; i < tc2.size(); ++i) {
+            cs.push_back({-1 - (int)i, tc2[i].grid, true});
+            runs.push_back([&, i]() -> Error {
+                hipError_t e = launch_spmm_tiled(to2[i].v, W, true, split, pl->esize, Y.as<void>(), nullptr,
+                                                 Z.as<void>(), U.as<void>(), part.as<uint32_t>(), tc2[i].grid, mp, st);
+                return e == hipSuccess ? Error{} : Error::device(e, "autotune (tiled)");
+            });
+        }
         int bi = 0;
-        BWR_TRY(pick_fastest(runs, st, &bi));
-        pl->G2 = cs[bi].g;
+        std::vector<double> tt;
+        BWR_TRY(pick_fastest(runs, st, &bi, &tt));
+        if (tune_log())
+            for (size_t i = 0; i < cs.size(); ++i) {
+                if (cs[i].g > 0)
+                    fprintf(stderr, "[bwr tune] second product row split G=%d fused=%d blocks=%d: %.2f us\n", cs[i].g,
+                            (int)cs[i].fused, cs[i].nbk, tt[i]);
+                else {
+                    const auto& c = tc2[-1 - cs[i].g];
+                    fprintf(stderr, "[bwr tune] second product tiled R=%d cb=%d grid=%d: %.2f us\n", c.R, c.cb,
+                            c.grid, tt[i]);
+                }
+            }
+        if (cs[bi].g > 0) {
+            pl->G2 = cs[bi].g;
+        } else {
+            pl->t2 = tc2[-1 - cs[bi].g];
+        }
         pl->NB = cs[bi].nbk;
         pl->fused = cs[bi].fused;
     }
+    to1.clear();
+    to2.clear();
     // 32-bit residues: does running each product in two column passes (each gathering from half of the
-    // block, which then fits an XCD's L2) beat one pass?
+    // block, which then fits an XCD's L2) beat one pass?  (Not for a tiled product: its slabs already fit.)
     if (pl->esize == 4 && M.packed && env_int("BWR_NO_PARTS", 0) == 0 && getenv("BWR_PARTS") == nullptr) {
         SplitOp so1, so2;
-        if (pl->G1 > 0 && nb >= 2) {
+        if (pl->G1 > 0 && nb >= 2 && pl->t1.R == 0) {
             BWR_TRY(build_split(op1, nb, M.nnz, W, st, &so1));
             auto run = [&](const SplitOp* so) -> Error {
                 hipError_t e = first_product(M, op1, so, pl->G1, *pl, mp, X.as<void>(), nullptr, Y.as<void>(), st);
@@ -556,7 +844,7 @@ Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl
             BWR_TRY(pick_fastest({[&]() { return run(nullptr); }, [&]() { return run(&so1); }}, st, &bi));
             pl->parts1 = bi == 1 ? 2 : 1;
         }
-        if (pl->G2 > 0 && outer >= 2) {
+        if (pl->G2 > 0 && outer >= 2 && pl->t2.R == 0) {
             BWR_TRY(build_split(op2, outer, M.nnz, W, st, &so2));
             auto run = [&](const SplitOp* so) -> Error {
                 hipError_t e = second_product(M, op2, so, pl->G2, pl->fused, pl->NB, *pl, mp, Y.as<void>(), nullptr,
@@ -632,7 +920,7 @@ Error run_sequence(const SequenceArgs& a, hipStream_t st) {
 
     StepPlan pl = plan_step(M, a.transpose, a.s, mp.p);
     if (a.len >= 64 && M.nnz >= 100000 && env_int("BWR_NO_TUNE", 0) == 0 && getenv("BWR_G1") == nullptr &&
-        getenv("BWR_G2") == nullptr)
+        getenv("BWR_G2") == nullptr && env_int("BWR_TILED", -1) != 1)
         BWR_TRY(tuned_plan(M, a.transpose, mp, &pl, st));
     if (a.plan_out) *a.plan_out = pl;
 
@@ -640,6 +928,17 @@ Error run_sequence(const SequenceArgs& a, hipStream_t st) {
     SplitOp so1, so2;
     if (pl.parts1 == 2) BWR_TRY(build_split(op1, nb, M.nnz, W, st, &so1));
     if (pl.parts2 == 2) BWR_TRY(build_split(op2, outer, M.nnz, W, st, &so2));
+    TiledOp own1, own2;
+    const TiledOp* to1 = nullptr;
+    const TiledOp* to2 = nullptr;
+    if (pl.t1.R > 0) {
+        BWR_TRY(get_tiled(M, op1, nb, pl.t1, st, &own1, &to1));
+        BWR_HIP(prepare_spmm_tiled(to1->v, W, false, !smallp, pl.esize));
+    }
+    if (pl.t2.R > 0) {
+        BWR_TRY(get_tiled(M, op2, outer, pl.t2, st, &own2, &to2));
+        BWR_HIP(prepare_spmm_tiled(to2->v, W, true, !smallp, pl.esize));
+    }
     // a length-sorted encoding works in relabelled coordinates: U, V, D_c (iterated side) and D_r (other
     // side) are gathered into that order, which leaves every S_k unchanged
     const uint32_t* aU = a.U;
@@ -725,7 +1024,8 @@ Error run_sequence(const SequenceArgs& a, hipStream_t st) {
                     break;
                 }
                 for (int64_t i = 0; i < CH && err.ok(); ++i) {
-                    err = launch_step(M, op1, op2, &so1, &so2, pl, mp, bufs, cur, nxt, slots + per_step * (size_t)i, st);
+                    err = launch_step(M, op1, op2, &so1, &so2, pl, mp, bufs, cur, nxt, slots + per_step * (size_t)i, st,
+                                      to1, to2);
                     std::swap(cur, nxt);
                 }
                 e = hipStreamEndCapture(st, &graph);
@@ -743,7 +1043,8 @@ Error run_sequence(const SequenceArgs& a, hipStream_t st) {
             }
         } else {
             for (int64_t i = 0; i < cnt && err.ok(); ++i) {
-                err = launch_step(M, op1, op2, &so1, &so2, pl, mp, bufs, cur, nxt, slots + per_step * (size_t)i, st);
+                err = launch_step(M, op1, op2, &so1, &so2, pl, mp, bufs, cur, nxt, slots + per_step * (size_t)i, st,
+                                  to1, to2);
                 std::swap(cur, nxt);
             }
             if (!err.ok()) break;
@@ -788,10 +1089,25 @@ Error apply_once(const DeviceMatrix& M, bool transpose, ModP mp, int32_t s, cons
         BWR_HIP(launch_reduce_vec(nb, d_col, mp, dc.as<uint32_t>(), st));
         dcp = dc.as<uint32_t>();
     }
-    // Z = D_c A^T D_r A D_c X
+    // Z = D_c A^T D_r A D_c X; BWR_TILED=1 runs each product through the tiled kernel where it applies
     BWR_HIP(launch_pad_scale(nb, s, W, X, dcp, dcp ? 1 : 0, mp, Xp.as<void>(), 4, st));
-    BWR_TRY(spmm(M, op1, W, mp, Xp.as<uint32_t>(), drp, Y.as<uint32_t>(), st));
-    BWR_TRY(spmm(M, op2, W, mp, Y.as<uint32_t>(), dcp, Zp.as<uint32_t>(), st));
+    const bool split = mp.p > 65536u;
+    const bool tiled = env_int("BWR_TILED", -1) == 1 && M.packed;
+    TiledOp to1, to2;
+    if (tiled && tiled_acc_ok(M, op1.max_len, mp.p)) {
+        auto c = tile_candidates(op1.rows, nb, W, 4, split, false, M.max_abs);
+        if (!c.empty()) BWR_TRY(build_tiled(op1, nb, M.nnz, M.max_abs, c[0], st, &to1));
+        if (to1.on) BWR_HIP(launch_spmm_tiled(to1.v, W, false, split, 4, Xp.as<void>(), drp, Y.as<void>(), nullptr,
+                                              nullptr, c[0].grid, mp, st));
+    }
+    if (!to1.on) BWR_TRY(spmm(M, op1, W, mp, Xp.as<uint32_t>(), drp, Y.as<uint32_t>(), st));
+    if (tiled && tiled_acc_ok(M, op2.max_len, mp.p)) {
+        auto c = tile_candidates(op2.rows, outer, W, 4, split, false, M.max_abs);
+        if (!c.empty()) BWR_TRY(build_tiled(op2, outer, M.nnz, M.max_abs, c[0], st, &to2));
+        if (to2.on) BWR_HIP(launch_spmm_tiled(to2.v, W, false, split, 4, Y.as<void>(), dcp, Zp.as<void>(), nullptr,
+                                              nullptr, c[0].grid, mp, st));
+    }
+    if (!to2.on) BWR_TRY(spmm(M, op2, W, mp, Y.as<uint32_t>(), dcp, Zp.as<uint32_t>(), st));
     BWR_HIP(launch_unpad(nb, s, W, Zp.as<void>(), 4, Z, st));
     BWR_HIP(hipStreamSynchronize(st));
     return {};
@@ -805,7 +1121,8 @@ Error time_step_kernels(const DeviceMatrix& M, bool transpose, ModP mp, int32_t 
     operands(M, transpose, &op1, &op2);
     const int64_t nb = op2.rows, outer = op1.rows;
     StepPlan pl = plan_step(M, transpose, s, mp.p);
-    if (M.nnz >= 100000 && env_int("BWR_NO_TUNE", 0) == 0 && getenv("BWR_G1") == nullptr && getenv("BWR_G2") == nullptr)
+    if (M.nnz >= 100000 && env_int("BWR_NO_TUNE", 0) == 0 && getenv("BWR_G1") == nullptr && getenv("BWR_G2") == nullptr &&
+        env_int("BWR_TILED", -1) != 1)
         BWR_TRY(tuned_plan(M, transpose, mp, &pl, st));
     if (plan_out) *plan_out = pl;
     const size_t es = (size_t)pl.esize;
@@ -830,19 +1147,25 @@ Error time_step_kernels(const DeviceMatrix& M, bool transpose, ModP mp, int32_t 
     SplitOp so1, so2;
     if (pl.parts1 == 2) BWR_TRY(build_split(op1, nb, M.nnz, W, st, &so1));
     if (pl.parts2 == 2) BWR_TRY(build_split(op2, outer, M.nnz, W, st, &so2));
+    TiledOp own1, own2;
+    const TiledOp* to1 = nullptr;
+    const TiledOp* to2 = nullptr;
+    if (pl.t1.R > 0) BWR_TRY(get_tiled(M, op1, nb, pl.t1, st, &own1, &to1));
+    if (pl.t2.R > 0) BWR_TRY(get_tiled(M, op2, outer, pl.t2, st, &own2, &to2));
     // [0] first product, [1] second product (+ projection when fused), [2] separate projection (0 when fused);
     // a product in two column passes counts both
     BWR_TRY(time_launches(iters, st, [&]() -> Error {
-        if (pl.G1 > 0) {
-            hipError_t e = first_product(M, op1, &so1, pl.G1, pl, mp, X.as<void>(), d1.as<uint32_t>(), Y.as<void>(), st);
-            return e == hipSuccess ? Error{} : Error::device(e, "spmm_split");
+        if (pl.G1 > 0 || to1) {
+            hipError_t e = first_product(M, op1, &so1, pl.G1, pl, mp, X.as<void>(), d1.as<uint32_t>(), Y.as<void>(), st,
+                                         to1);
+            return e == hipSuccess ? Error{} : Error::device(e, "sparse product (first)");
         }
         return spmm(M, op1, W, mp, X.as<uint32_t>(), d1.as<uint32_t>(), Y.as<uint32_t>(), st);
     }, &us[0]));
     BWR_TRY(time_launches(iters, st, [&]() -> Error {
-        if (pl.G2 > 0) {
+        if (pl.G2 > 0 || to2) {
             hipError_t e = second_product(M, op2, &so2, pl.G2, pl.fused, pl.NB, pl, mp, Y.as<void>(),
-                                          d2.as<uint32_t>(), Z.as<void>(), U.as<void>(), part.as<uint32_t>(), st);
+                                          d2.as<uint32_t>(), Z.as<void>(), U.as<void>(), part.as<uint32_t>(), st, to2);
             return e == hipSuccess ? Error{} : Error::device(e, "spmm_split");
         }
         return spmm(M, op2, W, mp, Y.as<uint32_t>(), d2.as<uint32_t>(), Z.as<uint32_t>(), st);

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <functional>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -34,6 +35,8 @@ class DevBuf {
     ~DevBuf() { release(); }
     Error alloc(size_t bytes, hipStream_t st);
     void release();
+    // the stream a later release is ordered on (a buffer kept beyond the stream it was made on)
+    void set_stream(hipStream_t st) { st_ = st; }
     template <class T>
     T* as() const { return reinterpret_cast<T*>(ptr_); }
     size_t bytes() const { return bytes_; }
@@ -43,6 +46,8 @@ class DevBuf {
     size_t bytes_ = 0;
     hipStream_t st_ = nullptr;
 };
+
+struct TiledStore;  // tiled encodings kept with a matrix (engine.cpp)
 
 // A sparse integer matrix on the device, encoded for the two products of a
 // step: CSR of A and CSR of A^T.  Packed form (prime independent): column
@@ -59,7 +64,15 @@ struct DeviceMatrix {
     // column perm_c[j] (int32, device), so that rows of A and of A^T come in order of decreasing length
     bool sorted = false;
     DevBuf perm_r, perm_c;
+    // Optional store of the tiled encodings the sequences of this matrix use (engine.cpp), for matrices kept
+    // across calls: each geometry is built once and reused.  Null: built per call.
+    std::shared_ptr<TiledStore> tiled;
 };
+
+// A store for DeviceMatrix::tiled whose buffers are released on stream `home`.
+std::shared_ptr<TiledStore> make_tiled_store(hipStream_t home);
+// Orders the later release of every buffer of M on stream `home`.
+void rehome(DeviceMatrix& M, hipStream_t home);
 
 struct CsrView {  // caller-owned CSR (host or device pointers)
     int64_t m, n, nnz;
@@ -104,6 +117,14 @@ struct StepPlan {
     // column parts of each product (1 or 2): with 2, the entries gathering from each half of the block
     // run as separate passes (32-bit residues only), so that each pass gathers from a half that fits L2
     int parts1 = 1, parts2 = 1;
+    // two-dimensional tiled form of a product (spmm_tiled.hip), R = 0: not tiled.  nrb interleaved row
+    // blocks of at most R output rows, 2^cb gathered rows per slab, grid persistent workgroups.  A tiled
+    // second product always has the projection fused, with one partial per workgroup (NB = t2.grid).
+    struct Tile {
+        int R = 0, cb = 0, grid = 0;
+        int64_t nrb = 0;
+    };
+    Tile t1, t2;
 };
 
 struct SequenceArgs {

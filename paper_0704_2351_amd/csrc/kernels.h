@@ -112,3 +112,35 @@ hipError_t launch_spmm_split(int W, int G, bool proj, int acc, bool smallp, int 
                              const void* U, uint32_t* partial, int nblocks, ModP mp, hipStream_t st,
                              int pass = 0, uint32_t* carry = nullptr);
 }  // namespace bwr
+
+namespace bwr {
+// Two-dimensional tiled sparse x block product (spmm_tiled.hip): nrb row blocks of at most R output rows
+// (block b holds rows b, b + nrb, ...) accumulated in LDS, the gathered block read slab by slab (C = 2^cb
+// block rows per slab) so that a slab stays in an XCD's L2.  Entries: uint32 (local row << (cb + vb)) | (slab column << vb) | (value & (2^vb - 1)), contiguous per
+// tile (row block, slab) in that order, tile_ptr[nrb * K + 1].
+struct TiledOperand {
+    int64_t rows = 0, nrb = 0;
+    int K = 0, R = 0, rb = 0, cb = 0, vb = 0;
+    const uint32_t* tile_ptr = nullptr;
+    const uint32_t* ent = nullptr;
+};
+// dynamic LDS of one workgroup (accumulators, tile pointers, final projection sums)
+size_t tiled_lds_bytes(int W, bool split, bool proj, int R, int K);
+int tiled_threads();
+// Tiled encoding of a packed operand (rows x cols, int32 row pointers, packed entries with |value| <
+// 2^(vb-1)), nrb * R >= rows: cnt and pos hold nrb * K * R (+ 1 for pos) int32, scan_tmp scan_tmp_words(nrb * K * R);
+// tile_ptr nrb * K + 1 entries, out nnz entries.
+hipError_t launch_tiled_build(int64_t rows, int64_t nrb, const int32_t* rp, const uint32_t* ent, int K, int R,
+                              int cb, int vb, int32_t* cnt, int32_t* pos, int32_t* scan_tmp, uint32_t* tile_ptr,
+                              uint32_t* out, hipStream_t st);
+// Y = scale * (T X) mod p over the tiled operand T, grid persistent workgroups (one row block at a time).
+// split: residues summed as 16-bit halves (required exactly when p > 2^16; the caller guarantees
+// max row length * max |a| * 65535 < 2^31), else int32 sums (max row length * max |a| * (p - 1) < 2^31).
+// With proj, partial[b][i * W + j] (b < grid) = the workgroup's share of sum_r U[r][i] Y[r][j] mod p.
+hipError_t launch_spmm_tiled(const TiledOperand& t, int W, bool proj, bool split, int esize, const void* X,
+                             const uint32_t* scale, void* Y, const void* U, uint32_t* partial, int grid, ModP mp,
+                             hipStream_t st);
+// Raises the dynamic-LDS limit of the kernel that launch_spmm_tiled would launch (done by every launch too;
+// call it before a graph capture that will hold the first launch).
+hipError_t prepare_spmm_tiled(const TiledOperand& t, int W, bool proj, bool split, int esize);
+}  // namespace bwr

@@ -1,0 +1,447 @@
+// Two-dimensional tiled sparse x block product mod p (the "A^T A u" operation of
+// a sequence step, Table "tab:r-opp"), optionally fused with the U^T projection
+// of its output (projections by blocks, Section 2.3).
+//
+// Why tiles.  A row-parallel product gathers one W-residue row of the input
+// block per non-zero, at a random row.  When the block is much larger than an
+// XCD's L2 (4 MB), nearly every gather moves a whole cache line from beyond the
+// L2 for a 16- or 32-byte row, so the kernel moves many times its algorithmic
+// bytes.  Here the output rows are cut into row blocks of R rows and the input
+// rows (the columns of the sparse operand) into slabs of C = 2^cb rows, small
+// enough that a slab of the block stays in L2.  A workgroup owns one row block
+// at a time: its R x W accumulators live in LDS, and it streams the block's
+// non-zeros slab by slab, so every workgroup of an XCD gathers from the same
+// slab at about the same time and the slab is fetched into that L2 once per
+// round of row blocks instead of once per gather.
+//
+// Row blocks interleave: block b holds rows b, b + nrb, b + 2 nrb, ... (local
+// row r is row b + r nrb), so that every block carries about the same number
+// of non-zeros whatever the row order (the rows come sorted by length), and
+// nrb is a multiple of the persistent grid: the workgroups then start each
+// round of blocks together and walk the slabs at the same pace, which is what
+// keeps one slab shared in an XCD's L2.
+//
+// Encoding (built on the device from the packed CSR, tiled_build below): the
+// non-zeros of tile (row block b, slab k) are contiguous, tiles in order
+// (b, k), entries of a tile in order of local row; tile_ptr[b * K + k] is the
+// first entry of the tile (nrb * K + 1 entries).  One uint32 per non-zero:
+//     bits [0, vb)          the value, vb-bit two's complement
+//     bits [vb, vb + cb)    column inside the slab
+//     bits [vb + cb, 32)    row inside the row block
+// so the matrix costs 4 bytes per non-zero and no row pointers.
+//
+// Accumulation: for p <= 2^16 one int32 per output entry (the caller checks
+// max row length * max |a| * (p - 1) < 2^31); for larger primes each residue
+// is split into 16-bit halves summed in two int32 (the caller checks
+// max row length * max |a| * 65535 < 2^31).  Adds go to LDS with atomic adds
+// (integer sums, so their order never changes the result), then one reduction
+// mod p, the row scale and a coalesced store per output entry.
+//
+// Projection (PROJ): after a row block is stored its reduced rows stay in LDS
+// and 4 x 4 tiles of the W x W partial U^T Z are accumulated per thread over
+// the rows it visits; at the end of the kernel the threads' partials meet in
+// LDS (64-bit sums) and each workgroup writes one W x W partial, reduced later
+// by k_reduce_partials.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
+#include "kernels.h"
+
+namespace bwr {
+
+namespace {
+
+constexpr int TT = 1024;  // threads of a tiled workgroup (16 waves: one workgroup per CU, LDS-bound)
+constexpr int BTPB = 256;
+
+// 4 residues (projection operands)
+__device__ __forceinline__ void ld4(const uint32_t* p, uint32_t (&x)[4]) {
+    uint4 v = *reinterpret_cast<const uint4*>(p);
+    x[0] = v.x;
+    x[1] = v.y;
+    x[2] = v.z;
+    x[3] = v.w;
+}
+__device__ __forceinline__ void ld4(const uint16_t* p, uint32_t (&x)[4]) {
+    uint2 v = *reinterpret_cast<const uint2*>(p);
+    x[0] = v.x & 0xffffu;
+    x[1] = v.x >> 16;
+    x[2] = v.y & 0xffffu;
+    x[3] = v.y >> 16;
+}
+
+// NWD consecutive 32-bit words (8, 16 or 32 bytes, aligned)
+template <int NWD>
+__device__ __forceinline__ void ldw(const void* p, uint32_t (&w)[NWD]) {
+    if constexpr (NWD == 2) {
+        const uint2 v = *reinterpret_cast<const uint2*>(p);
+        w[0] = v.x;
+        w[1] = v.y;
+    } else {
+        static_assert(NWD % 4 == 0, "8, 16 or 32 bytes");
+#pragma unroll
+        for (int h = 0; h < NWD / 4; ++h) {
+            const uint4 v = reinterpret_cast<const uint4*>(p)[h];
+            w[4 * h] = v.x;
+            w[4 * h + 1] = v.y;
+            w[4 * h + 2] = v.z;
+            w[4 * h + 3] = v.w;
+        }
+    }
+}
+template <int NWD>
+__device__ __forceinline__ void stw(void* p, const uint32_t (&w)[NWD]) {
+    if constexpr (NWD == 2) {
+        *reinterpret_cast<uint2*>(p) = make_uint2(w[0], w[1]);
+    } else {
+#pragma unroll
+        for (int h = 0; h < NWD / 4; ++h)
+            reinterpret_cast<uint4*>(p)[h] = make_uint4(w[4 * h], w[4 * h + 1], w[4 * h + 2], w[4 * h + 3]);
+    }
+}
+
+// residue c of a lane's packed words
+template <typename E>
+__device__ __forceinline__ uint32_t residue(const uint32_t* w, int c) {
+    if constexpr (sizeof(E) == 2)
+        return (w[c >> 1] >> ((c & 1) * 16)) & 0xffffu;
+    else
+        return w[c];
+}
+template <typename E>
+__device__ __forceinline__ void put_residue(uint32_t* w, int c, uint32_t y) {
+    if constexpr (sizeof(E) == 2)
+        w[c >> 1] |= y << ((c & 1) * 16);
+    else
+        w[c] = y;
+}
+
+// W: padded block width; E: stored residue type; SPLIT: 16-bit halves (p > 2^16); PROJ: fused projection.
+// Dynamic LDS: NACC * RS int32 accumulators (NACC = W, or 2 W with SPLIT), then K + 1 tile pointers; with
+// PROJ at least W * W * 8 bytes for the final partial sums.
+//
+// A lane owns the CPL = min(W, 32 bytes of residues) columns q CPL .. of an entry, so for 16-byte or
+// 32-byte gathered rows one lane reads the whole row (LPE = 1 lane per entry).  Each lane has UN entries in
+// flight, and the entry words of the next round are loaded before this round's gathers, so one memory
+// round trip (gathers and the next entries together) is paid per round instead of two.
+template <int W, typename E, bool SPLIT, bool PROJ>
+__global__ __launch_bounds__(TT) void k_spmm_tiled(int64_t nrows, int64_t nrb, int K, int R, int RS, int cb,
+                                                   int vb, const uint32_t* __restrict__ tile_ptr,
+                                                   const uint32_t* __restrict__ ent, const E* __restrict__ X,
+                                                   const uint32_t* __restrict__ scale, E* __restrict__ Y,
+                                                   const E* __restrict__ U, uint32_t* __restrict__ partial, ModP mp) {
+    extern __shared__ __align__(16) int32_t lds[];
+    constexpr int NACC = SPLIT ? 2 * W : W;
+    constexpr int CPL = W < 32 / (int)sizeof(E) ? W : 32 / (int)sizeof(E);
+    constexpr int LPE = W / CPL;                 // lanes per entry
+    constexpr int EPI = TT / LPE;                // entries per pass of the workgroup
+    constexpr int NWD = CPL * (int)sizeof(E) / 4;  // words a lane gathers per entry
+    constexpr int UN = 4;                        // entries per lane in flight
+    constexpr int WB = W / 4;                    // 4 x 4 tiles of the projection partial per side
+    constexpr int NT = WB * WB;
+    constexpr int NG = TT / NT;                  // row groups of the projection
+    static_assert(W >= 4 && W <= 64 && (W & (W - 1)) == 0, "W must be a power of two in 4..64");
+    int32_t* acc = lds;
+    uint32_t* tp = reinterpret_cast<uint32_t*>(lds + NACC * RS);
+    const int q = threadIdx.x % LPE;
+    const int es = threadIdx.x / LPE;
+    const uint32_t cmask = (1u << cb) - 1u;
+    const int vsh = 32 - vb;
+    const int rsh = cb + vb;
+    const int pt = threadIdx.x % NT, pg = threadIdx.x / NT;
+    const int pti = pt / WB, ptj = pt % WB;
+
+    using PAcc = typename std::conditional<SPLIT, uint32_t, uint64_t>::type;
+    PAcc pacc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) pacc[a][b] = 0;
+
+    for (int64_t rb = blockIdx.x; rb < nrb; rb += gridDim.x) {
+        int4* acc4 = reinterpret_cast<int4*>(acc);
+        for (int i = threadIdx.x; i < NACC * RS / 4; i += TT) acc4[i] = make_int4(0, 0, 0, 0);
+        for (int i = threadIdx.x; i <= K; i += TT) tp[i] = tile_ptr[rb * K + i];
+        __syncthreads();
+        const uint32_t end = tp[K];
+        uint32_t e0 = tp[0] + (uint32_t)es;
+        uint32_t wn[UN];
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+            const uint32_t idx = e0 + u * EPI;
+            wn[u] = idx < end ? __builtin_nontemporal_load(ent + idx) : 0u;
+        }
+        // the slab of an entry: k advances (a lane's entries only move forward through the row block's
+        // tiles); knext caches tp[k + 1]
+        int k = 0;
+        uint32_t knext = tp[1];
+        for (; e0 < end; e0 += UN * EPI) {
+            uint32_t w[UN];
+#pragma unroll
+            for (int u = 0; u < UN; ++u) w[u] = wn[u];
+#pragma unroll
+            for (int u = 0; u < UN; ++u) {
+                const uint32_t idx = e0 + (UN + u) * EPI;
+                wn[u] = idx < end ? __builtin_nontemporal_load(ent + idx) : 0u;
+            }
+            uint32_t xv[UN][NWD];
+#pragma unroll
+            for (int u = 0; u < UN; ++u) {
+                const uint32_t idx = e0 + u * EPI;
+                if (idx < end) {
+                    while (idx >= knext) knext = tp[++k + 1];
+                    const size_t xr = ((size_t)k << cb) + ((w[u] >> vb) & cmask);
+                    ldw<NWD>(X + xr * W + q * CPL, xv[u]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < UN; ++u) {
+                if (e0 + u * EPI < end) {
+                    const int lr = (int)(w[u] >> rsh);
+                    const int32_t a = (int32_t)(w[u] << vsh) >> vsh;
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) {
+                        const uint32_t x = residue<E>(xv[u], c);
+                        if constexpr (SPLIT) {
+                            atomicAdd(&acc[(q * CPL + c) * RS + lr], a * (int32_t)(x & 0xffffu));
+                            atomicAdd(&acc[(W + q * CPL + c) * RS + lr], a * (int32_t)(x >> 16));
+                        } else {
+                            atomicAdd(&acc[(q * CPL + c) * RS + lr], a * (int32_t)x);
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // reduce, scale, store: lane (row, column group), so consecutive lanes store consecutive rows
+        // rows of block rb: rb, rb + nrb, rb + 2 nrb, ... (local row r is row rb + r nrb)
+        const int nr = (int)((nrows - rb + nrb - 1) / nrb);
+        uint32_t* zl = reinterpret_cast<uint32_t*>(acc);
+        for (int i = threadIdx.x; i < nr * LPE; i += TT) {
+            const int r = i / LPE, qq = i % LPE;
+            const int64_t row = rb + (int64_t)r * nrb;
+            const uint32_t sc = scale ? scale[row] : 1u;
+            uint32_t yw[NWD];
+#pragma unroll
+            for (int h = 0; h < NWD; ++h) yw[h] = 0;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int idx = (qq * CPL + c) * RS + r;
+                uint32_t y;
+                if constexpr (SPLIT) {
+                    const uint32_t red =
+                        reds64(mp, (int64_t)acc[(W + qq * CPL + c) * RS + r] * 65536 + (int64_t)acc[idx]);
+                    y = mulmod(mp, red, sc);
+                } else {
+                    y = mulmod16(mp, reds32(mp, acc[idx]), sc);
+                }
+                put_residue<E>(yw, c, y);
+                if constexpr (PROJ) zl[idx] = y;
+            }
+            stw<NWD>(Y + (size_t)row * W + qq * CPL, yw);
+        }
+        if constexpr (PROJ) {
+            __syncthreads();
+            // 4 rows per round, their U loads issued together
+            for (int r0 = pg; r0 < nr; r0 += 4 * NG) {
+                uint32_t u[4][4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int r = r0 + j * NG;
+                    if (r < nr) ld4(U + (size_t)(rb + (int64_t)r * nrb) * W + pti * 4, u[j]);
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int r = r0 + j * NG;
+                    if (r >= nr) break;
+                    uint32_t z[4];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) z[b] = zl[(ptj * 4 + b) * RS + r];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) {
+                            if constexpr (SPLIT)
+                                pacc[a][b] = addmod(mp, pacc[a][b], mulmod(mp, u[j][a], z[b]));
+                            else
+                                pacc[a][b] += (uint64_t)(u[j][a] * z[b]);
+                        }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if constexpr (PROJ) {
+        // the threads' partials meet in W x W 64-bit LDS sums; one W x W partial per workgroup
+        unsigned long long* red = reinterpret_cast<unsigned long long*>(lds);
+        for (int e = threadIdx.x; e < W * W; e += TT) red[e] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                atomicAdd(&red[(pti * 4 + a) * W + ptj * 4 + b], (unsigned long long)pacc[a][b]);
+        __syncthreads();
+        for (int e = threadIdx.x; e < W * W; e += TT) partial[(size_t)blockIdx.x * W * W + e] = red64(mp, red[e]);
+    }
+}
+
+// ---- encoding ----
+
+// cnt[(b * K + k) * R + lr] = entries of row b + lr nrb in slab k
+__global__ __launch_bounds__(BTPB) void k_tile_count(int64_t rows, int64_t nrb, const int32_t* __restrict__ rp,
+                                                     const uint32_t* __restrict__ ent, int K, int R, int cb,
+                                                     int32_t* __restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * BTPB + threadIdx.x;
+    if (i >= rows) return;
+    const int64_t b = i % nrb;
+    const int lr = (int)(i / nrb);
+    for (int32_t t = rp[i]; t < rp[i + 1]; ++t) {
+        const uint32_t col = ent[t] & 0xFFFFFFu;
+        atomicAdd(&cnt[(b * K + (col >> cb)) * R + lr], 1);
+    }
+}
+
+// tile_ptr[t] = pos[t * R] for t <= ntiles (pos holds ntiles * R + 1 entries)
+__global__ __launch_bounds__(BTPB) void k_tile_ptrs(int64_t ntiles, int R, const int32_t* __restrict__ pos,
+                                                    uint32_t* __restrict__ tile_ptr) {
+    const int64_t t = (int64_t)blockIdx.x * BTPB + threadIdx.x;
+    if (t <= ntiles) tile_ptr[t] = (uint32_t)pos[t * R];
+}
+
+// one thread per row: its entries go to the next free places of their (row block, slab, local row) runs, in
+// the row's order (each run belongs to one row, so the order is deterministic)
+__global__ __launch_bounds__(BTPB) void k_tile_scatter(int64_t rows, int64_t nrb, const int32_t* __restrict__ rp,
+                                                       const uint32_t* __restrict__ ent, int K, int R, int cb,
+                                                       int vb, int32_t* __restrict__ pos, uint32_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * BTPB + threadIdx.x;
+    if (i >= rows) return;
+    const int64_t b = i % nrb;
+    const int lr = (int)(i / nrb);
+    const uint32_t cmask = (1u << cb) - 1u, vmask = (1u << vb) - 1u;
+    for (int32_t t = rp[i]; t < rp[i + 1]; ++t) {
+        const uint32_t w = ent[t];
+        const uint32_t col = w & 0xFFFFFFu;
+        const int32_t a = (int32_t)w >> 24;
+        const int64_t slot = (b * K + (col >> cb)) * R + lr;
+        const int32_t p = pos[slot];
+        pos[slot] = p + 1;
+        out[p] = ((uint32_t)lr << (cb + vb)) | ((col & cmask) << vb) | ((uint32_t)a & vmask);
+    }
+}
+
+// Raises a kernel's dynamic-LDS limit on the current device to the device maximum, once (under a lock).
+hipError_t allow_max_lds(const void* fn, size_t want) {
+    static std::mutex mu;
+    static std::vector<std::pair<const void*, int>> done;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto& d : done)
+        if (d.first == fn && d.second == dev) return hipSuccess;
+    int mx = 0;
+    e = hipDeviceGetAttribute(&mx, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return e;
+    if ((size_t)mx < want) return hipErrorInvalidValue;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    if (e == hipSuccess) done.emplace_back(fn, dev);
+    return e;
+}
+
+template <int W, typename E, bool SPLIT, bool PROJ>
+hipError_t launch_t(const TiledOperand& t, const void* X, const uint32_t* scale, void* Y, const void* U,
+                    uint32_t* partial, int grid, ModP mp, hipStream_t st) {
+    const size_t lds = tiled_lds_bytes(W, SPLIT, PROJ, t.R, t.K);
+    hipError_t e = allow_max_lds(reinterpret_cast<const void*>(&k_spmm_tiled<W, E, SPLIT, PROJ>), lds);
+    if (e != hipSuccess || grid == 0) return e;  // grid 0: only raise the LDS limit (before a graph capture)
+    k_spmm_tiled<W, E, SPLIT, PROJ><<<(unsigned)grid, TT, lds, st>>>(
+        t.rows, t.nrb, t.K, t.R, t.R + 1, t.cb, t.vb, t.tile_ptr, t.ent, (const E*)X, scale, (E*)Y, (const E*)U,
+        partial, mp);
+    return hipGetLastError();
+}
+
+template <int W>
+hipError_t launch_w(const TiledOperand& t, bool proj, bool split, int esize, const void* X, const uint32_t* scale,
+                    void* Y, const void* U, uint32_t* partial, int grid, ModP mp, hipStream_t st) {
+    if (esize == 2) {
+        if (split) return hipErrorInvalidValue;
+        return proj ? launch_t<W, uint16_t, false, true>(t, X, scale, Y, U, partial, grid, mp, st)
+                    : launch_t<W, uint16_t, false, false>(t, X, scale, Y, U, partial, grid, mp, st);
+    }
+    if (split)
+        return proj ? launch_t<W, uint32_t, true, true>(t, X, scale, Y, U, partial, grid, mp, st)
+                    : launch_t<W, uint32_t, true, false>(t, X, scale, Y, U, partial, grid, mp, st);
+    return proj ? launch_t<W, uint32_t, false, true>(t, X, scale, Y, U, partial, grid, mp, st)
+                : launch_t<W, uint32_t, false, false>(t, X, scale, Y, U, partial, grid, mp, st);
+}
+
+}  // namespace
+
+size_t tiled_lds_bytes(int W, bool split, bool proj, int R, int K) {
+    const size_t nacc = (size_t)(split ? 2 * W : W);
+    size_t b = sizeof(int32_t) * (nacc * (size_t)(R + 1) + (size_t)K + 1);
+    if (proj) b = std::max<size_t>(b, (size_t)W * W * sizeof(uint64_t));
+    return (b + 15) & ~(size_t)15;
+}
+
+int tiled_threads() { return TT; }
+
+hipError_t launch_tiled_build(int64_t rows, int64_t nrb, const int32_t* rp, const uint32_t* ent, int K, int R,
+                              int cb, int vb, int32_t* cnt, int32_t* pos, int32_t* scan_tmp, uint32_t* tile_ptr,
+                              uint32_t* out, hipStream_t st) {
+    if (nrb < 1 || nrb * (int64_t)R < rows) return hipErrorInvalidValue;
+    const int64_t ntiles = nrb * K;
+    const int64_t count = ntiles * R;
+    hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)std::max<int64_t>(count, 1), st);
+    if (e != hipSuccess) return e;
+    const unsigned g = (unsigned)std::max<int64_t>(1, (rows + BTPB - 1) / BTPB);
+    if (rows > 0) {
+        k_tile_count<<<g, BTPB, 0, st>>>(rows, nrb, rp, ent, K, R, cb, cnt);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if ((e = launch_exclusive_scan(count, cnt, pos, scan_tmp, st)) != hipSuccess) return e;
+    k_tile_ptrs<<<(unsigned)((ntiles + 1 + BTPB - 1) / BTPB), BTPB, 0, st>>>(ntiles, R, pos, tile_ptr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (rows > 0) {
+        k_tile_scatter<<<g, BTPB, 0, st>>>(rows, nrb, rp, ent, K, R, cb, vb, pos, out);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t prepare_spmm_tiled(const TiledOperand& t, int W, bool proj, bool split, int esize) {
+    if (esize != 2 && esize != 4) return hipErrorInvalidValue;
+    const ModP mp = ModP::make(split ? 2147483647u : 65521u);
+    switch (W) {
+        case 4: return launch_w<4>(t, proj, split, esize, nullptr, nullptr, nullptr, nullptr, nullptr, 0, mp, 0);
+        case 8: return launch_w<8>(t, proj, split, esize, nullptr, nullptr, nullptr, nullptr, nullptr, 0, mp, 0);
+        case 16: return launch_w<16>(t, proj, split, esize, nullptr, nullptr, nullptr, nullptr, nullptr, 0, mp, 0);
+        case 32: return launch_w<32>(t, proj, split, esize, nullptr, nullptr, nullptr, nullptr, nullptr, 0, mp, 0);
+        case 64: return launch_w<64>(t, proj, split, esize, nullptr, nullptr, nullptr, nullptr, nullptr, 0, mp, 0);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_spmm_tiled(const TiledOperand& t, int W, bool proj, bool split, int esize, const void* X,
+                             const uint32_t* scale, void* Y, const void* U, uint32_t* partial, int grid, ModP mp,
+                             hipStream_t st) {
+    if (grid < 1 || t.R < 1 || t.nrb < 1 || t.nrb * (int64_t)t.R < t.rows || t.K < 1 || t.cb < 1 || t.vb < 2 || t.rb + t.cb + t.vb > 32 ||
+        (1LL << t.rb) < t.R || (proj && (!U || !partial)) || (esize != 2 && esize != 4) ||
+        split != (mp.p > 65536u))
+        return hipErrorInvalidValue;
+    switch (W) {
+        case 4: return launch_w<4>(t, proj, split, esize, X, scale, Y, U, partial, grid, mp, st);
+        case 8: return launch_w<8>(t, proj, split, esize, X, scale, Y, U, partial, grid, mp, st);
+        case 16: return launch_w<16>(t, proj, split, esize, X, scale, Y, U, partial, grid, mp, st);
+        case 32: return launch_w<32>(t, proj, split, esize, X, scale, Y, U, partial, grid, mp, st);
+        case 64: return launch_w<64>(t, proj, split, esize, X, scale, Y, U, partial, grid, mp, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace bwr

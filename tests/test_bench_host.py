@@ -1,5 +1,7 @@
-"""Host logic of bench.py: the JSON record's contract fields, the roofline
-arithmetic and the single-GPU guard (no GPU needed)."""
+"""Host logic of bench.py: the roofline arithmetic and the choice of the
+dominant kernel, the counter-summary lookup and its construction from
+rocprofv3 CSV output, and the single-GPU guard (no GPU needed)."""
+import csv
 import json
 import os
 import subprocess
@@ -11,59 +13,95 @@ from workloads import planted
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def fake_run():
+def fake_plan(tiled=True):
+    return {"W": 16, "G1": 4, "G2": 4, "fused": 1, "NB": 256, "esize": 2, "parts1": 1, "parts2": 1,
+            "T1R": 1954 if tiled else 0, "T1cb": 13, "T1grid": 256, "T2R": 1954 if tiled else 0, "T2cb": 13,
+            "T2grid": 256}
+
+
+def test_roofline_entry_dominant_kernel_and_arithmetic():
     A = planted(300, 200, 150, 6, 1)
-    info = {"s": 8, "len": 52, "check_terms": 4, "t_sequence": 0.01, "t_sigma": 0.02, "sigma_threads": 4}
-    us = {65521: [10.0, 20.0, 0.0], 2**31 - 1: [12.0, 24.0, 0.0]}
-    plan = {"W": 8, "G1": 2, "G2": 4, "fused": 1, "NB": 64, "esize": 2}
-    return A, [info, info], us, {65521: plan, 2**31 - 1: dict(plan, esize=4)}
-
-
-def test_result_line_contract():
-    A, infos, us, plans = fake_run()
-    out = bench.result_line(A, 8, (65521, 2**31 - 1), 1, 1, 0.5, infos, us, plans)
-    for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
-              "vs_baseline", "dtype", "data", "config", "roofline"):
-        assert k in out, k
-    assert out["config"]["workload"] and out["n_gpus"] == 1 and out["vs_baseline"] is None
-    work = 2 * (2.0 * A.nnz * 8 * 55)
-    assert abs(out["value"] - round(work / 0.5 / 1e9, 3)) < 1e-9
-    rf = out["roofline"]
-    b2 = 4 * (A.n + 1) + 5 * A.nnz + 4 * 8 * (A.m + A.n)
-    assert rf["bytes_per_launch"] == b2
+    s = 16
+    b1 = 4 * (A.m + 1) + 5 * A.nnz + 4 * s * (A.n + A.m)
+    b2 = 4 * (A.n + 1) + 5 * A.nnz + 4 * s * (A.m + A.n)
+    # second product dominant
+    rf = bench.roofline_entry(A, s, 65521, [10.0, 20.0, 0.0], fake_plan())
+    assert rf["bytes_per_launch"] == b2 and rf["avg_launch_us"] == 20.0
     assert abs(rf["achieved"] - round(b2 / 20e-6 / 1e9, 1)) < 1e-9
     assert abs(rf["frac"] - round(rf["achieved"] / 8000.0, 4)) < 1e-4
-    json.dumps(out)
+    assert rf["kernel"].startswith("k_spmm_tiled<16, unsigned short, false, true>")
+    assert rf["other_product"]["bytes_per_launch"] == b1
+    assert rf["step"]["bytes"] == b1 + b2 and rf["step"]["kernel_us"] == 30.0
+    # first product dominant; a separate projection counts with the second product
+    rf = bench.roofline_entry(A, s, 65521, [25.0, 10.0, 5.0], fake_plan(False))
+    assert rf["bytes_per_launch"] == b1 and rf["avg_launch_us"] == 25.0
+    assert rf["kernel"].startswith("k_spmm_split<16, 4, ACC, true, false, unsigned short, 0>")
+    assert rf["other_product"]["avg_launch_us"] == 15.0
+    json.dumps(rf)
 
 
-def test_traffic_is_null_without_matching_summary(tmp_path, monkeypatch):
-    import hashlib
+def test_product_kernel_names():
+    n, src, _ = bench.product_kernel(fake_plan(), 1, 16, 2**31 - 1)
+    assert n == "k_spmm_tiled<16, unsigned short, true, false>" and src.endswith("spmm_tiled.hip")
+    n, src, _ = bench.product_kernel(dict(fake_plan(False), esize=4), 2, 16, 2**31 - 1)
+    assert n == "k_spmm_split<16, 4, ACC, false, true, unsigned int, 0>" and src.endswith("spmm.hip")
 
+
+def _write_csv(path, rows):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for r in rows:
+            w.writerow(r)
+
+
+def test_traffic_from_and_lookup(tmp_path, monkeypatch):
+    """traffic.json built from two counter runs: the copy of 256 MiB calibrates both counters, each kernel's
+    per-dispatch average is scaled; the lookup refuses another revision of the source."""
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.kernel_traffic(8, 4, 2, True) is None
+    for rel, text in (("paper_0704_2351_amd/csrc/spmm_tiled.hip", "tiled v1"),
+                      ("paper_0704_2351_amd/csrc/spmm.hip", "split v1")):
+        (tmp_path / rel).parent.mkdir(parents=True, exist_ok=True)
+        (tmp_path / rel).write_text(text)
     (tmp_path / "profiles").mkdir()
-    (tmp_path / "paper_0704_2351_amd" / "csrc").mkdir(parents=True)
-    (tmp_path / "paper_0704_2351_amd" / "csrc" / "spmm.hip").write_text("kernel v2")
-    name16 = "k_spmm_split<8, 4, 1, true, true, unsigned short, 0>"
-    name32 = "k_spmm_split<8, 4, 2, false, true, unsigned int, 0>"
-    rec = {"source": "paper_0704_2351_amd/csrc/spmm.hip", "source_sha256": "0" * 64,
-           "kernels": {name16: {"bytes_per_launch": 123}, name32: {"bytes_per_launch": 456}}}
-    (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(rec))
-    assert bench.kernel_traffic(8, 4, 2, True) is None  # another revision of the source
-    rec["source_sha256"] = hashlib.sha256(b"kernel v2").hexdigest()
-    (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(rec))
-    assert bench.kernel_traffic(8, 4, 2, True) == 123
-    assert bench.kernel_traffic(8, 4, 4, True) == 456
-    assert bench.kernel_traffic(8, 8, 2, True) is None  # instantiation not measured
-    assert bench.kernel_traffic(8, 4, 2, False) is None
+    kt = ("void bwr::(anonymous namespace)::k_spmm_tiled<16, unsigned short, false, true>(long, long, int, "
+          "unsigned int const*, bwr::ModP)")
+    ks = "void bwr::(anonymous namespace)::k_spmm_split<16, 4, 1, true, false, unsigned short, 0>(long, bwr::ModP)"
+    cp = "void at::native::elementwise_kernel<128, 4, copy>(int, at::native::copy_kernel)"
+    big = 256 * 1024
+    _write_csv(str(tmp_path / "f" / "run_counter_collection.csv"),
+               [{"Kernel_Name": kt, "Counter_Name": "FETCH_SIZE", "Counter_Value": 1000.0},
+                {"Kernel_Name": kt, "Counter_Name": "FETCH_SIZE", "Counter_Value": 3000.0},
+                {"Kernel_Name": ks, "Counter_Name": "FETCH_SIZE", "Counter_Value": 500.0},
+                {"Kernel_Name": cp, "Counter_Name": "FETCH_SIZE", "Counter_Value": big / 2}])
+    _write_csv(str(tmp_path / "w" / "run_counter_collection.csv"),
+               [{"Kernel_Name": kt, "Counter_Name": "WRITE_SIZE", "Counter_Value": 100.0},
+                {"Kernel_Name": kt, "Counter_Name": "WRITE_SIZE", "Counter_Value": 100.0},
+                {"Kernel_Name": ks, "Counter_Name": "WRITE_SIZE", "Counter_Value": 50.0},
+                {"Kernel_Name": cp, "Counter_Name": "WRITE_SIZE", "Counter_Value": big}])
+    rec = bench.traffic_from(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "profiles" / "traffic.json"))
+    assert rec["fetch_factor"] == 2.0 and rec["write_factor"] == 1.0
+    assert bench.kernel_traffic("k_spmm_tiled<16, unsigned short, false, true>") == 1024 * (2000 * 2 + 100)
+    assert bench.kernel_traffic("k_spmm_split<16, 4, ACC, true, false, unsigned short, 0>") == 1024 * (500 * 2 + 50)
+    assert bench.kernel_traffic("k_spmm_tiled<16, unsigned short, false, false>") is None  # not measured
+    (tmp_path / "paper_0704_2351_amd/csrc/spmm_tiled.hip").write_text("tiled v2")
+    assert bench.kernel_traffic("k_spmm_tiled<16, unsigned short, false, true>") is None  # another revision
+    assert bench.kernel_traffic("k_spmm_split<16, 4, ACC, true, false, unsigned short, 0>") == 1024 * 1050
 
 
-def test_committed_traffic_record_matches_source():
-    """The committed counter summary belongs to the current kernel source and holds the instantiations
-    the autotuner picks on the 200000 x 150000 workload at p = 65521."""
+def test_committed_traffic_record_belongs_to_the_sources():
+    """The committed counter summary is current for every source it names (else the bench reports traffic
+    null), and it holds the kernels of the default workload's plan."""
     rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
-    assert bench.kernel_traffic(8, 4, 2, True) == rec["kernels"][
-        "k_spmm_split<8, 4, 1, true, true, unsigned short, 0>"]["bytes_per_launch"]
+    assert "sources" in rec and rec["kernels"]
+    for src, digest in rec["sources"].items():
+        assert bench._source_digest(src) == digest, src
+
+
+def test_cpu_info():
+    model, threads = bench.cpu_info()
+    assert isinstance(model, str) and threads >= 1
 
 
 def test_more_than_one_gpu_is_refused():
