@@ -78,7 +78,8 @@ typedef struct {
                            * only the last chunks count here. */
     double t_readout;     /* seconds: check and read-out */
     int32_t sigma_threads;
-    int32_t pad;
+    int32_t trials;       /* independent draws made (see bwr_set_trials); the other fields describe the draw
+                           * that gave the rank, the times are summed over the draws */
 } bwr_rank_info;
 
 /* Timings of one batched rank computation. */
@@ -109,6 +110,17 @@ int64_t bwr_sequence_length(int64_t nb, int32_t s);
 
 /* Host threads used by the sigma-basis (default: min(hardware threads, 16)). */
 int bwr_set_threads(int32_t n);
+
+/* Independent draws per rank computation, 1 .. 64 (default 1), for every rank
+ * entry point (bwr_rank_modp, bwr_rank_modp_dev, bwr_rank_modp_batch,
+ * bwr_rank_integer, and the server's requests submitted afterwards).  Draw t
+ * uses seed + t for U, V, D_r and D_c.  The result of one draw is never above
+ * the true rank (Section 2.5: the algorithm errs only by returning less), so
+ * the largest result over the draws is kept; a single-matrix computation stops
+ * early once a draw reaches min(m, n).  Like bwr_set_threads, it must not run
+ * while another call is in progress.  bwr_get_trials returns the setting. */
+int bwr_set_trials(int32_t n);
+int32_t bwr_get_trials(void);
 
 /* The random residues the rank draws, from a counter-based SplitMix64
  * (Steele, Lea, Flood 2014): with mix() the SplitMix64 finaliser and
@@ -232,8 +244,9 @@ int bwr_sequence_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* pr
  * advances before, 0 never waits), so a request admitted now starts after at
  * most one advance already on the device.  Submitted requests queue up and
  * join their running batch at the next step
- * boundary while the HBM budget (estimated footprint of encoded matrix,
- * blocks and sequence) and the slot count allow.  A finished sequence gets
+ * boundary while the HBM budget (the summed device bytes of the admitted
+ * requests: encoded matrix, blocks and sequence, plus the upload of one being
+ * encoded) and the slot count allow.  A finished sequence gets
  * its sigma-basis and read-out and the request is answered; results are
  * identical to bwr_rank_modp(A, p, block, seed).  Calls on one server are
  * thread-safe. */
@@ -247,12 +260,19 @@ typedef struct {
     int64_t max_queue;      /* largest queue length seen */
     int64_t max_active;     /* largest number of requests in the batch at once */
     int64_t steps;          /* batched steps run */
+    int64_t peak_bytes;     /* largest sum, over the requests admitted at once, of their device bytes (encoded
+                               matrix, blocks, sequence; plus the upload of one being encoded): at most the
+                               budget unless a single request alone was admitted into an idle server */
 } bwr_server_stats;
 
 /* Creates a server on the current device (block size 1..32). */
 int bwr_server_create(uint64_t hbm_budget_bytes, int32_t max_slots, int32_t block, bwr_server** out);
-/* Copies A (host CSR) to the device and queues the request; BWR_ENOMEM if it
- * alone exceeds the budget.  *ticket identifies the request. */
+/* Copies A (host CSR) into host memory and queues the request, with the
+ * number of draws bwr_set_trials sets (a request whose best rank so far is
+ * below min(m, n) rejoins the queue with the next seed while draws are left).
+ * The worker uploads and encodes the matrix when it admits the request, so
+ * queued requests hold no device memory.  BWR_ENOMEM if it alone exceeds the
+ * budget.  *ticket identifies the request. */
 int bwr_server_submit(bwr_server* srv, const bwr_csr* A, uint32_t p, uint64_t seed, uint64_t* ticket);
 /* *done = 1 and *rank set once answered (the request's error code otherwise). */
 int bwr_server_poll(bwr_server* srv, uint64_t ticket, int32_t* done, int64_t* rank);
@@ -327,7 +347,11 @@ int bwr_rank_from_sequence(const uint32_t* S, int64_t len, int64_t check, int32_
  *   BWR_BATCH_CHUNK        steps per batched graph (even, default 64)
  *   BWR_READOUT_THREADS    host threads reading out finished batched or
  *                          served sequences (default 3)
- *   BWR_SERVER_AHEAD       see the serving section */
+ *   BWR_SERVER_AHEAD       see the serving section
+ *   BWR_SERVER_FAIL_ADVANCE=k  (tests of error handling) the server's
+ *                          advance after k advances reports an error instead
+ *                          of launching, once; the requests in its batches
+ *                          are answered with that error */
 
 #ifdef __cplusplus
 }

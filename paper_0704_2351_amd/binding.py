@@ -21,7 +21,8 @@ EXPORTED = ("bwr_version", "bwr_last_error", "bwr_is_prime", "bwr_sequence_lengt
             "bwr_rank_modp_dev", "bwr_min_generator", "bwr_rank_from_sequence", "bwr_time_step_kernels_dev",
             "bwr_min_generator_dev", "bwr_min_generators_dev", "bwr_rank_modp_batch", "bwr_rank_integer", "bwr_sequence_batch", "bwr_server_create",
             "bwr_server_submit", "bwr_server_poll", "bwr_server_wait", "bwr_server_get_stats", "bwr_server_destroy",
-            "bwr_matrix_create_dev", "bwr_matrix_sequence_dev", "bwr_matrix_destroy")
+            "bwr_matrix_create_dev", "bwr_matrix_sequence_dev", "bwr_matrix_destroy", "bwr_set_trials",
+            "bwr_get_trials")
 
 
 class BwrError(RuntimeError):
@@ -49,10 +50,10 @@ class RankInfo(ctypes.Structure):
                 ("transposed", ctypes.c_int32), ("len", ctypes.c_int64), ("check_terms", ctypes.c_int64),
                 ("sum_delta", ctypes.c_int64), ("t_encode", ctypes.c_double), ("t_sequence", ctypes.c_double),
                 ("t_sigma", ctypes.c_double), ("t_readout", ctypes.c_double), ("sigma_threads", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("trials", ctypes.c_int32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib = None
@@ -72,6 +73,8 @@ def lib():
             "bwr_is_prime": (ctypes.c_int, [u32]),
             "bwr_sequence_length": (i64, [i64, i32]),
             "bwr_set_threads": (ctypes.c_int, [i32]),
+            "bwr_set_trials": (ctypes.c_int, [i32]),
+            "bwr_get_trials": (i32, []),
             "bwr_random_block": (ctypes.c_int, [u64, i32, i64, i32, u32, i32, vp]),
             "bwr_sequence": (ctypes.c_int, [vp, vp, vp, vp, vp, u32, i32, i64, vp]),
             "bwr_sequence_dev": (ctypes.c_int, [vp, vp, vp, vp, vp, u32, i32, i64, vp, vp]),
@@ -146,6 +149,15 @@ def sequence_length(nb: int, s: int) -> int:
 
 def set_threads(n: int) -> None:
     _check(lib().bwr_set_threads(int(n)))
+
+
+def set_trials(n: int) -> None:
+    """Independent draws per rank computation (the largest rank over the draws is kept)."""
+    _check(lib().bwr_set_trials(int(n)))
+
+
+def get_trials() -> int:
+    return int(lib().bwr_get_trials())
 
 
 def random_block(seed: int, stream: int, rows: int, s: int, p: int, diag: bool = False) -> np.ndarray:
@@ -398,7 +410,7 @@ def sequence_batch(mats, primes, s: int, seed: int, lengths):
 class ServerStats(ctypes.Structure):
     _fields_ = [("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("solves_per_s", ctypes.c_double),
                 ("busy_s", ctypes.c_double), ("completed", ctypes.c_int64), ("max_queue", ctypes.c_int64),
-                ("max_active", ctypes.c_int64), ("steps", ctypes.c_int64)]
+                ("max_active", ctypes.c_int64), ("steps", ctypes.c_int64), ("peak_bytes", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -28,6 +28,9 @@ namespace {
 
 thread_local std::string g_err;
 
+// independent draws per rank computation (bwr_set_trials)
+std::atomic<int32_t> g_trials{1};
+
 int fail(const Error& e) {
     g_err = e.msg;
     return e.code;
@@ -230,26 +233,15 @@ struct StreamDrain {
     }
 };
 
-Error rank_dev_impl(const CsrView& A, uint32_t p, int32_t block, uint64_t seed, hipStream_t st, RankOut* out) {
-    Error e = check_prime(p);
-    if (!e.ok()) return e;
-    if (block < 1 || block > 64) return Error::inval("block size must be in 1..64");
+// One draw of the rank algorithm on an encoded matrix (Section 2.5, steps 1-4): U, V, D_r, D_c from `seed`,
+// the sequence with the sigma-basis beside it, the generator check and the read-out.
+Error rank_one_draw(const DeviceMatrix& M, const CsrView& A, uint32_t p, int32_t block, uint64_t seed, hipStream_t st,
+                    RankOut* out) {
+    Error e;
     bwr_rank_info& info = out->info;
-    std::memset(&info, 0, sizeof(info));
-    const double t0 = now_s();
     const bool transpose = A.m < A.n;
     const int64_t nb = std::min(A.m, A.n);
     const int64_t outer = std::max(A.m, A.n);
-    info.nb = nb;
-    info.transposed = transpose ? 1 : 0;
-    DeviceMatrix M;
-    if (!(e = encode_matrix(A, p, st, &M, true)).ok()) return e;
-    info.t_encode = now_s() - t0;
-    if (nb == 0 || A.nnz == 0) {
-        out->rank = 0;
-        info.rank = 0;
-        return {};
-    }
     const int32_t s = (int32_t)std::min<int64_t>(block, nb);
     const int64_t L = 2 + (2 * nb + s - 1) / s;
     const int64_t total = L + CHECK_TERMS;
@@ -347,6 +339,54 @@ Error rank_dev_impl(const CsrView& A, uint32_t p, int32_t block, uint64_t seed, 
 }
 
 
+
+// Rank of A with `trials` independent draws (seeds seed, seed + 1, ...): each draw's result is at most the
+// true rank (the method's error is one-sided, Section 2.5), so the largest is kept; the draws stop early
+// once a draw reaches min(m, n).  The matrix is encoded once for all draws.
+Error rank_dev_impl(const CsrView& A, uint32_t p, int32_t block, uint64_t seed, hipStream_t st, RankOut* out,
+                    int32_t trials) {
+    Error e = check_prime(p);
+    if (!e.ok()) return e;
+    if (block < 1 || block > 64) return Error::inval("block size must be in 1..64");
+    if (trials < 1) return Error::inval("trials must be >= 1");
+    std::memset(&out->info, 0, sizeof(out->info));
+    const double t0 = now_s();
+    const int64_t nb = std::min(A.m, A.n);
+    DeviceMatrix M;
+    if (!(e = encode_matrix(A, p, st, &M, true)).ok()) return e;
+    const double t_enc = now_s() - t0;
+    out->info.nb = nb;
+    out->info.transposed = A.m < A.n ? 1 : 0;
+    out->info.t_encode = t_enc;
+    out->info.trials = 0;
+    out->rank = 0;
+    if (nb == 0 || A.nnz == 0) return {};
+    double tseq = 0, tsig = 0, tro = 0;
+    for (int32_t t = 0; t < trials; ++t) {
+        RankOut one;
+        std::memset(&one.info, 0, sizeof(one.info));
+        one.info.nb = nb;
+        one.info.transposed = A.m < A.n ? 1 : 0;
+        if (!(e = rank_one_draw(M, A, p, block, seed + (uint64_t)t, st, &one)).ok()) return e;
+        tseq += one.info.t_sequence;
+        tsig += one.info.t_sigma;
+        tro += one.info.t_readout;
+        if (t == 0 || one.rank > out->rank) {
+            const int64_t best_before = out->rank;
+            out->info = one.info;
+            out->rank = one.rank;
+            (void)best_before;
+        }
+        out->info.trials = t + 1;
+        if (out->rank >= nb) break;
+    }
+    out->info.t_encode = t_enc;
+    out->info.t_sequence = tseq;
+    out->info.t_sigma = tsig;
+    out->info.t_readout = tro;
+    return {};
+}
+
 int pow2_at_most(double x, int lo, int hi) {
     int g = lo;
     while (g * 2 <= hi && g * 2 <= x) g *= 2;
@@ -401,6 +441,15 @@ int64_t bwr_sequence_length(int64_t nb, int32_t s) {
     if (s < 1 || nb < 0) return -1;
     return 2 + (2 * nb + s - 1) / s;
 }
+
+int bwr_set_trials(int32_t n) {
+    if (n < 1 || n > 64) return fail(BWR_EINVAL, "trials must be in 1..64");
+    g_trials.store(n);
+    g_err.clear();
+    return BWR_OK;
+}
+
+int32_t bwr_get_trials(void) { return g_trials.load(); }
 
 int bwr_set_threads(int32_t n) {
     if (n < 1) return fail(BWR_EINVAL, "thread count must be positive");
@@ -589,7 +638,7 @@ int bwr_rank_modp(const bwr_csr* A, uint32_t p, int32_t block, uint64_t seed, in
     HostUpload up;
     if (!(e = upload(A, st, &up)).ok()) return fail(e);
     RankOut ro;
-    if (!(e = rank_dev_impl(up.dev, p, block, seed, st, &ro)).ok()) return fail(e);
+    if (!(e = rank_dev_impl(up.dev, p, block, seed, st, &ro, g_trials.load())).ok()) return fail(e);
     *rank_out = ro.rank;
     if (info) *info = ro.info;
     g_err.clear();
@@ -603,7 +652,7 @@ int bwr_rank_modp_dev(const bwr_csr* A_dev, uint32_t p, int32_t block, uint64_t 
     Error e;
     hipStream_t st = work_stream(stream, &e);
     if (!e.ok()) return fail(e);
-    e = rank_dev_impl(view(A_dev), p, block, seed, st, &ro);
+    e = rank_dev_impl(view(A_dev), p, block, seed, st, &ro, g_trials.load());
     if (!e.ok()) return fail(e);
     *rank_out = ro.rank;
     if (info) *info = ro.info;
@@ -735,6 +784,7 @@ int bwr_rank_modp_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* p
         if (!(e = check_host_csr(view(A[j]))).ok()) return fail(e);
     }
     const double t0 = now_s();
+    const int32_t trials = g_trials.load();
     bwr_batch_info bi;
     std::memset(&bi, 0, sizeof(bi));
     hipStream_t st = lib_stream(&e);
@@ -799,8 +849,12 @@ int bwr_rank_modp_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* p
                 for (size_t i; le.ok() && (i = solo_next.fetch_add(1)) < solo.size();) {
                     const int j = solo[i].first, t = solo[i].second;
                     RankOut ro;
-                    le = rank_dev_impl(ups[j].dev, primes[t], block, seed, wst, &ro);
-                    if (!le.ok()) break;
+                    le = rank_dev_impl(ups[j].dev, primes[t], block, seed, wst, &ro, trials);
+                    if (!le.ok()) {
+                        // nothing this thread queued may still read the uploads once the call returns
+                        (void)hipStreamSynchronize(wst);
+                        break;
+                    }
                     std::lock_guard<std::mutex> lk(solo_mu);
                     ranks[(size_t)j * nprimes + t] = ro.rank;
                     bi.t_sequence += ro.info.t_sequence;
@@ -852,23 +906,26 @@ int bwr_rank_modp_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* p
             const int64_t nb = std::min(A[j]->m, A[j]->n);
             const int32_t s = (int32_t)std::min<int64_t>(block, nb);
             const int64_t L = 2 + (2 * nb + s - 1) / s;
-            for (int k0 = 0; k0 < nbp; k0 += bp.per_job) {
-                BatchSpec sp;
-                sp.M = &Ms[j];
-                sp.transpose = tr[j];
-                Own o{j, L, s, {0, 0, 0, 0}};
-                for (int k = k0; k < std::min(nbp, k0 + bp.per_job); ++k) {
-                    o.tix[k - k0] = bt[k];
-                    sp.primes.push_back(primes[bt[k]]);
+            // one job per group of primes and per draw (seeds seed, seed + 1, ...): the ranks of a matrix's draws
+            // meet in their maximum below
+            for (int32_t trial = 0; trial < trials; ++trial)
+                for (int k0 = 0; k0 < nbp; k0 += bp.per_job) {
+                    BatchSpec sp;
+                    sp.M = &Ms[j];
+                    sp.transpose = tr[j];
+                    Own o{j, L, s, {0, 0, 0, 0}};
+                    for (int k = k0; k < std::min(nbp, k0 + bp.per_job); ++k) {
+                        o.tix[k - k0] = bt[k];
+                        sp.primes.push_back(primes[bt[k]]);
+                    }
+                    sp.s = s;
+                    sp.seed = seed + (uint64_t)trial;
+                    sp.len = L + CHECK_TERMS;
+                    int id = 0;
+                    if (!(e = R.add(sp, &id)).ok()) return fail(e);
+                    owner.push_back(o);
+                    ++bi.jobs;
                 }
-                sp.s = s;
-                sp.seed = seed;
-                sp.len = L + CHECK_TERMS;
-                int id = 0;
-                if (!(e = R.add(sp, &id)).ok()) return fail(e);
-                owner.push_back(o);
-                ++bi.jobs;
-            }
         }
         const double t1 = now_s();
         double t_sig = 0;
@@ -924,7 +981,8 @@ int bwr_rank_modp_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* p
             for (const ReadoutPool::Result& r : pool.collect(R.active() == 0 || !first.ok())) {
                 const int id = (int)(r.tag / BATCH_MAX_PRIMES), t = (int)(r.tag % BATCH_MAX_PRIMES);
                 if (!r.err.ok() && first.ok()) first = r.err;
-                ranks[(size_t)owner[id].j * nprimes + owner[id].tix[t]] = r.rank;
+                int64_t& dst = ranks[(size_t)owner[id].j * nprimes + owner[id].tix[t]];
+                dst = std::max(dst, r.rank);
                 t_sig += r.seconds;
                 if (--left[id] == 0) {
                     R.release(id);
@@ -1062,7 +1120,7 @@ int bwr_server_submit(bwr_server* srv, const bwr_csr* A, uint32_t p, uint64_t se
     Error e = check_prime(p);
     if (!e.ok()) return fail(e);
     if (!(e = check_host_csr(view(A))).ok()) return fail(e);
-    if (!(e = srv->impl->submit(view(A), p, seed, ticket)).ok()) return fail(e);
+    if (!(e = srv->impl->submit(view(A), p, seed, g_trials.load(), ticket)).ok()) return fail(e);
     g_err.clear();
     return BWR_OK;
 }
@@ -1096,6 +1154,7 @@ int bwr_server_get_stats(bwr_server* srv, bwr_server_stats* out) {
     out->max_queue = st.max_queue;
     out->max_active = st.max_active;
     out->steps = st.steps;
+    out->peak_bytes = st.peak_bytes;
     g_err.clear();
     return BWR_OK;
 }

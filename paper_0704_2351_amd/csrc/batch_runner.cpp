@@ -94,6 +94,12 @@ int64_t BatchRunner::footprint(const DeviceMatrix& M, bool transpose, int W, int
 void BatchRunner::release(int id) {
     Job& J = *jobs_[id];
     if (J.released) return;
+    if (!J.done) {
+        // a job released before its last step (an error path) leaves the batch: the next advance rebuilds the
+        // active set and its graph without it, so no launch reads the buffers freed below
+        J.done = true;
+        dirty_ = true;
+    }
     J.X0.release();
     J.X1.release();
     J.Y.release();

@@ -44,7 +44,9 @@ class BatchRunner {
     const uint32_t* sequence(int id, int t) const;
     int64_t length(int id) const;
     const BatchSpec& spec(int id) const;
-    // Frees the job's device memory (stream-ordered).
+    // Frees the job's device memory (stream-ordered, after the work already queued on the runner's stream).
+    // A job released before it is done leaves the batch: it is marked done and the next advance rebuilds
+    // the active set and the step graph without it.
     void release(int id);
     int64_t bytes_in_use() const;
     static int64_t footprint(const DeviceMatrix& M, bool transpose, int W, int nprimes, int s, int64_t len);

@@ -36,18 +36,31 @@ double now_s() {
 
 constexpr int64_t CHECK_TERMS = 4;
 
+#define BWR_TRY_S(expr)               \
+    do {                              \
+        Error er_ = (expr);           \
+        if (!er_.ok()) return er_;    \
+    } while (0)
+
 }  // namespace
 
 struct Server::Req {
     uint64_t ticket = 0;
-    DevBuf rp, col, val;  // device copy of the CSR
+    // host copy of the CSR until the request is admitted and encoded (queued requests hold no device memory)
+    int64_t m = 0, n = 0, nnz = 0;
+    std::vector<int64_t> hrp;
+    std::vector<int32_t> hcol, hval;
     DeviceMatrix M;
+    bool encoded = false;
     bool transpose = false;
     uint32_t p = 0;
     uint64_t seed = 0;
+    int32_t trials = 1, draws = 0;  // independent draws asked for and made (draw t uses seed + t)
     int32_t s = 0;
-    int64_t L = 0;
-    int64_t footprint = 0;
+    int64_t nb = 0, L = 0;
+    int64_t footprint = 0;  // device bytes while admitted: encoded matrix + the runner's blocks and sequence
+    int64_t transient = 0;  // extra device bytes while it is being uploaded and encoded
+    bool counted = false;   // footprint counted in held_
     double arrival = 0, admitted = 0, finished = 0;
     int cls = 1;  // runner: 0 for primes <= 2^16, 1 otherwise
     int job = -1;
@@ -65,6 +78,7 @@ Error Server::start() {
     hipError_t e = hipGetDevice(&device_);
     for (int c = 0; c < 2 && e == hipSuccess; ++c) e = hipStreamCreateWithFlags(&compute_[c], hipStreamNonBlocking);
     if (const char* a = getenv("BWR_SERVER_AHEAD")) ahead_ = std::max(0, std::min(MAX_AHEAD, atoi(a)));
+    if (const char* f = getenv("BWR_SERVER_FAIL_ADVANCE")) fail_after_ = atoi(f);
     for (int c = 0; c < 2 && e == hipSuccess; ++c)
         for (int i = 0; i < ahead_ && e == hipSuccess; ++i)
             e = hipEventCreateWithFlags(&ahead_ev_[c][i], hipEventDisableTiming);
@@ -109,37 +123,22 @@ void Server::stop() {
     upload_ = nullptr;
 }
 
-Error Server::submit(const CsrView& A, uint32_t p, uint64_t seed, uint64_t* ticket) {
+Error Server::submit(const CsrView& A, uint32_t p, uint64_t seed, int32_t trials, uint64_t* ticket) {
     auto R = std::make_shared<Req>();
     R->arrival = now_s();
     R->p = p;
     R->seed = seed;
+    R->trials = std::max(1, trials);
     R->transpose = A.m < A.n;
-    (void)hipSetDevice(device_);
-    {
-        std::lock_guard<std::mutex> up(upload_mu_);
-        const size_t nnz = (size_t)A.nnz;
-        Error e;
-        if (!(e = R->rp.alloc(sizeof(int64_t) * (size_t)(A.m + 1), upload_)).ok()) return e;
-        if (!(e = R->col.alloc(4 * std::max<size_t>(nnz, 1), upload_)).ok()) return e;
-        if (!(e = R->val.alloc(4 * std::max<size_t>(nnz, 1), upload_)).ok()) return e;
-        hipError_t he = hipMemcpyAsync(R->rp.as<void>(), A.row_ptr, 8 * (size_t)(A.m + 1), hipMemcpyHostToDevice,
-                                       upload_);
-        if (he == hipSuccess && nnz)
-            he = hipMemcpyAsync(R->col.as<void>(), A.col_idx, 4 * nnz, hipMemcpyHostToDevice, upload_);
-        if (he == hipSuccess && nnz) he = hipMemcpyAsync(R->val.as<void>(), A.val, 4 * nnz, hipMemcpyHostToDevice, upload_);
-        if (he != hipSuccess) return Error::device(he, "server upload");
-        CsrView dv{A.m, A.n, A.nnz, R->rp.as<int64_t>(), R->col.as<int32_t>(), R->val.as<int32_t>()};
-        if (!(e = encode_matrix(dv, p, upload_, &R->M, true)).ok()) return e;
-        he = hipStreamSynchronize(upload_);
-        if (he != hipSuccess) return Error::device(he, "server upload");
-        // the encoded copy is all the request needs from here on
-        R->rp.release();
-        R->col.release();
-        R->val.release();
-    }
+    R->m = A.m;
+    R->n = A.n;
+    R->nnz = A.nnz;
     const int64_t nb = std::min(A.m, A.n);
-    if (nb == 0 || A.nnz == 0 || !R->M.packed) {
+    R->nb = nb;
+    // the batch kernels take the packed encoding: entries in [-127, 127], dimensions up to 2^24
+    bool packed = A.m <= (1LL << 24) && A.n <= (1LL << 24);
+    for (int64_t t = 0; packed && t < A.nnz; ++t) packed = A.val[t] >= -127 && A.val[t] <= 127;
+    if (nb == 0 || A.nnz == 0 || !packed) {
         // nothing to iterate, or entries the batch kernels cannot take: answer at once
         R->done = true;
         R->finished = now_s();
@@ -150,9 +149,20 @@ Error Server::submit(const CsrView& A, uint32_t p, uint64_t seed, uint64_t* tick
     } else {
         R->s = (int32_t)std::min<int64_t>(block_, nb);
         R->L = 2 + (2 * nb + R->s - 1) / R->s;
-        R->footprint = BatchRunner::footprint(R->M, R->transpose, W_, 1, R->s, R->L + CHECK_TERMS) +
-                       8 * (R->M.m + R->M.n + 2) + 8 * R->M.nnz;
-        if (R->footprint > budget_) return Error{ENOMEM_, "request larger than the server's HBM budget"};
+        DeviceMatrix shape;
+        shape.m = A.m;
+        shape.n = A.n;
+        shape.nnz = A.nnz;
+        // encoded CSR of A and A^T with their relabellings, and the runner's blocks and sequence
+        R->footprint = BatchRunner::footprint(shape, R->transpose, W_, 1, R->s, R->L + CHECK_TERMS) +
+                       8 * (A.m + A.n + 2) + 8 * A.nnz;
+        // the uploaded CSR (int64 row pointers, int32 columns and values) and the relabelled copy the encoder
+        // builds from it, with its counters
+        R->transient = 2 * (8 * (A.m + 1) + 8 * A.nnz) + 16 * std::max(A.m, A.n) + 4096;
+        if (R->footprint + R->transient > budget_) return Error{ENOMEM_, "request larger than the server's HBM budget"};
+        R->hrp.assign(A.row_ptr, A.row_ptr + A.m + 1);
+        R->hcol.assign(A.col_idx, A.col_idx + A.nnz);
+        R->hval.assign(A.val, A.val + A.nnz);
     }
     std::lock_guard<std::mutex> lk(mu_);
     R->ticket = ++next_ticket_;
@@ -168,6 +178,33 @@ Error Server::submit(const CsrView& A, uint32_t p, uint64_t seed, uint64_t* tick
     }
     if (first_arrival_ == 0) first_arrival_ = R->arrival;
     cv_.notify_all();
+    return {};
+}
+
+// Uploads and encodes an admitted request's matrix on the worker thread (upload stream), then drops the host
+// copy.
+Error Server::encode(Req& R) {
+    DevBuf rp, col, val;
+    const size_t nnz = (size_t)R.nnz;
+    BWR_TRY_S(rp.alloc(sizeof(int64_t) * (size_t)(R.m + 1), upload_));
+    BWR_TRY_S(col.alloc(4 * std::max<size_t>(nnz, 1), upload_));
+    BWR_TRY_S(val.alloc(4 * std::max<size_t>(nnz, 1), upload_));
+    hipError_t he = hipMemcpyAsync(rp.as<void>(), R.hrp.data(), 8 * R.hrp.size(), hipMemcpyHostToDevice, upload_);
+    if (he == hipSuccess && nnz) he = hipMemcpyAsync(col.as<void>(), R.hcol.data(), 4 * nnz, hipMemcpyHostToDevice, upload_);
+    if (he == hipSuccess && nnz) he = hipMemcpyAsync(val.as<void>(), R.hval.data(), 4 * nnz, hipMemcpyHostToDevice, upload_);
+    if (he != hipSuccess) {
+        (void)hipStreamSynchronize(upload_);
+        return Error::device(he, "server upload");
+    }
+    const CsrView dv{R.m, R.n, R.nnz, rp.as<int64_t>(), col.as<int32_t>(), val.as<int32_t>()};
+    Error e = encode_matrix(dv, R.p, upload_, &R.M, true);
+    he = hipStreamSynchronize(upload_);  // the host copies and the uploaded CSR are no longer read
+    if (e.ok() && he != hipSuccess) e = Error::device(he, "server upload");
+    if (!e.ok()) return e;
+    R.hrp = std::vector<int64_t>();
+    R.hcol = std::vector<int32_t>();
+    R.hval = std::vector<int32_t>();
+    R.encoded = true;
     return {};
 }
 
@@ -210,7 +247,24 @@ ServerStats Server::stats() {
     const double span = last_finish_ - first_arrival_;
     st.solves_per_s = (span > 0 && completed_ > 0) ? (double)completed_ / span : 0.0;
     st.busy_s = busy_s_;
+    st.peak_bytes = peak_held_;
     return st;
+}
+
+// Answers R (under mu_): its memory leaves the budget, its latency is recorded.
+void Server::answer_locked(Req& R, int code, const std::string& msg, int64_t rank) {
+    R.done = true;
+    R.code = code;
+    R.msg = msg;
+    R.rank = rank;
+    R.finished = now_s();
+    latencies_.push_back(R.finished - R.arrival);
+    ++completed_;
+    last_finish_ = R.finished;
+    if (R.counted) held_ -= R.footprint;
+    R.counted = false;
+    R.M = DeviceMatrix();
+    done_cv_.notify_all();
 }
 
 void Server::loop() {
@@ -221,34 +275,44 @@ void Server::loop() {
     std::vector<std::shared_ptr<Req>> active;       // sequences in the batch
     std::map<uint64_t, std::shared_ptr<Req>> reading;  // (runner << 32 | job id) -> request being read out
     for (;;) {
-        // admission at a step boundary
+        // admission at a step boundary: a request enters while the device bytes of every admitted request
+        // (encoded matrix, blocks, sequence), its own included, stay within the budget
         {
             std::unique_lock<std::mutex> lk(mu_);
             if (active.empty() && reading.empty()) cv_.wait(lk, [&] { return quit_ || !queue_.empty(); });
             if (quit_) break;
             while (!queue_.empty() && (int)(active.size() + reading.size()) < max_slots_) {
                 std::shared_ptr<Req> R = reqs_[queue_.front()];
-                const int64_t in_use = runners_[0]->bytes_in_use() + runners_[1]->bytes_in_use();
-                if (in_use + R->footprint > budget_ && !(active.empty() && reading.empty())) break;
+                if (!R->counted) {
+                    const int64_t need = R->footprint + R->transient;
+                    if (held_ + need > budget_ && held_ > 0) break;
+                    held_ += need;
+                    peak_held_ = std::max(peak_held_, held_);
+                    R->counted = true;
+                }
                 queue_.pop_front();
                 lk.unlock();
-                BatchSpec sp;
-                sp.M = &R->M;
-                sp.transpose = R->transpose;
-                sp.primes = {R->p};
-                sp.s = R->s;
-                sp.seed = R->seed;
-                sp.len = R->L + CHECK_TERMS;
-                R->cls = R->p <= 65536u ? 0 : 1;
-                Error e = runners_[R->cls]->add(sp, &R->job);
+                Error e;
+                if (!R->encoded) {
+                    e = encode(*R);
+                    std::lock_guard<std::mutex> lk2(mu_);
+                    held_ -= R->transient;  // the upload and the encoder's temporaries are released
+                }
+                if (e.ok()) {
+                    BatchSpec sp;
+                    sp.M = &R->M;
+                    sp.transpose = R->transpose;
+                    sp.primes = {R->p};
+                    sp.s = R->s;
+                    sp.seed = R->seed + (uint64_t)R->draws;
+                    sp.len = R->L + CHECK_TERMS;
+                    R->cls = R->p <= 65536u ? 0 : 1;
+                    e = runners_[R->cls]->add(sp, &R->job);
+                }
                 lk.lock();
-                R->admitted = now_s();
+                if (R->draws == 0) R->admitted = now_s();
                 if (!e.ok()) {
-                    R->done = true;
-                    R->code = e.code;
-                    R->msg = e.msg;
-                    R->finished = now_s();
-                    done_cv_.notify_all();
+                    answer_locked(*R, e.code, e.msg, 0);
                     continue;
                 }
                 active.push_back(R);
@@ -268,6 +332,11 @@ void Server::loop() {
                 const hipError_t he = hipEventSynchronize(ahead_ev_[cls][slot]);
                 if (he != hipSuccess) e = Error::device(he, "server advance wait");
             }
+            if (e.ok() && fail_after_ >= 0 && advances_ >= fail_after_) {
+                e = Error{EDEVICE_, "advance failed (BWR_SERVER_FAIL_ADVANCE)"};
+                fail_after_ = -1;  // once
+            }
+            ++advances_;
             if (e.ok()) e = run.advance(64, &fin);
             if (e.ok() && ahead_ > 0) {
                 const hipError_t he = hipEventRecord(ahead_ev_[cls][slot], compute_[cls]);
@@ -291,15 +360,7 @@ void Server::loop() {
                     const Error er = e.ok() ? Error::device(he, "read-out event") : e;
                     run.release(id);
                     std::lock_guard<std::mutex> lk(mu_);
-                    R->done = true;
-                    R->code = er.code;
-                    R->msg = er.msg;
-                    R->finished = now_s();
-                    latencies_.push_back(R->finished - R->arrival);
-                    ++completed_;
-                    last_finish_ = R->finished;
-                    R->M = DeviceMatrix();
-                    done_cv_.notify_all();
+                    answer_locked(*R, er.code, er.msg, 0);
                     continue;
                 }
                 const uint64_t tag = ((uint64_t)cls << 32) | (uint32_t)id;
@@ -308,17 +369,16 @@ void Server::loop() {
             }
         }
         if (!e.ok()) {
+            // a failed advance: every request still in a batch is answered with the error and its job released
             for (hipStream_t c : compute_) (void)hipStreamSynchronize(c);
+            for (auto& R : active) runners_[R->cls]->release(R->job);
             std::lock_guard<std::mutex> lk(mu_);
-            for (auto& R : active) {
-                R->done = true;
-                R->code = e.code;
-                R->msg = e.msg;
-            }
+            for (auto& R : active) answer_locked(*R, e.code, e.msg, 0);
             active.clear();
-            done_cv_.notify_all();
         }
-        // answer the requests whose read-out finished (wait for one when nothing else is running)
+        // answer the requests whose read-out finished (wait for one when nothing else is running); a request
+        // with draws left whose best rank is below min(m, n) goes back to the front of the queue with its
+        // matrix kept
         for (const ReadoutPool::Result& r : pool.collect(active.empty() && !reading.empty())) {
             auto it = reading.find(r.tag);
             if (it == reading.end()) continue;
@@ -326,16 +386,18 @@ void Server::loop() {
             reading.erase(it);
             runners_[r.tag >> 32]->release((int)(r.tag & 0xffffffffu));
             std::lock_guard<std::mutex> lk(mu_);
-            R->done = true;
-            R->rank = r.rank;
-            R->code = r.err.code;
-            R->msg = r.err.msg;
-            R->finished = now_s();
-            latencies_.push_back(R->finished - R->arrival);
-            ++completed_;
-            last_finish_ = R->finished;
-            R->M = DeviceMatrix();
-            done_cv_.notify_all();
+            if (!r.err.ok()) {
+                answer_locked(*R, r.err.code, r.err.msg, 0);
+                continue;
+            }
+            R->rank = R->draws == 0 ? r.rank : std::max(R->rank, r.rank);
+            ++R->draws;
+            if (R->draws < R->trials && R->rank < R->nb && !quit_) {
+                queue_.push_front(R->ticket);
+                cv_.notify_all();
+                continue;
+            }
+            answer_locked(*R, 0, std::string(), R->rank);
         }
         busy_s_ += now_s() - t0;
     }

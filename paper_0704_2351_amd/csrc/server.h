@@ -9,6 +9,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -22,6 +23,7 @@ struct ServerStats {
     double solves_per_s;    // completed / (last answer - first submit)
     double busy_s;          // worker time spent advancing and answering
     int64_t completed, max_queue, max_active, steps;
+    int64_t peak_bytes;     // largest sum of admitted requests' device bytes (encoded matrices included)
 };
 
 class Server {
@@ -30,8 +32,9 @@ class Server {
     ~Server();
     Error start();
     void stop();
-    // Copies and encodes A on the device before returning, then queues it.
-    Error submit(const CsrView& A_host, uint32_t p, uint64_t seed, uint64_t* ticket);
+    // Copies A into host memory and queues it (trials independent draws, the largest rank kept); the worker
+    // uploads and encodes it when it is admitted.
+    Error submit(const CsrView& A_host, uint32_t p, uint64_t seed, int32_t trials, uint64_t* ticket);
     Error poll(uint64_t ticket, bool* done, int64_t* rank);
     Error wait(uint64_t ticket, int64_t* rank);
     ServerStats stats();
@@ -39,6 +42,8 @@ class Server {
    private:
     struct Req;
     void loop();
+    Error encode(Req& R);
+    void answer_locked(Req& R, int code, const std::string& msg, int64_t rank);
     int64_t budget_;
     int max_slots_;
     int32_t block_;
@@ -66,6 +71,11 @@ class Server {
     bool quit_ = false;
     std::vector<double> latencies_;
     int64_t completed_ = 0, max_queue_ = 0, max_active_ = 0, steps_ = 0;
+    // device bytes of the admitted requests (footprints, plus the transient of one being encoded)
+    int64_t held_ = 0, peak_held_ = 0;
+    // error handling test hook: BWR_SERVER_FAIL_ADVANCE=k makes the advance after k advances report an error
+    // instead of launching (once); the requests in the batch are then answered with that error
+    int64_t advances_ = 0, fail_after_ = -1;
     double first_arrival_ = 0, last_finish_ = 0, busy_s_ = 0;
 };
 

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_symbols():
     with open(os.path.join(ROOT, "include", "bwrank.h")) as f:
         text = f.read()
-    return sorted(set(re.findall(r"^\s*(?:int|int64_t|void|const char\*)\s+(bwr_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|int32_t|int64_t|size_t|void|const char\*)\s+(bwr_\w+)\s*\(", text, re.M)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -182,3 +182,20 @@ def test_host_sigma_bases_on_threads():
     r = subprocess.run([sys.executable, "-c", _THREADS_SCRIPT, ROOT], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
     assert r.stdout.strip().endswith("errors [] mismatches 0"), r.stdout + r.stderr[-2000:]
+
+
+def test_trials_setting_bounds():
+    """bwr_set_trials accepts 1 .. 64 and refuses anything else with BWR_EINVAL, leaving the setting."""
+    import paper_0704_2351_amd as bw
+
+    old = bw.get_trials()
+    try:
+        bw.set_trials(3)
+        assert bw.get_trials() == 3
+        for bad in (0, -1, 65):
+            with pytest.raises(bw.BwrError) as ei:
+                bw.set_trials(bad)
+            assert ei.value.code == -1
+        assert bw.get_trials() == 3
+    finally:
+        bw.set_trials(old)

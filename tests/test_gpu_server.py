@@ -74,18 +74,29 @@ def test_server_continuous_arrivals():
 
 
 def test_server_admission_by_budget():
+    """The device bytes of the requests admitted at once (encoded matrices, blocks, sequences, and the upload
+    of the one being encoded) never exceed the budget, which bounds how many run together."""
     need_gpu()
     announce("server budget")
-    reqs = requests(8, 3)
-    # a budget that holds only a couple of these requests at once
-    srv = bw.Server(40 << 20, 64, 8)
+    reqs = [(planted(2250, 1500, 1200, 9, 6600 + j), CONFIG4_PRIMES[j % 4], 3 + j) for j in range(8)]
+    # unconstrained: all eight admitted together
+    srv = bw.Server(4 << 30, 64, 8)
+    tickets = [srv.submit(A, p, sd) for A, p, sd in reqs]
+    assert [srv.wait(t) for t in tickets] == [A.planted_rank for A, _, _ in reqs]
+    free = srv.stats()
+    srv.close()
+    announce(f"  unconstrained stats {free}")
+    # half of that peak: fewer requests at once, every rank still right, the peak within the budget
+    budget = free["peak_bytes"] // 2
+    srv = bw.Server(budget, 64, 8)
     tickets = [srv.submit(A, p, sd) for A, p, sd in reqs]
     ranks = [srv.wait(t) for t in tickets]
     st = srv.stats()
-    announce(f"  stats {st}")
     srv.close()
+    announce(f"  budget {budget} stats {st}")
     assert ranks == [A.planted_rank for A, _, _ in reqs]
     assert st["max_active"] < len(reqs)
+    assert 0 < st["peak_bytes"] <= budget
     # a request larger than the whole budget is refused
     srv = bw.Server(1 << 20, 4, 8)
     with pytest.raises(bw.BwrError) as ei:
@@ -121,3 +132,28 @@ def test_server_readouts_beside_captures(monkeypatch, ahead):
     srv.close()
     assert ranks == [A.planted_rank for A, _, _ in reqs]
     assert st["completed"] == 40 and st["max_active"] > 4
+
+
+def test_server_failed_advance_answers_and_recovers(monkeypatch):
+    """An advance that reports an error (forced from the host, no kernel is launched) answers every request in
+    the batch with that error and releases its job; requests submitted afterwards are answered correctly."""
+    need_gpu()
+    announce("server failed advance")
+    monkeypatch.setenv("BWR_SERVER_FAIL_ADVANCE", "1")
+    # 252 terms each: several advances of 64 steps, so the second advance finds them all in the batch
+    reqs = [(planted(1500, 1000, 800, 9, 8800 + j), CONFIG4_PRIMES[j % 4], 5 + j) for j in range(4)]
+    srv = bw.Server(4 << 30, 16, 8)
+    tickets = [srv.submit(A, p, sd) for A, p, sd in reqs]
+    codes = []
+    for t in tickets:
+        try:
+            codes.append(srv.wait(t))
+        except bw.BwrError as e:
+            codes.append(e.code)
+    assert -4 in codes  # at least the requests in the failed batch carry BWR_EDEVICE
+    later = requests(3, 6)
+    ranks = [srv.wait(srv.submit(A, p, sd)) for A, p, sd in later]
+    st = srv.stats()
+    srv.close()
+    assert ranks == [A.planted_rank for A, _, _ in later]
+    assert st["completed"] == 7
