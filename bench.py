@@ -168,7 +168,7 @@ def product_kernel(plan, which, s, p):
     W = plan["W"]
     split = "true" if p > 65536 else "false"
     if plan[f"T{which}R"] > 0:
-        proj = "true" if which == 2 else "false"
+        proj = "1" if which == 2 else "0"
         return (f"k_spmm_tiled<{W}, {etype}, {split}, {proj}>", "paper_0704_2351_amd/csrc/spmm_tiled.hip",
                 f"tiled: row blocks of {plan[f'T{which}R']} rows, slabs of 2^{plan[f'T{which}cb']} block rows, "
                 f"{plan[f'T{which}grid']} workgroups")
@@ -336,6 +336,54 @@ def sequence_mode(args):
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, p, s, ge_mats=(("2000x1500", config1()), ("200000x150000", config2())))
+    print(json.dumps(out), flush=True)
+
+
+def gram_mode(args):
+    """The symmetric projection U = V (Section 2.3) in Gram form at the default workload's size: two sequence terms
+    per application of B (S_2k = W_k^T W_k, S_2k+1 = (A D_c W_k)^T D_r (A D_c W_k), W_k = B^k V; identities the paper
+    does not use).  Steps of --terms terms from a kept matrix, then the whole rank with this projection."""
+    import torch
+
+    import paper_0704_2351_amd as bw
+    from workloads import config3
+
+    s, p = 16, 65521
+    log("generating the planted 2000000 x 1000000 matrix")
+    A = config3()
+    m, n, nnz = A.m, A.n, A.nnz
+    Ad = bw.csr_to_device(A, "cuda:0")
+    torch.cuda.synchronize()
+    bw.time_step_kernels_dev(Ad, p, s, False, 5, with_plan=True)  # the autotuner's plan, cached
+    M = bw.Matrix(Ad, p)
+    U, V, dr, dc = draws(p, s, m, n, torch)
+    terms = args.terms
+    apps = (terms - 1 + 1) // 2
+    for w in range(args.warmup):
+        M.sequence_sym_dev(V, p, terms, dr, dc, gram=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        M.sequence_sym_dev(V, p, terms, dr, dc, gram=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    M.close()
+    out = {"metric": METRIC, "mode": "symmetric_gram", "unit": "Gnnz·vec/s",
+           "value": round(2.0 * nnz * s * apps * args.steps / el / 1e9, 3),
+           "terms_per_s": round((terms - 1) * args.steps / el, 1), "ms_per_step": round(1000 * el / args.steps, 3),
+           "applications_per_step": apps, "terms_per_step": terms, "steps": args.steps,
+           "note": "two terms per application of B (Gram identities, not in the paper); value counts the sparse "
+                   "products' multiply-adds",
+           "config": {"workload": f"symmetric sequence (U = V) mod {p} of the planted {m} x {n} matrix "
+                                  f"({nnz / 1e6:.1f} M non-zeros), block {s}"}}
+    if not args.no_rank:
+        log("rank with the symmetric projection in Gram form")
+        t0 = time.perf_counter()
+        r, info = bw.rank_modp_sym_dev(Ad, p, s, 1, gram=True)
+        torch.cuda.synchronize()
+        out["rank"] = {"rank": int(r), "planted_rank": int(A.planted_rank), "equals_planted": bool(r == A.planted_rank),
+                       "seconds": round(time.perf_counter() - t0, 2), "t_sequence": round(info["t_sequence"], 2),
+                       "t_sigma_after_sequence": round(info["t_sigma"], 3)}
     print(json.dumps(out), flush=True)
 
 
@@ -581,6 +629,9 @@ def main():
                     help="only the whole rank of the 2000000 x 1000000 matrix")
     ap.add_argument("--rank-c2", action="store_true",
                     help="ranks of the 200000 x 150000 matrix at p = 65521 and 2^31 - 1 (one step = both)")
+    ap.add_argument("--gram", action="store_true",
+                    help="the symmetric projection in Gram form (two terms per application of B) at the default "
+                         "workload's size, then its rank")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="the default workload's step kernels back to back, then a 256 MiB device copy (the "
                          "command the counter summaries are taken on)")
@@ -610,6 +661,8 @@ def main():
         return rank_c2_mode(args)
     if args.profile_kernels:
         return profile_kernels_mode(args)
+    if args.gram:
+        return gram_mode(args)
     return sequence_mode(args)
 
 

@@ -150,6 +150,58 @@ int bwr_sequence_dev(const bwr_csr* A_dev, const uint32_t* d_row, const uint32_t
 int bwr_apply_dev(const bwr_csr* A_dev, const uint32_t* d_row, const uint32_t* d_col, const uint32_t* X,
                   uint32_t p, int32_t s, uint32_t* Z, void* stream);
 
+/* ---- symmetric projection (Section 2.3, block symmetry) -------------------
+ * With the symmetric projection U = V the terms S_k = V^T B^k V are symmetric
+ * (B = D_c A^T D_r A D_c is symmetric).  bwr_sequence_sym_dev computes them
+ * for k < len (V: n x s, device; layouts as bwr_sequence_dev).  gram = 0:
+ * each term is formed as (D_c^-1 V)^T X_k like the independent projection
+ * and every term is checked to be symmetric on the device (a term that is
+ * not: BWR_EDEVICE), a check of the sparse products themselves.  gram = 1:
+ * the standard identities S_2k = W_k^T W_k and S_2k+1 = (A D_c W_k)^T D_r
+ * (A D_c W_k), W_k = B^k V, give two terms per application of B, so the
+ * sequence takes about half the sparse products (the paper does not use
+ * them); only the entries i <= j are summed and the others mirrored.
+ * bwr_rank_modp_sym(_dev): the rank algorithm (Section 2.5) with this
+ * projection (V drawn from the seed as for bwr_rank_modp; draws as set by
+ * bwr_set_trials).  The paper notes that the symmetric projection lowers the
+ * probability of success; the result is still never above the true rank.
+ * When d_row has entries divisible by p the Gram form weighs those rows by
+ * 0, which gives the same terms. */
+int bwr_sequence_sym_dev(const bwr_csr* A_dev, const uint32_t* d_row, const uint32_t* d_col, const uint32_t* V,
+                         uint32_t p, int32_t s, int64_t len, int32_t gram, uint32_t* S_out, void* stream);
+int bwr_rank_modp_sym(const bwr_csr* A, uint32_t p, int32_t block, uint64_t seed, int32_t gram, int64_t* rank_out,
+                      bwr_rank_info* info);
+int bwr_rank_modp_sym_dev(const bwr_csr* A_dev, uint32_t p, int32_t block, uint64_t seed, int32_t gram, void* stream,
+                          int64_t* rank_out, bwr_rank_info* info);
+
+/* ---- caller-owned workspace -----------------------------------------------
+ * bwr_sequence_dev (Sections 2.2-2.3) and bwr_rank_modp_dev (Section 2.5)
+ * with every device buffer of the computation carved from `workspace`, a
+ * caller-allocated device region (e.g. a torch tensor) of workspace_bytes,
+ * 256-byte aligned: these calls make no device allocation of their own.
+ * bwr_sequence_workspace and bwr_rank_workspace return a sufficient size
+ * (an upper bound, counted from the buffers the computation carves: the
+ * encoded CSR of A and A^T with their relabelled copy, the iterated blocks,
+ * the partial sums; for the rank also the draws and the sequence), or 0 for
+ * invalid arguments.  Results are identical to the allocating forms.  Inside
+ * a workspace the products use the row-split kernels with the heuristic
+ * launch plan (no autotuner trials, no tiled encodings) and the rank's
+ * sigma-basis runs on the host.  BWR_ENOMEM (nothing computed) if the
+ * workspace is too small; BWR_EINVAL if it is NULL or misaligned.  The
+ * workspace is the caller's: the call reads and writes it on a library
+ * stream after waiting for `stream`, returns once its work is complete, and
+ * keeps nothing in it; two calls in flight must not share one workspace. */
+size_t bwr_sequence_workspace(int64_t m, int64_t n, int64_t nnz, int32_t s);
+/* Device allocations the library has made in this process so far (a count
+ * that the workspace forms leave unchanged; for tests and monitoring). */
+int64_t bwr_device_allocations(void);
+size_t bwr_rank_workspace(int64_t m, int64_t n, int64_t nnz, int32_t block);
+int bwr_sequence_dev_ws(const bwr_csr* A_dev, const uint32_t* d_row, const uint32_t* d_col, const uint32_t* U,
+                        const uint32_t* V, uint32_t p, int32_t s, int64_t len, uint32_t* S_out, void* workspace,
+                        size_t workspace_bytes, void* stream);
+int bwr_rank_modp_dev_ws(const bwr_csr* A_dev, uint32_t p, int32_t block, uint64_t seed, void* workspace,
+                         size_t workspace_bytes, void* stream, int64_t* rank_out, bwr_rank_info* info);
+
 /* ---- a matrix encoded once, for several sequences ------------------------
  * The blackbox of Section 2.3 (B = D_c A^T D_r A D_c) applied many times to
  * one A: bwr_matrix_create_dev validates and encodes the device CSR A once
@@ -167,6 +219,9 @@ typedef struct bwr_matrix bwr_matrix;
 int bwr_matrix_create_dev(const bwr_csr* A_dev, uint32_t p, void* stream, bwr_matrix** out);
 int bwr_matrix_sequence_dev(bwr_matrix* M, const uint32_t* d_row, const uint32_t* d_col, const uint32_t* U,
                             const uint32_t* V, uint32_t p, int32_t s, int64_t len, uint32_t* S_out, void* stream);
+/* The symmetric sequence S_k = V^T B^k V of a kept matrix (as bwr_sequence_sym_dev). */
+int bwr_matrix_sequence_sym_dev(bwr_matrix* M, const uint32_t* d_row, const uint32_t* d_col, const uint32_t* V,
+                                uint32_t p, int32_t s, int64_t len, int32_t gram, uint32_t* S_out, void* stream);
 void bwr_matrix_destroy(bwr_matrix* M);
 
 /* Rank of A over GF(p) by the block Wiedemann rank algorithm (Section 2.5):

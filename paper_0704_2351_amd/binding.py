@@ -22,7 +22,9 @@ EXPORTED = ("bwr_version", "bwr_last_error", "bwr_is_prime", "bwr_sequence_lengt
             "bwr_min_generator_dev", "bwr_min_generators_dev", "bwr_rank_modp_batch", "bwr_rank_integer", "bwr_sequence_batch", "bwr_server_create",
             "bwr_server_submit", "bwr_server_poll", "bwr_server_wait", "bwr_server_get_stats", "bwr_server_destroy",
             "bwr_matrix_create_dev", "bwr_matrix_sequence_dev", "bwr_matrix_destroy", "bwr_set_trials",
-            "bwr_get_trials")
+            "bwr_get_trials", "bwr_sequence_workspace", "bwr_rank_workspace", "bwr_sequence_dev_ws",
+            "bwr_rank_modp_dev_ws", "bwr_device_allocations", "bwr_sequence_sym_dev", "bwr_rank_modp_sym",
+            "bwr_rank_modp_sym_dev", "bwr_matrix_sequence_sym_dev")
 
 
 class BwrError(RuntimeError):
@@ -98,6 +100,15 @@ def lib():
             "bwr_matrix_create_dev": (ctypes.c_int, [vp, u32, vp, vp]),
             "bwr_matrix_sequence_dev": (ctypes.c_int, [vp, vp, vp, vp, vp, u32, i32, i64, vp, vp]),
             "bwr_matrix_destroy": (None, [vp]),
+            "bwr_sequence_workspace": (ctypes.c_size_t, [i64, i64, i64, i32]),
+            "bwr_device_allocations": (i64, []),
+            "bwr_sequence_sym_dev": (ctypes.c_int, [vp, vp, vp, vp, u32, i32, i64, i32, vp, vp]),
+            "bwr_rank_modp_sym": (ctypes.c_int, [vp, u32, i32, u64, i32, vp, vp]),
+            "bwr_rank_modp_sym_dev": (ctypes.c_int, [vp, u32, i32, u64, i32, vp, vp, vp]),
+            "bwr_matrix_sequence_sym_dev": (ctypes.c_int, [vp, vp, vp, vp, u32, i32, i64, i32, vp, vp]),
+            "bwr_rank_workspace": (ctypes.c_size_t, [i64, i64, i64, i32]),
+            "bwr_sequence_dev_ws": (ctypes.c_int, [vp, vp, vp, vp, vp, u32, i32, i64, vp, vp, ctypes.c_size_t, vp]),
+            "bwr_rank_modp_dev_ws": (ctypes.c_int, [vp, u32, i32, u64, vp, ctypes.c_size_t, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -281,6 +292,15 @@ class Matrix:
                                              int(length), _dptr(out), _stream()))
         return out[:length]
 
+    def sequence_sym_dev(self, V, p: int, length: int, d_row=None, d_col=None, gram: bool = False, out=None):
+        torch = _torch()
+        s = V.shape[1]
+        if out is None:
+            out = torch.empty((max(length, 1), s, s), dtype=torch.int32, device=V.device)
+        _check(lib().bwr_matrix_sequence_sym_dev(self._h, _dptr(d_row), _dptr(d_col), _dptr(V), int(p), int(s),
+                                                 int(length), int(bool(gram)), _dptr(out), _stream()))
+        return out[:length]
+
     def close(self):
         if self._h:
             lib().bwr_matrix_destroy(self._h)
@@ -291,6 +311,85 @@ class Matrix:
             self.close()
         except Exception:
             pass
+
+
+def device_allocations() -> int:
+    """Device allocations the library has made in this process (bwr_device_allocations)."""
+    return int(lib().bwr_device_allocations())
+
+
+def sequence_workspace(m: int, n: int, nnz: int, s: int) -> int:
+    """Device bytes bwr_sequence_dev_ws needs (0: invalid arguments)."""
+    return int(lib().bwr_sequence_workspace(int(m), int(n), int(nnz), int(s)))
+
+
+def rank_workspace(m: int, n: int, nnz: int, block: int) -> int:
+    """Device bytes bwr_rank_modp_dev_ws needs (0: invalid arguments)."""
+    return int(lib().bwr_rank_workspace(int(m), int(n), int(nnz), int(block)))
+
+
+def _workspace(nbytes, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def sequence_dev_ws(Ad, U, V, p: int, length: int, d_row=None, d_col=None, workspace=None, out=None):
+    """bwr_sequence_dev_ws: the sequence with every device buffer carved from `workspace` (a torch uint8 device
+    tensor; allocated here with bwr_sequence_workspace bytes when None)."""
+    torch = _torch()
+    st = _dev_csr(Ad)
+    s = U.shape[1]
+    if workspace is None:
+        workspace = _workspace(sequence_workspace(Ad["m"], Ad["n"], Ad["nnz"], s), U.device)
+    if out is None:
+        out = torch.empty((max(length, 1), s, s), dtype=torch.int32, device=U.device)
+    _check(lib().bwr_sequence_dev_ws(ctypes.byref(st), _dptr(d_row), _dptr(d_col), _dptr(U), _dptr(V), int(p),
+                                     int(s), int(length), _dptr(out), _dptr(workspace), int(workspace.numel()),
+                                     _stream()))
+    return out[:length]
+
+
+def rank_modp_dev_ws(Ad, p: int, block: int, seed: int, workspace=None):
+    """bwr_rank_modp_dev_ws: (rank, info) with every device buffer carved from `workspace`."""
+    st = _dev_csr(Ad)
+    if workspace is None:
+        workspace = _workspace(rank_workspace(Ad["m"], Ad["n"], Ad["nnz"], block), Ad["row_ptr"].device)
+    r = ctypes.c_int64(0)
+    info = RankInfo()
+    _check(lib().bwr_rank_modp_dev_ws(ctypes.byref(st), int(p), int(block), int(seed), _dptr(workspace),
+                                      int(workspace.numel()), _stream(), ctypes.byref(r), ctypes.byref(info)))
+    return int(r.value), info.as_dict()
+
+
+def sequence_sym_dev(Ad, V, p: int, length: int, d_row=None, d_col=None, gram: bool = False, out=None):
+    """Symmetric sequence S_k = V^T B^k V (bwr_sequence_sym_dev); gram: two terms per application of B."""
+    torch = _torch()
+    st = _dev_csr(Ad)
+    s = V.shape[1]
+    if out is None:
+        out = torch.empty((max(length, 1), s, s), dtype=torch.int32, device=V.device)
+    _check(lib().bwr_sequence_sym_dev(ctypes.byref(st), _dptr(d_row), _dptr(d_col), _dptr(V), int(p), int(s),
+                                      int(length), int(bool(gram)), _dptr(out), _stream()))
+    return out[:length]
+
+
+def rank_modp_sym(A, p: int, block: int, seed: int, gram: bool = False):
+    """(rank, info) with the symmetric projection U = V (bwr_rank_modp_sym)."""
+    st, keep = _host_csr(A)
+    r = ctypes.c_int64(0)
+    info = RankInfo()
+    _check(lib().bwr_rank_modp_sym(ctypes.byref(st), int(p), int(block), int(seed), int(bool(gram)), ctypes.byref(r),
+                                   ctypes.byref(info)))
+    return int(r.value), info.as_dict()
+
+
+def rank_modp_sym_dev(Ad, p: int, block: int, seed: int, gram: bool = False):
+    st = _dev_csr(Ad)
+    r = ctypes.c_int64(0)
+    info = RankInfo()
+    _check(lib().bwr_rank_modp_sym_dev(ctypes.byref(st), int(p), int(block), int(seed), int(bool(gram)), _stream(),
+                                       ctypes.byref(r), ctypes.byref(info)))
+    return int(r.value), info.as_dict()
 
 
 def apply_dev(Ad, X, p: int, d_row=None, d_col=None, out=None):

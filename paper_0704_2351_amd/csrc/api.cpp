@@ -235,8 +235,9 @@ struct StreamDrain {
 
 // One draw of the rank algorithm on an encoded matrix (Section 2.5, steps 1-4): U, V, D_r, D_c from `seed`,
 // the sequence with the sigma-basis beside it, the generator check and the read-out.
+// proj: 0 = independent U and V; 1 = symmetric projection U = V (Section 2.3); 2 = symmetric, in Gram form.
 Error rank_one_draw(const DeviceMatrix& M, const CsrView& A, uint32_t p, int32_t block, uint64_t seed, hipStream_t st,
-                    RankOut* out) {
+                    RankOut* out, int proj) {
     Error e;
     bwr_rank_info& info = out->info;
     const bool transpose = A.m < A.n;
@@ -245,7 +246,8 @@ Error rank_one_draw(const DeviceMatrix& M, const CsrView& A, uint32_t p, int32_t
     const int32_t s = (int32_t)std::min<int64_t>(block, nb);
     const int64_t L = 2 + (2 * nb + s - 1) / s;
     const int64_t total = L + CHECK_TERMS;
-    const bool on_device = gpu_leaf_order(s) > 0 && !getenv("BWR_HOST_SIGMA");
+    // inside an arena the generator is computed on the host (the device sigma-basis allocates as it recurses)
+    const bool on_device = gpu_leaf_order(s) > 0 && !getenv("BWR_HOST_SIGMA") && !current_arena();
     const int64_t min_chunk = on_device ? online_min_chunk(L) : 0;
     info.s = s;
     info.len = L;
@@ -273,6 +275,8 @@ Error rank_one_draw(const DeviceMatrix& M, const CsrView& A, uint32_t p, int32_t
     a.V = V.as<uint32_t>();
     a.len = total;
     a.S_out = S.as<uint32_t>();
+    a.symmetric = proj != 0;
+    a.gram = proj == 2;
     // device sigma-basis: its chunks run on stream 1 as the terms they need are reduced
     StreamDrain drain;  // declared first so that it runs after og's destructor has joined og's thread
     OnlineGenerator og;
@@ -344,7 +348,7 @@ Error rank_one_draw(const DeviceMatrix& M, const CsrView& A, uint32_t p, int32_t
 // true rank (the method's error is one-sided, Section 2.5), so the largest is kept; the draws stop early
 // once a draw reaches min(m, n).  The matrix is encoded once for all draws.
 Error rank_dev_impl(const CsrView& A, uint32_t p, int32_t block, uint64_t seed, hipStream_t st, RankOut* out,
-                    int32_t trials) {
+                    int32_t trials, int proj = 0) {
     Error e = check_prime(p);
     if (!e.ok()) return e;
     if (block < 1 || block > 64) return Error::inval("block size must be in 1..64");
@@ -367,7 +371,7 @@ Error rank_dev_impl(const CsrView& A, uint32_t p, int32_t block, uint64_t seed, 
         std::memset(&one.info, 0, sizeof(one.info));
         one.info.nb = nb;
         one.info.transposed = A.m < A.n ? 1 : 0;
-        if (!(e = rank_one_draw(M, A, p, block, seed + (uint64_t)t, st, &one)).ok()) return e;
+        if (!(e = rank_one_draw(M, A, p, block, seed + (uint64_t)t, st, &one, proj)).ok()) return e;
         tseq += one.info.t_sequence;
         tsig += one.info.t_sigma;
         tro += one.info.t_readout;
@@ -534,6 +538,144 @@ int bwr_apply_dev(const bwr_csr* A_dev, const uint32_t* d_row, const uint32_t* d
     return BWR_OK;
 }
 
+// ---- symmetric projection ----
+
+int bwr_sequence_sym_dev(const bwr_csr* A_dev, const uint32_t* d_row, const uint32_t* d_col, const uint32_t* V,
+                         uint32_t p, int32_t s, int64_t len, int32_t gram, uint32_t* S_out, void* stream) {
+    if (!A_dev) return fail(BWR_EINVAL, "NULL matrix");
+    Error e = check_prime(p);
+    if (!e.ok()) return fail(e);
+    if (s < 1 || s > 64) return fail(BWR_EINVAL, "block size must be in 1..64");
+    if (len < 0) return fail(BWR_EINVAL, "len must be >= 0");
+    if (len > 0 && (!S_out || (A_dev->n > 0 && !V))) return fail(BWR_EINVAL, "NULL output or block");
+    if (len == 0) return BWR_OK;
+    hipStream_t st = work_stream(stream, &e);
+    if (!e.ok()) return fail(e);
+    DeviceMatrix M;
+    e = encode_matrix(view(A_dev), p, st, &M, true);
+    if (e.ok()) {
+        SequenceArgs a;
+        a.M = &M;
+        a.mp = ModP::make(p);
+        a.s = s;
+        a.d_row = d_row;
+        a.d_col = d_col;
+        a.U = V;
+        a.V = V;
+        a.len = len;
+        a.S_out = S_out;
+        a.symmetric = true;
+        a.gram = gram != 0;
+        e = run_sequence(a, st);
+    }
+    const hipError_t he = hipStreamSynchronize(st);
+    if (e.ok() && he != hipSuccess) e = Error::device(he, "sequence");
+    if (!e.ok()) return fail(e);
+    g_err.clear();
+    return BWR_OK;
+}
+
+int bwr_rank_modp_sym_dev(const bwr_csr* A_dev, uint32_t p, int32_t block, uint64_t seed, int32_t gram, void* stream,
+                          int64_t* rank_out, bwr_rank_info* info) {
+    if (!A_dev || !rank_out) return fail(BWR_EINVAL, "NULL argument");
+    Error e;
+    hipStream_t st = work_stream(stream, &e);
+    if (!e.ok()) return fail(e);
+    RankOut ro;
+    e = rank_dev_impl(view(A_dev), p, block, seed, st, &ro, g_trials.load(), gram ? 2 : 1);
+    const hipError_t he = hipStreamSynchronize(st);
+    if (e.ok() && he != hipSuccess) e = Error::device(he, "rank");
+    if (!e.ok()) return fail(e);
+    *rank_out = ro.rank;
+    if (info) *info = ro.info;
+    g_err.clear();
+    return BWR_OK;
+}
+
+int bwr_rank_modp_sym(const bwr_csr* A, uint32_t p, int32_t block, uint64_t seed, int32_t gram, int64_t* rank_out,
+                      bwr_rank_info* info) {
+    if (!A || !rank_out) return fail(BWR_EINVAL, "NULL argument");
+    Error e;
+    hipStream_t st = lib_stream(&e);
+    if (!e.ok()) return fail(e);
+    HostUpload up;
+    if (!(e = upload(A, st, &up)).ok()) return fail(e);
+    RankOut ro;
+    e = rank_dev_impl(up.dev, p, block, seed, st, &ro, g_trials.load(), gram ? 2 : 1);
+    const hipError_t he = hipStreamSynchronize(st);
+    if (e.ok() && he != hipSuccess) e = Error::device(he, "rank");
+    if (!e.ok()) return fail(e);
+    *rank_out = ro.rank;
+    if (info) *info = ro.info;
+    g_err.clear();
+    return BWR_OK;
+}
+
+// ---- caller-owned workspace ----
+
+int64_t bwr_device_allocations(void) { return device_allocations(); }
+
+size_t bwr_sequence_workspace(int64_t m, int64_t n, int64_t nnz, int32_t s) {
+    if (m < 0 || n < 0 || nnz < 0 || s < 1 || s > 64) return 0;
+    return sequence_workspace_bytes(m, n, nnz, s, false);
+}
+
+size_t bwr_rank_workspace(int64_t m, int64_t n, int64_t nnz, int32_t block) {
+    if (m < 0 || n < 0 || nnz < 0 || block < 1 || block > 64) return 0;
+    const int64_t nb = std::min(m, n), outer = std::max(m, n);
+    const int64_t s = std::max<int64_t>(1, std::min<int64_t>(block, nb));
+    const int64_t total = 2 + (2 * nb + s - 1) / s + CHECK_TERMS;
+    // a draw's U, V, D_r, D_c and its sequence, beside what the sequence itself needs
+    const int64_t draws = 8 * nb * s + 4 * outer + 4 * nb + 4 * total * s * s + 8 * 256;
+    return (size_t)draws + sequence_workspace_bytes(m, n, nnz, (int32_t)s, m < n);
+}
+
+int bwr_sequence_dev_ws(const bwr_csr* A_dev, const uint32_t* d_row, const uint32_t* d_col, const uint32_t* U,
+                        const uint32_t* V, uint32_t p, int32_t s, int64_t len, uint32_t* S_out, void* workspace,
+                        size_t workspace_bytes, void* stream) {
+    if (!A_dev) return fail(BWR_EINVAL, "NULL matrix");
+    if (!workspace || ((uintptr_t)workspace & 255)) return fail(BWR_EINVAL, "workspace must be 256-byte aligned");
+    Error e;
+    hipStream_t st = work_stream(stream, &e);
+    if (!e.ok()) return fail(e);
+    Arena ar;
+    ar.base = (char*)workspace;
+    ar.size = workspace_bytes;
+    {
+        ArenaScope scope(&ar);
+        e = sequence_dev_impl(view(A_dev), d_row, d_col, U, V, p, s, len, S_out, st);
+    }
+    const hipError_t he = hipStreamSynchronize(st);
+    if (e.ok() && he != hipSuccess) e = Error::device(he, "sequence");
+    if (!e.ok()) return fail(e);
+    g_err.clear();
+    return BWR_OK;
+}
+
+int bwr_rank_modp_dev_ws(const bwr_csr* A_dev, uint32_t p, int32_t block, uint64_t seed, void* workspace,
+                         size_t workspace_bytes, void* stream, int64_t* rank_out, bwr_rank_info* info) {
+    if (!A_dev || !rank_out) return fail(BWR_EINVAL, "NULL argument");
+    if (!workspace || ((uintptr_t)workspace & 255)) return fail(BWR_EINVAL, "workspace must be 256-byte aligned");
+    Error e;
+    hipStream_t st = work_stream(stream, &e);
+    if (!e.ok()) return fail(e);
+    Arena ar;
+    ar.base = (char*)workspace;
+    ar.size = workspace_bytes;
+    RankOut ro;
+    {
+        ArenaScope scope(&ar);
+        e = rank_dev_impl(view(A_dev), p, block, seed, st, &ro, g_trials.load());
+    }
+    const hipError_t he = hipStreamSynchronize(st);
+    if (e.ok() && he != hipSuccess) e = Error::device(he, "rank");
+    if (!e.ok()) return fail(e);
+    *rank_out = ro.rank;
+    if (info) *info = ro.info;
+    g_err.clear();
+    return BWR_OK;
+}
+
 // ---- a matrix encoded once for several sequences ----
 
 }  // extern "C"
@@ -594,6 +736,38 @@ int bwr_matrix_sequence_dev(bwr_matrix* M, const uint32_t* d_row, const uint32_t
     a.V = V;
     a.len = len;
     a.S_out = S_out;
+    e = run_sequence(a, st);
+    hipError_t he = hipStreamSynchronize(st);
+    if (e.ok() && he != hipSuccess) e = Error::device(he, "sequence");
+    if (!e.ok()) return fail(e);
+    g_err.clear();
+    return BWR_OK;
+}
+
+int bwr_matrix_sequence_sym_dev(bwr_matrix* M, const uint32_t* d_row, const uint32_t* d_col, const uint32_t* V,
+                                uint32_t p, int32_t s, int64_t len, int32_t gram, uint32_t* S_out, void* stream) {
+    if (!M) return fail(BWR_EINVAL, "NULL matrix");
+    Error e = check_prime(p);
+    if (!e.ok()) return fail(e);
+    if (s < 1 || s > 64) return fail(BWR_EINVAL, "block size must be in 1..64");
+    if (len < 0) return fail(BWR_EINVAL, "len must be >= 0");
+    if (len > 0 && (!S_out || (M->M.n > 0 && !V))) return fail(BWR_EINVAL, "NULL output or block");
+    if (!M->M.packed && M->M.wide_p != p) return fail(BWR_EINVAL, "matrix was encoded for another prime");
+    if (len == 0) return BWR_OK;
+    hipStream_t st = work_stream(stream, &e);
+    if (!e.ok()) return fail(e);
+    SequenceArgs a;
+    a.M = &M->M;
+    a.mp = ModP::make(p);
+    a.s = s;
+    a.d_row = d_row;
+    a.d_col = d_col;
+    a.U = V;
+    a.V = V;
+    a.len = len;
+    a.S_out = S_out;
+    a.symmetric = true;
+    a.gram = gram != 0;
     e = run_sequence(a, st);
     hipError_t he = hipStreamSynchronize(st);
     if (e.ok() && he != hipSuccess) e = Error::device(he, "sequence");

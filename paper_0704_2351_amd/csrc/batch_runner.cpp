@@ -66,6 +66,8 @@ BatchRunner::BatchRunner(int W, int G1, int G2, hipStream_t st, int esize)
 }
 
 BatchRunner::~BatchRunner() {
+    // no launch of the graph may still be in flight when it is destroyed
+    if (exec_ || graph_) (void)hipStreamSynchronize(st_);
     if (exec_) (void)hipGraphExecDestroy(exec_);
     if (graph_) (void)hipGraphDestroy(graph_);
 }
@@ -268,6 +270,9 @@ Error BatchRunner::rebuild() {
     }
     acc1_ = env_acc(batch_acc_mode(len1, vabs, G1_));
     acc2_ = env_acc(batch_acc_mode(len2, vabs, G2_));
+    // the previous active set's graph is destroyed only after its launches have run (a launch in flight, and a
+    // tracer that inspects its dispatches when they complete, must not outlive the executable graph)
+    if (exec_ || graph_) BWR_HIP(hipStreamSynchronize(st_));
     if (exec_) (void)hipGraphExecDestroy(exec_);
     if (graph_) (void)hipGraphDestroy(graph_);
     exec_ = nullptr;

@@ -5,6 +5,7 @@
 #include "engine.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -33,14 +34,27 @@ Error Error::device(hipError_t e, const char* where) {
         if (!er_.ok()) return er_;    \
     } while (0)
 
+namespace {
+thread_local Arena* t_arena = nullptr;
+std::atomic<int64_t> g_device_allocs{0};  // hipMallocAsync calls made by DevBuf
+}  // namespace
+
+int64_t device_allocations() { return g_device_allocs.load(); }
+
+ArenaScope::ArenaScope(Arena* a) : prev_(t_arena) { t_arena = a; }
+ArenaScope::~ArenaScope() { t_arena = prev_; }
+Arena* current_arena() { return t_arena; }
+
 DevBuf& DevBuf::operator=(DevBuf&& o) noexcept {
     if (this != &o) {
         release();
         ptr_ = o.ptr_;
         bytes_ = o.bytes_;
         st_ = o.st_;
+        arena_ = o.arena_;
         o.ptr_ = nullptr;
         o.bytes_ = 0;
+        o.arena_ = nullptr;
     }
     return *this;
 }
@@ -50,6 +64,21 @@ Error DevBuf::alloc(size_t bytes, hipStream_t st) {
     st_ = st;
     bytes_ = bytes;
     if (bytes == 0) return {};
+    if (Arena* a = t_arena) {
+        const size_t off = (a->used + 255) & ~(size_t)255;
+        const size_t want = (bytes + 255) & ~(size_t)255;
+        if (off + want > a->size) {
+            bytes_ = 0;
+            return {ENOMEM_, "workspace too small: " + std::to_string(off + want) + " bytes needed so far, " +
+                                 std::to_string(a->size) + " given"};
+        }
+        ptr_ = a->base + off;
+        a->used = off + want;
+        a->peak = std::max(a->peak, a->used);
+        arena_ = a;
+        return {};
+    }
+    g_device_allocs.fetch_add(1);
     hipError_t e = hipMallocAsync(&ptr_, bytes, st);
     if (e != hipSuccess) {
         ptr_ = nullptr;
@@ -61,9 +90,16 @@ Error DevBuf::alloc(size_t bytes, hipStream_t st) {
 }
 
 void DevBuf::release() {
-    if (ptr_) (void)hipFreeAsync(ptr_, st_);
+    if (ptr_ && arena_) {
+        // the topmost carving returns its bytes (stream order keeps earlier readers ahead of later writers)
+        const size_t want = (bytes_ + 255) & ~(size_t)255;
+        if ((char*)ptr_ + want == arena_->base + arena_->used) arena_->used = (size_t)((char*)ptr_ - arena_->base);
+    } else if (ptr_) {
+        (void)hipFreeAsync(ptr_, st_);
+    }
     ptr_ = nullptr;
     bytes_ = 0;
+    arena_ = nullptr;
 }
 
 int padded_width(int32_t s) {
@@ -134,7 +170,7 @@ Error encode_plain(const CsrView& A, uint32_t p, hipStream_t st, DeviceMatrix* M
         BWR_TRY(M->val_t.alloc(sizeof(uint32_t) * nnz, st));
     }
     if (A.m == 0) {
-        BWR_HIP(hipMemsetAsync(M->rp_a.as<int32_t>(), 0, sizeof(int32_t), st));
+        BWR_HIP(launch_fill_zero(M->rp_a.as<int32_t>(), sizeof(int32_t), st));
     } else if (M->packed) {
         BWR_HIP(launch_pack_rows(A.m, A.row_ptr, A.col_idx, A.val, M->rp_a.as<int32_t>(), M->ent_a.as<uint32_t>(), st));
     } else {
@@ -148,8 +184,8 @@ Error encode_plain(const CsrView& A, uint32_t p, hipStream_t st, DeviceMatrix* M
     BWR_TRY(cursor.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(A.n, 1), st));
     BWR_TRY(tmp.alloc(sizeof(int32_t) * (size_t)scan_tmp_words(A.n), st));
     BWR_TRY(mx.alloc(sizeof(int32_t), st));
-    BWR_HIP(hipMemsetAsync(cnt.as<int32_t>(), 0, sizeof(int32_t) * (size_t)std::max<int64_t>(A.n, 1), st));
-    BWR_HIP(hipMemsetAsync(cursor.as<int32_t>(), 0, sizeof(int32_t) * (size_t)std::max<int64_t>(A.n, 1), st));
+    BWR_HIP(launch_fill_zero(cnt.as<int32_t>(), sizeof(int32_t) * (size_t)std::max<int64_t>(A.n, 1), st));
+    BWR_HIP(launch_fill_zero(cursor.as<int32_t>(), sizeof(int32_t) * (size_t)std::max<int64_t>(A.n, 1), st));
     BWR_HIP(launch_col_count(A.m, A.row_ptr, A.col_idx, cnt.as<int32_t>(), st));
     BWR_HIP(launch_exclusive_scan(A.n, cnt.as<int32_t>(), M->rp_t.as<int32_t>(), tmp.as<int32_t>(), st));
     if (M->packed) {
@@ -514,8 +550,8 @@ hipError_t first_product(const DeviceMatrix& M, const Operand& op1, const SplitO
                          const TiledOp* to = nullptr) {
     const bool smallp = mp.p <= 65536u;
     if (to && to->on)
-        return launch_spmm_tiled(to->v, pl.W, false, !smallp, pl.esize, X, dr, Y, nullptr, nullptr, pl.t1.grid, mp,
-                                 st);
+        return launch_spmm_tiled(to->v, pl.W, 0, !smallp, pl.esize, X, dr, Y, nullptr, nullptr, nullptr, pl.t1.grid,
+                                 mp, st);
     if (so && so->on) {
         hipError_t e = launch_spmm_split(pl.W, G, false, acc_mode(M, op1.max_len, mp.p, G), smallp, pl.esize,
                                          op1.rows, so->p0.rp, so->p0.ent, X, nullptr, nullptr, nullptr, nullptr, 0, mp,
@@ -535,7 +571,8 @@ hipError_t second_product(const DeviceMatrix& M, const Operand& op2, const Split
                           const void* Ut, uint32_t* partial, hipStream_t st, const TiledOp* to = nullptr) {
     const bool smallp = mp.p <= 65536u;
     if (to && to->on)
-        return launch_spmm_tiled(to->v, pl.W, true, !smallp, pl.esize, Yin, dc2, Z, Ut, partial, pl.t2.grid, mp, st);
+        return launch_spmm_tiled(to->v, pl.W, 1, !smallp, pl.esize, Yin, dc2, Z, Ut, nullptr, partial, pl.t2.grid, mp,
+                                 st);
     if (so && so->on) {
         hipError_t e = launch_spmm_split(pl.W, G, false, acc_mode(M, op2.max_len, mp.p, G), smallp, pl.esize,
                                          op2.rows, so->p0.rp, so->p0.ent, Yin, nullptr, nullptr, nullptr, nullptr, 0,
@@ -638,7 +675,21 @@ int64_t fused_nb_cap(int W, int64_t want) {
     return std::max<int64_t>(1, std::min<int64_t>(want, FUSED_PARTIAL_WORDS / ((int64_t)W * W)));
 }
 
-StepPlan plan_step(const DeviceMatrix& M, bool transpose, int32_t s, uint32_t p) {
+size_t sequence_workspace_bytes(int64_t m, int64_t n, int64_t nnz, int32_t s, bool transpose) {
+    const int W = padded_width(s);
+    if (!W || m < 0 || n < 0 || nnz < 0) return 0;
+    const int64_t nb = transpose ? m : n, outer = transpose ? n : m;
+    // encode_matrix with the length-sorted relabelling: the first encoding, the relabelled CSR copy, the second
+    // encoding and its counters (wide residues included): at most 40 nnz + 20 m + 24 n bytes and a few KB
+    const int64_t enc = 40 * nnz + 24 * (m + n) + (64 << 10);
+    // run_sequence: gathered U, V, D_c, D_r; U~, X_0, X_1 (nb x W) and Y (outer x W) of at most 4-byte residues;
+    // the reduced diagonals; ARENA_CHUNK steps of projection partials (at most max(2^19, 512 W^2) words a step)
+    const int64_t blocks = 8 * nb * s + 8 * nb + 8 * outer + 4 * (int64_t)W * (3 * nb + outer);
+    const int64_t part = 4 * std::max<int64_t>(524288, 512LL * W * W) * ARENA_CHUNK;
+    return (size_t)(enc + blocks + part + 64 * 256);
+}
+
+StepPlan plan_step(const DeviceMatrix& M, bool transpose, int32_t s, uint32_t p, bool allow_tiled) {
     StepPlan pl;
     pl.W = padded_width(s);
     Operand op1, op2;
@@ -666,7 +717,7 @@ StepPlan plan_step(const DeviceMatrix& M, bool transpose, int32_t s, uint32_t p)
         pl.NB = proj_blocks(nb, pl.W);
     }
     // BWR_TILED=1: both products tiled (first geometry of tile_candidates) wherever the encoding allows it
-    if (env_int("BWR_TILED", -1) == 1 && pl.G1 > 0 && pl.G2 > 0) {
+    if (allow_tiled && env_int("BWR_TILED", -1) == 1 && pl.G1 > 0 && pl.G2 > 0) {
         const bool split = p > 65536u;
         if (tiled_acc_ok(M, op1.max_len, p)) {
             auto c = tile_candidates(op1.rows, nb, pl.W, pl.esize, split, false, M.max_abs);
@@ -703,9 +754,9 @@ Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl
                                                  (int64_t)proj_blocks(nb, W) * W * W);
     BWR_TRY(part.alloc(sizeof(uint32_t) * (size_t)part_words, st));
     // timing inputs: contents do not change the memory traffic
-    BWR_HIP(hipMemsetAsync(X.as<void>(), 0, X.bytes(), st));
-    BWR_HIP(hipMemsetAsync(U.as<void>(), 0, U.bytes(), st));
-    BWR_HIP(hipMemsetAsync(Y.as<void>(), 0, Y.bytes(), st));
+    BWR_HIP(launch_fill_zero(X.as<void>(), X.bytes(), st));
+    BWR_HIP(launch_fill_zero(U.as<void>(), U.bytes(), st));
+    BWR_HIP(launch_fill_zero(Y.as<void>(), Y.bytes(), st));
     // two-dimensional tiled candidates for matrices of at least 2^20 non-zeros (BWR_TILED=0: none)
     const bool split = !smallp;
     const bool tiles_on = M.packed && M.nnz >= (1 << 20) && env_int("BWR_TILED", -1) != 0;
@@ -737,8 +788,8 @@ Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl
         for (size_t i = 0; i < tc1.size(); ++i) {
             gs.push_back(-1 - (int)i);
             runs.push_back([&, i]() -> Error {
-                hipError_t e = launch_spmm_tiled(to1[i].v, W, false, split, pl->esize, X.as<void>(), nullptr,
-                                                 Y.as<void>(), nullptr, nullptr, tc1[i].grid, mp, st);
+                hipError_t e = launch_spmm_tiled(to1[i].v, W, 0, split, pl->esize, X.as<void>(), nullptr,
+                                                 Y.as<void>(), nullptr, nullptr, nullptr, tc1[i].grid, mp, st);
                 return e == hipSuccess ? Error{} : Error::device(e, "autotune (tiled)");
             });
         }
@@ -801,8 +852,9 @@ Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl
         for (size_t i = 0; i < tc2.size(); ++i) {
             cs.push_back({-1 - (int)i, tc2[i].grid, true});
             runs.push_back([&, i]() -> Error {
-                hipError_t e = launch_spmm_tiled(to2[i].v, W, true, split, pl->esize, Y.as<void>(), nullptr,
-                                                 Z.as<void>(), U.as<void>(), part.as<uint32_t>(), tc2[i].grid, mp, st);
+                hipError_t e = launch_spmm_tiled(to2[i].v, W, 1, split, pl->esize, Y.as<void>(), nullptr,
+                                                 Z.as<void>(), U.as<void>(), nullptr, part.as<uint32_t>(), tc2[i].grid,
+                                                 mp, st);
                 return e == hipSuccess ? Error{} : Error::device(e, "autotune (tiled)");
             });
         }
@@ -905,6 +957,142 @@ Error tuned_plan(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl, h
 
 }  // namespace
 
+namespace {
+
+// The symmetric sequence in Gram form (symmetric.hip): S_0 = X_0^T D_c^-2 X_0, then per application of B the
+// terms S_2k+1 = Y_k^T D_r^-1 Y_k (from the first product's output) and S_2k+2 = X_k+1^T D_c^-2 X_k+1 (from the
+// second's); the products run without a fused projection.  Chunks of CH applications are captured as one HIP
+// graph and replayed, like the plain sequence.
+Error gram_sequence(const SequenceArgs& a, const DeviceMatrix& M, const Operand& op1, const Operand& op2,
+                    const StepPlan& pl, const SplitOp* so1, const SplitOp* so2, const TiledOp* to1, const TiledOp* to2,
+                    void* X0, void* X1, void* Y, const uint32_t* drp, const uint32_t* dc2p, const uint32_t* aDr,
+                    const uint32_t* aDc, int32_t* flag, hipStream_t st) {
+    const int W = pl.W;
+    const int64_t nb = op2.rows, outer = op1.rows;
+    const ModP mp = a.mp;
+    const bool smallp = mp.p <= 65536u;
+    const int64_t E = (int64_t)W * W;
+    DevBuf w1, w2, part, part0;
+    BWR_TRY(w1.alloc(sizeof(uint32_t) * (size_t)std::max<int64_t>(outer, 1), st));
+    BWR_TRY(w2.alloc(sizeof(uint32_t) * (size_t)std::max<int64_t>(nb, 1), st));
+    BWR_HIP(launch_inv_diag(outer, aDr, mp, 1, w1.as<uint32_t>(), st));
+    BWR_HIP(launch_inv_diag(nb, aDc, mp, 2, w2.as<uint32_t>(), st));
+    // partial blocks of each product's Gram term: the tiled kernels form it in their epilogue (one partial per
+    // workgroup), the others through k_gram
+    const bool t1 = to1 && to1->on, t2 = to2 && to2->on;
+    const int NBg = std::max(proj_blocks(std::max<int64_t>(nb, 1), W), proj_blocks(std::max<int64_t>(outer, 1), W));
+    const int nb1 = t1 ? pl.t1.grid : NBg, nb2 = t2 ? pl.t2.grid : NBg;
+    const int64_t P = (int64_t)(nb1 + nb2) * E;  // partial words per application
+    int64_t CH = current_arena() ? ARENA_CHUNK : 128;  // applications per chunk (2 CH terms)
+    CH = std::max<int64_t>(2, std::min<int64_t>(CH, (int64_t)((256u << 20) / (P * 4))) & ~(int64_t)1);
+    BWR_TRY(part.alloc(sizeof(uint32_t) * (size_t)(P * CH), st));
+    BWR_TRY(part0.alloc(sizeof(uint32_t) * (size_t)(NBg * E), st));
+    uint32_t* slots = part.as<uint32_t>();
+    // S_0 = X_0^T D_c^-2 X_0
+    if (nb > 0) {
+        BWR_HIP(launch_gram(W, smallp, nb, X0, pl.esize, w2.as<uint32_t>(), part0.as<uint32_t>(), NBg, mp, st));
+    } else {
+        BWR_HIP(launch_fill_zero(part0.as<void>(), sizeof(uint32_t) * (size_t)(NBg * E), st));
+    }
+    BWR_HIP(launch_reduce_partials(W, a.s, NBg, 1, part0.as<uint32_t>(), a.S_out, mp, st));
+    BWR_HIP(launch_mirror(1, a.s, a.S_out, st));
+    if (a.progress) BWR_TRY(a.progress(1));
+    // one application: S_2k+1 from the first product's output, S_2k+2 from the second's
+    auto app = [&](const void* cur, void* nxt, uint32_t* slot) -> Error {
+        hipError_t e;
+        if (t1) {
+            e = launch_spmm_tiled(to1->v, W, 2, !smallp, pl.esize, cur, drp, Y, nullptr, w1.as<uint32_t>(), slot,
+                                  pl.t1.grid, mp, st);
+        } else {
+            if (pl.G1 > 0)
+                e = first_product(M, op1, so1, pl.G1, pl, mp, cur, drp, Y, st, nullptr);
+            else
+                e = spmm(M, op1, W, mp, (const uint32_t*)cur, drp, (uint32_t*)Y, st).ok() ? hipSuccess
+                                                                                          : hipErrorUnknown;
+            if (e == hipSuccess) e = launch_gram(W, smallp, outer, Y, pl.esize, w1.as<uint32_t>(), slot, NBg, mp, st);
+        }
+        if (e != hipSuccess) return Error::device(e, "gram step (first product)");
+        uint32_t* slot2 = slot + (size_t)nb1 * E;
+        if (t2) {
+            e = launch_spmm_tiled(to2->v, W, 2, !smallp, pl.esize, Y, dc2p, nxt, nullptr, w2.as<uint32_t>(), slot2,
+                                  pl.t2.grid, mp, st);
+        } else {
+            if (pl.G2 > 0)
+                e = second_product(M, op2, so2, pl.G2, false, 0, pl, mp, Y, dc2p, nxt, nullptr, nullptr, st);
+            else
+                e = spmm(M, op2, W, mp, (const uint32_t*)Y, dc2p, (uint32_t*)nxt, st).ok() ? hipSuccess
+                                                                                           : hipErrorUnknown;
+            if (e == hipSuccess) e = launch_gram(W, smallp, nb, nxt, pl.esize, w2.as<uint32_t>(), slot2, NBg, mp, st);
+        }
+        if (e != hipSuccess) return Error::device(e, "gram step (second product)");
+        return {};
+    };
+    void* cur = X0;
+    void* nxt = X1;
+    const bool use_graph = env_int("BWR_NO_GRAPH", 0) == 0 && nb > 0 && (a.len - 1) >= 4 * CH;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    Error err;
+    for (int64_t t = 1; t < a.len && err.ok();) {
+        const int64_t apps = std::min<int64_t>(CH, (a.len - t + 1) / 2);
+        if (use_graph && apps == CH) {
+            if (!exec) {
+                hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+                if (e != hipSuccess) {
+                    err = Error::device(e, "hipStreamBeginCapture");
+                    break;
+                }
+                for (int64_t i = 0; i < CH && err.ok(); ++i) {
+                    err = app(cur, nxt, slots + P * i);
+                    std::swap(cur, nxt);
+                }
+                e = hipStreamEndCapture(st, &graph);
+                if (err.ok() && e != hipSuccess) err = Error::device(e, "hipStreamEndCapture");
+                if (err.ok()) {
+                    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                    if (e != hipSuccess) err = Error::device(e, "hipGraphInstantiate");
+                }
+                if (!err.ok()) break;
+            }
+            const hipError_t e = hipGraphLaunch(exec, st);
+            if (e != hipSuccess) {
+                err = Error::device(e, "hipGraphLaunch");
+                break;
+            }
+        } else {
+            for (int64_t i = 0; i < apps && err.ok(); ++i) {
+                err = app(cur, nxt, slots + P * i);
+                std::swap(cur, nxt);
+            }
+            if (!err.ok()) break;
+        }
+        // terms t, t + 2, ... from the first products; t + 1, t + 3, ... from the second
+        const int64_t nterms = std::min<int64_t>(2 * apps, a.len - t);
+        uint32_t* out = a.S_out + (size_t)t * a.s * a.s;
+        hipError_t e = launch_reduce_partials(W, a.s, nb1, (nterms + 1) / 2, slots, out, mp, st, P, 2);
+        if (e == hipSuccess)
+            e = launch_reduce_partials(W, a.s, nb2, nterms / 2, slots + (size_t)nb1 * E, out + (size_t)a.s * a.s, mp,
+                                       st, P, 2);
+        if (e == hipSuccess) e = launch_mirror(nterms, a.s, out, st);
+        if (e != hipSuccess) err = Error::device(e, "gram reduce");
+        t += nterms;
+        if (err.ok() && a.progress) err = a.progress(t);
+    }
+    int32_t bad = 0;
+    hipError_t he = hipSuccess;
+    if (err.ok()) he = hipMemcpyAsync(&bad, flag, sizeof(bad), hipMemcpyDeviceToHost, st);
+    const hipError_t hs = hipStreamSynchronize(st);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (!err.ok()) return err;
+    if (he != hipSuccess) return Error::device(he, "hipMemcpyAsync");
+    if (hs != hipSuccess) return Error::device(hs, "hipStreamSynchronize");
+    if (bad) return Error::inval("d_col has an entry divisible by p");
+    return {};
+}
+
+}  // namespace
+
 Error run_sequence(const SequenceArgs& a, hipStream_t st) {
     const DeviceMatrix& M = *a.M;
     if (!M.packed && M.wide_p != a.mp.p) return Error::inval("matrix was encoded for another prime");
@@ -918,10 +1106,14 @@ Error run_sequence(const SequenceArgs& a, hipStream_t st) {
     const ModP mp = a.mp;
     const bool smallp = mp.p <= 65536u;
 
-    StepPlan pl = plan_step(M, a.transpose, a.s, mp.p);
-    if (a.len >= 64 && M.nnz >= 100000 && env_int("BWR_NO_TUNE", 0) == 0 && getenv("BWR_G1") == nullptr &&
+    // inside an arena (caller workspace, or the entry point that allocates nothing): the heuristic row-split
+    // plan, no tuning trials and no tiled encodings, whose buffers sequence_workspace_bytes bounds
+    const bool in_arena = current_arena() != nullptr;
+    StepPlan pl = plan_step(M, a.transpose, a.s, mp.p, !in_arena);
+    if (!in_arena && a.len >= 64 && M.nnz >= 100000 && env_int("BWR_NO_TUNE", 0) == 0 && getenv("BWR_G1") == nullptr &&
         getenv("BWR_G2") == nullptr && env_int("BWR_TILED", -1) != 1)
         BWR_TRY(tuned_plan(M, a.transpose, mp, &pl, st));
+    if (in_arena) pl.parts1 = pl.parts2 = 1;
     if (a.plan_out) *a.plan_out = pl;
 
     const size_t es = (size_t)pl.esize;
@@ -933,15 +1125,17 @@ Error run_sequence(const SequenceArgs& a, hipStream_t st) {
     const TiledOp* to2 = nullptr;
     if (pl.t1.R > 0) {
         BWR_TRY(get_tiled(M, op1, nb, pl.t1, st, &own1, &to1));
-        BWR_HIP(prepare_spmm_tiled(to1->v, W, false, !smallp, pl.esize));
+        BWR_HIP(prepare_spmm_tiled(to1->v, W, 0, !smallp, pl.esize));
+        BWR_HIP(prepare_spmm_tiled(to1->v, W, 2, !smallp, pl.esize));
     }
     if (pl.t2.R > 0) {
         BWR_TRY(get_tiled(M, op2, outer, pl.t2, st, &own2, &to2));
-        BWR_HIP(prepare_spmm_tiled(to2->v, W, true, !smallp, pl.esize));
+        BWR_HIP(prepare_spmm_tiled(to2->v, W, 1, !smallp, pl.esize));
+        BWR_HIP(prepare_spmm_tiled(to2->v, W, 2, !smallp, pl.esize));
     }
     // a length-sorted encoding works in relabelled coordinates: U, V, D_c (iterated side) and D_r (other
     // side) are gathered into that order, which leaves every S_k unchanged
-    const uint32_t* aU = a.U;
+    const uint32_t* aU = a.symmetric ? a.V : a.U;
     const uint32_t* aV = a.V;
     const uint32_t* aDr = a.d_row;
     const uint32_t* aDc = a.d_col;
@@ -952,7 +1146,7 @@ Error run_sequence(const SequenceArgs& a, hipStream_t st) {
         if (nb > 0) {
             BWR_TRY(gU.alloc(sizeof(uint32_t) * (size_t)(nb * a.s), st));
             BWR_TRY(gV.alloc(sizeof(uint32_t) * (size_t)(nb * a.s), st));
-            BWR_HIP(launch_gather_rows(nb, a.s, pn, a.U, gU.as<uint32_t>(), st));
+            BWR_HIP(launch_gather_rows(nb, a.s, pn, aU, gU.as<uint32_t>(), st));
             BWR_HIP(launch_gather_rows(nb, a.s, pn, a.V, gV.as<uint32_t>(), st));
             aU = gU.as<uint32_t>();
             aV = gV.as<uint32_t>();
@@ -974,7 +1168,7 @@ Error run_sequence(const SequenceArgs& a, hipStream_t st) {
     BWR_TRY(X1.alloc(es * (size_t)(nb * W), st));
     BWR_TRY(Y.alloc(es * (size_t)std::max<int64_t>(outer * W, 1), st));
     BWR_TRY(flag.alloc(sizeof(int32_t), st));
-    BWR_HIP(hipMemsetAsync(flag.as<int32_t>(), 0, sizeof(int32_t), st));
+    BWR_HIP(launch_fill_zero(flag.as<int32_t>(), sizeof(int32_t), st));
     const uint32_t* drp = nullptr;
     const uint32_t* dc2p = nullptr;
     if (aDr && outer > 0) {
@@ -992,18 +1186,21 @@ Error run_sequence(const SequenceArgs& a, hipStream_t st) {
     BWR_HIP(launch_pad_scale(nb, a.s, W, aV, aDc, aDc ? 1 : 0, mp, X0.as<void>(), pl.esize, st));
 
     const size_t per_step = (size_t)pl.NB * W * W;
-    int64_t CH = 256;
+    int64_t CH = in_arena ? ARENA_CHUNK : 256;
     CH = std::max<int64_t>(2, std::min<int64_t>(CH, (int64_t)((256u << 20) / (per_step * 4))) & ~(int64_t)1);
     BWR_TRY(part.alloc(sizeof(uint32_t) * per_step * (size_t)CH, st));
     uint32_t* slots = part.as<uint32_t>();
     Bufs bufs{drp, dc2p, Ut.as<void>(), Y.as<void>()};
 
+    if (a.symmetric && a.gram) return gram_sequence(a, M, op1, op2, pl, &so1, &so2, to1, to2, X0.as<void>(),
+                                                    X1.as<void>(), Y.as<void>(), drp, dc2p, aDr, aDc, flag.as<int32_t>(),
+                                                    st);
     // S_0
     if (nb > 0) {
         hipError_t e = launch_project(W, smallp, nb, Ut.as<void>(), X0.as<void>(), pl.esize, slots, pl.NB, mp, st);
         if (e != hipSuccess) return Error::device(e, "project launch");
     } else {
-        BWR_HIP(hipMemsetAsync(slots, 0, sizeof(uint32_t) * per_step, st));
+        BWR_HIP(launch_fill_zero(slots, sizeof(uint32_t) * per_step, st));
     }
     BWR_HIP(launch_reduce_partials(W, a.s, pl.NB, 1, slots, a.S_out, mp, st));
     if (a.progress) BWR_TRY(a.progress(1));
@@ -1054,13 +1251,29 @@ Error run_sequence(const SequenceArgs& a, hipStream_t st) {
         k += cnt;
         if (err.ok() && a.progress) err = a.progress(k);
     }
+    // the graph is destroyed only once its launches have run: a launch in flight (and a tracer that inspects
+    // its dispatches when they complete) must not outlive the executable graph
+    // the symmetric projection's check: every term V^T B^k V must be symmetric (bit 2 of the flag)
+    DevBuf symflag;
+    if (err.ok() && a.symmetric) {
+        hipError_t e = symflag.alloc(sizeof(int32_t), st).ok() ? launch_fill_zero(symflag.as<void>(), 4, st)
+                                                                : hipErrorOutOfMemory;
+        if (e == hipSuccess) e = launch_sym_check(a.len, a.s, a.S_out, symflag.as<int32_t>(), st);
+        if (e != hipSuccess) err = Error::device(e, "symmetry check");
+    }
+    int32_t bad = 0, asym = 0;
+    hipError_t he = hipSuccess;
+    if (err.ok()) he = hipMemcpyAsync(&bad, flag.as<int32_t>(), sizeof(bad), hipMemcpyDeviceToHost, st);
+    if (err.ok() && he == hipSuccess && a.symmetric)
+        he = hipMemcpyAsync(&asym, symflag.as<int32_t>(), sizeof(asym), hipMemcpyDeviceToHost, st);
+    const hipError_t hs = hipStreamSynchronize(st);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (!err.ok()) return err;
-    int32_t bad = 0;
-    BWR_HIP(hipMemcpyAsync(&bad, flag.as<int32_t>(), sizeof(bad), hipMemcpyDeviceToHost, st));
-    BWR_HIP(hipStreamSynchronize(st));
+    if (he != hipSuccess) return Error::device(he, "hipMemcpyAsync");
+    if (hs != hipSuccess) return Error::device(hs, "hipStreamSynchronize");
     if (bad) return Error::inval("d_col has an entry divisible by p");
+    if (asym) return Error::device(hipErrorUnknown, "symmetric projection check: a term V^T B^k V is not symmetric");
     return {};
 }
 
@@ -1097,15 +1310,15 @@ Error apply_once(const DeviceMatrix& M, bool transpose, ModP mp, int32_t s, cons
     if (tiled && tiled_acc_ok(M, op1.max_len, mp.p)) {
         auto c = tile_candidates(op1.rows, nb, W, 4, split, false, M.max_abs);
         if (!c.empty()) BWR_TRY(build_tiled(op1, nb, M.nnz, M.max_abs, c[0], st, &to1));
-        if (to1.on) BWR_HIP(launch_spmm_tiled(to1.v, W, false, split, 4, Xp.as<void>(), drp, Y.as<void>(), nullptr,
-                                              nullptr, c[0].grid, mp, st));
+        if (to1.on) BWR_HIP(launch_spmm_tiled(to1.v, W, 0, split, 4, Xp.as<void>(), drp, Y.as<void>(), nullptr,
+                                              nullptr, nullptr, c[0].grid, mp, st));
     }
     if (!to1.on) BWR_TRY(spmm(M, op1, W, mp, Xp.as<uint32_t>(), drp, Y.as<uint32_t>(), st));
     if (tiled && tiled_acc_ok(M, op2.max_len, mp.p)) {
         auto c = tile_candidates(op2.rows, outer, W, 4, split, false, M.max_abs);
         if (!c.empty()) BWR_TRY(build_tiled(op2, outer, M.nnz, M.max_abs, c[0], st, &to2));
-        if (to2.on) BWR_HIP(launch_spmm_tiled(to2.v, W, false, split, 4, Y.as<void>(), dcp, Zp.as<void>(), nullptr,
-                                              nullptr, c[0].grid, mp, st));
+        if (to2.on) BWR_HIP(launch_spmm_tiled(to2.v, W, 0, split, 4, Y.as<void>(), dcp, Zp.as<void>(), nullptr,
+                                              nullptr, nullptr, c[0].grid, mp, st));
     }
     if (!to2.on) BWR_TRY(spmm(M, op2, W, mp, Y.as<uint32_t>(), dcp, Zp.as<uint32_t>(), st));
     BWR_HIP(launch_unpad(nb, s, W, Zp.as<void>(), 4, Z, st));

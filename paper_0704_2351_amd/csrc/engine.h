@@ -24,7 +24,29 @@ struct Error {
     static Error device(hipError_t e, const char* where);
 };
 
-// Device buffer owned by the library (freed on destruction, stream-ordered).
+// A device region that DevBuf::alloc carves from, instead of allocating, while it is installed on the calling
+// thread (ArenaScope): the caller-workspace entry points and the entry point that allocates nothing.  Carving
+// is a bump of `used` (256-byte aligned); a buffer released while it is the topmost one gives its bytes back.
+struct Arena {
+    char* base = nullptr;
+    size_t size = 0, used = 0, peak = 0;
+};
+class ArenaScope {
+   public:
+    explicit ArenaScope(Arena* a);
+    ~ArenaScope();
+    ArenaScope(const ArenaScope&) = delete;
+    ArenaScope& operator=(const ArenaScope&) = delete;
+
+   private:
+    Arena* prev_;
+};
+Arena* current_arena();
+// device allocations the library has made so far (every DevBuf that did not come from an arena)
+int64_t device_allocations();
+
+// Device buffer owned by the library (freed on destruction, stream-ordered), or carved from the installed
+// arena.
 class DevBuf {
    public:
     DevBuf() = default;
@@ -45,6 +67,7 @@ class DevBuf {
     void* ptr_ = nullptr;
     size_t bytes_ = 0;
     hipStream_t st_ = nullptr;
+    Arena* arena_ = nullptr;  // set when carved from an arena
 };
 
 struct TiledStore;  // tiled encodings kept with a matrix (engine.cpp)
@@ -142,6 +165,11 @@ struct SequenceArgs {
     // optional: called from the enqueueing thread each time the reductions of the terms
     // S_0 .. S_{t-1} have been enqueued on the sequence stream (t increasing, last t = len)
     std::function<Error(int64_t t)> progress;
+    // Symmetric projection U = V (U is ignored): S_k = V^T B^k V (Section 2.3), every term checked to be
+    // symmetric after the run (an error otherwise).  With gram, two terms per application of B through the
+    // weighted Gram identities of symmetric.hip (terms exact, symmetric by construction; not in the paper).
+    bool symmetric = false;
+    bool gram = false;
 };
 
 Error run_sequence(const SequenceArgs& a, hipStream_t st);
@@ -161,7 +189,16 @@ Error time_step_kernels(const DeviceMatrix& M, bool transpose, ModP mp, int32_t 
                         double us[3], StepPlan* plan_out = nullptr);
 
 // Heuristic plan, and its refinement by timing every valid split factor on M.
-StepPlan plan_step(const DeviceMatrix& M, bool transpose, int32_t s, uint32_t p);
+// allow_tiled = false: only the row-split kernels (the plan used inside an arena, whose memory need has a
+// closed form: sequence_workspace_bytes).
+StepPlan plan_step(const DeviceMatrix& M, bool transpose, int32_t s, uint32_t p, bool allow_tiled = true);
+
+// Device bytes an arena must hold for encode_matrix (sorted) plus run_sequence on an m x n matrix with nnz
+// entries, block s, B on the n side (transpose = false) or the m side: an upper bound, counted from the
+// buffers those functions carve (see engine.cpp).
+size_t sequence_workspace_bytes(int64_t m, int64_t n, int64_t nnz, int32_t s, bool transpose);
+// Steps per chunk of partial sums inside an arena.
+constexpr int64_t ARENA_CHUNK = 16;
 Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl, hipStream_t st);
 
 }  // namespace bwr

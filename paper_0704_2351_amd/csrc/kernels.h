@@ -78,6 +78,8 @@ hipError_t launch_unpad(int64_t n, int32_t s, int32_t W, const void* in, int esi
 hipError_t launch_square_diag(int64_t n, const uint32_t* d, ModP mp, uint32_t* d2, int32_t* bad, hipStream_t st);
 // reduce an arbitrary uint32 diagonal into [0, p)
 hipError_t launch_reduce_vec(int64_t n, const uint32_t* in, ModP mp, uint32_t* out, hipStream_t st);
+// bytes of zeros at p: a kernel, so that code a caller may capture in a graph records no memset node
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 
 // Y[r] = scale[r] * sum_t a_rt X[col_t]  (mod p), for r < nrows.  scale may be null (1).
 // acc32: the caller guarantees max_len * max|a| * (p - 1) < 2^31 and p <= 2^16.
@@ -90,9 +92,10 @@ hipError_t launch_spmm_wide(int W, int64_t nrows, const int32_t* rp, const int32
 int proj_blocks(int64_t n, int W);
 hipError_t launch_project(int W, bool smallp, int64_t n, const void* U, const void* X, int esize, uint32_t* partial,
                           int nblocks, ModP mp, hipStream_t st);
-// S[k][i][j] (i, j < s) = sum_b partial[k][b][i * W + j] mod p, for k < nsteps.
+// S[k sstride][i][j] (i, j < s) = sum_b partial[k pstride + b W^2 + i W + j] mod p, for k < nsteps
+// (pstride 0: nblocks W^2, the partials of consecutive steps back to back).
 hipError_t launch_reduce_partials(int W, int32_t s, int nblocks, int64_t nsteps, const uint32_t* partial, uint32_t* S,
-                                  ModP mp, hipStream_t st);
+                                  ModP mp, hipStream_t st, int64_t pstride = 0, int64_t sstride = 1);
 
 }  // namespace bwr
 
@@ -136,11 +139,25 @@ hipError_t launch_tiled_build(int64_t rows, int64_t nrb, const int32_t* rp, cons
 // Y = scale * (T X) mod p over the tiled operand T, grid persistent workgroups (one row block at a time).
 // split: residues summed as 16-bit halves (required exactly when p > 2^16; the caller guarantees
 // max row length * max |a| * 65535 < 2^31), else int32 sums (max row length * max |a| * (p - 1) < 2^31).
-// With proj, partial[b][i * W + j] (b < grid) = the workgroup's share of sum_r U[r][i] Y[r][j] mod p.
-hipError_t launch_spmm_tiled(const TiledOperand& t, int W, bool proj, bool split, int esize, const void* X,
-                             const uint32_t* scale, void* Y, const void* U, uint32_t* partial, int grid, ModP mp,
-                             hipStream_t st);
+// pmode 1: partial[b][i * W + j] (b < grid) = the workgroup's share of sum_r U[r][i] Y[r][j] mod p; pmode 2: of
+// sum_r wgt[r] Y[r][i] Y[r][j] (the Gram form of the symmetric projection); pmode 0: no partials.
+hipError_t launch_spmm_tiled(const TiledOperand& t, int W, int pmode, bool split, int esize, const void* X,
+                             const uint32_t* scale, void* Y, const void* U, const uint32_t* wgt, uint32_t* partial,
+                             int grid, ModP mp, hipStream_t st);
 // Raises the dynamic-LDS limit of the kernel that launch_spmm_tiled would launch (done by every launch too;
 // call it before a graph capture that will hold the first launch).
-hipError_t prepare_spmm_tiled(const TiledOperand& t, int W, bool proj, bool split, int esize);
+hipError_t prepare_spmm_tiled(const TiledOperand& t, int W, int pmode, bool split, int esize);
+}  // namespace bwr
+
+namespace bwr {
+// Symmetric projection U = V (symmetric.hip).  Weighted Gram partials: partial[b][i W + j] = sum over the rows of
+// block b of w[r] X[r][i] X[r][j] mod p for i <= j, 0 for i > j (w null: weight 1; X: esize-byte residues).
+hipError_t launch_gram(int W, bool smallp, int64_t n, const void* X, int esize, const uint32_t* w, uint32_t* partial,
+                       int nblocks, ModP mp, hipStream_t st);
+// S[k][j][i] = S[k][i][j] for i < j (k < nsteps).
+hipError_t launch_mirror(int64_t nsteps, int32_t s, uint32_t* S, hipStream_t st);
+// *bad |= 1 when some S[k][i][j] != S[k][j][i] (k < nsteps).
+hipError_t launch_sym_check(int64_t nsteps, int32_t s, const uint32_t* S, int32_t* bad, hipStream_t st);
+// out[r] = d[r]^-power mod p (power 1 or 2), 0 where d[r] = 0 mod p; d null: all 1.
+hipError_t launch_inv_diag(int64_t n, const uint32_t* d, ModP mp, int power, uint32_t* out, hipStream_t st);
 }  // namespace bwr

@@ -16,6 +16,8 @@
 // accumulators when max_len * max|a| * (p-1) < 2^31 (16-bit primes), int64
 // otherwise, and one Barrett reduction per output element.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <stdint.h>
 
 #include <type_traits>
@@ -283,6 +285,13 @@ __global__ __launch_bounds__(TPB) void k_square_diag(int64_t n, const uint32_t* 
     d2[r] = mulmod(mp, x, x);
 }
 
+// words 32-bit zeros at p (grid-stride), then `tail` zero bytes at t: a memset that is an ordinary kernel
+__global__ __launch_bounds__(TPB) void k_fill_zero(uint32_t* __restrict__ p, int64_t words, uint8_t* __restrict__ t,
+                                                   int tail) {
+    for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < words; i += (int64_t)gridDim.x * TPB) p[i] = 0u;
+    if (blockIdx.x == 0 && (int)threadIdx.x < tail) t[threadIdx.x] = 0;
+}
+
 __global__ __launch_bounds__(TPB) void k_reduce_vec(int64_t n, const uint32_t* __restrict__ in, ModP mp,
                                                     uint32_t* __restrict__ out) {
     int64_t r = (int64_t)blockIdx.x * TPB + threadIdx.x;
@@ -470,14 +479,14 @@ __global__ __launch_bounds__(TPB) void k_project(int64_t n, const T* __restrict_
 // lanes split the partials (each wave reads 64 consecutive words), then LDS adds the groups.
 constexpr int RED_TPB = 1024;
 __global__ __launch_bounds__(RED_TPB) void k_reduce_partials(int W, int32_t s, int nblocks,
-                                                             const uint32_t* __restrict__ partial,
-                                                             uint32_t* __restrict__ S, ModP mp) {
+                                                             const uint32_t* __restrict__ partial, int64_t pstride,
+                                                             uint32_t* __restrict__ S, int64_t sstride, ModP mp) {
     __shared__ uint64_t sh[RED_TPB / 64][64];
     const int64_t k = blockIdx.x;
     const int per = s * s;
     const int64_t E = (int64_t)W * W;
     const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
-    const uint32_t* base = partial + k * nblocks * E;
+    const uint32_t* base = partial + k * pstride;
     for (int e0 = 0; e0 < per; e0 += 64) {
         const int e = e0 + lane;
         uint64_t acc = 0;
@@ -491,7 +500,7 @@ __global__ __launch_bounds__(RED_TPB) void k_reduce_partials(int W, int32_t s, i
             uint64_t t = 0;
 #pragma unroll
             for (int q = 0; q < RED_TPB / 64; ++q) t += sh[q][lane];
-            S[k * per + e] = red64(mp, t);
+            S[k * sstride * per + e] = red64(mp, t);
         }
         __syncthreads();
     }
@@ -528,14 +537,14 @@ __global__ __launch_bounds__(TPB) void k_split_scatter(int64_t rows, const int32
 
 // ---------------------------------------------------------------- launchers
 hipError_t launch_rowptr_check(int64_t m, int64_t nnz, const int64_t* rp, int32_t* bad_dev, hipStream_t st) {
-    hipError_t err = hipMemsetAsync(bad_dev, 0, sizeof(int32_t), st);
+    hipError_t err = launch_fill_zero(bad_dev, sizeof(int32_t), st);
     if (err != hipSuccess) return err;
     k_rowptr_check<<<grid_for(m + 1, TPB), TPB, 0, st>>>(m, nnz, rp, bad_dev);
     return hipGetLastError();
 }
 
 hipError_t launch_max_i32(int64_t count, const int32_t* in, int32_t* out_dev, hipStream_t st) {
-    hipError_t err = hipMemsetAsync(out_dev, 0, sizeof(int32_t), st);
+    hipError_t err = launch_fill_zero(out_dev, sizeof(int32_t), st);
     if (err != hipSuccess || count == 0) return err;
     k_max_i32<<<grid_for(count, TPB), TPB, 0, st>>>(count, in, out_dev);
     return hipGetLastError();
@@ -543,7 +552,7 @@ hipError_t launch_max_i32(int64_t count, const int32_t* in, int32_t* out_dev, hi
 
 hipError_t launch_csr_stats(int64_t m, int64_t n, const int64_t* rp, const int32_t* col, const int32_t* val,
                             CsrStats* out_dev, hipStream_t st) {
-    hipError_t err = hipMemsetAsync(out_dev, 0, sizeof(CsrStats), st);
+    hipError_t err = launch_fill_zero(out_dev, sizeof(CsrStats), st);
     if (err != hipSuccess || m == 0) return err;
     k_csr_stats<<<grid_for(m, TPB), TPB, 0, st>>>(m, n, rp, col, val, out_dev);
     return hipGetLastError();
@@ -653,6 +662,18 @@ hipError_t launch_reduce_vec(int64_t n, const uint32_t* in, ModP mp, uint32_t* o
     return hipGetLastError();
 }
 
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
+    if (bytes == 0) return hipSuccess;
+    const int64_t words = (int64_t)(bytes / 4);
+    const int64_t tail = (int64_t)(bytes % 4);
+    const int64_t n = std::max<int64_t>(words, tail ? 1 : 0);
+    const int64_t blocks = std::min<int64_t>((n + TPB - 1) / TPB, 65536);
+    k_fill_zero<<<(unsigned)std::max<int64_t>(blocks, 1), TPB, 0, st>>>(reinterpret_cast<uint32_t*>(p), words,
+                                                                       reinterpret_cast<uint8_t*>(p) + 4 * words,
+                                                                       (int)tail);
+    return hipGetLastError();
+}
+
 template <int W>
 static hipError_t spmm_packed_w(bool acc32, bool smallp, int64_t nrows, const int32_t* rp, const uint32_t* ent,
                                 const uint32_t* X, const uint32_t* scale, uint32_t* Y, ModP mp, hipStream_t st) {
@@ -746,9 +767,10 @@ hipError_t launch_project(int W, bool smallp, int64_t n, const void* U, const vo
 }
 
 hipError_t launch_reduce_partials(int W, int32_t s, int nblocks, int64_t nsteps, const uint32_t* partial, uint32_t* S,
-                                  ModP mp, hipStream_t st) {
+                                  ModP mp, hipStream_t st, int64_t pstride, int64_t sstride) {
     if (nsteps <= 0 || s <= 0) return hipSuccess;
-    k_reduce_partials<<<(unsigned)nsteps, RED_TPB, 0, st>>>(W, s, nblocks, partial, S, mp);
+    if (pstride <= 0) pstride = (int64_t)nblocks * W * W;
+    k_reduce_partials<<<(unsigned)nsteps, RED_TPB, 0, st>>>(W, s, nblocks, partial, pstride, S, sstride, mp);
     return hipGetLastError();
 }
 

@@ -37,7 +37,7 @@
 // (integer sums, so their order never changes the result), then one reduction
 // mod p, the row scale and a coalesced store per output entry.
 //
-// Projection (PROJ): after a row block is stored its reduced rows stay in LDS
+// Projection (PM = 1): after a row block is stored its reduced rows stay in LDS
 // and 4 x 4 tiles of the W x W partial U^T Z are accumulated per thread over
 // the rows it visits; at the end of the kernel the threads' partials meet in
 // LDS (64-bit sums) and each workgroup writes one W x W partial, reduced later
@@ -120,20 +120,23 @@ __device__ __forceinline__ void put_residue(uint32_t* w, int c, uint32_t y) {
         w[c] = y;
 }
 
-// W: padded block width; E: stored residue type; SPLIT: 16-bit halves (p > 2^16); PROJ: fused projection.
+// W: padded block width; E: stored residue type; SPLIT: 16-bit halves (p > 2^16); PM: fused projection of the
+// output Z: 0 none, 1 U^T Z (U from memory), 2 the weighted Gram matrix Z^T diag(wgt) Z (symmetric.hip's form).
 // Dynamic LDS: NACC * RS int32 accumulators (NACC = W, or 2 W with SPLIT), then K + 1 tile pointers; with
-// PROJ at least W * W * 8 bytes for the final partial sums.
+// a projection at least W * W * 8 bytes for the final partial sums.
 //
 // A lane owns the CPL = min(W, 32 bytes of residues) columns q CPL .. of an entry, so for 16-byte or
 // 32-byte gathered rows one lane reads the whole row (LPE = 1 lane per entry).  Each lane has UN entries in
 // flight, and the entry words of the next round are loaded before this round's gathers, so one memory
 // round trip (gathers and the next entries together) is paid per round instead of two.
-template <int W, typename E, bool SPLIT, bool PROJ>
+template <int W, typename E, bool SPLIT, int PM>
 __global__ __launch_bounds__(TT) void k_spmm_tiled(int64_t nrows, int64_t nrb, int K, int R, int RS, int cb,
                                                    int vb, const uint32_t* __restrict__ tile_ptr,
                                                    const uint32_t* __restrict__ ent, const E* __restrict__ X,
                                                    const uint32_t* __restrict__ scale, E* __restrict__ Y,
-                                                   const E* __restrict__ U, uint32_t* __restrict__ partial, ModP mp) {
+                                                   const E* __restrict__ U, const uint32_t* __restrict__ wgt,
+                                                   uint32_t* __restrict__ partial, ModP mp) {
+    constexpr bool PROJ = PM != 0;
     extern __shared__ __align__(16) int32_t lds[];
     constexpr int NACC = SPLIT ? 2 * W : W;
     constexpr int CPL = W < 32 / (int)sizeof(E) ? W : 32 / (int)sizeof(E);
@@ -252,7 +255,18 @@ __global__ __launch_bounds__(TT) void k_spmm_tiled(int64_t nrows, int64_t nrb, i
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int r = r0 + j * NG;
-                    if (r < nr) ld4(U + (size_t)(rb + (int64_t)r * nrb) * W + pti * 4, u[j]);
+                    if (r >= nr) continue;
+                    if constexpr (PM == 1) {
+                        ld4(U + (size_t)(rb + (int64_t)r * nrb) * W + pti * 4, u[j]);
+                    } else {
+                        // Gram form: u = wgt[row] * z_i, from this block's own output in LDS
+                        const uint32_t wr = wgt[rb + (int64_t)r * nrb];
+#pragma unroll
+                        for (int a = 0; a < 4; ++a) {
+                            const uint32_t zi = zl[(pti * 4 + a) * RS + r];
+                            u[j][a] = SPLIT ? mulmod(mp, wr, zi) : mulmod16(mp, wr, zi);
+                        }
+                    }
                 }
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
@@ -353,31 +367,39 @@ hipError_t allow_max_lds(const void* fn, size_t want) {
     return e;
 }
 
-template <int W, typename E, bool SPLIT, bool PROJ>
+template <int W, typename E, bool SPLIT, int PM>
 hipError_t launch_t(const TiledOperand& t, const void* X, const uint32_t* scale, void* Y, const void* U,
-                    uint32_t* partial, int grid, ModP mp, hipStream_t st) {
-    const size_t lds = tiled_lds_bytes(W, SPLIT, PROJ, t.R, t.K);
-    hipError_t e = allow_max_lds(reinterpret_cast<const void*>(&k_spmm_tiled<W, E, SPLIT, PROJ>), lds);
+                    const uint32_t* wgt, uint32_t* partial, int grid, ModP mp, hipStream_t st) {
+    const size_t lds = tiled_lds_bytes(W, SPLIT, PM != 0, t.R, t.K);
+    hipError_t e = allow_max_lds(reinterpret_cast<const void*>(&k_spmm_tiled<W, E, SPLIT, PM>), lds);
     if (e != hipSuccess || grid == 0) return e;  // grid 0: only raise the LDS limit (before a graph capture)
-    k_spmm_tiled<W, E, SPLIT, PROJ><<<(unsigned)grid, TT, lds, st>>>(
+    k_spmm_tiled<W, E, SPLIT, PM><<<(unsigned)grid, TT, lds, st>>>(
         t.rows, t.nrb, t.K, t.R, t.R + 1, t.cb, t.vb, t.tile_ptr, t.ent, (const E*)X, scale, (E*)Y, (const E*)U,
-        partial, mp);
+        wgt, partial, mp);
     return hipGetLastError();
 }
 
+template <int W, typename E, bool SPLIT>
+hipError_t launch_m(const TiledOperand& t, int pmode, const void* X, const uint32_t* scale, void* Y, const void* U,
+                    const uint32_t* wgt, uint32_t* partial, int grid, ModP mp, hipStream_t st) {
+    switch (pmode) {
+        case 0: return launch_t<W, E, SPLIT, 0>(t, X, scale, Y, U, wgt, partial, grid, mp, st);
+        case 1: return launch_t<W, E, SPLIT, 1>(t, X, scale, Y, U, wgt, partial, grid, mp, st);
+        case 2: return launch_t<W, E, SPLIT, 2>(t, X, scale, Y, U, wgt, partial, grid, mp, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <int W>
-hipError_t launch_w(const TiledOperand& t, bool proj, bool split, int esize, const void* X, const uint32_t* scale,
-                    void* Y, const void* U, uint32_t* partial, int grid, ModP mp, hipStream_t st) {
+hipError_t launch_w(const TiledOperand& t, int pmode, bool split, int esize, const void* X, const uint32_t* scale,
+                    void* Y, const void* U, const uint32_t* wgt, uint32_t* partial, int grid, ModP mp,
+                    hipStream_t st) {
     if (esize == 2) {
         if (split) return hipErrorInvalidValue;
-        return proj ? launch_t<W, uint16_t, false, true>(t, X, scale, Y, U, partial, grid, mp, st)
-                    : launch_t<W, uint16_t, false, false>(t, X, scale, Y, U, partial, grid, mp, st);
+        return launch_m<W, uint16_t, false>(t, pmode, X, scale, Y, U, wgt, partial, grid, mp, st);
     }
-    if (split)
-        return proj ? launch_t<W, uint32_t, true, true>(t, X, scale, Y, U, partial, grid, mp, st)
-                    : launch_t<W, uint32_t, true, false>(t, X, scale, Y, U, partial, grid, mp, st);
-    return proj ? launch_t<W, uint32_t, false, true>(t, X, scale, Y, U, partial, grid, mp, st)
-                : launch_t<W, uint32_t, false, false>(t, X, scale, Y, U, partial, grid, mp, st);
+    if (split) return launch_m<W, uint32_t, true>(t, pmode, X, scale, Y, U, wgt, partial, grid, mp, st);
+    return launch_m<W, uint32_t, false>(t, pmode, X, scale, Y, U, wgt, partial, grid, mp, st);
 }
 
 }  // namespace
@@ -397,7 +419,7 @@ hipError_t launch_tiled_build(int64_t rows, int64_t nrb, const int32_t* rp, cons
     if (nrb < 1 || nrb * (int64_t)R < rows) return hipErrorInvalidValue;
     const int64_t ntiles = nrb * K;
     const int64_t count = ntiles * R;
-    hipError_t e = hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)std::max<int64_t>(count, 1), st);
+    hipError_t e = launch_fill_zero(cnt, sizeof(int32_t) * (size_t)std::max<int64_t>(count, 1), st);
     if (e != hipSuccess) return e;
     const unsigned g = (unsigned)std::max<int64_t>(1, (rows + BTPB - 1) / BTPB);
     if (rows > 0) {
@@ -414,32 +436,33 @@ hipError_t launch_tiled_build(int64_t rows, int64_t nrb, const int32_t* rp, cons
     return hipSuccess;
 }
 
-hipError_t prepare_spmm_tiled(const TiledOperand& t, int W, bool proj, bool split, int esize) {
+hipError_t prepare_spmm_tiled(const TiledOperand& t, int W, int pmode, bool split, int esize) {
     if (esize != 2 && esize != 4) return hipErrorInvalidValue;
     const ModP mp = ModP::make(split ? 2147483647u : 65521u);
     switch (W) {
-        case 4: return launch_w<4>(t, proj, split, esize, nullptr, nullptr, nullptr, nullptr, nullptr, 0, mp, 0);
-        case 8: return launch_w<8>(t, proj, split, esize, nullptr, nullptr, nullptr, nullptr, nullptr, 0, mp, 0);
-        case 16: return launch_w<16>(t, proj, split, esize, nullptr, nullptr, nullptr, nullptr, nullptr, 0, mp, 0);
-        case 32: return launch_w<32>(t, proj, split, esize, nullptr, nullptr, nullptr, nullptr, nullptr, 0, mp, 0);
-        case 64: return launch_w<64>(t, proj, split, esize, nullptr, nullptr, nullptr, nullptr, nullptr, 0, mp, 0);
+        case 4: return launch_w<4>(t, pmode, split, esize, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, mp, 0);
+        case 8: return launch_w<8>(t, pmode, split, esize, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, mp, 0);
+        case 16: return launch_w<16>(t, pmode, split, esize, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, mp, 0);
+        case 32: return launch_w<32>(t, pmode, split, esize, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, mp, 0);
+        case 64: return launch_w<64>(t, pmode, split, esize, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, mp, 0);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_spmm_tiled(const TiledOperand& t, int W, bool proj, bool split, int esize, const void* X,
-                             const uint32_t* scale, void* Y, const void* U, uint32_t* partial, int grid, ModP mp,
-                             hipStream_t st) {
-    if (grid < 1 || t.R < 1 || t.nrb < 1 || t.nrb * (int64_t)t.R < t.rows || t.K < 1 || t.cb < 1 || t.vb < 2 || t.rb + t.cb + t.vb > 32 ||
-        (1LL << t.rb) < t.R || (proj && (!U || !partial)) || (esize != 2 && esize != 4) ||
+hipError_t launch_spmm_tiled(const TiledOperand& t, int W, int pmode, bool split, int esize, const void* X,
+                             const uint32_t* scale, void* Y, const void* U, const uint32_t* wgt, uint32_t* partial,
+                             int grid, ModP mp, hipStream_t st) {
+    if (grid < 1 || t.R < 1 || t.nrb < 1 || t.nrb * (int64_t)t.R < t.rows || t.K < 1 || t.cb < 1 || t.vb < 2 ||
+        t.rb + t.cb + t.vb > 32 || (1LL << t.rb) < t.R || pmode < 0 || pmode > 2 ||
+        (pmode == 1 && (!U || !partial)) || (pmode == 2 && (!wgt || !partial)) || (esize != 2 && esize != 4) ||
         split != (mp.p > 65536u))
         return hipErrorInvalidValue;
     switch (W) {
-        case 4: return launch_w<4>(t, proj, split, esize, X, scale, Y, U, partial, grid, mp, st);
-        case 8: return launch_w<8>(t, proj, split, esize, X, scale, Y, U, partial, grid, mp, st);
-        case 16: return launch_w<16>(t, proj, split, esize, X, scale, Y, U, partial, grid, mp, st);
-        case 32: return launch_w<32>(t, proj, split, esize, X, scale, Y, U, partial, grid, mp, st);
-        case 64: return launch_w<64>(t, proj, split, esize, X, scale, Y, U, partial, grid, mp, st);
+        case 4: return launch_w<4>(t, pmode, split, esize, X, scale, Y, U, wgt, partial, grid, mp, st);
+        case 8: return launch_w<8>(t, pmode, split, esize, X, scale, Y, U, wgt, partial, grid, mp, st);
+        case 16: return launch_w<16>(t, pmode, split, esize, X, scale, Y, U, wgt, partial, grid, mp, st);
+        case 32: return launch_w<32>(t, pmode, split, esize, X, scale, Y, U, wgt, partial, grid, mp, st);
+        case 64: return launch_w<64>(t, pmode, split, esize, X, scale, Y, U, wgt, partial, grid, mp, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -199,3 +199,16 @@ def test_trials_setting_bounds():
         assert bw.get_trials() == 3
     finally:
         bw.set_trials(old)
+
+
+def test_workspace_sizes():
+    """The workspace sizes are positive, grow with the matrix and the block, and are 0 for invalid arguments."""
+    a = bw.sequence_workspace(2000, 1500, 28000, 4)
+    assert a > 0
+    assert bw.sequence_workspace(2000, 1500, 56000, 4) > a
+    assert bw.sequence_workspace(2000, 1500, 28000, 16) > a
+    assert bw.rank_workspace(2000, 1500, 28000, 4) > a
+    assert bw.rank_workspace(1500, 2000, 28000, 4) > 0
+    for bad in ((-1, 10, 10, 4), (10, 10, -5, 4), (10, 10, 10, 0), (10, 10, 10, 65)):
+        assert bw.sequence_workspace(*bad) == 0
+        assert bw.rank_workspace(*bad) == 0

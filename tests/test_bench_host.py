@@ -29,7 +29,7 @@ def test_roofline_entry_dominant_kernel_and_arithmetic():
     assert rf["bytes_per_launch"] == b2 and rf["avg_launch_us"] == 20.0
     assert abs(rf["achieved"] - round(b2 / 20e-6 / 1e9, 1)) < 1e-9
     assert abs(rf["frac"] - round(rf["achieved"] / 8000.0, 4)) < 1e-4
-    assert rf["kernel"].startswith("k_spmm_tiled<16, unsigned short, false, true>")
+    assert rf["kernel"].startswith("k_spmm_tiled<16, unsigned short, false, 1>")
     assert rf["other_product"]["bytes_per_launch"] == b1
     assert rf["step"]["bytes"] == b1 + b2 and rf["step"]["kernel_us"] == 30.0
     # first product dominant; a separate projection counts with the second product
@@ -42,7 +42,7 @@ def test_roofline_entry_dominant_kernel_and_arithmetic():
 
 def test_product_kernel_names():
     n, src, _ = bench.product_kernel(fake_plan(), 1, 16, 2**31 - 1)
-    assert n == "k_spmm_tiled<16, unsigned short, true, false>" and src.endswith("spmm_tiled.hip")
+    assert n == "k_spmm_tiled<16, unsigned short, true, 0>" and src.endswith("spmm_tiled.hip")
     n, src, _ = bench.product_kernel(dict(fake_plan(False), esize=4), 2, 16, 2**31 - 1)
     assert n == "k_spmm_split<16, 4, ACC, false, true, unsigned int, 0>" and src.endswith("spmm.hip")
 
@@ -65,7 +65,7 @@ def test_traffic_from_and_lookup(tmp_path, monkeypatch):
         (tmp_path / rel).parent.mkdir(parents=True, exist_ok=True)
         (tmp_path / rel).write_text(text)
     (tmp_path / "profiles").mkdir()
-    kt = ("void bwr::(anonymous namespace)::k_spmm_tiled<16, unsigned short, false, true>(long, long, int, "
+    kt = ("void bwr::(anonymous namespace)::k_spmm_tiled<16, unsigned short, false, 1>(long, long, int, "
           "unsigned int const*, bwr::ModP)")
     ks = "void bwr::(anonymous namespace)::k_spmm_split<16, 4, 1, true, false, unsigned short, 0>(long, bwr::ModP)"
     cp = "void at::native::elementwise_kernel<128, 4, copy>(int, at::native::copy_kernel)"
@@ -82,11 +82,11 @@ def test_traffic_from_and_lookup(tmp_path, monkeypatch):
                 {"Kernel_Name": cp, "Counter_Name": "WRITE_SIZE", "Counter_Value": big}])
     rec = bench.traffic_from(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "profiles" / "traffic.json"))
     assert rec["fetch_factor"] == 2.0 and rec["write_factor"] == 1.0
-    assert bench.kernel_traffic("k_spmm_tiled<16, unsigned short, false, true>") == 1024 * (2000 * 2 + 100)
+    assert bench.kernel_traffic("k_spmm_tiled<16, unsigned short, false, 1>") == 1024 * (2000 * 2 + 100)
     assert bench.kernel_traffic("k_spmm_split<16, 4, ACC, true, false, unsigned short, 0>") == 1024 * (500 * 2 + 50)
-    assert bench.kernel_traffic("k_spmm_tiled<16, unsigned short, false, false>") is None  # not measured
+    assert bench.kernel_traffic("k_spmm_tiled<16, unsigned short, false, 0>") is None  # not measured
     (tmp_path / "paper_0704_2351_amd/csrc/spmm_tiled.hip").write_text("tiled v2")
-    assert bench.kernel_traffic("k_spmm_tiled<16, unsigned short, false, true>") is None  # another revision
+    assert bench.kernel_traffic("k_spmm_tiled<16, unsigned short, false, 1>") is None  # another revision
     assert bench.kernel_traffic("k_spmm_split<16, 4, ACC, true, false, unsigned short, 0>") == 1024 * 1050
 
 
