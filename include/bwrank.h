@@ -150,6 +150,22 @@ int bwr_sequence_dev(const bwr_csr* A_dev, const uint32_t* d_row, const uint32_t
 int bwr_apply_dev(const bwr_csr* A_dev, const uint32_t* d_row, const uint32_t* d_col, const uint32_t* X,
                   uint32_t p, int32_t s, uint32_t* Z, void* stream);
 
+/* ---- for callers that cannot allocate -------------------------------------
+ * bwr_sequence_dev_noalloc is bwr_sequence_dev for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): every device buffer of the call is carved
+ * from a static device array of 256 MiB that the library holds on each GPU
+ * it runs on (until the process ends); the call makes no device allocation
+ * and instantiates no graph.  Limit: bwr_sequence_workspace(m, n, nnz, s) must
+ * not exceed 256 MiB (about 5 M non-zeros at s = 8), else BWR_EINVAL with
+ * nothing computed.  Calls on one GPU share its array: they take turns under
+ * a lock (calls from several threads on one device run one after another;
+ * issued without that lock they would race), and the array keeps the last
+ * call's contents, so each call clears what it needs zeroed.  Results equal
+ * bwr_sequence_dev's. */
+int bwr_sequence_dev_noalloc(const bwr_csr* A_dev, const uint32_t* d_row, const uint32_t* d_col, const uint32_t* U,
+                             const uint32_t* V, uint32_t p, int32_t s, int64_t len, uint32_t* S_out, void* stream);
+
 /* ---- symmetric projection (Section 2.3, block symmetry) -------------------
  * With the symmetric projection U = V the terms S_k = V^T B^k V are symmetric
  * (B = D_c A^T D_r A D_c is symmetric).  bwr_sequence_sym_dev computes them

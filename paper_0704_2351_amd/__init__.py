@@ -9,4 +9,4 @@ from .binding import (BwrError, LIB_PATH, EXPORTED, lib, version, is_prime, sequ
                       sequence_dev, apply_dev, rank_modp_dev, time_step_kernels_dev, min_generator_dev,
                       min_generators_dev, rank_modp_batch, rank_integer, sequence_batch, Server, Matrix,
                       sequence_workspace, rank_workspace, sequence_dev_ws, rank_modp_dev_ws, device_allocations,
-                      sequence_sym_dev, rank_modp_sym, rank_modp_sym_dev)
+                      sequence_sym_dev, rank_modp_sym, rank_modp_sym_dev, sequence_dev_noalloc)

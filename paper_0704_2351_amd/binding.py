@@ -24,7 +24,7 @@ EXPORTED = ("bwr_version", "bwr_last_error", "bwr_is_prime", "bwr_sequence_lengt
             "bwr_matrix_create_dev", "bwr_matrix_sequence_dev", "bwr_matrix_destroy", "bwr_set_trials",
             "bwr_get_trials", "bwr_sequence_workspace", "bwr_rank_workspace", "bwr_sequence_dev_ws",
             "bwr_rank_modp_dev_ws", "bwr_device_allocations", "bwr_sequence_sym_dev", "bwr_rank_modp_sym",
-            "bwr_rank_modp_sym_dev", "bwr_matrix_sequence_sym_dev")
+            "bwr_rank_modp_sym_dev", "bwr_matrix_sequence_sym_dev", "bwr_sequence_dev_noalloc")
 
 
 class BwrError(RuntimeError):
@@ -106,6 +106,7 @@ def lib():
             "bwr_rank_modp_sym": (ctypes.c_int, [vp, u32, i32, u64, i32, vp, vp]),
             "bwr_rank_modp_sym_dev": (ctypes.c_int, [vp, u32, i32, u64, i32, vp, vp, vp]),
             "bwr_matrix_sequence_sym_dev": (ctypes.c_int, [vp, vp, vp, vp, u32, i32, i64, i32, vp, vp]),
+            "bwr_sequence_dev_noalloc": (ctypes.c_int, [vp, vp, vp, vp, vp, u32, i32, i64, vp, vp]),
             "bwr_rank_workspace": (ctypes.c_size_t, [i64, i64, i64, i32]),
             "bwr_sequence_dev_ws": (ctypes.c_int, [vp, vp, vp, vp, vp, u32, i32, i64, vp, vp, ctypes.c_size_t, vp]),
             "bwr_rank_modp_dev_ws": (ctypes.c_int, [vp, u32, i32, u64, vp, ctypes.c_size_t, vp, vp, vp]),
@@ -390,6 +391,19 @@ def rank_modp_sym_dev(Ad, p: int, block: int, seed: int, gram: bool = False):
     _check(lib().bwr_rank_modp_sym_dev(ctypes.byref(st), int(p), int(block), int(seed), int(bool(gram)), _stream(),
                                        ctypes.byref(r), ctypes.byref(info)))
     return int(r.value), info.as_dict()
+
+
+def sequence_dev_noalloc(Ad, U, V, p: int, length: int, d_row=None, d_col=None, out=None):
+    """bwr_sequence_dev_noalloc: the device sequence with no device allocation by the library (its buffers come
+    from the library's static per-GPU scratch); `out` may be given to avoid torch's allocation too."""
+    torch = _torch()
+    st = _dev_csr(Ad)
+    s = U.shape[1]
+    if out is None:
+        out = torch.empty((max(length, 1), s, s), dtype=torch.int32, device=U.device)
+    _check(lib().bwr_sequence_dev_noalloc(ctypes.byref(st), _dptr(d_row), _dptr(d_col), _dptr(U), _dptr(V), int(p),
+                                          int(s), int(length), _dptr(out), _stream()))
+    return out[:length]
 
 
 def apply_dev(Ad, X, p: int, d_row=None, d_col=None, out=None):

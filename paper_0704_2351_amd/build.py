@@ -15,7 +15,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libbwrank.so")
-SOURCES = ["kernels.hip", "spmm.hip", "spmm_tiled.hip", "symmetric.hip", "sigma_gpu.hip", "batch.hip", "engine.cpp", "sigma.cpp", "sigma_gpu.cpp",
+SOURCES = ["kernels.hip", "spmm.hip", "spmm_tiled.hip", "symmetric.hip", "noalloc.hip", "sigma_gpu.hip", "batch.hip", "engine.cpp", "sigma.cpp", "sigma_gpu.cpp",
            "batch_runner.cpp", "readout.cpp", "server.cpp", "api.cpp"]
 ARCH = os.environ.get("BWR_OFFLOAD_ARCH", "gfx950")
 

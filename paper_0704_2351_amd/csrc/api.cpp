@@ -538,6 +538,38 @@ int bwr_apply_dev(const bwr_csr* A_dev, const uint32_t* d_row, const uint32_t* d
     return BWR_OK;
 }
 
+// ---- the sequence without any device allocation ----
+
+int bwr_sequence_dev_noalloc(const bwr_csr* A_dev, const uint32_t* d_row, const uint32_t* d_col, const uint32_t* U,
+                             const uint32_t* V, uint32_t p, int32_t s, int64_t len, uint32_t* S_out, void* stream) {
+    if (!A_dev) return fail(BWR_EINVAL, "NULL matrix");
+    if (s < 1 || s > 64) return fail(BWR_EINVAL, "block size must be in 1..64");
+    const size_t need = sequence_workspace_bytes(A_dev->m, A_dev->n, A_dev->nnz, s, false);
+    if (need == 0 || need > noalloc_scratch_bytes())
+        return fail(BWR_EINVAL, "matrix too large for bwr_sequence_dev_noalloc: it needs " + std::to_string(need) +
+                                    " bytes of device scratch, the library holds " +
+                                    std::to_string(noalloc_scratch_bytes()));
+    Error e;
+    hipStream_t st = work_stream(stream, &e);
+    if (!e.ok()) return fail(e);
+    void* base = nullptr;
+    std::mutex* use = nullptr;
+    if (!(e = noalloc_scratch(&base, &use)).ok()) return fail(e);
+    std::lock_guard<std::mutex> lk(*use);  // calls on one device take turns with the array
+    Arena ar;
+    ar.base = (char*)base;
+    ar.size = noalloc_scratch_bytes();
+    {
+        ArenaScope scope(&ar);
+        e = sequence_dev_impl(view(A_dev), d_row, d_col, U, V, p, s, len, S_out, st);
+    }
+    const hipError_t he = hipStreamSynchronize(st);
+    if (e.ok() && he != hipSuccess) e = Error::device(he, "sequence");
+    if (!e.ok()) return fail(e);
+    g_err.clear();
+    return BWR_OK;
+}
+
 // ---- symmetric projection ----
 
 int bwr_sequence_sym_dev(const bwr_csr* A_dev, const uint32_t* d_row, const uint32_t* d_col, const uint32_t* V,

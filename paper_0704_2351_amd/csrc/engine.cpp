@@ -1029,7 +1029,7 @@ Error gram_sequence(const SequenceArgs& a, const DeviceMatrix& M, const Operand&
     };
     void* cur = X0;
     void* nxt = X1;
-    const bool use_graph = env_int("BWR_NO_GRAPH", 0) == 0 && nb > 0 && (a.len - 1) >= 4 * CH;
+    const bool use_graph = !current_arena() && env_int("BWR_NO_GRAPH", 0) == 0 && nb > 0 && (a.len - 1) >= 4 * CH;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     Error err;
@@ -1207,7 +1207,8 @@ Error run_sequence(const SequenceArgs& a, hipStream_t st) {
 
     void* cur = X0.as<void>();
     void* nxt = X1.as<void>();
-    const bool use_graph = env_int("BWR_NO_GRAPH", 0) == 0 && a.len - 1 >= 2 * CH && nb > 0;
+    // no graphs inside an arena: instantiating one is work (and memory) of the runtime's own
+    const bool use_graph = !in_arena && env_int("BWR_NO_GRAPH", 0) == 0 && a.len - 1 >= 2 * CH && nb > 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     Error err;

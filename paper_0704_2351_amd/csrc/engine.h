@@ -6,6 +6,7 @@
 
 #include <functional>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -44,6 +45,11 @@ class ArenaScope {
 Arena* current_arena();
 // device allocations the library has made so far (every DevBuf that did not come from an arena)
 int64_t device_allocations();
+
+// The static device scratch of the entry point that allocates nothing (noalloc.hip): its size, and on the
+// current device its address (resolved once per device) with the lock its users take turns under.
+size_t noalloc_scratch_bytes();
+Error noalloc_scratch(void** ptr, std::mutex** use);
 
 // Device buffer owned by the library (freed on destruction, stream-ordered), or carved from the installed
 // arena.
