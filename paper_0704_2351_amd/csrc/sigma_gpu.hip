@@ -168,52 +168,6 @@ __global__ __launch_bounds__(TPB) void k_ntt_lds(uint32_t* __restrict__ a, int64
     for (int i = threadIdx.x; i < S; i += TPB) base[i] = sh[i];
 }
 
-// ------------------------------------------------------------------ pointwise products
-// C[t][i][l][x] = sum_j A[t][i][j][x] B[t][j][l][x] mod q_t; a thread owns (t, i, 8 columns, x).
-constexpr int PW_COLS = 8;
-
-__global__ __launch_bounds__(TPB) void k_pointwise(const uint32_t* __restrict__ A, const uint32_t* __restrict__ B,
-                                                   uint32_t* __restrict__ C, int r, int k, int c, int64_t N, int T,
-                                                   NttConsts cs) {
-    const int cgroups = (c + PW_COLS - 1) / PW_COLS;
-    int64_t idx = (int64_t)blockIdx.x * TPB + threadIdx.x;
-    int64_t total = (int64_t)T * r * cgroups * N;
-    if (idx >= total) return;
-    int64_t x = idx % N;
-    int64_t rest = idx / N;
-    int lg = (int)(rest % cgroups);
-    rest /= cgroups;
-    int i = (int)(rest % r);
-    int t = (int)(rest / r);
-    const uint32_t q = cs.q[t];
-    const ModP mq = cs.mq[t];
-    const uint32_t* At = A + (size_t)t * r * k * N;
-    const uint32_t* Bt = B + (size_t)t * k * c * N;
-    uint64_t lo[PW_COLS], hi[PW_COLS];
-#pragma unroll
-    for (int u = 0; u < PW_COLS; ++u) lo[u] = hi[u] = 0;
-    const int l0 = lg * PW_COLS;
-    for (int j = 0; j < k; ++j) {
-        const uint64_t a = At[((size_t)i * k + j) * N + x];
-        if (!a) continue;
-#pragma unroll
-        for (int u = 0; u < PW_COLS; ++u) {
-            if (l0 + u < c) {
-                uint64_t pr = a * Bt[((size_t)j * c + l0 + u) * N + x];
-                lo[u] += pr & 0xffffffffu;
-                hi[u] += pr >> 32;
-            }
-        }
-    }
-    const uint32_t r32 = cs.r32[t];
-#pragma unroll
-    for (int u = 0; u < PW_COLS; ++u)
-        if (l0 + u < c)
-            C[((size_t)t * r * c + (size_t)i * c + l0 + u) * N + x] =
-                addq(red64(mq, lo[u]), mulmod(mq, red64(mq, hi[u]), r32), q);
-    (void)q;
-}
-
 // ------------------------------------------------------------------ CRT
 // out[e][x - lo] for x in [lo, hi): residues scaled by N^-1 mod q_t, Garner, then mod the prime of
 // poly e's batch (per_batch polys each).
@@ -248,9 +202,10 @@ __global__ __launch_bounds__(TPB) void k_crt(const uint32_t* __restrict__ C, int
     out[idx] = v;
 }
 
-// Same product with a 4 x 4 tile of (i, l) per thread and transform point: per inner index j the thread
-// loads 4 values of A and 4 of B for 16 products (instead of 9 loads for 8), summed in 64 bits and
-// reduced every 3 terms (3 (q - 1)^2 + q < 2^64 for q < 2^31).
+// ------------------------------------------------------------------ pointwise products
+// C[t][i][l][x] = sum_j A[t][i][j][x] B[t][j][l][x] mod q_t over the transform points x, a 4 x 4 tile of
+// (i, l) per thread and transform point: per inner index j the thread loads 4 values of A and 4 of B for
+// 16 products, summed in 64 bits and reduced every 3 terms (3 (q - 1)^2 + q < 2^64 for q < 2^31).
 constexpr int PW_TILE = 4;
 __global__ __launch_bounds__(TPB) void k_pointwise_tiled(const uint32_t* __restrict__ A,
                                                          const uint32_t* __restrict__ B, uint32_t* __restrict__ C,
