@@ -171,7 +171,7 @@ def product_kernel(plan, which, s, p):
         proj = "1" if which == 2 else "0"
         return (f"k_spmm_tiled<{W}, {etype}, {split}, {proj}>", "paper_0704_2351_amd/csrc/spmm_tiled.hip",
                 f"tiled: row blocks of {plan[f'T{which}R']} rows, slabs of 2^{plan[f'T{which}cb']} block rows, "
-                f"{plan[f'T{which}grid']} workgroups")
+                f"{plan[f'T{which}grid']} workgroups, {plan.get(f'T{which}un', 4)} entries in flight per lane")
     G = plan[f"G{which}"]
     fused = "true" if (which == 2 and plan["fused"]) else "false"
     return (f"k_spmm_split<{W}, {G}, ACC, {'true' if p <= 65536 else 'false'}, {fused}, {etype}, 0>",
@@ -410,10 +410,11 @@ def profile_kernels_mode(args):
           flush=True)
 
 
-def traffic_from(fetch_dir, write_dir, out_path):
+def traffic_from(fetch_dir, write_dir, out_path, last=None):
     """profiles/traffic.json from two rocprofv3 --pmc runs of --profile-kernels (FETCH_SIZE, then WRITE_SIZE):
     per dispatch KiB of every sparse-product kernel, scaled by what the same counter reads for the 256 MiB
-    device copy of that run (reads 256 MiB, writes 256 MiB)."""
+    device copy of that run (reads 256 MiB, writes 256 MiB).  With `last`, only the last `last` dispatches of
+    each kernel count (the timing loop of the plan the autotuner chose, after its trials)."""
     import csv
     import glob
 
@@ -424,7 +425,10 @@ def traffic_from(fetch_dir, write_dir, out_path):
                 if row.get("Counter_Name") != counter:
                     continue
                 k = row["Kernel_Name"]
-                vals.setdefault(k, []).append(float(row["Counter_Value"]))
+                vals.setdefault(k, []).append((int(row.get("Dispatch_Id") or 0), float(row["Counter_Value"])))
+        for k in vals:
+            v = [x for _, x in sorted(vals[k])]
+            vals[k] = v[-last:] if last else v
         return vals
 
     fetch, write = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
@@ -452,7 +456,8 @@ def traffic_from(fetch_dir, write_dir, out_path):
            "workload": "2000000 x 1000000 planted (37.2 M non-zeros), block 16, p = 65521",
            "command": "rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -- python3 bench.py --profile-kernels",
            "fetch_factor": round(ff, 4), "write_factor": round(fw, 4),
-           "note": "average over every dispatch of the kernel in the run (autotuner trials and timing loop)",
+           "note": (f"average over the last {last} dispatches of each kernel (the chosen plan's timing loop)" if last
+                    else "average over every dispatch of the kernel in the run (autotuner trials and timing loop)"),
            "kernels": dict(sorted(kernels.items()))}
     with open(out_path, "w") as f:
         json.dump(rec, f, indent=1)
@@ -637,14 +642,16 @@ def main():
                          "command the counter summaries are taken on)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc output folders of --profile-kernels "
-                         "(FETCH_SIZE, then WRITE_SIZE); needs no GPU")
+                         "(FETCH_SIZE, then WRITE_SIZE), counting the last --kernel-iters dispatches of each "
+                         "kernel (give the counter runs' value); needs no GPU")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is described, "
               f"not built", file=sys.stderr)
         sys.exit(2)
     if args.traffic_from:
-        rec = traffic_from(args.traffic_from[0], args.traffic_from[1], os.path.join(ROOT, "profiles", "traffic.json"))
+        rec = traffic_from(args.traffic_from[0], args.traffic_from[1], os.path.join(ROOT, "profiles", "traffic.json"),
+                           last=args.kernel_iters)
         print(json.dumps({k: v for k, v in rec.items() if k != "kernels"}), flush=True)
         return
 

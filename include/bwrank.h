@@ -265,9 +265,10 @@ int bwr_rank_modp_dev(const bwr_csr* A_dev, uint32_t p, int32_t block, uint64_t 
  * projection fused (0/1), projection blocks, bytes per stored residue,
  * column passes of the first product, column passes of the second, then for
  * each product its two-dimensional tiling: rows per row block (0 = not
- * tiled), log2 of the block rows per slab, workgroups} (14 int32; row split
- * 0 = the one-row-per-lane kernel).  For measurement; computes nothing the
- * caller keeps. */
+ * tiled), log2 of the block rows per slab, workgroups; then for each product
+ * the entries each lane of a tiled product keeps in flight} (16 int32; row
+ * split 0 = the one-row-per-lane kernel).  For measurement; computes nothing
+ * the caller keeps. */
 int bwr_time_step_kernels_dev(const bwr_csr* A_dev, uint32_t p, int32_t s, int32_t transpose, int32_t iters,
                               void* stream, double* us_out, int32_t* plan_out);
 
@@ -403,8 +404,9 @@ int bwr_rank_from_sequence(const uint32_t* S, int64_t len, int64_t check, int32_
  *                          bwr_apply_dev); BWR_TILED=0 keeps the tuner from
  *                          trying it.  BWR_TILED_WGS (workgroups per CU),
  *                          BWR_TILED_SLAB (bytes of the block per slab),
- *                          BWR_TILED_R (row block cap) and BWR_TILED_GRID
- *                          (workgroup cap) pin its geometry
+ *                          BWR_TILED_R (row block cap), BWR_TILED_GRID
+ *                          (workgroup cap) and BWR_TILED_UN (entries in
+ *                          flight per lane, 1-4) pin its geometry
  *   BWR_NO_SORT=1          no length-sorted relabelling of rows and columns
  *   BWR_NO_GRAPH=1         launch every step instead of replaying HIP graphs
  *   BWR_HOST_SIGMA=1       sigma-basis on the host instead of the device

@@ -430,15 +430,15 @@ def time_step_kernels_dev(Ad, p: int, s: int, transpose: bool = False, iters: in
     """Average microseconds of [first product, second product, projection] (HIP events on torch's stream);
     with_plan=True also returns the launch plan {W, G1, G2, fused, NB, esize, parts1, parts2, and the tiling of
     each product: T1R, T1cb, T1grid, T2R, T2cb, T2grid (rows per row block, 0 = not tiled; log2 slab rows;
-    workgroups)}."""
+    workgroups), T1un, T2un (entries in flight per lane)}."""
     st = _dev_csr(Ad)
     us = np.zeros(3, dtype=np.float64)
-    plan = np.zeros(14, dtype=np.int32)
+    plan = np.zeros(16, dtype=np.int32)
     _check(lib().bwr_time_step_kernels_dev(ctypes.byref(st), int(p), int(s), int(transpose), int(iters), _stream(),
                                            us.ctypes.data, plan.ctypes.data))
     if with_plan:
         keys = ("W", "G1", "G2", "fused", "NB", "esize", "parts1", "parts2", "T1R", "T1cb", "T1grid", "T2R",
-                "T2cb", "T2grid")
+                "T2cb", "T2grid", "T1un", "T2un")
         return us, {k: int(v) for k, v in zip(keys, plan)}
     return us
 

@@ -878,8 +878,9 @@ int bwr_time_step_kernels_dev(const bwr_csr* A_dev, uint32_t p, int32_t s, int32
     StepPlan pl;
     if (!(e = time_step_kernels(M, transpose != 0, ModP::make(p), s, iters, st, us_out, &pl)).ok()) return fail(e);
     if (plan_out) {
-        const int32_t v[14] = {pl.W,      pl.G1,     pl.G2,       pl.fused ? 1 : 0, pl.NB,     pl.esize,  pl.parts1,
-                               pl.parts2, pl.t1.R,   pl.t1.cb,    pl.t1.grid,       pl.t2.R,   pl.t2.cb,  pl.t2.grid};
+        const int32_t v[16] = {pl.W,      pl.G1,      pl.G2,   pl.fused ? 1 : 0, pl.NB,      pl.esize,
+                               pl.parts1, pl.parts2,  pl.t1.R, pl.t1.cb,         pl.t1.grid, pl.t2.R,
+                               pl.t2.cb,  pl.t2.grid, pl.t1.un, pl.t2.un};
         std::memcpy(plan_out, v, sizeof(v));
     }
     g_err.clear();

@@ -363,10 +363,12 @@ TiledOperand tiled_view(int64_t rows, int64_t cols, const StepPlan::Tile& t, int
     return v;
 }
 
-// Row blocks for at most Rmax rows each and `slots` resident workgroups: whole rounds of grid blocks
-// (grid = min(blocks, slots)), each block as small as that count allows.
-void finish_tile(int64_t rows, int64_t Rmax, int64_t slots, StepPlan::Tile* t) {
-    const int64_t nrb0 = (rows + Rmax - 1) / Rmax;
+// Row blocks for at most Rmax rows each and `slots` resident workgroups: whole rounds of grid blocks, each
+// block as small as that count allows; with fill, at least one block per slot while there are rows for them,
+// so that a single round still occupies every CU.
+void finish_tile(int64_t rows, int64_t Rmax, int64_t slots, StepPlan::Tile* t, bool fill = true) {
+    int64_t nrb0 = (rows + Rmax - 1) / Rmax;
+    if (fill) nrb0 = std::max(nrb0, std::min(slots, rows));
     const int64_t grid = std::max<int64_t>(1, std::min(nrb0, slots));
     t->nrb = grid * ((nrb0 + grid - 1) / grid);
     t->R = (int)((rows + t->nrb - 1) / t->nrb);
@@ -402,9 +404,10 @@ bool tile_geometry(int64_t rows, int64_t cols, int W, int esize, bool split, boo
 }
 
 // Tiled geometries the autotuner tries: row blocks for one or two workgroups per CU, slabs of 128 to 512 KB of
-// the block (measured at the 2M x 1M size: larger slabs lose, 256 and 128 KB are within a few per cent).
-// BWR_TILED_WGS, BWR_TILED_SLAB (bytes), BWR_TILED_R (cap on the row block) and BWR_TILED_GRID (cap on the
-// workgroups) pin one geometry.
+// the block (measured at the 2M x 1M size: larger slabs lose, 256 and 128 KB are within a few per cent), one or
+// two entries in flight per lane (one won at that size: a pass then spans fewer slabs).  BWR_TILED_WGS,
+// BWR_TILED_SLAB (bytes), BWR_TILED_R (cap on the row block), BWR_TILED_GRID (cap on the workgroups) and
+// BWR_TILED_UN (entries in flight) pin one geometry.
 std::vector<StepPlan::Tile> tile_candidates(int64_t rows, int64_t cols, int W, int esize, bool split, bool proj,
                                             int32_t max_abs) {
     std::vector<StepPlan::Tile> out;
@@ -419,14 +422,19 @@ std::vector<StepPlan::Tile> tile_candidates(int64_t rows, int64_t cols, int W, i
             StepPlan::Tile t;
             if (!tile_geometry(rows, cols, W, esize, split, proj, max_abs, sl, w, &t)) continue;
             const int64_t slots = (int64_t)device_attr(hipDeviceAttributeMultiprocessorCount, 256) * std::min(2, std::max(1, w));
-            if (er && atoi(er) >= 1 && t.R > atoi(er)) finish_tile(rows, atoi(er), slots, &t);
+            if (er && atoi(er) >= 1 && t.R > atoi(er)) finish_tile(rows, atoi(er), slots, &t, false);
             if (const char* eg = getenv("BWR_TILED_GRID")) {
                 if (atoi(eg) >= 1) t.grid = (int)std::min<int64_t>(t.grid, atoi(eg));
                 if (atoi(eg) == -1) t.grid = (int)t.nrb;  // one workgroup per row block
             }
-            bool dup = false;
-            for (const auto& o : out) dup |= (o.R == t.R && o.cb == t.cb && o.grid == t.grid && o.nrb == t.nrb);
-            if (!dup) out.push_back(t);
+            const char* eu = getenv("BWR_TILED_UN");
+            for (int un : eu ? std::vector<int>{std::min(4, std::max(1, atoi(eu)))} : std::vector<int>{1, 2}) {
+                t.un = un;
+                bool dup = false;
+                for (const auto& o : out)
+                    dup |= (o.R == t.R && o.cb == t.cb && o.grid == t.grid && o.nrb == t.nrb && o.un == t.un);
+                if (!dup) out.push_back(t);
+            }
         }
     return out;
 }
@@ -436,6 +444,14 @@ struct TiledOp {
     TiledOperand v;
     bool on = false;
 };
+
+// launch shape of geometry t over the tiled encoding o
+TiledLaunch tiled_launch(const TiledOp&, const StepPlan::Tile& t) {
+    TiledLaunch L;
+    L.grid = t.grid;
+    L.un = t.un;
+    return L;
+}
 
 // Tiled encoding of a packed operand for the geometry cfg (see launch_tiled_build).
 Error build_tiled(const Operand& op, int64_t cols, int64_t nnz, int32_t max_abs, const StepPlan::Tile& cfg,
@@ -550,8 +566,8 @@ hipError_t first_product(const DeviceMatrix& M, const Operand& op1, const SplitO
                          const TiledOp* to = nullptr) {
     const bool smallp = mp.p <= 65536u;
     if (to && to->on)
-        return launch_spmm_tiled(to->v, pl.W, 0, !smallp, pl.esize, X, dr, Y, nullptr, nullptr, nullptr, pl.t1.grid,
-                                 mp, st);
+        return launch_spmm_tiled(to->v, pl.W, 0, !smallp, pl.esize, X, dr, Y, nullptr, nullptr, nullptr,
+                                 tiled_launch(*to, pl.t1), mp, st);
     if (so && so->on) {
         hipError_t e = launch_spmm_split(pl.W, G, false, acc_mode(M, op1.max_len, mp.p, G), smallp, pl.esize,
                                          op1.rows, so->p0.rp, so->p0.ent, X, nullptr, nullptr, nullptr, nullptr, 0, mp,
@@ -571,8 +587,8 @@ hipError_t second_product(const DeviceMatrix& M, const Operand& op2, const Split
                           const void* Ut, uint32_t* partial, hipStream_t st, const TiledOp* to = nullptr) {
     const bool smallp = mp.p <= 65536u;
     if (to && to->on)
-        return launch_spmm_tiled(to->v, pl.W, 1, !smallp, pl.esize, Yin, dc2, Z, Ut, nullptr, partial, pl.t2.grid, mp,
-                                 st);
+        return launch_spmm_tiled(to->v, pl.W, 1, !smallp, pl.esize, Yin, dc2, Z, Ut, nullptr, partial,
+                                 tiled_launch(*to, pl.t2), mp, st);
     if (so && so->on) {
         hipError_t e = launch_spmm_split(pl.W, G, false, acc_mode(M, op2.max_len, mp.p, G), smallp, pl.esize,
                                          op2.rows, so->p0.rp, so->p0.ent, Yin, nullptr, nullptr, nullptr, nullptr, 0,
@@ -789,7 +805,8 @@ Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl
             gs.push_back(-1 - (int)i);
             runs.push_back([&, i]() -> Error {
                 hipError_t e = launch_spmm_tiled(to1[i].v, W, 0, split, pl->esize, X.as<void>(), nullptr,
-                                                 Y.as<void>(), nullptr, nullptr, nullptr, tc1[i].grid, mp, st);
+                                                 Y.as<void>(), nullptr, nullptr, nullptr,
+                                                 tiled_launch(to1[i], tc1[i]), mp, st);
                 return e == hipSuccess ? Error{} : Error::device(e, "autotune (tiled)");
             });
         }
@@ -802,8 +819,8 @@ Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl
                     fprintf(stderr, "[bwr tune] first product  row split G=%d: %.2f us\n", gs[i], tt[i]);
                 else {
                     const auto& c = tc1[-1 - gs[i]];
-                    fprintf(stderr, "[bwr tune] first product  tiled R=%d cb=%d grid=%d: %.2f us\n", c.R, c.cb,
-                            c.grid, tt[i]);
+                    fprintf(stderr, "[bwr tune] first product  tiled R=%d cb=%d grid=%d un=%d: %.2f us\n", c.R,
+                            c.cb, c.grid, c.un, tt[i]);
                 }
             }
         if (gs[bi] > 0)
@@ -853,8 +870,8 @@ Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl
             cs.push_back({-1 - (int)i, tc2[i].grid, true});
             runs.push_back([&, i]() -> Error {
                 hipError_t e = launch_spmm_tiled(to2[i].v, W, 1, split, pl->esize, Y.as<void>(), nullptr,
-                                                 Z.as<void>(), U.as<void>(), nullptr, part.as<uint32_t>(), tc2[i].grid,
-                                                 mp, st);
+                                                 Z.as<void>(), U.as<void>(), nullptr, part.as<uint32_t>(),
+                                                 tiled_launch(to2[i], tc2[i]), mp, st);
                 return e == hipSuccess ? Error{} : Error::device(e, "autotune (tiled)");
             });
         }
@@ -868,8 +885,8 @@ Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl
                             (int)cs[i].fused, cs[i].nbk, tt[i]);
                 else {
                     const auto& c = tc2[-1 - cs[i].g];
-                    fprintf(stderr, "[bwr tune] second product tiled R=%d cb=%d grid=%d: %.2f us\n", c.R, c.cb,
-                            c.grid, tt[i]);
+                    fprintf(stderr, "[bwr tune] second product tiled R=%d cb=%d grid=%d un=%d: %.2f us\n", c.R,
+                            c.cb, c.grid, c.un, tt[i]);
                 }
             }
         if (cs[bi].g > 0) {
@@ -1002,7 +1019,7 @@ Error gram_sequence(const SequenceArgs& a, const DeviceMatrix& M, const Operand&
         hipError_t e;
         if (t1) {
             e = launch_spmm_tiled(to1->v, W, 2, !smallp, pl.esize, cur, drp, Y, nullptr, w1.as<uint32_t>(), slot,
-                                  pl.t1.grid, mp, st);
+                                  tiled_launch(*to1, pl.t1), mp, st);
         } else {
             if (pl.G1 > 0)
                 e = first_product(M, op1, so1, pl.G1, pl, mp, cur, drp, Y, st, nullptr);
@@ -1015,7 +1032,7 @@ Error gram_sequence(const SequenceArgs& a, const DeviceMatrix& M, const Operand&
         uint32_t* slot2 = slot + (size_t)nb1 * E;
         if (t2) {
             e = launch_spmm_tiled(to2->v, W, 2, !smallp, pl.esize, Y, dc2p, nxt, nullptr, w2.as<uint32_t>(), slot2,
-                                  pl.t2.grid, mp, st);
+                                  tiled_launch(*to2, pl.t2), mp, st);
         } else {
             if (pl.G2 > 0)
                 e = second_product(M, op2, so2, pl.G2, false, 0, pl, mp, Y, dc2p, nxt, nullptr, nullptr, st);
@@ -1312,14 +1329,14 @@ Error apply_once(const DeviceMatrix& M, bool transpose, ModP mp, int32_t s, cons
         auto c = tile_candidates(op1.rows, nb, W, 4, split, false, M.max_abs);
         if (!c.empty()) BWR_TRY(build_tiled(op1, nb, M.nnz, M.max_abs, c[0], st, &to1));
         if (to1.on) BWR_HIP(launch_spmm_tiled(to1.v, W, 0, split, 4, Xp.as<void>(), drp, Y.as<void>(), nullptr,
-                                              nullptr, nullptr, c[0].grid, mp, st));
+                                              nullptr, nullptr, tiled_launch(to1, c[0]), mp, st));
     }
     if (!to1.on) BWR_TRY(spmm(M, op1, W, mp, Xp.as<uint32_t>(), drp, Y.as<uint32_t>(), st));
     if (tiled && tiled_acc_ok(M, op2.max_len, mp.p)) {
         auto c = tile_candidates(op2.rows, outer, W, 4, split, false, M.max_abs);
         if (!c.empty()) BWR_TRY(build_tiled(op2, outer, M.nnz, M.max_abs, c[0], st, &to2));
         if (to2.on) BWR_HIP(launch_spmm_tiled(to2.v, W, 0, split, 4, Y.as<void>(), dcp, Zp.as<void>(), nullptr,
-                                              nullptr, nullptr, c[0].grid, mp, st));
+                                              nullptr, nullptr, tiled_launch(to2, c[0]), mp, st));
     }
     if (!to2.on) BWR_TRY(spmm(M, op2, W, mp, Y.as<uint32_t>(), dcp, Zp.as<uint32_t>(), st));
     BWR_HIP(launch_unpad(nb, s, W, Zp.as<void>(), 4, Z, st));

@@ -136,14 +136,20 @@ int tiled_threads();
 hipError_t launch_tiled_build(int64_t rows, int64_t nrb, const int32_t* rp, const uint32_t* ent, int K, int R,
                               int cb, int vb, int32_t* cnt, int32_t* pos, int32_t* scan_tmp, uint32_t* tile_ptr,
                               uint32_t* out, hipStream_t st);
-// Y = scale * (T X) mod p over the tiled operand T, grid persistent workgroups (one row block at a time).
+// Launch shape of a tiled product: grid persistent workgroups (one row block at a time); un (1 .. 4) entries
+// each lane keeps in flight per pass.
+struct TiledLaunch {
+    int grid = 0;
+    int un = 4;
+};
+// Y = scale * (T X) mod p over the tiled operand T.
 // split: residues summed as 16-bit halves (required exactly when p > 2^16; the caller guarantees
 // max row length * max |a| * 65535 < 2^31), else int32 sums (max row length * max |a| * (p - 1) < 2^31).
 // pmode 1: partial[b][i * W + j] (b < grid) = the workgroup's share of sum_r U[r][i] Y[r][j] mod p; pmode 2: of
 // sum_r wgt[r] Y[r][i] Y[r][j] (the Gram form of the symmetric projection); pmode 0: no partials.
 hipError_t launch_spmm_tiled(const TiledOperand& t, int W, int pmode, bool split, int esize, const void* X,
                              const uint32_t* scale, void* Y, const void* U, const uint32_t* wgt, uint32_t* partial,
-                             int grid, ModP mp, hipStream_t st);
+                             const TiledLaunch& L, ModP mp, hipStream_t st);
 // Raises the dynamic-LDS limit of the kernel that launch_spmm_tiled would launch (done by every launch too;
 // call it before a graph capture that will hold the first launch).
 hipError_t prepare_spmm_tiled(const TiledOperand& t, int W, int pmode, bool split, int esize);

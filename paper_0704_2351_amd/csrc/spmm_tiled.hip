@@ -33,15 +33,18 @@
 // Accumulation: for p <= 2^16 one int32 per output entry (the caller checks
 // max row length * max |a| * (p - 1) < 2^31); for larger primes each residue
 // is split into 16-bit halves summed in two int32 (the caller checks
-// max row length * max |a| * 65535 < 2^31).  Adds go to LDS with atomic adds
+// max row length * max |a| * 65535 < 2^31).  Every product is a value of at
+// most vb <= 24 bits times a residue or half below 2^16, so it is formed with
+// the full-rate 24-bit multiply.  Adds go to LDS with atomic adds
 // (integer sums, so their order never changes the result), then one reduction
 // mod p, the row scale and a coalesced store per output entry.
 //
 // Projection (PM = 1): after a row block is stored its reduced rows stay in LDS
 // and 4 x 4 tiles of the W x W partial U^T Z are accumulated per thread over
-// the rows it visits; at the end of the kernel the threads' partials meet in
-// LDS (64-bit sums) and each workgroup writes one W x W partial, reduced later
-// by k_reduce_partials.
+// the rows it visits; the threads' tiles then meet in LDS (64-bit sums) and are
+// added to the workgroup's running sums, so the tiles occupy registers only
+// during the projection; at the end each workgroup writes one W x W partial,
+// reduced later by k_reduce_partials.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -57,6 +60,7 @@ namespace {
 
 constexpr int TT = 1024;  // threads of a tiled workgroup (16 waves: one workgroup per CU, LDS-bound)
 constexpr int BTPB = 256;
+constexpr int UNMAX = 4;  // entries a lane keeps in flight per pass, at most
 
 // 4 residues (projection operands)
 __device__ __forceinline__ void ld4(const uint32_t* p, uint32_t (&x)[4]) {
@@ -126,16 +130,16 @@ __device__ __forceinline__ void put_residue(uint32_t* w, int c, uint32_t y) {
 // a projection at least W * W * 8 bytes for the final partial sums.
 //
 // A lane owns the CPL = min(W, 32 bytes of residues) columns q CPL .. of an entry, so for 16-byte or
-// 32-byte gathered rows one lane reads the whole row (LPE = 1 lane per entry).  Each lane has UN entries in
-// flight, and the entry words of the next round are loaded before this round's gathers, so one memory
-// round trip (gathers and the next entries together) is paid per round instead of two.
+// 32-byte gathered rows one lane reads the whole row (LPE = 1 lane per entry).  A pass gives each lane un
+// (1 .. UNMAX) entries in flight, and the entry words of the next pass are loaded before this pass's
+// gathers, so one memory round trip (gathers and the next entries together) is paid per pass instead of two.
 template <int W, typename E, bool SPLIT, int PM>
 __global__ __launch_bounds__(TT) void k_spmm_tiled(int64_t nrows, int64_t nrb, int K, int R, int RS, int cb,
                                                    int vb, const uint32_t* __restrict__ tile_ptr,
                                                    const uint32_t* __restrict__ ent, const E* __restrict__ X,
                                                    const uint32_t* __restrict__ scale, E* __restrict__ Y,
                                                    const E* __restrict__ U, const uint32_t* __restrict__ wgt,
-                                                   uint32_t* __restrict__ partial, ModP mp) {
+                                                   uint32_t* __restrict__ partial, int un, ModP mp) {
     constexpr bool PROJ = PM != 0;
     extern __shared__ __align__(16) int32_t lds[];
     constexpr int NACC = SPLIT ? 2 * W : W;
@@ -143,7 +147,6 @@ __global__ __launch_bounds__(TT) void k_spmm_tiled(int64_t nrows, int64_t nrb, i
     constexpr int LPE = W / CPL;                 // lanes per entry
     constexpr int EPI = TT / LPE;                // entries per pass of the workgroup
     constexpr int NWD = CPL * (int)sizeof(E) / 4;  // words a lane gathers per entry
-    constexpr int UN = 4;                        // entries per lane in flight
     constexpr int WB = W / 4;                    // 4 x 4 tiles of the projection partial per side
     constexpr int NT = WB * WB;
     constexpr int NG = TT / NT;                  // row groups of the projection
@@ -159,12 +162,13 @@ __global__ __launch_bounds__(TT) void k_spmm_tiled(int64_t nrows, int64_t nrb, i
     const int pti = pt / WB, ptj = pt % WB;
 
     using PAcc = typename std::conditional<SPLIT, uint32_t, uint64_t>::type;
-    PAcc pacc[4][4];
+    // the workgroup's W x W projection sums over its row blocks, entry threadIdx.x + h TT in tot[h]
+    constexpr int NTOT = (W * W + TT - 1) / TT;
+    unsigned long long tot[NTOT];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) pacc[a][b] = 0;
+    for (int h = 0; h < NTOT; ++h) tot[h] = 0;
 
+    const uint32_t EPS = (uint32_t)un * EPI;  // entries per pass
     for (int64_t rb = blockIdx.x; rb < nrb; rb += gridDim.x) {
         int4* acc4 = reinterpret_cast<int4*>(acc);
         for (int i = threadIdx.x; i < NACC * RS / 4; i += TT) acc4[i] = make_int4(0, 0, 0, 0);
@@ -172,48 +176,48 @@ __global__ __launch_bounds__(TT) void k_spmm_tiled(int64_t nrows, int64_t nrb, i
         __syncthreads();
         const uint32_t end = tp[K];
         uint32_t e0 = tp[0] + (uint32_t)es;
-        uint32_t wn[UN];
+        uint32_t wn[UNMAX];
 #pragma unroll
-        for (int u = 0; u < UN; ++u) {
+        for (int u = 0; u < UNMAX; ++u) {
             const uint32_t idx = e0 + u * EPI;
-            wn[u] = idx < end ? __builtin_nontemporal_load(ent + idx) : 0u;
+            wn[u] = (u < un && idx < end) ? __builtin_nontemporal_load(ent + idx) : 0u;
         }
         // the slab of an entry: k advances (a lane's entries only move forward through the row block's
         // tiles); knext caches tp[k + 1]
         int k = 0;
         uint32_t knext = tp[1];
-        for (; e0 < end; e0 += UN * EPI) {
-            uint32_t w[UN];
+        for (; e0 < end; e0 += EPS) {
+            uint32_t w[UNMAX];
 #pragma unroll
-            for (int u = 0; u < UN; ++u) w[u] = wn[u];
+            for (int u = 0; u < UNMAX; ++u) w[u] = wn[u];
 #pragma unroll
-            for (int u = 0; u < UN; ++u) {
-                const uint32_t idx = e0 + (UN + u) * EPI;
-                wn[u] = idx < end ? __builtin_nontemporal_load(ent + idx) : 0u;
+            for (int u = 0; u < UNMAX; ++u) {
+                const uint32_t idx = e0 + EPS + u * EPI;
+                wn[u] = (u < un && idx < end) ? __builtin_nontemporal_load(ent + idx) : 0u;
             }
-            uint32_t xv[UN][NWD];
+            uint32_t xv[UNMAX][NWD];
 #pragma unroll
-            for (int u = 0; u < UN; ++u) {
+            for (int u = 0; u < UNMAX; ++u) {
                 const uint32_t idx = e0 + u * EPI;
-                if (idx < end) {
+                if (u < un && idx < end) {
                     while (idx >= knext) knext = tp[++k + 1];
                     const size_t xr = ((size_t)k << cb) + ((w[u] >> vb) & cmask);
                     ldw<NWD>(X + xr * W + q * CPL, xv[u]);
                 }
             }
 #pragma unroll
-            for (int u = 0; u < UN; ++u) {
-                if (e0 + u * EPI < end) {
+            for (int u = 0; u < UNMAX; ++u) {
+                if (u < un && e0 + u * EPI < end) {
                     const int lr = (int)(w[u] >> rsh);
                     const int32_t a = (int32_t)(w[u] << vsh) >> vsh;
 #pragma unroll
                     for (int c = 0; c < CPL; ++c) {
                         const uint32_t x = residue<E>(xv[u], c);
                         if constexpr (SPLIT) {
-                            atomicAdd(&acc[(q * CPL + c) * RS + lr], a * (int32_t)(x & 0xffffu));
-                            atomicAdd(&acc[(W + q * CPL + c) * RS + lr], a * (int32_t)(x >> 16));
+                            atomicAdd(&acc[(q * CPL + c) * RS + lr], __mul24(a, (int32_t)(x & 0xffffu)));
+                            atomicAdd(&acc[(W + q * CPL + c) * RS + lr], __mul24(a, (int32_t)(x >> 16)));
                         } else {
-                            atomicAdd(&acc[(q * CPL + c) * RS + lr], a * (int32_t)x);
+                            atomicAdd(&acc[(q * CPL + c) * RS + lr], __mul24(a, (int32_t)x));
                         }
                     }
                 }
@@ -248,6 +252,12 @@ __global__ __launch_bounds__(TT) void k_spmm_tiled(int64_t nrows, int64_t nrb, i
             stw<NWD>(Y + (size_t)row * W + qq * CPL, yw);
         }
         if constexpr (PROJ) {
+            // 4 x 4 tiles of this row block's partial per thread (live only here, not in the gather loop)
+            PAcc pacc[4][4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) pacc[a][b] = 0;
             __syncthreads();
             // 4 rows per round, their U loads issued together
             for (int r0 = pg; r0 < nr; r0 += 4 * NG) {
@@ -286,21 +296,29 @@ __global__ __launch_bounds__(TT) void k_spmm_tiled(int64_t nrows, int64_t nrb, i
                         }
                 }
             }
+            // the threads' tiles meet in W x W 64-bit LDS sums (over the reduced rows, now read)
+            __syncthreads();
+            unsigned long long* red = reinterpret_cast<unsigned long long*>(lds);
+            for (int e = threadIdx.x; e < W * W; e += TT) red[e] = 0;
+            __syncthreads();
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    atomicAdd(&red[(pti * 4 + a) * W + ptj * 4 + b], (unsigned long long)pacc[a][b]);
+            __syncthreads();
+#pragma unroll
+            for (int h = 0; h < NTOT; ++h)
+                if (threadIdx.x + h * TT < W * W) tot[h] += red[threadIdx.x + h * TT];
         }
         __syncthreads();
     }
     if constexpr (PROJ) {
-        // the threads' partials meet in W x W 64-bit LDS sums; one W x W partial per workgroup
-        unsigned long long* red = reinterpret_cast<unsigned long long*>(lds);
-        for (int e = threadIdx.x; e < W * W; e += TT) red[e] = 0;
-        __syncthreads();
+        // one W x W partial per workgroup
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-                atomicAdd(&red[(pti * 4 + a) * W + ptj * 4 + b], (unsigned long long)pacc[a][b]);
-        __syncthreads();
-        for (int e = threadIdx.x; e < W * W; e += TT) partial[(size_t)blockIdx.x * W * W + e] = red64(mp, red[e]);
+        for (int h = 0; h < NTOT; ++h)
+            if (threadIdx.x + h * TT < W * W)
+                partial[(size_t)blockIdx.x * W * W + threadIdx.x + h * TT] = red64(mp, tot[h]);
     }
 }
 
@@ -369,37 +387,37 @@ hipError_t allow_max_lds(const void* fn, size_t want) {
 
 template <int W, typename E, bool SPLIT, int PM>
 hipError_t launch_t(const TiledOperand& t, const void* X, const uint32_t* scale, void* Y, const void* U,
-                    const uint32_t* wgt, uint32_t* partial, int grid, ModP mp, hipStream_t st) {
+                    const uint32_t* wgt, uint32_t* partial, const TiledLaunch& L, ModP mp, hipStream_t st) {
     const size_t lds = tiled_lds_bytes(W, SPLIT, PM != 0, t.R, t.K);
     hipError_t e = allow_max_lds(reinterpret_cast<const void*>(&k_spmm_tiled<W, E, SPLIT, PM>), lds);
-    if (e != hipSuccess || grid == 0) return e;  // grid 0: only raise the LDS limit (before a graph capture)
-    k_spmm_tiled<W, E, SPLIT, PM><<<(unsigned)grid, TT, lds, st>>>(
+    if (e != hipSuccess || L.grid == 0) return e;  // grid 0: only raise the LDS limit (before a graph capture)
+    k_spmm_tiled<W, E, SPLIT, PM><<<(unsigned)L.grid, TT, lds, st>>>(
         t.rows, t.nrb, t.K, t.R, t.R + 1, t.cb, t.vb, t.tile_ptr, t.ent, (const E*)X, scale, (E*)Y, (const E*)U,
-        wgt, partial, mp);
+        wgt, partial, L.un, mp);
     return hipGetLastError();
 }
 
 template <int W, typename E, bool SPLIT>
 hipError_t launch_m(const TiledOperand& t, int pmode, const void* X, const uint32_t* scale, void* Y, const void* U,
-                    const uint32_t* wgt, uint32_t* partial, int grid, ModP mp, hipStream_t st) {
+                    const uint32_t* wgt, uint32_t* partial, const TiledLaunch& L, ModP mp, hipStream_t st) {
     switch (pmode) {
-        case 0: return launch_t<W, E, SPLIT, 0>(t, X, scale, Y, U, wgt, partial, grid, mp, st);
-        case 1: return launch_t<W, E, SPLIT, 1>(t, X, scale, Y, U, wgt, partial, grid, mp, st);
-        case 2: return launch_t<W, E, SPLIT, 2>(t, X, scale, Y, U, wgt, partial, grid, mp, st);
+        case 0: return launch_t<W, E, SPLIT, 0>(t, X, scale, Y, U, wgt, partial, L, mp, st);
+        case 1: return launch_t<W, E, SPLIT, 1>(t, X, scale, Y, U, wgt, partial, L, mp, st);
+        case 2: return launch_t<W, E, SPLIT, 2>(t, X, scale, Y, U, wgt, partial, L, mp, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <int W>
 hipError_t launch_w(const TiledOperand& t, int pmode, bool split, int esize, const void* X, const uint32_t* scale,
-                    void* Y, const void* U, const uint32_t* wgt, uint32_t* partial, int grid, ModP mp,
+                    void* Y, const void* U, const uint32_t* wgt, uint32_t* partial, const TiledLaunch& L, ModP mp,
                     hipStream_t st) {
     if (esize == 2) {
         if (split) return hipErrorInvalidValue;
-        return launch_m<W, uint16_t, false>(t, pmode, X, scale, Y, U, wgt, partial, grid, mp, st);
+        return launch_m<W, uint16_t, false>(t, pmode, X, scale, Y, U, wgt, partial, L, mp, st);
     }
-    if (split) return launch_m<W, uint32_t, true>(t, pmode, X, scale, Y, U, wgt, partial, grid, mp, st);
-    return launch_m<W, uint32_t, false>(t, pmode, X, scale, Y, U, wgt, partial, grid, mp, st);
+    if (split) return launch_m<W, uint32_t, true>(t, pmode, X, scale, Y, U, wgt, partial, L, mp, st);
+    return launch_m<W, uint32_t, false>(t, pmode, X, scale, Y, U, wgt, partial, L, mp, st);
 }
 
 }  // namespace
@@ -439,30 +457,31 @@ hipError_t launch_tiled_build(int64_t rows, int64_t nrb, const int32_t* rp, cons
 hipError_t prepare_spmm_tiled(const TiledOperand& t, int W, int pmode, bool split, int esize) {
     if (esize != 2 && esize != 4) return hipErrorInvalidValue;
     const ModP mp = ModP::make(split ? 2147483647u : 65521u);
+    const TiledLaunch L{};  // grid 0
     switch (W) {
-        case 4: return launch_w<4>(t, pmode, split, esize, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, mp, 0);
-        case 8: return launch_w<8>(t, pmode, split, esize, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, mp, 0);
-        case 16: return launch_w<16>(t, pmode, split, esize, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, mp, 0);
-        case 32: return launch_w<32>(t, pmode, split, esize, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, mp, 0);
-        case 64: return launch_w<64>(t, pmode, split, esize, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, mp, 0);
+        case 4: return launch_w<4>(t, pmode, split, esize, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, L, mp, 0);
+        case 8: return launch_w<8>(t, pmode, split, esize, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, L, mp, 0);
+        case 16: return launch_w<16>(t, pmode, split, esize, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, L, mp, 0);
+        case 32: return launch_w<32>(t, pmode, split, esize, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, L, mp, 0);
+        case 64: return launch_w<64>(t, pmode, split, esize, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, L, mp, 0);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_spmm_tiled(const TiledOperand& t, int W, int pmode, bool split, int esize, const void* X,
                              const uint32_t* scale, void* Y, const void* U, const uint32_t* wgt, uint32_t* partial,
-                             int grid, ModP mp, hipStream_t st) {
-    if (grid < 1 || t.R < 1 || t.nrb < 1 || t.nrb * (int64_t)t.R < t.rows || t.K < 1 || t.cb < 1 || t.vb < 2 ||
-        t.rb + t.cb + t.vb > 32 || (1LL << t.rb) < t.R || pmode < 0 || pmode > 2 ||
-        (pmode == 1 && (!U || !partial)) || (pmode == 2 && (!wgt || !partial)) || (esize != 2 && esize != 4) ||
-        split != (mp.p > 65536u))
+                             const TiledLaunch& L, ModP mp, hipStream_t st) {
+    if (L.grid < 1 || L.un < 1 || L.un > UNMAX || t.R < 1 || t.nrb < 1 ||
+        t.nrb * (int64_t)t.R < t.rows || t.K < 1 || t.cb < 1 || t.vb < 2 || t.vb > 24 || t.rb + t.cb + t.vb > 32 ||
+        (1LL << t.rb) < t.R || pmode < 0 || pmode > 2 || (pmode == 1 && (!U || !partial)) ||
+        (pmode == 2 && (!wgt || !partial)) || (esize != 2 && esize != 4) || split != (mp.p > 65536u))
         return hipErrorInvalidValue;
     switch (W) {
-        case 4: return launch_w<4>(t, pmode, split, esize, X, scale, Y, U, wgt, partial, grid, mp, st);
-        case 8: return launch_w<8>(t, pmode, split, esize, X, scale, Y, U, wgt, partial, grid, mp, st);
-        case 16: return launch_w<16>(t, pmode, split, esize, X, scale, Y, U, wgt, partial, grid, mp, st);
-        case 32: return launch_w<32>(t, pmode, split, esize, X, scale, Y, U, wgt, partial, grid, mp, st);
-        case 64: return launch_w<64>(t, pmode, split, esize, X, scale, Y, U, wgt, partial, grid, mp, st);
+        case 4: return launch_w<4>(t, pmode, split, esize, X, scale, Y, U, wgt, partial, L, mp, st);
+        case 8: return launch_w<8>(t, pmode, split, esize, X, scale, Y, U, wgt, partial, L, mp, st);
+        case 16: return launch_w<16>(t, pmode, split, esize, X, scale, Y, U, wgt, partial, L, mp, st);
+        case 32: return launch_w<32>(t, pmode, split, esize, X, scale, Y, U, wgt, partial, L, mp, st);
+        case 64: return launch_w<64>(t, pmode, split, esize, X, scale, Y, U, wgt, partial, L, mp, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def fake_plan(tiled=True):
     return {"W": 16, "G1": 4, "G2": 4, "fused": 1, "NB": 256, "esize": 2, "parts1": 1, "parts2": 1,
             "T1R": 1954 if tiled else 0, "T1cb": 13, "T1grid": 256, "T2R": 1954 if tiled else 0, "T2cb": 13,
-            "T2grid": 256}
+            "T2grid": 256, "T1un": 1, "T2un": 1}
 
 
 def test_roofline_entry_dominant_kernel_and_arithmetic():

@@ -97,8 +97,8 @@ def test_tiled_apply_full_output(p, s, monkeypatch):
 
 @pytest.mark.parametrize("p", [65521, 2**31 - 1])
 def test_tiled_default_geometry(p, monkeypatch):
-    """Default geometry (row blocks as large as the LDS allows, megabyte slabs) on a matrix with several
-    row blocks per workgroup slot's first round: 6 terms."""
+    """Default geometry (one round of row blocks over every CU, slabs of 128 KB of the block) on a matrix
+    with fewer rows than one LDS-sized row block per CU holds: 6 terms."""
     need_gpu()
     announce(f"tiled default geometry p={p}")
     monkeypatch.setenv("BWR_TILED", "1")
@@ -126,3 +126,37 @@ def test_tiled_ranks_equal_elimination(p, monkeypatch):
     r2, info = bw.rank_modp(B, p, 8, 1)
     assert info["transposed"] == 1
     assert r2 == 700 == ge.rank_csr(B, p)
+
+
+@pytest.mark.parametrize("un", [1, 2, 3, 4])
+@pytest.mark.parametrize("p", [65521, 2**31 - 1])
+def test_tiled_entries_in_flight(un, p, monkeypatch):
+    """1 .. 4 entries in flight per lane: row blocks of about 64 rows, 96 workgroups over 512 row blocks
+    (grid-stride rounds of unequal length); 6 terms and one application of B against the oracle, then a
+    graph-replayed 300-term run with row blocks of 16 rows."""
+    torch = need_gpu()
+    announce(f"tiled entries in flight un={un} p={p}")
+    monkeypatch.setenv("BWR_TILED", "1")
+    monkeypatch.setenv("BWR_TILED_R", "64")
+    monkeypatch.setenv("BWR_TILED_SLAB", str(256 * 16 * 4))
+    monkeypatch.setenv("BWR_TILED_GRID", "96")
+    monkeypatch.setenv("BWR_TILED_UN", str(un))
+    A = planted(30000, 20000, 17000, 9, 4343)
+    rng = np.random.default_rng(un)
+    U, V = blocks(rng, A.n, 16, p)
+    dr = rng.integers(1, p, size=A.m)
+    dc = rng.integers(1, p, size=A.n)
+    got = bw.sequence(A, U, V, p, 6, dr, dc)
+    orc = oseq.Oracle(A.m, A.n, A.row_ptr, A.col_idx, A.val, p, dr, dc)
+    assert np.array_equal(got.astype(np.int64), orc.sequence(U, V, 6))
+    Ad = bw.csr_to_device(A)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.int64).astype(np.uint32).view(np.int32)).cuda()
+    Z = bw.apply_dev(Ad, t(V), p, t(dr), t(dc))
+    torch.cuda.synchronize()
+    assert np.array_equal(Z.cpu().numpy().view(np.uint32).astype(np.int64), orc.apply(V))
+    B = planted(3000, 2200, 1900, 7, 4444)
+    monkeypatch.setenv("BWR_TILED_R", "16")
+    monkeypatch.setenv("BWR_TILED_SLAB", str(16 * 8 * 4))
+    U8, V8 = blocks(rng, B.n, 8, p)
+    got = bw.sequence(B, U8, V8, p, 300)
+    assert np.array_equal(got.astype(np.int64), oseq.sequence(B, U8, V8, p, 300))
