@@ -404,10 +404,10 @@ bool tile_geometry(int64_t rows, int64_t cols, int W, int esize, bool split, boo
 }
 
 // Tiled geometries the autotuner tries: row blocks for one or two workgroups per CU, slabs of 128 to 512 KB of
-// the block (measured at the 2M x 1M size: larger slabs lose, 256 and 128 KB are within a few per cent), one or
-// two entries in flight per lane (one won at that size: a pass then spans fewer slabs).  BWR_TILED_WGS,
-// BWR_TILED_SLAB (bytes), BWR_TILED_R (cap on the row block), BWR_TILED_GRID (cap on the workgroups) and
-// BWR_TILED_UN (entries in flight) pin one geometry.
+// the block (measured at the 2M x 1M size: larger slabs lose, 256 and 128 KB are within a few per cent), one, two
+// or four entries in flight per lane (a pass of fewer entries spans fewer slabs, more entries keep more memory
+// requests in flight).  BWR_TILED_WGS, BWR_TILED_SLAB (bytes), BWR_TILED_R (cap on the row block),
+// BWR_TILED_GRID (cap on the workgroups) and BWR_TILED_UN (entries in flight) pin one geometry.
 std::vector<StepPlan::Tile> tile_candidates(int64_t rows, int64_t cols, int W, int esize, bool split, bool proj,
                                             int32_t max_abs) {
     std::vector<StepPlan::Tile> out;
@@ -428,7 +428,7 @@ std::vector<StepPlan::Tile> tile_candidates(int64_t rows, int64_t cols, int W, i
                 if (atoi(eg) == -1) t.grid = (int)t.nrb;  // one workgroup per row block
             }
             const char* eu = getenv("BWR_TILED_UN");
-            for (int un : eu ? std::vector<int>{std::min(4, std::max(1, atoi(eu)))} : std::vector<int>{1, 2}) {
+            for (int un : eu ? std::vector<int>{std::min(4, std::max(1, atoi(eu)))} : std::vector<int>{1, 2, 4}) {
                 t.un = un;
                 bool dup = false;
                 for (const auto& o : out)
@@ -777,15 +777,28 @@ Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl
     const bool split = !smallp;
     const bool tiles_on = M.packed && M.nnz >= (1 << 20) && env_int("BWR_TILED", -1) != 0;
     std::vector<StepPlan::Tile> tc1, tc2;
-    std::vector<TiledOp> to1, to2;
+    std::vector<TiledOp> to1, to2;  // one encoding per distinct geometry; b1[i], b2[i]: candidate i's
     if (tiles_on && pl->G1 > 0 && tiled_acc_ok(M, op1.max_len, mp.p))
         tc1 = tile_candidates(op1.rows, nb, W, pl->esize, split, false, M.max_abs);
     if (tiles_on && pl->G2 > 0 && tiled_acc_ok(M, op2.max_len, mp.p))
         tc2 = tile_candidates(op2.rows, outer, W, pl->esize, split, true, M.max_abs);
-    to1.resize(tc1.size());
-    to2.resize(tc2.size());
-    for (size_t i = 0; i < tc1.size(); ++i) BWR_TRY(build_tiled(op1, nb, M.nnz, M.max_abs, tc1[i], st, &to1[i]));
-    for (size_t i = 0; i < tc2.size(); ++i) BWR_TRY(build_tiled(op2, outer, M.nnz, M.max_abs, tc2[i], st, &to2[i]));
+    // candidates that differ only in their launch (entries in flight) share one encoding
+    auto encodings = [&](const Operand& op, int64_t cols, const std::vector<StepPlan::Tile>& tc,
+                         std::vector<TiledOp>* to, std::vector<size_t>* b) -> Error {
+        std::vector<const StepPlan::Tile*> geo;
+        for (const StepPlan::Tile& t : tc) {
+            size_t j = 0;
+            while (j < geo.size() && !(geo[j]->R == t.R && geo[j]->cb == t.cb && geo[j]->nrb == t.nrb)) ++j;
+            if (j == geo.size()) geo.push_back(&t);
+            b->push_back(j);
+        }
+        to->resize(geo.size());
+        for (size_t j = 0; j < geo.size(); ++j) BWR_TRY(build_tiled(op, cols, M.nnz, M.max_abs, *geo[j], st, &(*to)[j]));
+        return {};
+    };
+    std::vector<size_t> b1, b2;
+    BWR_TRY(encodings(op1, nb, tc1, &to1, &b1));
+    BWR_TRY(encodings(op2, outer, tc2, &to2, &b2));
     pl->t1 = StepPlan::Tile{};
     pl->t2 = StepPlan::Tile{};
     if (pl->G1 > 0) {
@@ -804,9 +817,9 @@ Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl
         for (size_t i = 0; i < tc1.size(); ++i) {
             gs.push_back(-1 - (int)i);
             runs.push_back([&, i]() -> Error {
-                hipError_t e = launch_spmm_tiled(to1[i].v, W, 0, split, pl->esize, X.as<void>(), nullptr,
+                hipError_t e = launch_spmm_tiled(to1[b1[i]].v, W, 0, split, pl->esize, X.as<void>(), nullptr,
                                                  Y.as<void>(), nullptr, nullptr, nullptr,
-                                                 tiled_launch(to1[i], tc1[i]), mp, st);
+                                                 tiled_launch(to1[b1[i]], tc1[i]), mp, st);
                 return e == hipSuccess ? Error{} : Error::device(e, "autotune (tiled)");
             });
         }
@@ -869,9 +882,9 @@ Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl
         for (size_t i = 0; i < tc2.size(); ++i) {
             cs.push_back({-1 - (int)i, tc2[i].grid, true});
             runs.push_back([&, i]() -> Error {
-                hipError_t e = launch_spmm_tiled(to2[i].v, W, 1, split, pl->esize, Y.as<void>(), nullptr,
+                hipError_t e = launch_spmm_tiled(to2[b2[i]].v, W, 1, split, pl->esize, Y.as<void>(), nullptr,
                                                  Z.as<void>(), U.as<void>(), nullptr, part.as<uint32_t>(),
-                                                 tiled_launch(to2[i], tc2[i]), mp, st);
+                                                 tiled_launch(to2[b2[i]], tc2[i]), mp, st);
                 return e == hipSuccess ? Error{} : Error::device(e, "autotune (tiled)");
             });
         }
