@@ -320,8 +320,12 @@ int bwr_sequence_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* pr
  * requests: encoded matrix, blocks and sequence, plus the upload of one being
  * encoded) and the slot count allow.  A finished sequence gets
  * its sigma-basis and read-out and the request is answered; results are
- * identical to bwr_rank_modp(A, p, block, seed).  Calls on one server are
- * thread-safe. */
+ * identical to bwr_rank_modp(A, p, block, seed).  A request with at least
+ * 2^20 non-zeros (BWR_SERVER_SOLO_NNZ; 0 sends every request to the batches)
+ * skips the batches: it is ranked by the single-matrix path (autotuned,
+ * tiled products) on a lane of its own that runs one such request at a time
+ * beside the batches, admitted against the same budget.  Calls on one server
+ * are thread-safe. */
 typedef struct bwr_server bwr_server;
 
 typedef struct {
@@ -420,7 +424,7 @@ int bwr_rank_from_sequence(const uint32_t* S, int64_t len, int64_t check, int32_
  *   BWR_BATCH_CHUNK        steps per batched graph (even, default 64)
  *   BWR_READOUT_THREADS    host threads reading out finished batched or
  *                          served sequences (default 3)
- *   BWR_SERVER_AHEAD       see the serving section
+ *   BWR_SERVER_AHEAD, BWR_SERVER_SOLO_NNZ  see the serving section
  *   BWR_SERVER_FAIL_ADVANCE=k  (tests of error handling) the server's
  *                          advance after k advances reports an error instead
  *                          of launching, once; the requests in its batches

@@ -429,6 +429,16 @@ BatchPlan plan_batch(const std::vector<Shape>& shapes, int nprimes, int s) {
 
 }  // namespace
 
+// The single-matrix rank of a device CSR, as bwr_rank_modp_dev with `trials` draws (the server's lane for
+// large requests).
+Error bwr::rank_single(const CsrView& A_dev, uint32_t p, int32_t block, uint64_t seed, int32_t trials,
+                       hipStream_t st, int64_t* rank) {
+    RankOut ro;
+    Error e = rank_dev_impl(A_dev, p, block, seed, st, &ro, trials);
+    if (e.ok()) *rank = ro.rank;
+    return e;
+}
+
 struct bwr_server {
     std::unique_ptr<bwr::Server> impl;
 };

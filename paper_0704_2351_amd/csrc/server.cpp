@@ -62,6 +62,7 @@ struct Server::Req {
     int64_t transient = 0;  // extra device bytes while it is being uploaded and encoded
     bool counted = false;   // footprint counted in held_
     double arrival = 0, admitted = 0, finished = 0;
+    bool solo = false;  // runs through the single-matrix path (solo lane)
     int cls = 1;  // runner: 0 for primes <= 2^16, 1 otherwise
     int job = -1;
     bool done = false;
@@ -94,7 +95,10 @@ Error Server::start() {
     if (!batch_supported(W_, G2_, true)) G2_ = W_ / 4;
     runners_[0] = std::make_unique<BatchRunner>(W_, G1_, G2_, compute_[0], 2);
     runners_[1] = std::make_unique<BatchRunner>(W_, G1_, G2_, compute_[1], 4);
+    solo_nnz_ = 1 << 20;
+    if (const char* v = getenv("BWR_SERVER_SOLO_NNZ")) solo_nnz_ = std::max<int64_t>(0, atoll(v));
     worker_ = std::thread([this] { loop(); });
+    if (solo_nnz_ > 0) solo_ = std::thread([this] { solo_loop(); });
     return {};
 }
 
@@ -105,7 +109,10 @@ void Server::stop() {
     }
     cv_.notify_all();
     done_cv_.notify_all();
+    solo_cv_.notify_all();
     if (worker_.joinable()) worker_.join();
+    if (solo_.joinable()) solo_.join();
+    solo_q_.clear();
     runners_[0].reset();
     runners_[1].reset();
     reqs_.clear();
@@ -159,6 +166,15 @@ Error Server::submit(const CsrView& A, uint32_t p, uint64_t seed, int32_t trials
         // the uploaded CSR (int64 row pointers, int32 columns and values) and the relabelled copy the encoder
         // builds from it, with its counters
         R->transient = 2 * (8 * (A.m + 1) + 8 * A.nnz) + 16 * std::max(A.m, A.n) + 4096;
+        if (solo_nnz_ > 0 && A.nnz >= solo_nnz_) {
+            // the single-matrix path's device memory: encoded CSR of A and A^T with their relabellings, the
+            // tiled encodings its autotuner builds (at most six geometries per product) and keeps, the blocks,
+            // the sequence and the sigma-basis (about 2 (2s)^2 L words)
+            R->solo = true;
+            R->footprint = 64 * A.nnz + 64 * (A.m + A.n + 2) + 16 * std::max(A.m, A.n) * R->s +
+                           8LL * (4 * R->s * R->s) * (R->L + CHECK_TERMS);
+            R->transient = 2 * (8 * (A.m + 1) + 8 * A.nnz);
+        }
         if (R->footprint + R->transient > budget_) return Error{ENOMEM_, "request larger than the server's HBM budget"};
         R->hrp.assign(A.row_ptr, A.row_ptr + A.m + 1);
         R->hcol.assign(A.col_idx, A.col_idx + A.nnz);
@@ -172,6 +188,9 @@ Error Server::submit(const CsrView& A, uint32_t p, uint64_t seed, int32_t trials
         latencies_.push_back(R->finished - R->arrival);
         ++completed_;
         done_cv_.notify_all();
+    } else if (R->solo) {
+        solo_q_.push_back(R);
+        solo_cv_.notify_all();
     } else {
         queue_.push_back(R->ticket);
         max_queue_ = std::max<int64_t>(max_queue_, (int64_t)queue_.size());
@@ -265,6 +284,63 @@ void Server::answer_locked(Req& R, int code, const std::string& msg, int64_t ran
     R.counted = false;
     R.M = DeviceMatrix();
     done_cv_.notify_all();
+    solo_cv_.notify_all();  // memory left the budget
+}
+
+// The solo lane: one large request at a time, admitted against the same budget as the batches, uploaded on
+// the lane's stream and ranked by the single-matrix path (trials draws, the largest rank kept).
+void Server::solo_loop() {
+    (void)hipSetDevice(device_);
+    hipStream_t st = nullptr;
+    const hipError_t se = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    for (;;) {
+        std::shared_ptr<Req> R;
+        {
+            std::unique_lock<std::mutex> lk(mu_);
+            solo_cv_.wait(lk, [&] {
+                if (quit_) return true;
+                if (solo_q_.empty()) return false;
+                const Req& F = *solo_q_.front();
+                return held_ == 0 || held_ + F.footprint + F.transient <= budget_;
+            });
+            if (quit_) break;
+            R = solo_q_.front();
+            solo_q_.pop_front();
+            held_ += R->footprint + R->transient;
+            peak_held_ = std::max(peak_held_, held_);
+            R->counted = true;
+            R->admitted = now_s();
+        }
+        Error e;
+        int64_t rank = 0;
+        if (se != hipSuccess) {
+            e = Error::device(se, "server solo stream");
+        } else {
+            DevBuf rp, col, val;
+            const size_t nnz = (size_t)R->nnz;
+            e = rp.alloc(sizeof(int64_t) * (size_t)(R->m + 1), st);
+            if (e.ok()) e = col.alloc(4 * std::max<size_t>(nnz, 1), st);
+            if (e.ok()) e = val.alloc(4 * std::max<size_t>(nnz, 1), st);
+            hipError_t he = hipSuccess;
+            if (e.ok()) he = hipMemcpyAsync(rp.as<void>(), R->hrp.data(), 8 * R->hrp.size(), hipMemcpyHostToDevice, st);
+            if (e.ok() && he == hipSuccess && nnz)
+                he = hipMemcpyAsync(col.as<void>(), R->hcol.data(), 4 * nnz, hipMemcpyHostToDevice, st);
+            if (e.ok() && he == hipSuccess && nnz)
+                he = hipMemcpyAsync(val.as<void>(), R->hval.data(), 4 * nnz, hipMemcpyHostToDevice, st);
+            if (e.ok() && he != hipSuccess) e = Error::device(he, "server upload");
+            if (e.ok()) {
+                const CsrView dv{R->m, R->n, R->nnz, rp.as<int64_t>(), col.as<int32_t>(), val.as<int32_t>()};
+                e = rank_single(dv, R->p, block_, R->seed, R->trials, st, &rank);
+            }
+            (void)hipStreamSynchronize(st);  // the uploads and everything reading them are done
+        }
+        std::lock_guard<std::mutex> lk(mu_);
+        R->hrp = std::vector<int64_t>();
+        R->hcol = std::vector<int32_t>();
+        R->hval = std::vector<int32_t>();
+        answer_locked(*R, e.ok() ? 0 : e.code, e.msg, e.ok() ? rank : 0);
+    }
+    if (se == hipSuccess) (void)hipStreamDestroy(st);
 }
 
 void Server::loop() {

@@ -18,6 +18,10 @@
 
 namespace bwr {
 
+// The single-matrix rank of a device CSR with `trials` independent draws (defined with the C-ABI).
+Error rank_single(const CsrView& A_dev, uint32_t p, int32_t block, uint64_t seed, int32_t trials, hipStream_t st,
+                  int64_t* rank);
+
 struct ServerStats {
     double p50_ms, p99_ms;  // latency = answer time - submit time
     double solves_per_s;    // completed / (last answer - first submit)
@@ -42,6 +46,7 @@ class Server {
    private:
     struct Req;
     void loop();
+    void solo_loop();
     Error encode(Req& R);
     void answer_locked(Req& R, int code, const std::string& msg, int64_t rank);
     int64_t budget_;
@@ -63,6 +68,13 @@ class Server {
     bool ahead_rec_[2][MAX_AHEAD] = {};
     int ahead_pos_[2] = {0, 0};
     std::thread worker_;
+    // requests of at least solo_nnz_ non-zeros (BWR_SERVER_SOLO_NNZ, 0: none) run one at a time through the
+    // single-matrix path (autotuned, tiled products) on a thread of their own, beside the batches: the batched
+    // kernels lose to the tuned single-matrix ones once a job's block outgrows an XCD's L2
+    int64_t solo_nnz_ = 0;
+    std::thread solo_;
+    std::deque<std::shared_ptr<Req>> solo_q_;
+    std::condition_variable solo_cv_;
     std::mutex mu_, upload_mu_;
     std::condition_variable cv_, done_cv_;
     std::map<uint64_t, std::shared_ptr<Req>> reqs_;

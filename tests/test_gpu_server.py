@@ -157,3 +157,42 @@ def test_server_failed_advance_answers_and_recovers(monkeypatch):
     srv.close()
     assert ranks == [A.planted_rank for A, _, _ in later]
     assert st["completed"] == 7
+
+
+def test_server_solo_lane(monkeypatch):
+    """Requests of at least BWR_SERVER_SOLO_NNZ non-zeros run through the single-matrix path on the server's
+    solo lane while the batches run the others: every answer equals the planted rank and the plain
+    single-matrix rank, also with two draws per request and with a budget that admits one request at a time."""
+    need_gpu()
+    announce("server solo lane")
+    monkeypatch.setenv("BWR_SERVER_SOLO_NNZ", "20000")
+    reqs = requests(8, 4) + [(planted(24000, 16000, 13000, 9, 7777), 65521, 5),
+                             (planted(30000, 20000, 15000, 9, 7778), 2**31 - 1, 6)]
+    assert sum(A.nnz >= 20000 for A, _, _ in reqs) >= 3 and sum(A.nnz < 20000 for A, _, _ in reqs) >= 3
+    srv = bw.Server(4 << 30, 16, 8)
+    tickets = [srv.submit(A, p, sd) for A, p, sd in reqs]
+    ranks = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    announce(f"  stats {st}")
+    assert ranks == [A.planted_rank for A, _, _ in reqs]
+    assert st["completed"] == len(reqs)
+    for A, p, sd in reqs[-2:]:
+        assert bw.rank_modp(A, p, 8, sd)[0] == A.planted_rank
+    bw.set_trials(2)
+    try:
+        srv = bw.Server(4 << 30, 16, 8)
+        tickets = [srv.submit(A, p, sd) for A, p, sd in reqs[-3:]]
+        assert [srv.wait(t) for t in tickets] == [A.planted_rank for A, _, _ in reqs[-3:]]
+        srv.close()
+    finally:
+        bw.set_trials(1)
+    # a budget near the largest single request: the lanes take turns, every answer still right
+    big = max(st["peak_bytes"] // 3, 64 << 20)
+    srv = bw.Server(big, 16, 8)
+    tickets = [srv.submit(A, p, sd) for A, p, sd in reqs]
+    assert [srv.wait(t) for t in tickets] == [A.planted_rank for A, _, _ in reqs]
+    st2 = srv.stats()
+    srv.close()
+    announce(f"  budget {big} stats {st2}")
+    assert 0 < st2["peak_bytes"] <= big
