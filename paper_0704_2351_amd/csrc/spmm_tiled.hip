@@ -39,6 +39,18 @@
 // (integer sums, so their order never changes the result), then one reduction
 // mod p, the row scale and a coalesced store per output entry.
 //
+// Packed accumulators (p <= 2^16): the sums of two adjacent columns share one
+// 64-bit word, T = 2^31 + sum_even + 2^32 sum_odd (mod 2^64), words row-major
+// (W / 2 per row).  A product pair is added as the signed 64-bit value
+// 2^32 a x_odd + a x_even with one 64-bit LDS atomic: since every partial sum
+// of a row stays within (-2^31, 2^31), the low half stays within [0, 2^32) and
+// never carries into the high half, so sum_even = low - 2^31 and sum_odd = the
+// high half exactly, whatever the order of the adds.  An entry's lanes visit
+// their column pairs in an order rotated by the entry's index, so the lanes of
+// one instruction spread over different LDS banks (measured at 2M x 1M,
+// block 16: the first product 19 % faster, the second 4 %, than one 32-bit add
+// per column in column-major order).
+//
 // Projection (PM = 1): after a row block is stored its reduced rows stay in LDS
 // and 4 x 4 tiles of the W x W partial U^T Z are accumulated per thread over
 // the rows it visits; the threads' tiles then meet in LDS (64-bit sums) and are
@@ -153,8 +165,16 @@ __global__ __launch_bounds__(TT) void k_spmm_tiled(int64_t nrows, int64_t nrb, i
     constexpr int NT = WB * WB;
     constexpr int NG = TT / NT;                  // row groups of the projection
     static_assert(W >= 4 && W <= 64 && (W & (W - 1)) == 0, "W must be a power of two in 4..64");
+    constexpr bool PK = !SPLIT;                  // packed 64-bit pairs, row-major (see the header)
+    constexpr int NP = CPL / 2;                  // column pairs of a lane
+    constexpr int WPP = NWD / NP;                // gathered words per column pair (1 or 2)
+    constexpr uint32_t BIAS = 0x80000000u;
+    static_assert(!PK || (CPL % 2 == 0 && (NP & (NP - 1)) == 0), "packed pairs need an even power-of-two CPL");
     int32_t* acc = lds;
+    unsigned long long* acc64 = reinterpret_cast<unsigned long long*>(lds);
     uint32_t* tp = reinterpret_cast<uint32_t*>(lds + NACC * RS);
+    // LDS index of the reduced value of column c of local row r (kept in place of the accumulators)
+    auto zix = [&](int c, int r) { return PK ? r * W + c : c * RS + r; };
     const int q = threadIdx.x % LPE;
     const int es = threadIdx.x / LPE;
     const uint32_t cmask = (1u << cb) - 1u;
@@ -173,7 +193,11 @@ __global__ __launch_bounds__(TT) void k_spmm_tiled(int64_t nrows, int64_t nrb, i
     const uint32_t EPS = (uint32_t)un * EPI;  // entries per pass
     for (int64_t rb = blockIdx.x; rb < nrb; rb += gridDim.x) {
         int4* acc4 = reinterpret_cast<int4*>(acc);
-        for (int i = threadIdx.x; i < NACC * RS / 4; i += TT) acc4[i] = make_int4(0, 0, 0, 0);
+        if constexpr (PK) {
+            for (int i = threadIdx.x; i < R * W / 4; i += TT) acc4[i] = make_int4((int)BIAS, 0, (int)BIAS, 0);
+        } else {
+            for (int i = threadIdx.x; i < NACC * RS / 4; i += TT) acc4[i] = make_int4(0, 0, 0, 0);
+        }
         for (int i = threadIdx.x; i <= K; i += TT) tp[i] = tile_ptr[rb * K + i];
         __syncthreads();
         const uint32_t end = tp[K];
@@ -212,14 +236,33 @@ __global__ __launch_bounds__(TT) void k_spmm_tiled(int64_t nrows, int64_t nrb, i
                 if (u < un && e0 + u * EPI < end) {
                     const int lr = (int)(w[u] >> rsh);
                     const int32_t a = (int32_t)(w[u] << vsh) >> vsh;
+                    if constexpr (PK) {
+                        // rotate the lane's pairs by the entry's index (selects on registers), then pair j of
+                        // the rotated order is the lane's pair (j + rot) mod NP
+                        const int rot = (int)(es + u * EPI) & (NP - 1);
+                        uint32_t* v = xv[u];
 #pragma unroll
-                    for (int c = 0; c < CPL; ++c) {
-                        const uint32_t x = residue<E>(xv[u], c);
-                        if constexpr (SPLIT) {
+                        for (int b = 1; b < NP; b <<= 1) {
+                            uint32_t t[NWD];
+#pragma unroll
+                            for (int h = 0; h < NWD; ++h) t[h] = v[(h + b * WPP) % NWD];
+#pragma unroll
+                            for (int h = 0; h < NWD; ++h) v[h] = (rot & b) ? t[h] : v[h];
+                        }
+                        unsigned long long* rowp = acc64 + (size_t)lr * (W / 2) + q * NP;
+#pragma unroll
+                        for (int j = 0; j < NP; ++j) {
+                            const int32_t lo = __mul24(a, (int32_t)residue<E>(v, 2 * j));
+                            const int32_t hi = __mul24(a, (int32_t)residue<E>(v, 2 * j + 1));
+                            const int64_t d = (int64_t)((uint64_t)(uint32_t)hi << 32) + (int64_t)lo;
+                            atomicAdd(rowp + ((j + rot) & (NP - 1)), (unsigned long long)d);
+                        }
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < CPL; ++c) {
+                            const uint32_t x = residue<E>(xv[u], c);
                             atomicAdd(&acc[(q * CPL + c) * RS + lr], __mul24(a, (int32_t)(x & 0xffffu)));
                             atomicAdd(&acc[(W + q * CPL + c) * RS + lr], __mul24(a, (int32_t)(x >> 16)));
-                        } else {
-                            atomicAdd(&acc[(q * CPL + c) * RS + lr], __mul24(a, (int32_t)x));
                         }
                     }
                 }
@@ -237,19 +280,29 @@ __global__ __launch_bounds__(TT) void k_spmm_tiled(int64_t nrows, int64_t nrb, i
             uint32_t yw[NWD];
 #pragma unroll
             for (int h = 0; h < NWD; ++h) yw[h] = 0;
+            if constexpr (PK) {
+                // the lane's NP words, read before the reduced values overwrite them in place
+                unsigned long long pw[NP];
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const int idx = (qq * CPL + c) * RS + r;
-                uint32_t y;
-                if constexpr (SPLIT) {
+                for (int j = 0; j < NP; ++j) pw[j] = acc64[(size_t)r * (W / 2) + qq * NP + j];
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    const unsigned long long t = pw[c / 2];
+                    const int32_t sum = (c & 1) ? (int32_t)(uint32_t)(t >> 32) : (int32_t)((uint32_t)t - BIAS);
+                    const uint32_t y = mulmod16(mp, reds32(mp, sum), sc);
+                    put_residue<E>(yw, c, y);
+                    if constexpr (PROJ) zl[zix(qq * CPL + c, r)] = y;
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    const int idx = (qq * CPL + c) * RS + r;
                     const uint32_t red =
                         reds64(mp, (int64_t)acc[(W + qq * CPL + c) * RS + r] * 65536 + (int64_t)acc[idx]);
-                    y = mulmod(mp, red, sc);
-                } else {
-                    y = mulmod16(mp, reds32(mp, acc[idx]), sc);
+                    const uint32_t y = mulmod(mp, red, sc);
+                    put_residue<E>(yw, c, y);
+                    if constexpr (PROJ) zl[idx] = y;
                 }
-                put_residue<E>(yw, c, y);
-                if constexpr (PROJ) zl[idx] = y;
             }
             stw<NWD>(Y + (size_t)row * W + qq * CPL, yw);
         }
@@ -275,7 +328,7 @@ __global__ __launch_bounds__(TT) void k_spmm_tiled(int64_t nrows, int64_t nrb, i
                         const uint32_t wr = wgt[rb + (int64_t)r * nrb];
 #pragma unroll
                         for (int a = 0; a < 4; ++a) {
-                            const uint32_t zi = zl[(pti * 4 + a) * RS + r];
+                            const uint32_t zi = zl[zix(pti * 4 + a, r)];
                             u[j][a] = SPLIT ? mulmod(mp, wr, zi) : mulmod16(mp, wr, zi);
                         }
                     }
@@ -286,7 +339,7 @@ __global__ __launch_bounds__(TT) void k_spmm_tiled(int64_t nrows, int64_t nrb, i
                     if (r >= nr) break;
                     uint32_t z[4];
 #pragma unroll
-                    for (int b = 0; b < 4; ++b) z[b] = zl[(ptj * 4 + b) * RS + r];
+                    for (int b = 0; b < 4; ++b) z[b] = zl[zix(ptj * 4 + b, r)];
 #pragma unroll
                     for (int a = 0; a < 4; ++a)
 #pragma unroll
