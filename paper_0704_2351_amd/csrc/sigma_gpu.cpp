@@ -53,11 +53,19 @@ Error device_tables(DevTables* out) {
         for (int t = 0; t < 3; ++t)
             ntt_tables(t, MAX_LG, &T.q[t], &h_tw[(2 * t) * N], &h_tw[(2 * t + 1) * N], &h_itw[(2 * t) * N],
                        &h_itw[(2 * t + 1) * N]);
+        // uploaded on a private non-blocking stream: an operation on the legacy stream would synchronize with
+        // every blocking stream, and fails while one of them is being captured into a graph by another thread
         uint32_t *a = nullptr, *b = nullptr;
-        BWR_HIP(hipMalloc(&a, h_tw.size() * 4));
-        BWR_HIP(hipMalloc(&b, h_itw.size() * 4));
-        BWR_HIP(hipMemcpy(a, h_tw.data(), h_tw.size() * 4, hipMemcpyHostToDevice));
-        BWR_HIP(hipMemcpy(b, h_itw.data(), h_itw.size() * 4, hipMemcpyHostToDevice));
+        hipStream_t up = nullptr;
+        BWR_HIP(hipStreamCreateWithFlags(&up, hipStreamNonBlocking));
+        hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&a), h_tw.size() * 4, up);
+        if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&b), h_itw.size() * 4, up);
+        if (e == hipSuccess) e = hipMemcpyAsync(a, h_tw.data(), h_tw.size() * 4, hipMemcpyHostToDevice, up);
+        if (e == hipSuccess) e = hipMemcpyAsync(b, h_itw.data(), h_itw.size() * 4, hipMemcpyHostToDevice, up);
+        const hipError_t es = hipStreamSynchronize(up);  // the host tables are read before they go out of scope
+        (void)hipStreamDestroy(up);
+        if (e == hipSuccess) e = es;
+        if (e != hipSuccess) return Error::device(e, "sigma-basis transform tables");
         T.tw = a;
         T.itw = b;
     }
