@@ -73,6 +73,7 @@ namespace {
 constexpr int TT = 1024;  // threads of a tiled workgroup (16 waves: one workgroup per CU, LDS-bound)
 constexpr int BTPB = 256;
 constexpr int UNMAX = 4;  // entries a lane keeps in flight per pass, at most
+typedef double dvec4 __attribute__((ext_vector_type(4)));  // accumulators of a 16 x 16 x 4 f64 MFMA
 
 // 4 residues (projection operands)
 __device__ __forceinline__ void ld4(const uint32_t* p, uint32_t (&x)[4]) {
@@ -166,6 +167,9 @@ __global__ __launch_bounds__(TT) void k_spmm_tiled(int64_t nrows, int64_t nrb, i
     constexpr int NG = TT / NT;                  // row groups of the projection
     static_assert(W >= 4 && W <= 64 && (W & (W - 1)) == 0, "W must be a power of two in 4..64");
     constexpr bool PK = !SPLIT;                  // packed 64-bit pairs, row-major (see the header)
+    // projection on the matrix cores for residues below 2^16 and W <= 32 (NTL 16-wide tiles per side)
+    constexpr bool MFP = PROJ && !SPLIT && W <= 32;
+    constexpr int NTL = W >= 16 ? W / 16 : 1;
     constexpr int NP = CPL / 2;                  // column pairs of a lane
     constexpr int WPP = NWD / NP;                // gathered words per column pair (1 or 2)
     constexpr uint32_t BIAS = 0x80000000u;
@@ -306,7 +310,64 @@ __global__ __launch_bounds__(TT) void k_spmm_tiled(int64_t nrows, int64_t nrb, i
             }
             stw<NWD>(Y + (size_t)row * W + qq * CPL, yw);
         }
-        if constexpr (PROJ) {
+        if constexpr (PROJ && MFP) {
+            // the block's partial as a dense contraction on the matrix cores: D (16 x 16 per tile pair) +=
+            // A (16 x 4) B (4 x 16) with A = the U (or weighted Z) values of 4 rows, transposed, and B = their
+            // reduced rows; lane l holds A[l % 16][l / 16] and B[l / 16][l % 16], i.e. both at row l / 16,
+            // column l % 16 of the 4 rows, and D[l / 16 + 4 i][l % 16] in its i-th accumulator.  Residues
+            // are below 2^16, so every product and every sum over the row block (fewer than 2^21 rows) is an
+            // integer below 2^53, exact in double precision.
+            const int ln = threadIdx.x & 63, wv = threadIdx.x >> 6, cc = ln & 15, kk = ln >> 4;
+            dvec4 dacc[NTL][NTL];
+#pragma unroll
+            for (int tm = 0; tm < NTL; ++tm)
+#pragma unroll
+                for (int tn = 0; tn < NTL; ++tn) dacc[tm][tn] = dvec4{0.0, 0.0, 0.0, 0.0};
+            __syncthreads();
+#pragma unroll 4
+            for (int rbase = wv * 4; rbase < nr; rbase += (TT / 64) * 4) {
+                const int r = rbase + kk;
+                double av[NTL], bv[NTL];
+#pragma unroll
+                for (int t = 0; t < NTL; ++t) {
+                    const int c = t * 16 + cc;
+                    uint32_t uu = 0, zz = 0;
+                    if (r < nr && c < W) {
+                        zz = zl[zix(c, r)];
+                        if constexpr (PM == 1)
+                            uu = (uint32_t)U[(size_t)(rb + (int64_t)r * nrb) * W + c];
+                        else
+                            uu = mulmod16(mp, wgt[rb + (int64_t)r * nrb], zz);
+                    }
+                    av[t] = (double)uu;
+                    bv[t] = (double)zz;
+                }
+#pragma unroll
+                for (int tm = 0; tm < NTL; ++tm)
+#pragma unroll
+                    for (int tn = 0; tn < NTL; ++tn)
+                        dacc[tm][tn] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[tm], bv[tn], dacc[tm][tn], 0, 0, 0);
+            }
+            // the waves' tiles meet in W x W 64-bit LDS sums (over the reduced rows, now read)
+            __syncthreads();
+            unsigned long long* red = reinterpret_cast<unsigned long long*>(lds);
+            for (int e = threadIdx.x; e < W * W; e += TT) red[e] = 0;
+            __syncthreads();
+#pragma unroll
+            for (int tm = 0; tm < NTL; ++tm)
+#pragma unroll
+                for (int tn = 0; tn < NTL; ++tn)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int mrow = tm * 16 + kk + 4 * i, ncol = tn * 16 + cc;
+                        if (mrow < W && ncol < W)
+                            atomicAdd(&red[mrow * W + ncol], (unsigned long long)dacc[tm][tn][i]);
+                    }
+            __syncthreads();
+#pragma unroll
+            for (int h = 0; h < NTOT; ++h)
+                if (threadIdx.x + h * TT < W * W) tot[h] += red[threadIdx.x + h * TT];
+        } else if constexpr (PROJ) {
             // 4 x 4 tiles of this row block's partial per thread (live only here, not in the gather loop)
             PAcc pacc[4][4];
 #pragma unroll
