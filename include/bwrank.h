@@ -410,7 +410,10 @@ int bwr_rank_from_sequence(const uint32_t* S, int64_t len, int64_t check, int32_
  *                          BWR_TILED_SLAB (bytes of the block per slab),
  *                          BWR_TILED_R (row block cap), BWR_TILED_GRID
  *                          (workgroup cap) and BWR_TILED_UN (entries in
- *                          flight per lane, 1-4) pin its geometry
+ *                          flight per lane, 1-4) pin its geometry;
+ *                          BWR_TILED_NO_STAGE=1 makes the fused projection
+ *                          load its operands directly instead of staging
+ *                          them in LDS
  *   BWR_NO_SORT=1          no length-sorted relabelling of rows and columns
  *   BWR_NO_GRAPH=1         launch every step instead of replaying HIP graphs
  *   BWR_HOST_SIGMA=1       sigma-basis on the host instead of the device

@@ -61,6 +61,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <mutex>
 #include <vector>
 
@@ -154,7 +155,7 @@ __global__ __launch_bounds__(TT) void k_spmm_tiled(int64_t nrows, int64_t nrb, i
                                                    const uint32_t* __restrict__ ent, const E* __restrict__ X,
                                                    const uint32_t* __restrict__ scale, E* __restrict__ Y,
                                                    const E* __restrict__ U, const uint32_t* __restrict__ wgt,
-                                                   uint32_t* __restrict__ partial, int un, ModP mp) {
+                                                   uint32_t* __restrict__ partial, int un, int sr, ModP mp) {
     constexpr bool PROJ = PM != 0;
     extern __shared__ __align__(16) int32_t lds[];
     constexpr int NACC = SPLIT ? 2 * W : W;
@@ -179,6 +180,10 @@ __global__ __launch_bounds__(TT) void k_spmm_tiled(int64_t nrows, int64_t nrb, i
     uint32_t* tp = reinterpret_cast<uint32_t*>(lds + NACC * RS);
     // LDS index of the reduced value of column c of local row r (kept in place of the accumulators)
     auto zix = [&](int c, int r) { return PK ? r * W + c : c * RS + r; };
+    // staging of the matrix-core projection's operands (sr > 0): the U rows (PM 1) or weights (PM 2) of sr rows
+    // at a time, after the tile pointers, 16-byte aligned
+    unsigned char* const stage =
+        reinterpret_cast<unsigned char*>(lds) + ((((size_t)NACC * RS + K + 1) * sizeof(int32_t) + 15) & ~(size_t)15);
     const int q = threadIdx.x % LPE;
     const int es = threadIdx.x / LPE;
     const uint32_t cmask = (1u << cb) - 1u;
@@ -324,29 +329,51 @@ __global__ __launch_bounds__(TT) void k_spmm_tiled(int64_t nrows, int64_t nrb, i
 #pragma unroll
                 for (int tn = 0; tn < NTL; ++tn) dacc[tm][tn] = dvec4{0.0, 0.0, 0.0, 0.0};
             __syncthreads();
-#pragma unroll 4
-            for (int rbase = wv * 4; rbase < nr; rbase += (TT / 64) * 4) {
-                const int r = rbase + kk;
-                double av[NTL], bv[NTL];
-#pragma unroll
-                for (int t = 0; t < NTL; ++t) {
-                    const int c = t * 16 + cc;
-                    uint32_t uu = 0, zz = 0;
-                    if (r < nr && c < W) {
-                        zz = zl[zix(c, r)];
-                        if constexpr (PM == 1)
-                            uu = (uint32_t)U[(size_t)(rb + (int64_t)r * nrb) * W + c];
-                        else
-                            uu = mulmod16(mp, wgt[rb + (int64_t)r * nrb], zz);
+            // rows in chunks of cs: with staging, every thread first copies its share of the chunk's U rows (or
+            // weights) into LDS, all loads in flight at once, so a chunk costs one memory latency
+            const int cs = sr > 0 ? sr : nr;
+            for (int c0 = 0; c0 < nr; c0 += cs) {
+                const int c1 = c0 + cs < nr ? c0 + cs : nr;
+                if (sr > 0) {
+                    if constexpr (PM == 1) {
+                        constexpr int PPR = W * (int)sizeof(E) / 8;  // 8-byte pieces of a U row
+                        for (int i = threadIdx.x; i < (c1 - c0) * PPR; i += TT)
+                            reinterpret_cast<uint2*>(stage)[i] = reinterpret_cast<const uint2*>(
+                                U + (size_t)(rb + (int64_t)(c0 + i / PPR) * nrb) * W)[i % PPR];
+                    } else {
+                        for (int i = threadIdx.x; i < c1 - c0; i += TT)
+                            reinterpret_cast<uint32_t*>(stage)[i] = wgt[rb + (int64_t)(c0 + i) * nrb];
                     }
-                    av[t] = (double)uu;
-                    bv[t] = (double)zz;
+                    __syncthreads();
                 }
+#pragma unroll 4
+                for (int rbase = c0 + wv * 4; rbase < c1; rbase += (TT / 64) * 4) {
+                    const int r = rbase + kk;
+                    double av[NTL], bv[NTL];
 #pragma unroll
-                for (int tm = 0; tm < NTL; ++tm)
+                    for (int t = 0; t < NTL; ++t) {
+                        const int c = t * 16 + cc;
+                        uint32_t uu = 0, zz = 0;
+                        if (r < c1 && c < W) {
+                            zz = zl[zix(c, r)];
+                            if constexpr (PM == 1)
+                                uu = sr > 0 ? (uint32_t)reinterpret_cast<const E*>(stage)[(r - c0) * W + c]
+                                            : (uint32_t)U[(size_t)(rb + (int64_t)r * nrb) * W + c];
+                            else
+                                uu = mulmod16(mp, sr > 0 ? reinterpret_cast<const uint32_t*>(stage)[r - c0]
+                                                         : wgt[rb + (int64_t)r * nrb], zz);
+                        }
+                        av[t] = (double)uu;
+                        bv[t] = (double)zz;
+                    }
 #pragma unroll
-                    for (int tn = 0; tn < NTL; ++tn)
-                        dacc[tm][tn] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[tm], bv[tn], dacc[tm][tn], 0, 0, 0);
+                    for (int tm = 0; tm < NTL; ++tm)
+#pragma unroll
+                        for (int tn = 0; tn < NTL; ++tn)
+                            dacc[tm][tn] =
+                                __builtin_amdgcn_mfma_f64_16x16x4f64(av[tm], bv[tn], dacc[tm][tn], 0, 0, 0);
+                }
+                if (sr > 0) __syncthreads();  // the chunk's staged rows are read before the next chunk's copy
             }
             // the waves' tiles meet in W x W 64-bit LDS sums (over the reduced rows, now read)
             __syncthreads();
@@ -501,15 +528,42 @@ hipError_t allow_max_lds(const void* fn, size_t want) {
     return e;
 }
 
+// Largest dynamic LDS of a workgroup on the current device (cached per device).
+size_t device_max_lds() {
+    static std::mutex mu;
+    static std::vector<int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
+    if (!cache[dev] && hipDeviceGetAttribute(&cache[dev], hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return 65536;
+    return (size_t)cache[dev];
+}
+
+constexpr int STAGE_ROWS_MAX = 1024;
+
 template <int W, typename E, bool SPLIT, int PM>
 hipError_t launch_t(const TiledOperand& t, const void* X, const uint32_t* scale, void* Y, const void* U,
                     const uint32_t* wgt, uint32_t* partial, const TiledLaunch& L, ModP mp, hipStream_t st) {
-    const size_t lds = tiled_lds_bytes(W, SPLIT, PM != 0, t.R, t.K);
+    size_t lds = tiled_lds_bytes(W, SPLIT, PM != 0, t.R, t.K);
+    // the matrix-core projection stages its operands in the LDS the accumulators leave free: chunks of sr rows
+    // (a multiple of 64, at most STAGE_ROWS_MAX; none when fewer than 64 rows fit: direct loads)
+    int sr = 0;
+    if constexpr (PM != 0 && !SPLIT && W <= 32) {
+        if (!getenv("BWR_TILED_NO_STAGE")) {
+            const size_t base = (((size_t)W * (t.R + 1) + t.K + 1) * 4 + 15) & ~(size_t)15;
+            const size_t per_row = PM == 1 ? (size_t)W * sizeof(E) : sizeof(uint32_t);
+            const size_t mx = device_max_lds();
+            sr = (int)std::min<size_t>(STAGE_ROWS_MAX, mx > base ? (mx - base) / per_row : 0) & ~63;
+            if (sr > 0) lds = std::max(lds, base + (size_t)sr * per_row);
+        }
+    }
     hipError_t e = allow_max_lds(reinterpret_cast<const void*>(&k_spmm_tiled<W, E, SPLIT, PM>), lds);
     if (e != hipSuccess || L.grid == 0) return e;  // grid 0: only raise the LDS limit (before a graph capture)
     k_spmm_tiled<W, E, SPLIT, PM><<<(unsigned)L.grid, TT, lds, st>>>(
         t.rows, t.nrb, t.K, t.R, t.R + 1, t.cb, t.vb, t.tile_ptr, t.ent, (const E*)X, scale, (E*)Y, (const E*)U,
-        wgt, partial, L.un, mp);
+        wgt, partial, L.un, sr, mp);
     return hipGetLastError();
 }
 
