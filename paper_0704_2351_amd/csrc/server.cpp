@@ -338,6 +338,7 @@ void Server::solo_loop() {
         R->hrp = std::vector<int64_t>();
         R->hcol = std::vector<int32_t>();
         R->hval = std::vector<int32_t>();
+        held_ -= R->transient;  // the upload; answer_locked releases the footprint
         answer_locked(*R, e.ok() ? 0 : e.code, e.msg, e.ok() ? rank : 0);
     }
     if (se == hipSuccess) (void)hipStreamDestroy(st);

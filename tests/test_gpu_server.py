@@ -196,3 +196,34 @@ def test_server_solo_lane(monkeypatch):
     srv.close()
     announce(f"  budget {big} stats {st2}")
     assert 0 < st2["peak_bytes"] <= big
+
+
+def test_server_solo_lane_releases_its_budget(monkeypatch):
+    """A budget that holds exactly one solo request: three of them, submitted together, run one after the other
+    (each releases all it held, the upload included, when answered); polled with a deadline, not waited on."""
+    need_gpu()
+    announce("server solo lane budget release")
+    monkeypatch.setenv("BWR_SERVER_SOLO_NNZ", "20000")
+    reqs = [(planted(24000, 16000, 13000, 9, 7790 + j), 65521, 5 + j) for j in range(3)]
+    reqs.sort(key=lambda q: -q[0].nnz)  # the budget is measured on the largest
+    srv = bw.Server(4 << 30, 16, 8)
+    assert srv.wait(srv.submit(*reqs[0])) == reqs[0][0].planted_rank
+    one = srv.stats()["peak_bytes"]
+    srv.close()
+    assert one > 0
+    srv = bw.Server(one, 16, 8)
+    tickets = [srv.submit(A, p, sd) for A, p, sd in reqs]
+    deadline = time.time() + 120
+    ranks = [None] * len(tickets)
+    while time.time() < deadline and any(r is None for r in ranks):
+        for i, t in enumerate(tickets):
+            if ranks[i] is None:
+                done, r = srv.poll(t)
+                if done:
+                    ranks[i] = r
+        time.sleep(0.05)
+    st = srv.stats()
+    srv.close()
+    announce(f"  budget {one} stats {st}")
+    assert ranks == [A.planted_rank for A, _, _ in reqs], ranks
+    assert st["peak_bytes"] <= one
