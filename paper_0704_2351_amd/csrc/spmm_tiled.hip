@@ -63,6 +63,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.h"
@@ -75,6 +76,24 @@ constexpr int TT = 1024;  // threads of a tiled workgroup (16 waves: one workgro
 constexpr int BTPB = 256;
 constexpr int UNMAX = 4;  // entries a lane keeps in flight per pass, at most
 typedef double dvec4 __attribute__((ext_vector_type(4)));  // accumulators of a 16 x 16 x 4 f64 MFMA
+// s_waitcnt operand of gfx9: vmcnt 0 (bits 3:0 and 15:14), expcnt and lgkmcnt left at their maximum (no wait)
+constexpr int VMCNT0 = 0x0F70;
+constexpr int STAGE_ROWS_MAX = 1024;  // rows of a staged chunk of the matrix-core projection's operands, at most
+constexpr int STAGE_PIECES = 4;       // 16-byte (or smaller) pieces a thread holds per staged chunk, at most
+
+// rows of a staged chunk for a kernel that stages rows of row_bytes bytes
+constexpr int stage_rows_cap(int row_bytes) {
+    const int pieces = row_bytes >= 16 ? row_bytes / 16 : 1;
+    return STAGE_PIECES * TT / pieces < STAGE_ROWS_MAX ? STAGE_PIECES * TT / pieces : STAGE_ROWS_MAX;
+}
+
+// a register piece of B bytes (staged copies; plain vector types, which stay in registers)
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+template <int B> struct PieceOf;
+template <> struct PieceOf<4> { using T = uint32_t; };
+template <> struct PieceOf<8> { using T = u32x2; };
+template <> struct PieceOf<16> { using T = u32x4; };
 
 // 4 residues (projection operands)
 __device__ __forceinline__ void ld4(const uint32_t* p, uint32_t (&x)[4]) {
@@ -146,9 +165,11 @@ __device__ __forceinline__ void put_residue(uint32_t* w, int c, uint32_t y) {
 // A lane owns the CPL = min(W, 16 bytes of residues) columns q CPL .. of an entry: the LPE lanes of an entry
 // load the consecutive 16-byte pieces of its gathered row in one instruction, which the memory pipeline
 // serves as one access per row (measured at 2M x 1M, block 16: 3-5 % faster than one lane loading the
-// 32-byte row in two instructions).  A pass gives each lane un (1 .. UNMAX) entries in flight, and the entry
-// words of the next pass are loaded before this pass's gathers, so one memory round trip (gathers and the
-// next entries together) is paid per pass instead of two.
+// 32-byte row in two instructions).  A pass takes un (1 .. UNMAX) entries per lane, whose words were loaded
+// one pass ahead; its gathers go out one after another, each after the lane's loads before it have arrived.
+// More gathers in flight measured slower: with all four of a pass outstanding together, 383 and 455 us per
+// product at 2M x 1M, block 16, against 287 and 309 us one at a time.  The random 16-byte gathers are bound
+// by the memory pipeline's miss handling, which more outstanding requests per CU congest.
 template <int W, typename E, bool SPLIT, int PM>
 __global__ __launch_bounds__(TT) void k_spmm_tiled(int64_t nrows, int64_t nrb, int K, int R, int RS, int cb,
                                                    int vb, const uint32_t* __restrict__ tile_ptr,
@@ -174,6 +195,16 @@ __global__ __launch_bounds__(TT) void k_spmm_tiled(int64_t nrows, int64_t nrb, i
     constexpr int NP = CPL / 2;                  // column pairs of a lane
     constexpr int WPP = NWD / NP;                // gathered words per column pair (1 or 2)
     constexpr uint32_t BIAS = 0x80000000u;
+    // a staged row (U row, or weight) is PPR pieces of PB bytes; a thread copies at most SPT pieces per chunk
+    constexpr int SRB = PM == 1 ? W * (int)sizeof(E) : 4;
+    constexpr int PB = SRB >= 16 ? 16 : SRB;
+    constexpr int PPR = SRB / PB;
+    constexpr int SRM = stage_rows_cap(SRB);
+    constexpr int SPT = MFP ? (SRM * PPR + TT - 1) / TT : 1;
+    using Piece = typename PieceOf<PB>::T;
+    // grouped epilogue loads (EG rows' scale factors a thread loads together) where registers allow
+    constexpr bool GE = !SPLIT && W <= 32;
+    constexpr int EG = GE ? 4 : 1;
     static_assert(!PK || (CPL % 2 == 0 && (NP & (NP - 1)) == 0), "packed pairs need an even power-of-two CPL");
     int32_t* acc = lds;
     unsigned long long* acc64 = reinterpret_cast<unsigned long long*>(lds);
@@ -237,6 +268,8 @@ __global__ __launch_bounds__(TT) void k_spmm_tiled(int64_t nrows, int64_t nrb, i
                 if (u < un && idx < end) {
                     while (idx >= knext) knext = tp[++k + 1];
                     const size_t xr = ((size_t)k << cb) + ((w[u] >> vb) & cmask);
+                    // one gather of a lane in flight at a time (see the header)
+                    __builtin_amdgcn_s_waitcnt(VMCNT0);
                     ldw<NWD>(X + xr * W + q * CPL, xv[u]);
                 }
             }
@@ -282,10 +315,36 @@ __global__ __launch_bounds__(TT) void k_spmm_tiled(int64_t nrows, int64_t nrb, i
         // rows of block rb: rb, rb + nrb, rb + 2 nrb, ... (local row r is row rb + r nrb)
         const int nr = (int)((nrows - rb + nrb - 1) / nrb);
         uint32_t* zl = reinterpret_cast<uint32_t*>(acc);
-        for (int i = threadIdx.x; i < nr * LPE; i += TT) {
+        // staged projection: chunks of cs rows; a thread's pieces of a chunk are all loaded before any is written
+        // to LDS, so a chunk costs one memory latency (on gfx9 a wait for a load also waits for earlier stores)
+        const int cs = sr > 0 ? (sr < SRM ? sr : SRM) : nr;
+        Piece pc[SPT];
+        // (every piece is loaded: indices past the chunk repeat its last piece, so no load waits in a branch)
+        auto stage_load = [&](int c0, int c1) {
+            const int n = (c1 - c0) * PPR;
+#pragma unroll
+            for (int h = 0; h < SPT; ++h) {
+                const int i = threadIdx.x + h * TT < n ? threadIdx.x + h * TT : n - 1;
+                const int64_t row = rb + (int64_t)(c0 + i / PPR) * nrb;
+                if constexpr (PM == 1)
+                    pc[h] = reinterpret_cast<const Piece*>(U + (size_t)row * W)[i % PPR];
+                else
+                    pc[h] = wgt[row];
+            }
+        };
+        auto stage_store = [&](int c0, int c1) {
+#pragma unroll
+            for (int h = 0; h < SPT; ++h) {
+                const int i = threadIdx.x + h * TT;
+                if (i < (c1 - c0) * PPR) reinterpret_cast<Piece*>(stage)[i] = pc[h];
+            }
+        };
+        // row r, column group qq of the block (i = r LPE + qq): reduce, scale by sc, store, keep the result for
+        // the projection
+        const int ne = nr * LPE;
+        auto epi_row = [&](int i, uint32_t sc) {
             const int r = i / LPE, qq = i % LPE;
             const int64_t row = rb + (int64_t)r * nrb;
-            const uint32_t sc = scale ? scale[row] : 1u;
             uint32_t yw[NWD];
 #pragma unroll
             for (int h = 0; h < NWD; ++h) yw[h] = 0;
@@ -314,6 +373,67 @@ __global__ __launch_bounds__(TT) void k_spmm_tiled(int64_t nrows, int64_t nrb, i
                 }
             }
             stw<NWD>(Y + (size_t)row * W + qq * CPL, yw);
+        };
+        if constexpr (!GE) {
+            // (kernels without registers to spare: one factor at a time)
+            for (int i = threadIdx.x; i < ne; i += TT) epi_row(i, scale ? scale[rb + (int64_t)(i / LPE) * nrb] : 1u);
+        } else {
+            // EG rows of a thread per group, their scale factors loaded together (indices past the block repeat
+            // its last row); the first group's factors and the first staged chunk are loaded before any wait
+            uint32_t scv[EG];
+            auto scale_group = [&](int i0) {
+                if (scale) {
+#pragma unroll
+                    for (int h = 0; h < EG; ++h) {
+                        const int i = i0 + h * TT < ne ? i0 + h * TT : ne - 1;
+                        scv[h] = scale[rb + (int64_t)(i / LPE) * nrb];
+                    }
+                } else {
+#pragma unroll
+                    for (int h = 0; h < EG; ++h) scv[h] = 1u;
+                }
+            };
+            if (MFP && sr > 0 && scale && ne > 0) {
+                // every address first, then every load, in every lane (a uniform branch: lanes past the block
+                // load its last row's factor and do not use it)
+                const int c1 = cs < nr ? cs : nr, n = c1 * PPR;
+                const uint32_t* sa[EG];
+                const Piece* pa[SPT];
+#pragma unroll
+                for (int h = 0; h < EG; ++h) {
+                    const int i = (int)threadIdx.x + h * TT < ne ? (int)threadIdx.x + h * TT : ne - 1;
+                    sa[h] = scale + rb + (int64_t)(i / LPE) * nrb;
+                }
+#pragma unroll
+                for (int h = 0; h < SPT; ++h) {
+                    const int i = (int)threadIdx.x + h * TT < n ? (int)threadIdx.x + h * TT : n - 1;
+                    const int64_t row = rb + (int64_t)(i / PPR) * nrb;
+                    if constexpr (PM == 1)
+                        pa[h] = reinterpret_cast<const Piece*>(U + (size_t)row * W) + i % PPR;
+                    else
+                        pa[h] = reinterpret_cast<const Piece*>(wgt + row);
+                }
+#pragma unroll
+                for (int h = 0; h < EG; ++h) scv[h] = *sa[h];
+#pragma unroll
+                for (int h = 0; h < SPT; ++h) pc[h] = *pa[h];
+            } else {
+                if ((int)threadIdx.x < ne) scale_group(threadIdx.x);
+                if constexpr (MFP)
+                    if (sr > 0) stage_load(0, cs < nr ? cs : nr);
+            }
+            for (int i0 = threadIdx.x; i0 < ne; i0 += EG * TT) {
+                if (i0 != (int)threadIdx.x) scale_group(i0);
+                // one row at a time (register pressure), each taking the next preloaded factor
+#pragma unroll 1
+                for (int h = 0; h < EG; ++h) {
+                    if (i0 + h * TT >= ne) break;
+                    const uint32_t sc = scv[0];
+#pragma unroll
+                    for (int g = 0; g + 1 < EG; ++g) scv[g] = scv[g + 1];
+                    epi_row(i0 + h * TT, sc);
+                }
+            }
         }
         if constexpr (PROJ && MFP) {
             // the block's partial as a dense contraction on the matrix cores: D (16 x 16 per tile pair) +=
@@ -328,52 +448,84 @@ __global__ __launch_bounds__(TT) void k_spmm_tiled(int64_t nrows, int64_t nrb, i
             for (int tm = 0; tm < NTL; ++tm)
 #pragma unroll
                 for (int tn = 0; tn < NTL; ++tn) dacc[tm][tn] = dvec4{0.0, 0.0, 0.0, 0.0};
-            __syncthreads();
-            // rows in chunks of cs: with staging, every thread first copies its share of the chunk's U rows (or
-            // weights) into LDS, all loads in flight at once, so a chunk costs one memory latency
-            const int cs = sr > 0 ? sr : nr;
-            for (int c0 = 0; c0 < nr; c0 += cs) {
-                const int c1 = c0 + cs < nr ? c0 + cs : nr;
-                if (sr > 0) {
-                    if constexpr (PM == 1) {
-                        constexpr int PPR = W * (int)sizeof(E) / 8;  // 8-byte pieces of a U row
-                        for (int i = threadIdx.x; i < (c1 - c0) * PPR; i += TT)
-                            reinterpret_cast<uint2*>(stage)[i] = reinterpret_cast<const uint2*>(
-                                U + (size_t)(rb + (int64_t)(c0 + i / PPR) * nrb) * W)[i % PPR];
-                    } else {
-                        for (int i = threadIdx.x; i < c1 - c0; i += TT)
-                            reinterpret_cast<uint32_t*>(stage)[i] = wgt[rb + (int64_t)(c0 + i) * nrb];
-                    }
-                    __syncthreads();
-                }
-#pragma unroll 4
-                for (int rbase = c0 + wv * 4; rbase < c1; rbase += (TT / 64) * 4) {
-                    const int r = rbase + kk;
-                    double av[NTL], bv[NTL];
+            // the products over rows c0 .. c1 - 1, their U rows (or weights) from the staged chunk (ST) or from
+            // memory
+            auto rows_mfma = [&](auto staged, int c0, int c1) {
+                constexpr bool ST = decltype(staged)::value;
+                // QD row quads of the wave per step: their LDS reads all go out before the first product (rows
+                // past the chunk read its last row and contribute 0), and the products alternate between two
+                // accumulator sets, so a step pays one LDS latency for QD products (one quad for W = 32: its
+                // four tiles leave no registers for more)
+                constexpr int QD = NTL == 1 ? 4 : 1;
+                dvec4 dacc2[NTL][NTL];
 #pragma unroll
-                    for (int t = 0; t < NTL; ++t) {
-                        const int c = t * 16 + cc;
-                        uint32_t uu = 0, zz = 0;
-                        if (r < c1 && c < W) {
-                            zz = zl[zix(c, r)];
-                            if constexpr (PM == 1)
-                                uu = sr > 0 ? (uint32_t)reinterpret_cast<const E*>(stage)[(r - c0) * W + c]
+                for (int tm = 0; tm < NTL; ++tm)
+#pragma unroll
+                    for (int tn = 0; tn < NTL; ++tn) dacc2[tm][tn] = dvec4{0.0, 0.0, 0.0, 0.0};
+                for (int rbase = c0 + wv * 4; rbase < c1; rbase += QD * (TT / 64) * 4) {
+                    double av[QD][NTL], bv[QD][NTL];
+#pragma unroll
+                    for (int d = 0; d < QD; ++d) {
+                        const int r0 = rbase + d * (TT / 64) * 4 + kk;
+                        const bool in = r0 < c1;
+                        const int r = in ? r0 : c1 - 1;
+#pragma unroll
+                        for (int t = 0; t < NTL; ++t) {
+                            const int c = t * 16 + cc;
+                            uint32_t uu = 0, zz = 0;
+                            if (c < W) {
+                                zz = zl[zix(c, r)];
+                                if constexpr (PM == 1)
+                                    uu = ST ? (uint32_t)reinterpret_cast<const E*>(stage)[(r - c0) * W + c]
                                             : (uint32_t)U[(size_t)(rb + (int64_t)r * nrb) * W + c];
-                            else
-                                uu = mulmod16(mp, sr > 0 ? reinterpret_cast<const uint32_t*>(stage)[r - c0]
+                                else
+                                    uu = mulmod16(mp, ST ? reinterpret_cast<const uint32_t*>(stage)[r - c0]
                                                          : wgt[rb + (int64_t)r * nrb], zz);
+                            }
+                            av[d][t] = in ? (double)uu : 0.0;
+                            bv[d][t] = (double)zz;
                         }
-                        av[t] = (double)uu;
-                        bv[t] = (double)zz;
                     }
+#pragma unroll
+                    for (int d = 0; d < QD; ++d)
+#pragma unroll
+                        for (int tm = 0; tm < NTL; ++tm)
+#pragma unroll
+                            for (int tn = 0; tn < NTL; ++tn) {
+                                if (d & 1)
+                                    dacc2[tm][tn] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[d][tm], bv[d][tn],
+                                                                                          dacc2[tm][tn], 0, 0, 0);
+                                else
+                                    dacc[tm][tn] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[d][tm], bv[d][tn],
+                                                                                         dacc[tm][tn], 0, 0, 0);
+                            }
+                }
+                if constexpr (QD > 1) {
 #pragma unroll
                     for (int tm = 0; tm < NTL; ++tm)
 #pragma unroll
-                        for (int tn = 0; tn < NTL; ++tn)
-                            dacc[tm][tn] =
-                                __builtin_amdgcn_mfma_f64_16x16x4f64(av[tm], bv[tn], dacc[tm][tn], 0, 0, 0);
+                        for (int tn = 0; tn < NTL; ++tn) dacc[tm][tn] += dacc2[tm][tn];
                 }
-                if (sr > 0) __syncthreads();  // the chunk's staged rows are read before the next chunk's copy
+            };
+            if (sr > 0) {
+                // chunk c is copied to LDS while chunk c + 1's loads are in flight, so the loads of every chunk
+                // after the first overlap the products of the one before
+                stage_store(0, cs < nr ? cs : nr);
+                __syncthreads();
+                for (int c0 = 0; c0 < nr; c0 += cs) {
+                    const int c1 = c0 + cs < nr ? c0 + cs : nr;
+                    const int c2 = c1 + cs < nr ? c1 + cs : nr;
+                    if (c1 < nr) stage_load(c1, c2);
+                    rows_mfma(std::true_type{}, c0, c1);
+                    if (c1 < nr) {
+                        __syncthreads();  // the chunk's staged rows are read before the next chunk's copy
+                        stage_store(c1, c2);
+                        __syncthreads();
+                    }
+                }
+            } else {
+                __syncthreads();
+                rows_mfma(std::false_type{}, 0, nr);
             }
             // the waves' tiles meet in W x W 64-bit LDS sums (over the reduced rows, now read)
             __syncthreads();
@@ -541,21 +693,19 @@ size_t device_max_lds() {
     return (size_t)cache[dev];
 }
 
-constexpr int STAGE_ROWS_MAX = 1024;
-
 template <int W, typename E, bool SPLIT, int PM>
 hipError_t launch_t(const TiledOperand& t, const void* X, const uint32_t* scale, void* Y, const void* U,
                     const uint32_t* wgt, uint32_t* partial, const TiledLaunch& L, ModP mp, hipStream_t st) {
     size_t lds = tiled_lds_bytes(W, SPLIT, PM != 0, t.R, t.K);
     // the matrix-core projection stages its operands in the LDS the accumulators leave free: chunks of sr rows
-    // (a multiple of 64, at most STAGE_ROWS_MAX; none when fewer than 64 rows fit: direct loads)
+    // (a multiple of 64, at most stage_rows_cap; none when fewer than 64 rows fit: direct loads)
     int sr = 0;
     if constexpr (PM != 0 && !SPLIT && W <= 32) {
         if (!getenv("BWR_TILED_NO_STAGE")) {
             const size_t base = (((size_t)W * (t.R + 1) + t.K + 1) * 4 + 15) & ~(size_t)15;
             const size_t per_row = PM == 1 ? (size_t)W * sizeof(E) : sizeof(uint32_t);
             const size_t mx = device_max_lds();
-            sr = (int)std::min<size_t>(STAGE_ROWS_MAX, mx > base ? (mx - base) / per_row : 0) & ~63;
+            sr = (int)std::min<size_t>(stage_rows_cap((int)per_row), mx > base ? (mx - base) / per_row : 0) & ~63;
             if (sr > 0) lds = std::max(lds, base + (size_t)sr * per_row);
         }
     }

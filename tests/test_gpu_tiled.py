@@ -56,6 +56,44 @@ def test_tiled_small_tiles(s, p, e32, monkeypatch):
     assert np.array_equal(got.astype(np.int64), want)
 
 
+def sparse_blocks_matrix(m, n, row_step, col_step, seed):
+    """Entries only in rows r = 0 mod row_step and columns c = 0 mod col_step: with row_step a multiple of the
+    number of row blocks, every row block but the first has no entries."""
+    rng = np.random.default_rng(seed)
+    rs = np.arange(0, m, row_step)
+    cs = np.arange(0, n, col_step)
+    rows = np.repeat(rs, 6)
+    cols = rng.choice(cs, size=rows.size)
+    vals = rng.choice([-2, -1, 1, 3], size=rows.size)
+    return coo_to_csr(m, n, rows, cols, vals)
+
+
+@pytest.mark.parametrize("p,s", [(65521, 16), (65521, 8), (2**31 - 1, 16)])
+@pytest.mark.parametrize("shape", ["empty-row-blocks", "rowless-row-block", "many-slabs"])
+def test_tiled_row_block_edges(shape, p, s, monkeypatch):
+    """Row-block starts: row blocks with no entries (700 x 300, entries in rows 0 mod 12 and columns 0 mod 6, 12
+    and 6 row blocks), a row block with no rows (2 x 40: 3 row blocks for 2 rows), and more slabs than threads
+    of a workgroup (600 x 20000, 16 block rows a slab: 1250 slabs in the first product), each over several row
+    blocks per workgroup; 5 terms against the oracle."""
+    need_gpu()
+    announce(f"tiled row-block edges {shape} s={s} p={p}")
+    W = s
+    small_tiles(monkeypatch, W, 2 if p <= 65536 else 4)
+    if shape == "empty-row-blocks":
+        A = sparse_blocks_matrix(700, 300, 12, 6, 5)
+    elif shape == "rowless-row-block":
+        A = sparse_blocks_matrix(2, 40, 1, 1, 6)
+    else:
+        A = sparse_blocks_matrix(600, 20000, 1, 1, 7)
+    rng = np.random.default_rng(s + 1)
+    U, V = blocks(rng, A.n, s, p)
+    dr = rng.integers(1, p, size=A.m)
+    dc = rng.integers(1, p, size=A.n)
+    got = bw.sequence(A, U, V, p, 5, dr, dc)
+    want = oseq.sequence(A, U, V, p, 5, dr, dc)
+    assert np.array_equal(got.astype(np.int64), want)
+
+
 @pytest.mark.parametrize("p", [65521, 2**31 - 1])
 def test_tiled_graph_chunks(p, monkeypatch):
     """600 terms: captured 256-step graphs replayed with the tiled kernels, then a tail."""
