@@ -266,7 +266,7 @@ int bwr_rank_modp_dev(const bwr_csr* A_dev, uint32_t p, int32_t block, uint64_t 
  * column passes of the first product, column passes of the second, then for
  * each product its two-dimensional tiling: rows per row block (0 = not
  * tiled), log2 of the block rows per slab, workgroups; then for each product
- * the entries each lane of a tiled product keeps in flight} (16 int32; row
+ * the entries each lane of a tiled product takes per pass} (16 int32; row
  * split 0 = the one-row-per-lane kernel).  For measurement; computes nothing
  * the caller keeps. */
 int bwr_time_step_kernels_dev(const bwr_csr* A_dev, uint32_t p, int32_t s, int32_t transpose, int32_t iters,
@@ -409,8 +409,8 @@ int bwr_rank_from_sequence(const uint32_t* S, int64_t len, int64_t check, int32_
  *                          trying it.  BWR_TILED_WGS (workgroups per CU),
  *                          BWR_TILED_SLAB (bytes of the block per slab),
  *                          BWR_TILED_R (row block cap), BWR_TILED_GRID
- *                          (workgroup cap) and BWR_TILED_UN (entries in
- *                          flight per lane, 1-4) pin its geometry;
+ *                          (workgroup cap) and BWR_TILED_UN (entries per
+ *                          lane per pass, 1-4) pin its geometry;
  *                          BWR_TILED_NO_STAGE=1 makes the fused projection
  *                          load its operands directly instead of staging
  *                          them in LDS

@@ -405,9 +405,9 @@ bool tile_geometry(int64_t rows, int64_t cols, int W, int esize, bool split, boo
 
 // Tiled geometries the autotuner tries: row blocks for one or two workgroups per CU, slabs of 128 to 512 KB of
 // the block (measured at the 2M x 1M size: larger slabs lose, 256 and 128 KB are within a few per cent), one, two
-// or four entries in flight per lane (a pass of fewer entries spans fewer slabs, more entries keep more memory
-// requests in flight).  BWR_TILED_WGS, BWR_TILED_SLAB (bytes), BWR_TILED_R (cap on the row block),
-// BWR_TILED_GRID (cap on the workgroups) and BWR_TILED_UN (entries in flight) pin one geometry.
+// or four entries per lane per pass (a pass of fewer entries spans fewer slabs; more entries load more entry
+// words ahead).  BWR_TILED_WGS, BWR_TILED_SLAB (bytes), BWR_TILED_R (cap on the row block), BWR_TILED_GRID (cap
+// on the workgroups) and BWR_TILED_UN (entries per lane per pass) pin one geometry.
 std::vector<StepPlan::Tile> tile_candidates(int64_t rows, int64_t cols, int W, int esize, bool split, bool proj,
                                             int32_t max_abs) {
     std::vector<StepPlan::Tile> out;
@@ -782,7 +782,7 @@ Error autotune_step(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl
         tc1 = tile_candidates(op1.rows, nb, W, pl->esize, split, false, M.max_abs);
     if (tiles_on && pl->G2 > 0 && tiled_acc_ok(M, op2.max_len, mp.p))
         tc2 = tile_candidates(op2.rows, outer, W, pl->esize, split, true, M.max_abs);
-    // candidates that differ only in their launch (entries in flight) share one encoding
+    // candidates that differ only in their launch (entries per pass) share one encoding
     auto encodings = [&](const Operand& op, int64_t cols, const std::vector<StepPlan::Tile>& tc,
                          std::vector<TiledOp>* to, std::vector<size_t>* b) -> Error {
         std::vector<const StepPlan::Tile*> geo;

@@ -152,7 +152,7 @@ struct StepPlan {
     struct Tile {
         int R = 0, cb = 0, grid = 0;
         int64_t nrb = 0;
-        int un = 1;  // entries each lane keeps in flight per pass (see TiledLaunch)
+        int un = 1;  // entries each lane takes per pass (see TiledLaunch)
     };
     Tile t1, t2;
 };

@@ -137,7 +137,7 @@ hipError_t launch_tiled_build(int64_t rows, int64_t nrb, const int32_t* rp, cons
                               int cb, int vb, int32_t* cnt, int32_t* pos, int32_t* scan_tmp, uint32_t* tile_ptr,
                               uint32_t* out, hipStream_t st);
 // Launch shape of a tiled product: grid persistent workgroups (one row block at a time); un (1 .. 4) entries
-// each lane keeps in flight per pass.
+// each lane takes per pass (their words loaded one pass ahead, their gathers issued one after another).
 struct TiledLaunch {
     int grid = 0;
     int un = 4;

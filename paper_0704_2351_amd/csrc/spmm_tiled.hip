@@ -74,7 +74,7 @@ namespace {
 
 constexpr int TT = 1024;  // threads of a tiled workgroup (16 waves: one workgroup per CU, LDS-bound)
 constexpr int BTPB = 256;
-constexpr int UNMAX = 4;  // entries a lane keeps in flight per pass, at most
+constexpr int UNMAX = 4;  // entries a lane takes per pass, at most
 typedef double dvec4 __attribute__((ext_vector_type(4)));  // accumulators of a 16 x 16 x 4 f64 MFMA
 // s_waitcnt operand of gfx9: vmcnt 0 (bits 3:0 and 15:14), expcnt and lgkmcnt left at their maximum (no wait)
 constexpr int VMCNT0 = 0x0F70;

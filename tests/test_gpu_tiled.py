@@ -169,12 +169,12 @@ def test_tiled_ranks_equal_elimination(p, monkeypatch):
 @pytest.mark.parametrize("un,stage", [(1, "1"), (2, "1"), (3, "0"), (4, "1"), (4, "0")])
 @pytest.mark.parametrize("p", [65521, 2**31 - 1])
 def test_tiled_entries_in_flight(un, stage, p, monkeypatch):
-    """1 .. 4 entries in flight per lane, the projection's operands staged in LDS or loaded directly
+    """1 .. 4 entries per lane per pass, the projection's operands staged in LDS or loaded directly
     (BWR_TILED_NO_STAGE): row blocks of about 64 rows, 96 workgroups over 512 row blocks (grid-stride rounds
     of unequal length); 6 terms and one application of B against the oracle, then a graph-replayed 300-term
     run with row blocks of 16 rows."""
     torch = need_gpu()
-    announce(f"tiled entries in flight un={un} stage={stage} p={p}")
+    announce(f"tiled entries per pass un={un} stage={stage} p={p}")
     if stage == "0":
         monkeypatch.setenv("BWR_TILED_NO_STAGE", "1")
     monkeypatch.setenv("BWR_TILED", "1")
