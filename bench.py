@@ -330,7 +330,7 @@ def sequence_mode(args):
         out["rank"] = {"rank": int(r), "planted_rank": int(A.planted_rank), "equals_planted": bool(r == A.planted_rank),
                        "seconds": round(el, 2), "t_sequence": round(info["t_sequence"], 2),
                        "t_sigma_after_sequence": round(info["t_sigma"], 3), "t_encode": round(info["t_encode"], 3),
-                       "gnnzvec_per_s": round(2.0 * nnz * info["s"] * (info["len"] + info["check_terms"] - 1) / el / 1e9,
+                       "gnnzvec_per_s": round(2.0 * nnz * info["s"] * (info["terms"] - 1) / el / 1e9,
                                               3)}
     del Ad
     torch.cuda.empty_cache()
@@ -477,16 +477,19 @@ def paper_rank_mode(args):
     A = config3()
     Ad = bw.csr_to_device(A, "cuda:0")
     torch.cuda.synchronize()
-    log(f"rank mod {p}, block {s}: {bw.sequence_length(min(A.m, A.n), s) + 4} terms (one call, about 2.5 min)")
+    log(f"rank mod {p}, block {s}: up to {bw.sequence_length(min(A.m, A.n), s) + 4} terms (one call, about "
+        f"75 s), early termination {'on' if bw.get_early_termination() else 'off'}")
     t0 = time.perf_counter()
     r, info = bw.rank_modp_dev(Ad, p, s, 1)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    work = 2.0 * A.nnz * info["s"] * (info["len"] + info["check_terms"] - 1)
+    work = 2.0 * A.nnz * info["s"] * (info["terms"] - 1)
     print(json.dumps({
         "metric": METRIC, "mode": "paper_rank", "unit": "Gnnz·vec/s", "value": round(work / el / 1e9, 3),
         "rank": int(r), "planted_rank": int(A.planted_rank), "rank_equals_planted": bool(r == A.planted_rank),
-        "seconds": round(el, 2), "info": info, "higher_is_better": True, "n_gpus": 1, "dtype": "u16",
+        "seconds": round(el, 2), "early_termination": bool(bw.get_early_termination()),
+        "terms_computed": int(info["terms"]),
+        "full_length": int(bw.sequence_length(min(A.m, A.n), s) + 4), "info": info, "higher_is_better": True, "n_gpus": 1, "dtype": "u16",
         "data": "synthetic planted-rank matrix (seeded)",
         "config": {"workload": f"planted {A.m} x {A.n}, rank {A.planted_rank}, {A.nnz / 1e6:.1f} M non-zeros, "
                                f"block {s}, p = {p}", "m": A.m, "n": A.n, "nnz": A.nnz}}), flush=True)
@@ -614,7 +617,7 @@ def rank_c2_mode(args):
         log(f"step {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    work = sum(2.0 * A.nnz * i["s"] * (i["len"] + i["check_terms"] - 1) for i in infos)
+    work = sum(2.0 * A.nnz * i["s"] * (i["terms"] - 1) for i in infos)
     rl = {}
     for p in primes:
         us, plan = bw.time_step_kernels_dev(Ad, p, s, False, args.kernel_iters, with_plan=True)
@@ -653,6 +656,10 @@ def main():
                     help="skip the one-request-at-a-time pass over the same trace")
     ap.add_argument("--paper-rank", action="store_true",
                     help="only the whole rank of the 2000000 x 1000000 matrix")
+    ap.add_argument("--early", action="store_true",
+                    help="early termination of the single-matrix ranks (--paper-rank, and the single-matrix "
+                         "lanes of --batch and --serve): the sequence stops once the sigma-basis beside it "
+                         "has converged")
     ap.add_argument("--rank-c2", action="store_true",
                     help="ranks of the 200000 x 150000 matrix at p = 65521 and 2^31 - 1 (one step = both)")
     ap.add_argument("--gram", action="store_true",
@@ -679,6 +686,10 @@ def main():
     import torch
 
     torch.cuda.set_device(0)
+    if args.early:
+        import paper_0704_2351_amd as bw
+
+        bw.set_early_termination(True)
     if args.batch:
         return batch_mode(args)
     if args.serve:

@@ -66,8 +66,9 @@ typedef struct {
     int64_t nb;           /* dimension B acts on: min(m, n) */
     int32_t s;            /* block size used: min(block, nb) */
     int32_t transposed;   /* 1 when B = D_c A D_r A^T D_c (m < n) */
-    int64_t len;          /* sequence terms used for the generator: 2 + ceil(2 nb / s) */
-    int64_t check_terms;  /* extra terms the generator was verified on */
+    int64_t len;          /* sequence terms used for the generator: 2 + ceil(2 nb / s), or the order at which
+                           * early termination kept the basis */
+    int64_t check_terms;  /* terms past len the generator was verified on */
     int64_t sum_delta;    /* sum of the generator's row degrees */
     double t_encode;      /* seconds: validation and device encoding of A */
     double t_sequence;    /* seconds: the L + check terms on the device */
@@ -80,6 +81,8 @@ typedef struct {
     int32_t sigma_threads;
     int32_t trials;       /* independent draws made (see bwr_set_trials); the other fields describe the draw
                            * that gave the rank, the times are summed over the draws */
+    int64_t terms;        /* sequence terms computed: len + check_terms, or more after an early stop
+                           * (bwr_set_early_termination) */
 } bwr_rank_info;
 
 /* Timings of one batched rank computation. */
@@ -121,6 +124,27 @@ int bwr_set_threads(int32_t n);
  * while another call is in progress.  bwr_get_trials returns the setting. */
 int bwr_set_trials(int32_t n);
 int32_t bwr_get_trials(void);
+
+/* Early termination of the sequence (the outlook of the paper's conclusion,
+ * Section 5: the sequence needs about 2 rank / s terms, not 2 min(m, n) / s,
+ * when the rank is below min(m, n)).  on = 1 applies to single-matrix ranks
+ * (bwr_rank_modp, bwr_rank_modp_dev, bwr_rank_modp_sym(_dev), the matrix
+ * handle and workspace forms) whose sequence has at least 4096 terms and
+ * whose sigma-basis runs on the device: the basis is computed beside the
+ * sequence in chunks cut as the terms arrive (max(512, L/32) orders, the
+ * first at L/8), and the sequence stops once the generator rows' shifted
+ * degrees have not changed over max(128, chunk/8) orders and 4 terms past
+ * that order are complete.  The generator of that order is then checked on
+ * the 4 terms past it and read out as usual (bwr_rank_info.len is its order,
+ * terms the number of terms computed).  A stall of that
+ * length in a sequence that is not yet complete is a further Monte Carlo
+ * event (the check terms past the kept order guard against it).  Off (0) by
+ * default.  The matrices that bwr_rank_modp_batch and the server send to
+ * their single-matrix lanes use it too; their batched sequences do not.
+ * Returns BWR_EINVAL for other values.
+ * Like bwr_set_trials, it must not run while another call is in progress. */
+int bwr_set_early_termination(int32_t on);
+int32_t bwr_get_early_termination(void);
 
 /* The random residues the rank draws, from a counter-based SplitMix64
  * (Steele, Lea, Flood 2014): with mix() the SplitMix64 finaliser and

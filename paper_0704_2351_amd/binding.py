@@ -24,7 +24,8 @@ EXPORTED = ("bwr_version", "bwr_last_error", "bwr_is_prime", "bwr_sequence_lengt
             "bwr_matrix_create_dev", "bwr_matrix_sequence_dev", "bwr_matrix_destroy", "bwr_set_trials",
             "bwr_get_trials", "bwr_sequence_workspace", "bwr_rank_workspace", "bwr_sequence_dev_ws",
             "bwr_rank_modp_dev_ws", "bwr_device_allocations", "bwr_sequence_sym_dev", "bwr_rank_modp_sym",
-            "bwr_rank_modp_sym_dev", "bwr_matrix_sequence_sym_dev", "bwr_sequence_dev_noalloc")
+            "bwr_rank_modp_sym_dev", "bwr_matrix_sequence_sym_dev", "bwr_sequence_dev_noalloc",
+            "bwr_set_early_termination", "bwr_get_early_termination")
 
 
 class BwrError(RuntimeError):
@@ -52,7 +53,7 @@ class RankInfo(ctypes.Structure):
                 ("transposed", ctypes.c_int32), ("len", ctypes.c_int64), ("check_terms", ctypes.c_int64),
                 ("sum_delta", ctypes.c_int64), ("t_encode", ctypes.c_double), ("t_sequence", ctypes.c_double),
                 ("t_sigma", ctypes.c_double), ("t_readout", ctypes.c_double), ("sigma_threads", ctypes.c_int32),
-                ("trials", ctypes.c_int32)]
+                ("trials", ctypes.c_int32), ("terms", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -77,6 +78,8 @@ def lib():
             "bwr_set_threads": (ctypes.c_int, [i32]),
             "bwr_set_trials": (ctypes.c_int, [i32]),
             "bwr_get_trials": (i32, []),
+            "bwr_set_early_termination": (ctypes.c_int, [i32]),
+            "bwr_get_early_termination": (i32, []),
             "bwr_random_block": (ctypes.c_int, [u64, i32, i64, i32, u32, i32, vp]),
             "bwr_sequence": (ctypes.c_int, [vp, vp, vp, vp, vp, u32, i32, i64, vp]),
             "bwr_sequence_dev": (ctypes.c_int, [vp, vp, vp, vp, vp, u32, i32, i64, vp, vp]),
@@ -170,6 +173,15 @@ def set_trials(n: int) -> None:
 
 def get_trials() -> int:
     return int(lib().bwr_get_trials())
+
+
+def set_early_termination(on: bool) -> None:
+    """Stop single-matrix rank sequences once the device sigma-basis beside them has converged."""
+    _check(lib().bwr_set_early_termination(1 if on else 0))
+
+
+def get_early_termination() -> bool:
+    return bool(lib().bwr_get_early_termination())
 
 
 def random_block(seed: int, stream: int, rows: int, s: int, p: int, diag: bool = False) -> np.ndarray:

@@ -30,6 +30,11 @@ thread_local std::string g_err;
 
 // independent draws per rank computation (bwr_set_trials)
 std::atomic<int32_t> g_trials{1};
+// early termination of single-matrix ranks (bwr_set_early_termination)
+std::atomic<int32_t> g_early{0};
+// early termination's cut lengths: at least these many orders, else L / 32 and a eighth of that
+constexpr int64_t EARLY_MIN_STEP = 512;
+constexpr int64_t EARLY_MIN_VERIFY = 128;
 
 int fail(const Error& e) {
     g_err = e.msg;
@@ -249,9 +254,12 @@ Error rank_one_draw(const DeviceMatrix& M, const CsrView& A, uint32_t p, int32_t
     // inside an arena the generator is computed on the host (the device sigma-basis allocates as it recurses)
     const bool on_device = gpu_leaf_order(s) > 0 && !getenv("BWR_HOST_SIGMA") && !current_arena();
     const int64_t min_chunk = on_device ? online_min_chunk(L) : 0;
+    // early termination needs the basis beside the sequence
+    const bool early = min_chunk > 0 && g_early.load() != 0;
     info.s = s;
     info.len = L;
     info.check_terms = CHECK_TERMS;
+    info.terms = total;
     const ModP mp = ModP::make(p);
     DevBuf U, V, dr, dc, S;
     if (!(e = U.alloc(sizeof(uint32_t) * (size_t)(nb * s), st)).ok()) return e;
@@ -284,14 +292,27 @@ Error rank_one_draw(const DeviceMatrix& M, const CsrView& A, uint32_t p, int32_t
         hipStream_t sst = lib_stream(&e, 1);
         if (!e.ok()) return e;
         drain.st = sst;
-        if (!(e = og.begin(S.as<uint32_t>(), L, s, p, min_chunk, sst)).ok()) return e;
+        if (early) {
+            const int64_t step = std::max<int64_t>(EARLY_MIN_STEP, L / 32);
+            e = og.begin_early(S.as<uint32_t>(), L, s, p, step, std::max<int64_t>(EARLY_MIN_VERIFY, step / 8), sst);
+        } else {
+            e = og.begin(S.as<uint32_t>(), L, s, p, min_chunk, sst);
+        }
+        if (!e.ok()) return e;
         // The generator's thread waits on the host for an event of st.  st captures a graph only for the
         // sequence's first chunk of steps (at least 32; graphs need two chunks' worth of terms, so L >= 61),
         // progress is called with t = 1 before that chunk and with t > 32 after it, and the first boundary
         // (a quarter of L, >= 15 when a graph is used) exceeds 1: st is never capturing during such a wait.
+        // In early-termination mode every chunk of terms after the first is fed (t = 1 comes before the
+        // captured chunk, so it is skipped there too), and the sequence stops once the basis has converged
+        // and the terms it will be checked on are complete.
         a.progress = [&](int64_t t) -> Error {
-            const int64_t next = og.next_boundary();
-            if (next < 0 || t < next) return {};
+            if (early) {
+                if (t <= 1) return {};
+            } else {
+                const int64_t next = og.next_boundary();
+                if (next < 0 || t < next) return {};
+            }
             hipEvent_t ev = nullptr;
             hipError_t r = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
             if (r == hipSuccess) r = hipEventRecord(ev, st);
@@ -302,7 +323,14 @@ Error rank_one_draw(const DeviceMatrix& M, const CsrView& A, uint32_t p, int32_t
             og.feed_async(t, ev);
             return {};
         };
+        if (early)
+            a.stop = [&](int64_t t) -> bool {
+                const int64_t c = og.converged();
+                return c > 0 && t >= c + CHECK_TERMS;
+            };
     }
+    int64_t have = total;  // terms computed
+    a.len_out = &have;
     const double t1 = now_s();
     if (!(e = run_sequence(a, st)).ok()) return e;
     he = hipStreamSynchronize(st);
@@ -311,10 +339,17 @@ Error rank_one_draw(const DeviceMatrix& M, const CsrView& A, uint32_t p, int32_t
     info.t_sequence = t2 - t1;
     Generator g;
     SigmaStats ss;
-    std::vector<uint32_t> Sh((size_t)(total * s * s));
+    int64_t Lg = L;  // order of the generator's basis
+    std::vector<uint32_t> Sh((size_t)(have * s * s));
     if (on_device && min_chunk > 0) {
-        og.feed_async(L, nullptr);
+        if (have < total && og.converged() == 0) return Error::inval("sequence stopped before the basis converged");
+        // after a stop the basis has converged and ignores further terms; otherwise feed them all
+        if (have == total) og.feed_async(L, nullptr);
         if (!(e = og.finish(&g)).ok()) return e;
+        Lg = og.order();
+        if (Lg + CHECK_TERMS > have) return Error::inval("too few terms past the generator's order to check it");
+        info.len = Lg;
+        info.terms = have;
         he = hipMemcpyAsync(Sh.data(), S.as<void>(), sizeof(uint32_t) * Sh.size(), hipMemcpyDeviceToHost, st);
         if (he == hipSuccess) he = hipStreamSynchronize(st);
         if (he != hipSuccess) return Error::device(he, "sequence download");
@@ -332,7 +367,9 @@ Error rank_one_draw(const DeviceMatrix& M, const CsrView& A, uint32_t p, int32_t
     const double t3 = now_s();
     info.t_sigma = t3 - t2;
     info.sigma_threads = on_device ? 0 : ss.threads;
-    if (!(e = check_generator(g, Sh.data(), L, total, p)).ok()) return e;
+    // the same number of check terms as the full length has (after an early stop more terms may be there:
+    // checking each costs about s^3 (L / s) operations on the host, 15 ms at 2M x 1M)
+    if (!(e = check_generator(g, Sh.data(), Lg, Lg + CHECK_TERMS, p)).ok()) return e;
     int64_t r = 0;
     if (!(e = rank_from_generator(g, p, &r)).ok()) return e;
     info.t_readout = now_s() - t3;
@@ -464,6 +501,15 @@ int bwr_set_trials(int32_t n) {
 }
 
 int32_t bwr_get_trials(void) { return g_trials.load(); }
+
+int bwr_set_early_termination(int32_t on) {
+    if (on != 0 && on != 1) return fail(BWR_EINVAL, "early termination is 0 (off) or 1 (on)");
+    g_early.store(on);
+    g_err.clear();
+    return BWR_OK;
+}
+
+int32_t bwr_get_early_termination(void) { return g_early.load(); }
 
 int bwr_set_threads(int32_t n) {
     if (n < 1) return fail(BWR_EINVAL, "thread count must be positive");

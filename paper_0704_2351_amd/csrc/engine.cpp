@@ -989,6 +989,32 @@ Error tuned_plan(const DeviceMatrix& M, bool transpose, ModP mp, StepPlan* pl, h
 
 namespace {
 
+// Keeps the enqueueing thread at most two chunks ahead of the device (SequenceArgs::stop): before chunk n
+// waits for the event recorded after chunk n - 2.  Recorded outside graph capture only.
+struct Pacer {
+    bool on = false;
+    int64_t n = 0;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    ~Pacer() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    Error before_chunk() {
+        if (!on || n < 2) return {};
+        const hipError_t e = hipEventSynchronize(ev[n & 1]);
+        return e == hipSuccess ? Error{} : Error::device(e, "hipEventSynchronize");
+    }
+    Error after_chunk(hipStream_t st) {
+        if (!on) return {};
+        hipEvent_t& e = ev[n & 1];
+        hipError_t r = e ? hipSuccess : hipEventCreateWithFlags(&e, hipEventDisableTiming);
+        if (r == hipSuccess) r = hipEventRecord(e, st);
+        if (r != hipSuccess) return Error::device(r, "hipEventRecord");
+        ++n;
+        return {};
+    }
+};
+
 // The symmetric sequence in Gram form (symmetric.hip): S_0 = X_0^T D_c^-2 X_0, then per application of B the
 // terms S_2k+1 = Y_k^T D_r^-1 Y_k (from the first product's output) and S_2k+2 = X_k+1^T D_c^-2 X_k+1 (from the
 // second's); the products run without a fused projection.  Chunks of CH applications are captured as one HIP
@@ -1063,7 +1089,11 @@ Error gram_sequence(const SequenceArgs& a, const DeviceMatrix& M, const Operand&
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     Error err;
-    for (int64_t t = 1; t < a.len && err.ok();) {
+    Pacer pace;
+    pace.on = (bool)a.stop;
+    int64_t t = 1;
+    while (t < a.len && err.ok()) {
+        if (!(err = pace.before_chunk()).ok()) break;
         const int64_t apps = std::min<int64_t>(CH, (a.len - t + 1) / 2);
         if (use_graph && apps == CH) {
             if (!exec) {
@@ -1107,7 +1137,10 @@ Error gram_sequence(const SequenceArgs& a, const DeviceMatrix& M, const Operand&
         if (e != hipSuccess) err = Error::device(e, "gram reduce");
         t += nterms;
         if (err.ok() && a.progress) err = a.progress(t);
+        if (err.ok()) err = pace.after_chunk(st);
+        if (err.ok() && a.stop && t < a.len && a.stop(t)) break;
     }
+    if (a.len_out) *a.len_out = std::min(t, a.len);
     int32_t bad = 0;
     hipError_t he = hipSuccess;
     if (err.ok()) he = hipMemcpyAsync(&bad, flag, sizeof(bad), hipMemcpyDeviceToHost, st);
@@ -1242,7 +1275,11 @@ Error run_sequence(const SequenceArgs& a, hipStream_t st) {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     Error err;
-    for (int64_t k = 1; k < a.len && err.ok();) {
+    Pacer pace;
+    pace.on = (bool)a.stop;
+    int64_t k = 1;
+    while (k < a.len && err.ok()) {
+        if (!(err = pace.before_chunk()).ok()) break;
         const int64_t cnt = std::min<int64_t>(CH, a.len - k);
         if (use_graph && cnt == CH) {
             if (!exec) {
@@ -1281,7 +1318,11 @@ Error run_sequence(const SequenceArgs& a, hipStream_t st) {
         if (e != hipSuccess) err = Error::device(e, "reduce launch");
         k += cnt;
         if (err.ok() && a.progress) err = a.progress(k);
+        if (err.ok()) err = pace.after_chunk(st);
+        if (err.ok() && a.stop && k < a.len && a.stop(k)) break;
     }
+    const int64_t done_len = std::min(k, a.len);
+    if (a.len_out) *a.len_out = done_len;
     // the graph is destroyed only once its launches have run: a launch in flight (and a tracer that inspects
     // its dispatches when they complete) must not outlive the executable graph
     // the symmetric projection's check: every term V^T B^k V must be symmetric (bit 2 of the flag)
@@ -1289,7 +1330,7 @@ Error run_sequence(const SequenceArgs& a, hipStream_t st) {
     if (err.ok() && a.symmetric) {
         hipError_t e = symflag.alloc(sizeof(int32_t), st).ok() ? launch_fill_zero(symflag.as<void>(), 4, st)
                                                                 : hipErrorOutOfMemory;
-        if (e == hipSuccess) e = launch_sym_check(a.len, a.s, a.S_out, symflag.as<int32_t>(), st);
+        if (e == hipSuccess) e = launch_sym_check(done_len, a.s, a.S_out, symflag.as<int32_t>(), st);
         if (e != hipSuccess) err = Error::device(e, "symmetry check");
     }
     int32_t bad = 0, asym = 0;

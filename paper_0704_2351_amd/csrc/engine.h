@@ -172,6 +172,11 @@ struct SequenceArgs {
     // optional: called from the enqueueing thread each time the reductions of the terms
     // S_0 .. S_{t-1} have been enqueued on the sequence stream (t increasing, last t = len)
     std::function<Error(int64_t t)> progress;
+    // optional: asked after each progress(t); true ends the sequence there, with S_0 .. S_{t-1} complete.
+    // While it is set the enqueueing thread stays at most two chunks of steps ahead of the device, so that
+    // a stop is taken close to the device's position rather than after every chunk has been queued.
+    std::function<bool(int64_t t)> stop;
+    int64_t* len_out = nullptr;  // optional: the number of terms computed (len unless stopped)
     // Symmetric projection U = V (U is ignored): S_k = V^T B^k V (Section 2.3), every term checked to be
     // symmetric after the run (an error otherwise).  With gram, two terms per application of B through the
     // weighted Gram identities of symmetric.hip (terms exact, symmetric by construction; not in the paper).

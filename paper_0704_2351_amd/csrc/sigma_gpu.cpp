@@ -237,6 +237,10 @@ Error OnlineGenerator::begin(const uint32_t* const* S_dev, int nb, int64_t L, in
     st_ = st;
     built_ = done_ = 0;
     next_ = pending_ = 0;
+    early_ = false;
+    prev_sum_ = -1;
+    prev_cut_ = 0;
+    conv_.store(0);
     cuts_.clear();
     if (L > 0) {
         int64_t c = 0;
@@ -262,10 +266,50 @@ Error OnlineGenerator::begin(const uint32_t* const* S_dev, int nb, int64_t L, in
     return {};
 }
 
+Error OnlineGenerator::begin_early(const uint32_t* S_dev, int64_t L, int32_t s, uint32_t p, int64_t step,
+                                   int64_t verify, hipStream_t st) {
+    if (step < 1 || verify < 1) return Error::inval("early termination needs positive chunk lengths");
+    BWR_TRY(begin(&S_dev, 1, L, s, &p, 0, st));
+    early_ = true;
+    step_ = step;
+    verify_ = verify;
+    cuts_.clear();
+    if (L > 0) cuts_.push_back(std::min(L, std::max(step, L / 8)));
+    return {};
+}
+
+// After the chunk ending at done_ (worker thread): compare the generator rows' degree sum with the previous
+// cut's, and choose the next cut.
+Error OnlineGenerator::after_chunk_early() {
+    const int m = 2 * s_;
+    std::vector<int64_t> d(m);
+    BWR_HIP(hipMemcpyAsync(d.data(), db_.as<void>(), sizeof(int64_t) * m, hipMemcpyDeviceToHost, st_));
+    BWR_HIP(hipStreamSynchronize(st_));
+    std::sort(d.begin(), d.end());
+    int64_t small = 0, all = 0;
+    for (int i = 0; i < m; ++i) {
+        all += d[i];
+        if (i < s_) small += d[i];
+    }
+    if (prev_sum_ >= 0 && small == prev_sum_ && done_ - prev_cut_ >= verify_) {
+        conv_.store(done_);
+        return {};
+    }
+    prev_sum_ = small;
+    prev_cut_ = done_;
+    if (done_ < L_) {
+        const bool stalled = (all - small) - small >= (int64_t)s_ * verify_;
+        cuts_.push_back(std::min(L_, done_ + (stalled ? verify_ : step_)));
+    }
+    return {};
+}
+
 OnlineGenerator::~OnlineGenerator() { (void)join_worker(); }
 
 void OnlineGenerator::feed_async(int64_t avail, hipEvent_t ready) {
-    while (pending_ < (int)cuts_.size() && cuts_[pending_] <= avail) ++pending_;
+    // in early-termination mode the worker owns the cuts (next_boundary() is not used there)
+    if (!early_)
+        while (pending_ < (int)cuts_.size() && cuts_[pending_] <= avail) ++pending_;
     {
         std::lock_guard<std::mutex> lk(mu_);
         queue_.emplace_back(avail, ready);
@@ -313,7 +357,7 @@ Error OnlineGenerator::join_worker() {
 
 Error OnlineGenerator::feed(int64_t avail, hipEvent_t ready) {
     avail = std::min(avail, L_);
-    if (avail <= built_) return {};
+    if (avail <= built_ || conv_.load() > 0) return {};
     // a host wait (feed_async runs this on the generator's own thread): a stream wait on an event of the
     // producer's stream would join a graph capture that stream may have begun since the event was recorded
     if (ready) BWR_HIP(hipEventSynchronize(ready));
@@ -339,6 +383,10 @@ Error OnlineGenerator::feed(int64_t avail, hipEvent_t ready) {
         }
         done_ = c1;
         ++next_;
+        if (early_) {
+            BWR_TRY(after_chunk_early());
+            if (conv_.load() > 0) break;
+        }
     }
     return {};
 }
@@ -347,7 +395,8 @@ Error OnlineGenerator::feed(int64_t avail, hipEvent_t ready) {
 
 Error OnlineGenerator::finish(Generator* out) {
     BWR_TRY(join_worker());
-    if (done_ != L_) return Error::inval("sigma-basis finished before every term was fed");
+    if (done_ != L_ && !(conv_.load() > 0 && done_ == conv_.load()))
+        return Error::inval("sigma-basis finished before every term was fed");
     const int m = 2 * s_, s = s_, nbt = pb_.n;
     DevBuf ib;
     DPoly P = Q_;

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <condition_variable>
 #include <deque>
 #include <mutex>
@@ -140,11 +141,28 @@ class OnlineGenerator {
     // per batch element).
     Error finish(Generator* out);
     // chunk end the next feed must reach to enqueue more work; -1 when every chunk is enqueued or queued
+    // (not in early-termination mode, whose cuts are chosen by the worker: feed every chunk of terms there)
     int64_t next_boundary() const { return pending_ < (int64_t)cuts_.size() ? cuts_[pending_] : -1; }
     int chunks() const { return (int)cuts_.size(); }
 
+    // Early termination (the outlook of the paper's conclusion; one sequence only).  The order range is cut
+    // as the terms arrive: the first cut at max(step, L/8), then every `step` orders.  After each chunk the
+    // sum of the s smallest shifted degrees (the generator rows' degrees) is compared with its value at the
+    // previous cut.  While the sequence still looks generic the s pivots of every order include generator
+    // rows, so that sum grows by about s/2 per order; when it has not changed over at least `verify` orders,
+    // none of those rows was a pivot over them, i.e. every generator row annihilated the terms of those
+    // orders.  The basis is then kept at that order (converged()), later feeds are ignored, and finish()
+    // returns the generator of that order.  Once the other s rows' degrees sum to at least s * verify more
+    // than the generator rows' (they have taken the pivots for that long), the next cut is only `verify`
+    // orders on, to confirm the stall early.
+    Error begin_early(const uint32_t* S_dev, int64_t L, int32_t s, uint32_t p, int64_t step, int64_t verify,
+                      hipStream_t st);
+    int64_t converged() const { return conv_.load(); }  // order of the kept basis, 0 while not converged
+    int64_t order() const { return done_; }              // order of the basis computed so far
+
    private:
     Error join_worker();
+    Error after_chunk_early();
     const uint32_t* S_[SIGMA_BATCH_MAX] = {};
     int64_t L_ = 0, built_ = 0, done_ = 0;
     int32_t s_ = 0;
@@ -163,6 +181,10 @@ class OnlineGenerator {
     std::deque<std::pair<int64_t, hipEvent_t>> queue_;
     bool closing_ = false;
     Error werr_;
+    // early termination
+    bool early_ = false;
+    int64_t step_ = 0, verify_ = 0, prev_sum_ = -1, prev_cut_ = 0;
+    std::atomic<int64_t> conv_{0};
 };
 
 // Window [lo, hi) of the products A_b B_b of two batches of device polynomial matrices, mod p_b.

@@ -212,3 +212,23 @@ def test_workspace_sizes():
     for bad in ((-1, 10, 10, 4), (10, 10, -5, 4), (10, 10, 10, 0), (10, 10, 10, 65)):
         assert bw.sequence_workspace(*bad) == 0
         assert bw.rank_workspace(*bad) == 0
+
+
+def test_early_termination_setting():
+    """bwr_set_early_termination takes 0 or 1 and refuses anything else with BWR_EINVAL, leaving the
+    setting; off by default."""
+    import paper_0704_2351_amd as bw
+    from paper_0704_2351_amd import binding
+
+    old = bw.get_early_termination()
+    assert old is False
+    try:
+        bw.set_early_termination(True)
+        assert bw.get_early_termination() is True
+        for bad in (2, -1):
+            with pytest.raises(bw.BwrError) as ei:
+                binding._check(bw.lib().bwr_set_early_termination(bad))
+            assert ei.value.code == -1
+        assert bw.get_early_termination() is True
+    finally:
+        bw.set_early_termination(old)

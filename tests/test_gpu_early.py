@@ -1,0 +1,88 @@
+"""Early termination (the outlook of the paper's conclusion): a single-matrix rank
+whose sequence stops once the device sigma-basis beside it has converged.  The
+rank must equal the planted rank (exact over every field) and the elimination
+oracle's, the generator must be taken at an order near 2 r / s + O(1) rather
+than at L = 2 + ceil(2 min(m, n) / s), and, when the rank is well below
+min(m, n), fewer terms must be computed than the full sequence has."""
+import numpy as np
+import pytest
+
+import paper_0704_2351_amd as bw
+from oracle import native
+from tests.gpu_util import announce, need_gpu
+from workloads import planted
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture
+def early():
+    need_gpu()
+    old = bw.get_early_termination()
+    bw.set_early_termination(True)
+    yield
+    bw.set_early_termination(old)
+
+
+def _full_len(A, s):
+    return bw.sequence_length(min(A.m, A.n), s)
+
+
+@pytest.mark.parametrize("p", [65521, 2**31 - 1])
+def test_low_rank_stops_early(early, p):
+    # r = 0.3 n: the generator's degree is about r / s, so about 2 r / s terms suffice
+    m, n, r, s = 90000, 60000, 18000, 8
+    announce(f"early termination: {m}x{n} rank {r}, s={s}, p={p}")
+    A = planted(m, n, r, 9, 20260 + (p & 7))
+    rank, info = bw.rank_modp(A, p, s, 1)
+    L = _full_len(A, s)
+    assert rank == r
+    assert info["len"] < L // 2, (info["len"], L)
+    assert info["len"] >= 2 * r // s, info["len"]
+    assert info["check_terms"] == 4
+    # terms computed: at least the generator's order plus the terms it was checked on, fewer than L
+    assert info["len"] + 4 <= info["terms"] < L, (info["len"], info["terms"], L)
+
+
+def test_equal_to_elimination_and_to_full_sequence(early):
+    # rank close to min(m, n): the stall comes late or not at all; the result must not change
+    m, n, r, s, p = 30000, 20000, 19000, 8, 65521
+    announce(f"early termination: {m}x{n} rank {r} against elimination and the full sequence")
+    A = planted(m, n, r, 9, 4242)
+    r_early, i_early = bw.rank_modp(A, p, s, 3)
+    bw.set_early_termination(False)
+    r_full, i_full = bw.rank_modp(A, p, s, 3)
+    bw.set_early_termination(True)
+    assert r_early == r_full == native.rank_csr_c(A, p) == r
+    assert i_full["len"] == _full_len(A, s) and i_full["terms"] == i_full["len"] + 4
+    assert i_early["len"] <= i_full["len"]
+
+
+def test_transposed_and_device_input(early):
+    # m < n: B acts on the row side; the device-pointer entry point shares the path
+    m, n, r, s, p = 40000, 60000, 12000, 8, 65521
+    announce(f"early termination: transposed {m}x{n} rank {r}, s={s}, device input")
+    A = planted(m, n, r, 9, 777)
+    Ad = bw.csr_to_device(A, "cuda:0")
+    rank, info = bw.rank_modp_dev(Ad, p, s, 5)
+    assert rank == r
+    assert info["transposed"] == 1
+    assert info["len"] < _full_len(A, s) // 2
+
+
+@pytest.mark.parametrize("gram", [False, True])
+def test_symmetric_projection(early, gram):
+    m, n, r, s, p = 60000, 40000, 10000, 8, 65521
+    announce(f"early termination: symmetric projection, gram={gram}")
+    A = planted(m, n, r, 9, 99 + int(gram))
+    rank, info = bw.rank_modp_sym(A, p, s, 1, gram=gram)
+    assert rank == r
+    assert info["len"] < _full_len(A, s) // 2
+
+
+def test_short_sequences_unchanged(early):
+    # under 4096 terms the basis runs after the sequence: early termination does not apply
+    A = planted(3000, 2000, 1200, 9, 5)
+    rank, info = bw.rank_modp(A, 65521, 4, 1)
+    assert rank == 1200 and info["len"] == _full_len(A, 4)
+

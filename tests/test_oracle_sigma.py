@@ -153,3 +153,34 @@ def test_readout_big_prime():
     A, dr, dc, S = tiny_case(5, m=18, n=12, r=8, k=3, s=2, p=p)
     L = 2 + -(-2 * A.n // 2)
     assert sigma.rank_from_sequence(S[:L], p) == 8
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("s", [2, 3])
+def test_early_termination_reading(seed, s):
+    """The reading behind early termination (the outlook of the conclusion), on the plain M-Basis: the
+    sum of the s smallest shifted degrees of the order-c basis of [S; -I] never decreases, grows over
+    every two orders while the generator rows still take pivots, and is constant from an order c* close
+    to 2 r / s on.  A stall over a few orders therefore marks c*, and the generator of the order where the
+    stall is seen has the same Popov form and read-out as the generator of the full length."""
+    A, dr, dc, S = tiny_case(seed, m=40, n=30, r=8 + seed, k=3, s=s)
+    r = A.planted_rank
+    L = 2 + -(-2 * A.n // s)
+    G = np.zeros((S.shape[0], 2 * s, s), dtype=np.int64)
+    G[:, :s, :] = S
+    G[0, s:, :] = (-np.eye(s, dtype=np.int64)) % P
+    shift = [0] * s + [1] * s
+    sums = [sum(sorted(sigma.mbasis(G, c, shift, P)[1])[:s]) for c in range(L + 1)]
+    assert all(a <= b for a, b in zip(sums, sums[1:]))
+    c_star = max(c for c in range(L + 1) if c == 0 or sums[c] != sums[c - 1])
+    assert c_star <= 2 * -(-(r + 1) // s) + 2, (c_star, r, s)
+    assert all(sums[c + 2] > sums[c] for c in range(c_star - 1)), sums
+    # the stall over v orders is first seen at c_star + v
+    v = 3
+    c_stop = next(c for c in range(v, L + 1) if sums[c] == sums[c - v])
+    assert c_stop == c_star + v
+    F_full, _, _ = sigma.min_generator(S[:L], P)
+    F_early, _, _ = sigma.min_generator(S[:c_stop], P)
+    assert np.array_equal(sigma.popov_form(F_early, P), sigma.popov_form(F_full, P))
+    assert sigma.annihilates(F_early, S, P)
+    assert sigma.rank_from_generator(F_early, P) == r == ge.rank_csr(A, P)
