@@ -233,6 +233,12 @@ Error encode_matrix(const CsrView& A, uint32_t p, hipStream_t st, DeviceMatrix* 
     for (int64_t j = 0; j < A.n; ++j) inv_c[perm_c[j]] = (int32_t)j;
     std::vector<int64_t> rp_new((size_t)A.m + 1, 0);
     for (int64_t i = 0; i < A.m; ++i) rp_new[i + 1] = rp_new[i] + lr[perm_r[i]];
+    // declared after the host vectors, so destroyed before them: an error return below must not free them
+    // while their asynchronous (possibly staged) copies are still pending
+    struct DrainOnExit {
+        hipStream_t st;
+        ~DrainOnExit() { (void)hipStreamSynchronize(st); }
+    } drain_before_free{st};
     DevBuf d_pr, d_pc, d_ic, d_rp, d_col, d_val;
     BWR_TRY(d_pr.alloc(sizeof(int32_t) * perm_r.size(), st));
     BWR_TRY(d_pc.alloc(sizeof(int32_t) * perm_c.size(), st));
