@@ -140,7 +140,9 @@ int32_t bwr_get_trials(void);
  * length in a sequence that is not yet complete is a further Monte Carlo
  * event (the check terms past the kept order guard against it).  Off (0) by
  * default.  The matrices that bwr_rank_modp_batch and the server send to
- * their single-matrix lanes use it too; their batched sequences do not.
+ * their single-matrix lanes use it too; their batched sequences do not, so
+ * with it on bwr_rank_modp_batch sends every matrix whose sequence can stop
+ * early (at least 4096 terms) to its single-matrix lanes.
  * Returns BWR_EINVAL for other values.
  * Like bwr_set_trials, it must not run while another call is in progress. */
 int bwr_set_early_termination(int32_t on);
@@ -305,8 +307,9 @@ int bwr_time_step_kernels_dev(const bwr_csr* A_dev, uint32_t p, int32_t s, int32
  * ranks_out[j * nprimes + t].  Matrices with entries outside [-127, 127] or
  * a dimension above 2^24, and matrices whose side-by-side block (larger
  * dimension x width x bytes per residue) exceeds 2 MB (BWR_BATCH_BLOCK_BYTES),
- * take the single-matrix path, on 2 host threads (BWR_BATCH_SOLO_THREADS) that
- * run beside the batched launches.  When the primes mix 16-bit and larger ones,
+ * take the single-matrix path, on 2 host threads (BWR_BATCH_SOLO_THREADS; 1
+ * when early termination is on, which sends more matrices there) that run
+ * beside the batched launches.  When the primes mix 16-bit and larger ones,
  * the 16-bit primes are batched with 16-bit residues and the larger ones take
  * the single-matrix path (BWR_BATCH_SPLIT=0: all primes batched, 32-bit
  * residues).  The sigma-bases of a job's primes run as one batched

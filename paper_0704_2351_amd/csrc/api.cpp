@@ -1088,6 +1088,16 @@ int bwr_rank_modp_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* p
         const int per_job = std::max(1, std::min(nbp, 32 / std::max(spad, 1)));
         if (outer * (int64_t)per_job * spad * besize > block_bytes_max) batched[j] = false;
     }
+    // With early termination on, a matrix whose single-matrix solve can stop early (a sequence of at least
+    // 4096 terms, whose sigma-basis then runs beside it on the device) goes to the single-matrix lanes: the
+    // batched sequences always run their full length.
+    if (g_early.load() != 0)
+        for (int j = 0; j < nmat; ++j) {
+            if (!batched[j]) continue;
+            const int64_t nb = std::min(A[j]->m, A[j]->n);
+            const int32_t s = (int32_t)std::min<int64_t>(block, nb);
+            if (gpu_leaf_order(s) > 0 && online_min_chunk(2 + (2 * nb + s - 1) / s) > 0) batched[j] = false;
+        }
     std::vector<std::pair<int, int>> solo;  // (matrix, prime) pairs for the single-matrix path
     for (int j = 0; j < nmat; ++j) {
         if (A[j]->nnz == 0 || A[j]->m == 0 || A[j]->n == 0) continue;
@@ -1103,7 +1113,11 @@ int bwr_rank_modp_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* p
         if (he != hipSuccess) return fail(Error::device(he, "upload"));
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-        const int nthr = (int)std::min<int64_t>((int64_t)solo.size(), std::max<int64_t>(1, env_i64("BWR_BATCH_SOLO_THREADS", BATCH_SOLO_THREADS)));
+        // with early termination the large matrices are solo and fill the GPU one at a time (16 of the batched
+        // configuration's matrices x 4 primes: 2.07 solves/s with one lane against 1.86 with two)
+        const int64_t dflt = g_early.load() != 0 ? 1 : BATCH_SOLO_THREADS;
+        const int nthr = (int)std::min<int64_t>((int64_t)solo.size(),
+                                                std::max<int64_t>(1, env_i64("BWR_BATCH_SOLO_THREADS", dflt)));
         for (int w = 0; w < nthr; ++w)
             solo_threads.emplace_back([&, dev] {
                 (void)hipSetDevice(dev);

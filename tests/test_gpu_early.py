@@ -86,3 +86,14 @@ def test_short_sequences_unchanged(early):
     rank, info = bw.rank_modp(A, 65521, 4, 1)
     assert rank == 1200 and info["len"] == _full_len(A, 4)
 
+
+
+def test_batched_call_with_early_termination(early):
+    # with early termination on, the batched call sends the matrices whose sequence can stop early to its
+    # single-matrix lanes and batches the rest; every rank must still be the planted one
+    mats = [planted(3000, 2000, 1500, 9, 11), planted(30000, 20000, 14000, 9, 12), planted(45000, 30000, 9000, 9, 13)]
+    announce("early termination: batched call, 3 matrices x 3 primes")
+    primes = [65521, 65519, 2**31 - 1]
+    ranks, _ = bw.rank_modp_batch(mats, primes, 8, 1)
+    want = np.array([[A.planted_rank] * len(primes) for A in mats])
+    assert np.array_equal(ranks, want), (ranks, want)
