@@ -97,3 +97,40 @@ def test_batched_call_with_early_termination(early):
     ranks, _ = bw.rank_modp_batch(mats, primes, 8, 1)
     want = np.array([[A.planted_rank] * len(primes) for A in mats])
     assert np.array_equal(ranks, want), (ranks, want)
+
+
+def test_with_trials(early):
+    # two draws, each stopping early; the larger rank is kept (both equal the planted rank here)
+    old = bw.get_trials()
+    bw.set_trials(2)
+    try:
+        A = planted(60000, 40000, 16000, 9, 31)
+        announce("early termination: two draws")
+        rank, info = bw.rank_modp(A, 65521, 8, 1)
+    finally:
+        bw.set_trials(old)
+    assert rank == 16000 and info["trials"] == 2
+    assert info["len"] < _full_len(A, 8) // 2
+
+
+def test_workspace_form_runs_full_length(early):
+    # inside a caller's workspace the generator is computed after the sequence (on the host), so early
+    # termination does not apply there; the rank is the same
+    A = planted(30000, 20000, 8000, 9, 41)
+    announce("early termination: workspace form")
+    Ad = bw.csr_to_device(A, "cuda:0")
+    rank, info = bw.rank_modp_dev_ws(Ad, 65521, 8, 1)
+    assert rank == 8000 and info["len"] == _full_len(A, 8)
+
+
+def test_server_solo_lane(early):
+    # a request of at least 2^20 non-zeros runs on the server's single-matrix lane, which stops early
+    A = planted(105000, 70000, 42000, 9, 51)
+    assert A.nnz >= 1 << 20
+    announce(f"early termination: server solo lane, {A.m}x{A.n}, {A.nnz} non-zeros")
+    srv = bw.Server(8 << 30, 8, 8)
+    try:
+        r = srv.wait(srv.submit(A, 65521, 1))
+    finally:
+        srv.close()
+    assert r == 42000
