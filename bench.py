@@ -9,7 +9,8 @@ autotuner has picked the launch plan before the timed region; every step is one
 bwr_matrix_sequence_dev call from the same U, V and diagonals, inputs resident
 in HBM.  After the timed steps the whole rank of the same matrix is computed
 once (bwr_rank_modp_dev: encoding, 2 + 2n/16 + 4 terms, sigma-basis, read-out)
-and checked against the planted rank.
+and checked against the planted rank, then once more with early termination
+(bwr_set_early_termination; --no-early-rank skips it).
 
 value = whole-job throughput in Gnnz.vec/s: the sparse multiply-adds of the
 two products of every application of B (2 nnz s per application), summed over
@@ -332,6 +333,24 @@ def sequence_mode(args):
                        "t_sigma_after_sequence": round(info["t_sigma"], 3), "t_encode": round(info["t_encode"], 3),
                        "gnnzvec_per_s": round(2.0 * nnz * info["s"] * (info["terms"] - 1) / el / 1e9,
                                               3)}
+        if not args.no_early_rank:
+            # the same rank with early termination (a library option, off by default): the sequence stops
+            # once the sigma-basis beside it shows that the generator has stopped growing
+            log("the same rank with early termination")
+            try:
+                bw.set_early_termination(True)
+                t0 = time.perf_counter()
+                r2, info2 = bw.rank_modp_dev(Ad, p, s, 1)
+                torch.cuda.synchronize()
+                el2 = time.perf_counter() - t0
+                out["rank_early_termination"] = {
+                    "rank": int(r2), "equals_planted": bool(r2 == A.planted_rank), "seconds": round(el2, 2),
+                    "terms_computed": int(info2["terms"]), "full_length": int(info["terms"]),
+                    "generator_order": int(info2["len"]), "t_sequence": round(info2["t_sequence"], 2)}
+            except Exception as ex:  # reported, not fatal: the line above is the benchmark
+                out["rank_early_termination"] = {"error": str(ex)}
+            finally:
+                bw.set_early_termination(False)
     del Ad
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
@@ -639,6 +658,8 @@ def main():
                     help="sequence terms per step of the default workload (terms - 1 applications of B)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rank", action="store_true", help="default workload: skip the whole rank after the steps")
+    ap.add_argument("--no-early-rank", action="store_true",
+                    help="default workload: skip the second whole rank, with early termination")
     ap.add_argument("--kernel-iters", type=int, default=50)
     ap.add_argument("--batch", action="store_true",
                     help="batched workload: planted matrices of the batched configuration, 4 primes, block 8; "
