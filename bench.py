@@ -224,7 +224,9 @@ def batch_mode(args):
     t0 = time.perf_counter()
     ranks, info = bw.rank_modp_batch(mats, primes, 8, 1)
     tb = time.perf_counter() - t0
-    ok_b = all(ranks[j, t] == A.planted_rank for j, A in enumerate(mats) for t in range(len(primes)))
+    short = [[int(j), int(primes[t]), int(ranks[j, t]), int(A.planted_rank)] for j, A in enumerate(mats)
+             for t in range(len(primes)) if ranks[j, t] != A.planted_rank]
+    ok_b = not short
     log(f"batched {tb:.2f} s, ranks ok: {ok_b}")
     t0 = time.perf_counter()
     plain_ok = True
@@ -240,6 +242,9 @@ def batch_mode(args):
         "plain_solves_per_s": round(nsolves / tp, 4), "speedup_vs_plain": round(tp / tb, 3),
         "batched_gnnzvec_per_s": round(work / tb / 1e9, 3), "plain_gnnzvec_per_s": round(work / tp / 1e9, 3),
         "ranks_equal_planted": bool(ok_b), "ranks_equal_plain": bool(plain_ok), "solves": nsolves,
+        "ranks_short_of_planted": short,  # [matrix index, p, rank, planted rank]
+        # with early termination the Gnnz.vec/s figures still count every sequence at its full length
+        "early_termination": bool(bw.get_early_termination()),
         "batch_info": info, "higher_is_better": True, "n_gpus": 1, "dtype": "u32",
         "data": "synthetic planted-rank matrices (seeded)",
         "config": {"workload": f"{len(mats)} of the 64 batched-configuration matrices (n log-uniform 5e3..2e5, "
