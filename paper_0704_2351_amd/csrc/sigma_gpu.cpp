@@ -273,6 +273,7 @@ Error OnlineGenerator::begin_early(const uint32_t* S_dev, int64_t L, int32_t s, 
     early_ = true;
     step_ = step;
     verify_ = verify;
+    vstep_ = verify;
     cuts_.clear();
     if (L > 0) cuts_.push_back(std::min(L, std::max(step, L / 8)));
     return {};
@@ -298,8 +299,15 @@ Error OnlineGenerator::after_chunk_early() {
     prev_sum_ = small;
     prev_cut_ = done_;
     if (done_ < L_) {
+        // a confirming cut that did not confirm doubles the next one (up to step_): a generator whose rows
+        // stall at orders far apart must not cost a chunk every `verify` orders
         const bool stalled = (all - small) - small >= (int64_t)s_ * verify_;
-        cuts_.push_back(std::min(L_, done_ + (stalled ? verify_ : step_)));
+        int64_t next = step_;
+        if (stalled) {
+            next = vstep_;
+            vstep_ = std::min(step_, 2 * vstep_);
+        }
+        cuts_.push_back(std::min(L_, done_ + next));
     }
     return {};
 }

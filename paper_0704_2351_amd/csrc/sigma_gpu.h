@@ -154,7 +154,8 @@ class OnlineGenerator {
     // orders.  The basis is then kept at that order (converged()), later feeds are ignored, and finish()
     // returns the generator of that order.  Once the other s rows' degrees sum to at least s * verify more
     // than the generator rows' (they have taken the pivots for that long), the next cut is only `verify`
-    // orders on, to confirm the stall early.
+    // orders on, to confirm the stall early (twice that after a confirming cut that did not confirm, and so
+    // on up to `step`).
     Error begin_early(const uint32_t* S_dev, int64_t L, int32_t s, uint32_t p, int64_t step, int64_t verify,
                       hipStream_t st);
     int64_t converged() const { return conv_.load(); }  // order of the kept basis, 0 while not converged
@@ -183,7 +184,7 @@ class OnlineGenerator {
     Error werr_;
     // early termination
     bool early_ = false;
-    int64_t step_ = 0, verify_ = 0, prev_sum_ = -1, prev_cut_ = 0;
+    int64_t step_ = 0, verify_ = 0, vstep_ = 0, prev_sum_ = -1, prev_cut_ = 0;
     std::atomic<int64_t> conv_{0};
 };
 
