@@ -96,6 +96,7 @@ typedef struct {
     int32_t jobs;       /* (matrix, group of primes) jobs */
     int32_t width;      /* block width of the batch (primes per job x block size, padded) */
     int32_t g1, g2;     /* lanes per row slice of the two products */
+    int32_t retries;    /* further draws made by the agreement retry (bwr_set_batch_retry) */
 } bwr_batch_info;
 
 /* Library version (major * 10000 + minor * 100 + patch). */
@@ -147,6 +148,21 @@ int32_t bwr_get_trials(void);
  * Like bwr_set_trials, it must not run while another call is in progress. */
 int bwr_set_early_termination(int32_t on);
 int32_t bwr_get_early_termination(void);
+
+/* Agreement retry of bwr_rank_modp_batch (and bwr_rank_integer): after the
+ * batch, a (matrix, prime) whose rank is below the largest rank of the same
+ * matrix at the other primes gets up to n further single-matrix draws (seeds
+ * seed + trials, seed + trials + 1, ...), stopping once it reaches that
+ * largest rank, and keeps the largest result.  Every draw returns at most the
+ * rank mod p (Section 2.5: the error is one-sided), so the result stays a
+ * valid Monte Carlo rank mod p; a prime that divides minors of A keeps its
+ * lower rank after the n draws.  The draws are made only where the primes
+ * disagree, so they cost little beside the batch; with n > 0 a batched rank
+ * may exceed bwr_rank_modp's with the same seed.  0 (the default) disables
+ * it; n in 0..16, else BWR_EINVAL.  Must not run while another call is in
+ * progress. */
+int bwr_set_batch_retry(int32_t n);
+int32_t bwr_get_batch_retry(void);
 
 /* The random residues the rank draws, from a counter-based SplitMix64
  * (Steele, Lea, Flood 2014): with mix() the SplitMix64 finaliser and
@@ -303,7 +319,8 @@ int bwr_time_step_kernels_dev(const bwr_csr* A_dev, uint32_t p, int32_t s, int32
  * (matrix, group of primes) job, and the primes of a job share one pass over
  * the matrix (their blocks sit side by side in one block of width
  * primes x block).  Each rank equals bwr_rank_modp(A[j], primes[t], block,
- * seed) exactly: same draws, same sequence, same read-out.
+ * seed) exactly: same draws, same sequence, same read-out (unless the
+ * agreement retry, bwr_set_batch_retry, raised it with further draws).
  * ranks_out[j * nprimes + t].  Matrices with entries outside [-127, 127] or
  * a dimension above 2^24, and matrices whose side-by-side block (larger
  * dimension x width x bytes per residue) exceeds 2 MB (BWR_BATCH_BLOCK_BYTES),

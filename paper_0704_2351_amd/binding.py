@@ -25,7 +25,8 @@ EXPORTED = ("bwr_version", "bwr_last_error", "bwr_is_prime", "bwr_sequence_lengt
             "bwr_get_trials", "bwr_sequence_workspace", "bwr_rank_workspace", "bwr_sequence_dev_ws",
             "bwr_rank_modp_dev_ws", "bwr_device_allocations", "bwr_sequence_sym_dev", "bwr_rank_modp_sym",
             "bwr_rank_modp_sym_dev", "bwr_matrix_sequence_sym_dev", "bwr_sequence_dev_noalloc",
-            "bwr_set_early_termination", "bwr_get_early_termination")
+            "bwr_set_early_termination", "bwr_get_early_termination", "bwr_set_batch_retry",
+            "bwr_get_batch_retry")
 
 
 class BwrError(RuntimeError):
@@ -42,7 +43,8 @@ class CSRStruct(ctypes.Structure):
 class BatchInfo(ctypes.Structure):
     _fields_ = [("t_encode", ctypes.c_double), ("t_sequence", ctypes.c_double), ("t_sigma", ctypes.c_double),
                 ("t_total", ctypes.c_double), ("steps", ctypes.c_int64), ("jobs", ctypes.c_int32),
-                ("width", ctypes.c_int32), ("g1", ctypes.c_int32), ("g2", ctypes.c_int32)]
+                ("width", ctypes.c_int32), ("g1", ctypes.c_int32), ("g2", ctypes.c_int32),
+                ("retries", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -80,6 +82,8 @@ def lib():
             "bwr_get_trials": (i32, []),
             "bwr_set_early_termination": (ctypes.c_int, [i32]),
             "bwr_get_early_termination": (i32, []),
+            "bwr_set_batch_retry": (ctypes.c_int, [i32]),
+            "bwr_get_batch_retry": (i32, []),
             "bwr_random_block": (ctypes.c_int, [u64, i32, i64, i32, u32, i32, vp]),
             "bwr_sequence": (ctypes.c_int, [vp, vp, vp, vp, vp, u32, i32, i64, vp]),
             "bwr_sequence_dev": (ctypes.c_int, [vp, vp, vp, vp, vp, u32, i32, i64, vp, vp]),
@@ -182,6 +186,15 @@ def set_early_termination(on: bool) -> None:
 
 def get_early_termination() -> bool:
     return bool(lib().bwr_get_early_termination())
+
+
+def set_batch_retry(n: int) -> None:
+    """Further draws (up to n) for a batched (matrix, prime) whose rank is below the matrix's largest rank."""
+    _check(lib().bwr_set_batch_retry(int(n)))
+
+
+def get_batch_retry() -> int:
+    return int(lib().bwr_get_batch_retry())
 
 
 def random_block(seed: int, stream: int, rows: int, s: int, p: int, diag: bool = False) -> np.ndarray:

@@ -32,6 +32,8 @@ thread_local std::string g_err;
 std::atomic<int32_t> g_trials{1};
 // early termination of single-matrix ranks (bwr_set_early_termination)
 std::atomic<int32_t> g_early{0};
+// further draws where the primes of a batched matrix disagree (bwr_set_batch_retry)
+std::atomic<int32_t> g_batch_retry{0};
 // early termination's cut lengths: at least these many orders, else L / 32 and a eighth of that
 constexpr int64_t EARLY_MIN_STEP = 512;
 constexpr int64_t EARLY_MIN_VERIFY = 128;
@@ -510,6 +512,15 @@ int bwr_set_early_termination(int32_t on) {
 }
 
 int32_t bwr_get_early_termination(void) { return g_early.load(); }
+
+int bwr_set_batch_retry(int32_t n) {
+    if (n < 0 || n > 16) return fail(BWR_EINVAL, "batch retry must be in 0..16");
+    g_batch_retry.store(n);
+    g_err.clear();
+    return BWR_OK;
+}
+
+int32_t bwr_get_batch_retry(void) { return g_batch_retry.load(); }
 
 int bwr_set_threads(int32_t n) {
     if (n < 1) return fail(BWR_EINVAL, "thread count must be positive");
@@ -1275,6 +1286,26 @@ int bwr_rank_modp_batch(const bwr_csr* const* A, int32_t nmat, const uint32_t* p
     }
     for (auto& t : solo_threads) t.join();
     if (!solo_err.ok()) return fail(solo_err);
+    // agreement retry: further draws for a prime whose rank is below the matrix's largest rank at the others
+    // (each draw is at most the rank mod p, so the largest is kept)
+    if (const int32_t retry = g_batch_retry.load(); retry > 0 && nprimes > 1) {
+        for (int j = 0; j < nmat; ++j) {
+            if (A[j]->nnz == 0 || A[j]->m == 0 || A[j]->n == 0) continue;
+            int64_t best = 0;
+            for (int t = 0; t < nprimes; ++t) best = std::max(best, ranks[(size_t)j * nprimes + t]);
+            for (int t = 0; t < nprimes; ++t) {
+                int64_t& r = ranks[(size_t)j * nprimes + t];
+                for (int32_t k = 0; k < retry && r < best; ++k) {
+                    RankOut ro;
+                    if (!(e = rank_dev_impl(ups[j].dev, primes[t], block, seed + (uint64_t)(trials + k), st, &ro, 1))
+                             .ok())
+                        return fail(e);
+                    r = std::max(r, ro.rank);
+                    ++bi.retries;
+                }
+            }
+        }
+    }
     std::memcpy(ranks_out, ranks.data(), sizeof(int64_t) * ranks.size());
     bi.t_total = now_s() - t0;
     if (info) *info = bi;

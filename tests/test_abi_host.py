@@ -232,3 +232,21 @@ def test_early_termination_setting():
         assert bw.get_early_termination() is True
     finally:
         bw.set_early_termination(old)
+
+
+def test_batch_retry_setting():
+    """bwr_set_batch_retry takes 0 .. 16 and refuses anything else with BWR_EINVAL; 0 by default."""
+    import paper_0704_2351_amd as bw
+
+    old = bw.get_batch_retry()
+    assert old == 0
+    try:
+        bw.set_batch_retry(2)
+        assert bw.get_batch_retry() == 2
+        for bad in (-1, 17):
+            with pytest.raises(bw.BwrError) as ei:
+                bw.set_batch_retry(bad)
+            assert ei.value.code == -1
+        assert bw.get_batch_retry() == 2
+    finally:
+        bw.set_batch_retry(old)

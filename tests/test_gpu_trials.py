@@ -71,3 +71,18 @@ def test_full_rank_stops_after_one_draw(trials):
     A = planted(900, 600, 600, 7, 5)
     r, info = bw.rank_modp(A, 65521, 8, 1)
     assert r == 600 and info["trials"] == 1
+
+
+def test_batched_agreement_retry(miss, trials):
+    """One draw, with the agreement retry: the 16-bit prime whose first draw falls short of the other primes'
+    rank gets a further draw and reaches the planted rank; the primes that agreed get none."""
+    announce("trials: batched agreement retry")
+    trials(1)
+    old = bw.get_batch_retry()
+    bw.set_batch_retry(2)
+    try:
+        ranks, info = bw.rank_modp_batch([miss], [65521, 65519, 2**31 - 1], 8, 1)
+    finally:
+        bw.set_batch_retry(old)
+    assert np.all(ranks == miss.planted_rank), ranks
+    assert 1 <= info["retries"] <= 2
