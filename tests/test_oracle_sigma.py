@@ -184,3 +184,28 @@ def test_early_termination_reading(seed, s):
     assert np.array_equal(sigma.popov_form(F_early, P), sigma.popov_form(F_full, P))
     assert sigma.annihilates(F_early, S, P)
     assert sigma.rank_from_generator(F_early, P) == r == ge.rank_csr(A, P)
+
+
+@pytest.mark.parametrize("p", [5, 7, 11])
+def test_readout_is_one_sided_at_tiny_primes(p):
+    """Each draw of the method gives at most the rank mod p (Section 2.5: the algorithm can only return less),
+    which is what makes the largest rank over several draws (trials, and the batched agreement retry) a valid
+    result.  At tiny primes the random diagonals and projections are often degenerate, so draws fall short
+    often: none may exceed the elimination rank, some fall short, and the largest over 16 draws reaches it."""
+    A = planted(20, 14, 9, 3, 77)
+    want = ge.rank_csr(A, p)
+    assert want == A.planted_rank == 9
+    s = 2
+    L = 2 + -(-2 * A.n // s)
+    got = []
+    for seed in range(16):
+        rng = np.random.default_rng(seed)
+        dr = rng.integers(1, p, size=A.m)
+        dc = rng.integers(1, p, size=A.n)
+        U = rng.integers(0, p, size=(A.n, s))
+        V = rng.integers(0, p, size=(A.n, s))
+        S = oseq.sequence(A, U, V, p, L, dr, dc)
+        got.append(sigma.rank_from_sequence(S, p))
+    assert max(got) == want, got
+    assert all(r <= want for r in got), got
+    assert min(got) < want, got
