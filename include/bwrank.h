@@ -11,6 +11,8 @@
  *   Section 2.5  the "Block Wiedemann Rank Algorithm": precondition, compute
  *                S_i = Y^T A~^i Y for i = 0 .. 2n/s + O(1), take the minimal
  *                generator F, return deg det F - codeg det F.
+ *   Section 4    (Conclusion, outlook) early termination of the sequence: an option
+ *                here (bwr_set_early_termination).
  *
  * Conventions for every entry point:
  *   - Return value 0 (BWR_OK) or a negative error code below; on error nothing
@@ -127,11 +129,12 @@ int bwr_set_trials(int32_t n);
 int32_t bwr_get_trials(void);
 
 /* Early termination of the sequence (the outlook of the paper's conclusion,
- * Section 5: the sequence needs about 2 rank / s terms, not 2 min(m, n) / s,
+ * Section 4: the sequence needs about 2 rank / s terms, not 2 min(m, n) / s,
  * when the rank is below min(m, n)).  on = 1 applies to single-matrix ranks
- * (bwr_rank_modp, bwr_rank_modp_dev, bwr_rank_modp_sym(_dev), the matrix
- * handle and workspace forms) whose sequence has at least 4096 terms and
- * whose sigma-basis runs on the device: the basis is computed beside the
+ * (bwr_rank_modp, bwr_rank_modp_dev, bwr_rank_modp_sym(_dev); not
+ * bwr_rank_modp_dev_ws, whose generator is computed after the sequence)
+ * whose sequence has at least 4096 terms and whose sigma-basis runs on the
+ * device: the basis is computed beside the
  * sequence in chunks cut as the terms arrive (max(512, L/32) orders, the
  * first at L/8), and the sequence stops once the generator rows' shifted
  * degrees have not changed over max(128, chunk/8) orders and 4 terms past
