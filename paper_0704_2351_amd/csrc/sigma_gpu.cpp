@@ -238,8 +238,7 @@ Error OnlineGenerator::begin(const uint32_t* const* S_dev, int nb, int64_t L, in
     built_ = done_ = 0;
     next_ = pending_ = 0;
     early_ = false;
-    prev_sum_ = -1;
-    prev_cut_ = 0;
+    ecs_ = EarlyCutState{};
     conv_.store(0);
     cuts_.clear();
     if (L > 0) {
@@ -273,42 +272,25 @@ Error OnlineGenerator::begin_early(const uint32_t* S_dev, int64_t L, int32_t s, 
     early_ = true;
     step_ = step;
     verify_ = verify;
-    vstep_ = verify;
+    ecs_ = EarlyCutState{};
+    ecs_.vstep = verify;
     cuts_.clear();
     if (L > 0) cuts_.push_back(std::min(L, std::max(step, L / 8)));
     return {};
 }
 
-// After the chunk ending at done_ (worker thread): compare the generator rows' degree sum with the previous
-// cut's, and choose the next cut.
+// After the chunk ending at done_ (worker thread): the generator rows' degree sum against the previous cut's
+// decides convergence and the next cut (early_cut.h).
 Error OnlineGenerator::after_chunk_early() {
-    const int m = 2 * s_;
-    std::vector<int64_t> d(m);
-    BWR_HIP(hipMemcpyAsync(d.data(), db_.as<void>(), sizeof(int64_t) * m, hipMemcpyDeviceToHost, st_));
+    std::vector<int64_t> d(2 * s_);
+    BWR_HIP(hipMemcpyAsync(d.data(), db_.as<void>(), sizeof(int64_t) * d.size(), hipMemcpyDeviceToHost, st_));
     BWR_HIP(hipStreamSynchronize(st_));
-    std::sort(d.begin(), d.end());
-    int64_t small = 0, all = 0;
-    for (int i = 0; i < m; ++i) {
-        all += d[i];
-        if (i < s_) small += d[i];
-    }
-    if (prev_sum_ >= 0 && small == prev_sum_ && done_ - prev_cut_ >= verify_) {
+    const EarlyCutDecision dec = early_cut_after_chunk(d.data(), s_, done_, L_, step_, verify_, &ecs_);
+    if (dec.converged) {
         conv_.store(done_);
         return {};
     }
-    prev_sum_ = small;
-    prev_cut_ = done_;
-    if (done_ < L_) {
-        // a confirming cut that did not confirm doubles the next one (up to step_): a generator whose rows
-        // stall at orders far apart must not cost a chunk every `verify` orders
-        const bool stalled = (all - small) - small >= (int64_t)s_ * verify_;
-        int64_t next = step_;
-        if (stalled) {
-            next = vstep_;
-            vstep_ = std::min(step_, 2 * vstep_);
-        }
-        cuts_.push_back(std::min(L_, done_ + next));
-    }
+    if (dec.next_cut >= 0) cuts_.push_back(dec.next_cut);
     return {};
 }
 

@@ -11,6 +11,7 @@
 #include <utility>
 #include <vector>
 
+#include "early_cut.h"
 #include "engine.h"
 #include "modp.h"
 #include "sigma.h"
@@ -184,7 +185,8 @@ class OnlineGenerator {
     Error werr_;
     // early termination
     bool early_ = false;
-    int64_t step_ = 0, verify_ = 0, vstep_ = 0, prev_sum_ = -1, prev_cut_ = 0;
+    int64_t step_ = 0, verify_ = 0;
+    EarlyCutState ecs_;
     std::atomic<int64_t> conv_{0};
 };
 
