@@ -209,3 +209,29 @@ def test_readout_is_one_sided_at_tiny_primes(p):
     assert max(got) == want, got
     assert all(r <= want for r in got), got
     assert min(got) < want, got
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_early_termination_reading_symmetric_projection(seed):
+    """The same premise with the symmetric projection U = V (Section 2.3), which early termination also
+    serves: the generator rows' degree sum stalls at c* <= 2 ceil((r+1)/s) + 2, and the generator at the
+    first stall seen over three orders reads out the rank."""
+    p, s = P, 2
+    rng = np.random.default_rng(500 + seed)
+    A = planted(36, 26, 7 + seed, 3, 900 + seed)
+    dr = rng.integers(1, p, size=A.m)
+    dc = rng.integers(1, p, size=A.n)
+    V = rng.integers(0, p, size=(A.n, s))
+    L = 2 + -(-2 * A.n // s)
+    S = oseq.sequence(A, V, V, p, L, dr, dc)
+    assert all(np.array_equal(S[k], S[k].T) for k in range(L))
+    G = np.zeros((L, 2 * s, s), dtype=np.int64)
+    G[:, :s, :] = S
+    G[0, s:, :] = (-np.eye(s, dtype=np.int64)) % p
+    shift = [0] * s + [1] * s
+    sums = [sum(sorted(sigma.mbasis(G, c, shift, p)[1])[:s]) for c in range(L + 1)]
+    c_star = max(c for c in range(L + 1) if c == 0 or sums[c] != sums[c - 1])
+    assert c_star <= 2 * -(-(A.planted_rank + 1) // s) + 2
+    c_stop = next(c for c in range(3, L + 1) if sums[c] == sums[c - 3])
+    F, _, _ = sigma.min_generator(S[:c_stop], p)
+    assert sigma.rank_from_generator(F, p) == A.planted_rank == ge.rank_csr(A, p)
