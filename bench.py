@@ -34,7 +34,9 @@ elimination rank of the 2000 x 1500 and 200000 x 150000 planted matrices.
 
 Other modes: --rank-c2 (ranks of the 200000 x 150000 matrix at p = 65521 and
 2^31 - 1), --paper-rank (the whole rank only), --batch, --serve, and
---profile-kernels / --traffic-from for the counter summaries.
+--profile-kernels / --traffic-from for the counter summaries.  --early turns
+early termination on for --paper-rank, --batch and --serve; --batch-retry n
+applies the batched agreement retry to both passes of --batch.
 """
 from __future__ import annotations
 
