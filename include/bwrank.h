@@ -140,7 +140,9 @@ int32_t bwr_get_trials(void);
  * degrees have not changed over max(128, chunk/8) orders and 4 terms past
  * that order are complete.  The generator of that order is then checked on
  * the 4 terms past it and read out as usual (bwr_rank_info.len is its order,
- * terms the number of terms computed).  A stall of that
+ * terms the number of terms computed); should that check fail (a stall
+ * before the sequence was complete), the draw is made again at the full
+ * length.  A stall of that
  * length in a sequence that is not yet complete is a further Monte Carlo
  * event (the check terms past the kept order guard against it).  Off (0) by
  * default.  The matrices that bwr_rank_modp_batch and the server send to
@@ -465,6 +467,12 @@ int bwr_rank_from_sequence(const uint32_t* S, int64_t len, int64_t check, int32_
  *   BWR_NO_GRAPH=1         launch every step instead of replaying HIP graphs
  *   BWR_HOST_SIGMA=1       sigma-basis on the host instead of the device
  *   BWR_SIGMA_MIN_CHUNK    see bwr_rank_info.t_sigma
+ *   BWR_EARLY_STEP, BWR_EARLY_VERIFY  (tests) the chunk and confirmation
+ *                          lengths of early termination; BWR_EARLY_FORCE_AT=c
+ *                          keeps the basis at the first cut at or past order
+ *                          c, stalled or not.  A generator kept too early
+ *                          fails its check, and the draw is then made again
+ *                          at the full length
  *   BWR_SIGMA_BATCH, BWR_BATCH_SPLIT, BWR_BATCH_BLOCK_BYTES,
  *   BWR_BATCH_SOLO_THREADS see bwr_rank_modp_batch
  *   BWR_BATCH_G1, BWR_BATCH_G2  lanes per row slice of the batched products

@@ -214,6 +214,7 @@ Error sequence_dev_impl(const CsrView& A, const uint32_t* d_row, const uint32_t*
 struct RankOut {
     int64_t rank = 0;
     bwr_rank_info info{};
+    bool stopped_early = false;  // the sequence of the draw stopped before its full length
 };
 
 constexpr int64_t CHECK_TERMS = 4;
@@ -244,7 +245,7 @@ struct StreamDrain {
 // the sequence with the sigma-basis beside it, the generator check and the read-out.
 // proj: 0 = independent U and V; 1 = symmetric projection U = V (Section 2.3); 2 = symmetric, in Gram form.
 Error rank_one_draw(const DeviceMatrix& M, const CsrView& A, uint32_t p, int32_t block, uint64_t seed, hipStream_t st,
-                    RankOut* out, int proj) {
+                    RankOut* out, int proj, bool allow_early = true) {
     Error e;
     bwr_rank_info& info = out->info;
     const bool transpose = A.m < A.n;
@@ -257,7 +258,7 @@ Error rank_one_draw(const DeviceMatrix& M, const CsrView& A, uint32_t p, int32_t
     const bool on_device = gpu_leaf_order(s) > 0 && !getenv("BWR_HOST_SIGMA") && !current_arena();
     const int64_t min_chunk = on_device ? online_min_chunk(L) : 0;
     // early termination needs the basis beside the sequence
-    const bool early = min_chunk > 0 && g_early.load() != 0;
+    const bool early = allow_early && min_chunk > 0 && g_early.load() != 0;
     info.s = s;
     info.len = L;
     info.check_terms = CHECK_TERMS;
@@ -295,8 +296,11 @@ Error rank_one_draw(const DeviceMatrix& M, const CsrView& A, uint32_t p, int32_t
         if (!e.ok()) return e;
         drain.st = sst;
         if (early) {
-            const int64_t step = std::max<int64_t>(EARLY_MIN_STEP, L / 32);
-            e = og.begin_early(S.as<uint32_t>(), L, s, p, step, std::max<int64_t>(EARLY_MIN_VERIFY, step / 8), sst);
+            // BWR_EARLY_STEP and BWR_EARLY_VERIFY override the cut lengths (tests use tiny ones)
+            const int64_t step = env_i64("BWR_EARLY_STEP", std::max<int64_t>(EARLY_MIN_STEP, L / 32));
+            const int64_t verify = env_i64("BWR_EARLY_VERIFY", std::max<int64_t>(EARLY_MIN_VERIFY, step / 8));
+            e = og.begin_early(S.as<uint32_t>(), L, s, p, step, verify, sst);
+            if (e.ok()) og.force_converge_at(env_i64("BWR_EARLY_FORCE_AT", 0));
         } else {
             e = og.begin(S.as<uint32_t>(), L, s, p, min_chunk, sst);
         }
@@ -352,6 +356,7 @@ Error rank_one_draw(const DeviceMatrix& M, const CsrView& A, uint32_t p, int32_t
         if (Lg + CHECK_TERMS > have) return Error::inval("too few terms past the generator's order to check it");
         info.len = Lg;
         info.terms = have;
+        out->stopped_early = Lg < L;
         he = hipMemcpyAsync(Sh.data(), S.as<void>(), sizeof(uint32_t) * Sh.size(), hipMemcpyDeviceToHost, st);
         if (he == hipSuccess) he = hipStreamSynchronize(st);
         if (he != hipSuccess) return Error::device(he, "sequence download");
@@ -410,7 +415,17 @@ Error rank_dev_impl(const CsrView& A, uint32_t p, int32_t block, uint64_t seed, 
         std::memset(&one.info, 0, sizeof(one.info));
         one.info.nb = nb;
         one.info.transposed = A.m < A.n ? 1 : 0;
-        if (!(e = rank_one_draw(M, A, p, block, seed + (uint64_t)t, st, &one, proj)).ok()) return e;
+        e = rank_one_draw(M, A, p, block, seed + (uint64_t)t, st, &one, proj);
+        if (e.code == ESHORT_ && one.stopped_early) {
+            // the generator kept by early termination failed its check (a premature stall): the same draw
+            // again at the full length
+            std::memset(&one.info, 0, sizeof(one.info));
+            one.info.nb = nb;
+            one.info.transposed = A.m < A.n ? 1 : 0;
+            one.stopped_early = false;
+            e = rank_one_draw(M, A, p, block, seed + (uint64_t)t, st, &one, proj, false);
+        }
+        if (!e.ok()) return e;
         tseq += one.info.t_sequence;
         tsig += one.info.t_sigma;
         tro += one.info.t_readout;

@@ -272,6 +272,7 @@ Error OnlineGenerator::begin_early(const uint32_t* S_dev, int64_t L, int32_t s, 
     early_ = true;
     step_ = step;
     verify_ = verify;
+    force_at_ = 0;
     ecs_ = EarlyCutState{};
     ecs_.vstep = verify;
     cuts_.clear();
@@ -286,7 +287,7 @@ Error OnlineGenerator::after_chunk_early() {
     BWR_HIP(hipMemcpyAsync(d.data(), db_.as<void>(), sizeof(int64_t) * d.size(), hipMemcpyDeviceToHost, st_));
     BWR_HIP(hipStreamSynchronize(st_));
     const EarlyCutDecision dec = early_cut_after_chunk(d.data(), s_, done_, L_, step_, verify_, &ecs_);
-    if (dec.converged) {
+    if (dec.converged || (force_at_ > 0 && done_ >= force_at_)) {
         conv_.store(done_);
         return {};
     }

@@ -160,6 +160,8 @@ class OnlineGenerator {
     Error begin_early(const uint32_t* S_dev, int64_t L, int32_t s, uint32_t p, int64_t step, int64_t verify,
                       hipStream_t st);
     int64_t converged() const { return conv_.load(); }  // order of the kept basis, 0 while not converged
+    // (tests of the fallback) declare convergence at the first cut at or past order c, stalled or not
+    void force_converge_at(int64_t c) { force_at_ = c; }
     int64_t order() const { return done_; }              // order of the basis computed so far
 
    private:
@@ -185,7 +187,7 @@ class OnlineGenerator {
     Error werr_;
     // early termination
     bool early_ = false;
-    int64_t step_ = 0, verify_ = 0;
+    int64_t step_ = 0, verify_ = 0, force_at_ = 0;
     EarlyCutState ecs_;
     std::atomic<int64_t> conv_{0};
 };

@@ -134,3 +134,27 @@ def test_server_solo_lane(early):
     finally:
         srv.close()
     assert r == 42000
+
+
+def test_short_confirmation_still_right(early, monkeypatch):
+    # confirmation over a single order with short chunks: while the sequence still looks generic the
+    # generator rows take pivots at every order or two, so even this confirms only a true stall
+    monkeypatch.setenv("BWR_EARLY_STEP", "64")
+    monkeypatch.setenv("BWR_EARLY_VERIFY", "1")
+    A = planted(30000, 20000, 9000, 9, 61)
+    announce("early termination: step 64, confirmation over 1 order")
+    for seed in (1, 2, 3):
+        rank, info = bw.rank_modp(A, 65521, 8, seed)
+        assert rank == 9000 and 2 * 9000 // 8 <= info["len"] < _full_len(A, 8), (seed, rank, info["len"])
+
+
+def test_premature_stop_falls_back_to_full_length(early, monkeypatch):
+    # the basis kept (by force) at the cut 1137, long before the generator is complete (about 2 r / s =
+    # 2250): the kept generator fails its check on the terms past its order, and the draw is made again at
+    # the full length, so the rank is right and no error reaches the caller
+    monkeypatch.setenv("BWR_EARLY_FORCE_AT", "700")
+    A = planted(30000, 20000, 9000, 9, 61)
+    announce("early termination: forced premature stop, fallback to the full length")
+    rank, info = bw.rank_modp(A, 65521, 8, 1)
+    assert rank == 9000
+    assert info["len"] == _full_len(A, 8) and info["terms"] == info["len"] + 4
