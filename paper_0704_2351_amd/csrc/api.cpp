@@ -34,7 +34,7 @@ std::atomic<int32_t> g_trials{1};
 std::atomic<int32_t> g_early{0};
 // further draws where the primes of a batched matrix disagree (bwr_set_batch_retry)
 std::atomic<int32_t> g_batch_retry{0};
-// early termination's cut lengths: at least these many orders, else L / 32 and a eighth of that
+// early termination's cut lengths: at least these many orders, else L / 32 and an eighth of that
 constexpr int64_t EARLY_MIN_STEP = 512;
 constexpr int64_t EARLY_MIN_VERIFY = 128;
 
