@@ -235,3 +235,25 @@ def test_early_termination_reading_symmetric_projection(seed):
     c_stop = next(c for c in range(3, L + 1) if sums[c] == sums[c - 3])
     F, _, _ = sigma.min_generator(S[:c_stop], p)
     assert sigma.rank_from_generator(F, p) == A.planted_rank == ge.rank_csr(A, p)
+
+
+@pytest.mark.parametrize("m,n,r,s", [(24, 16, 9, 2), (30, 21, 14, 3), (40, 28, 20, 4)])
+def test_sparse_projection_reading(m, n, r, s):
+    """The premise of sparse projections (the other outlook of the conclusion; not built on the GPU): with U
+    made of stacked s x s identity blocks (one non-zero per row, U[i, i mod s] = 1) and only V, D_r and D_c
+    random, the generator still annihilates the terms past L and reads out the rank, on every draw tried."""
+    A = planted(m, n, r, 3, 123)
+    want = ge.rank_csr(A, P)
+    assert want == r
+    U = np.zeros((n, s), dtype=np.int64)
+    U[np.arange(n), np.arange(n) % s] = 1
+    L = 2 + -(-2 * n // s)
+    for seed in range(6):
+        rng = np.random.default_rng(seed)
+        dr = rng.integers(1, P, size=m)
+        dc = rng.integers(1, P, size=n)
+        V = rng.integers(0, P, size=(n, s))
+        S = oseq.sequence(A, U, V, P, L + 4, dr, dc)
+        F, _, _ = sigma.min_generator(S[:L], P)
+        assert sigma.annihilates(F, S, P)
+        assert sigma.rank_from_generator(F, P) == want
